@@ -1,0 +1,448 @@
+/*
+ * orc_lbm.c -- plain, slow, FP64 CPU oracle for the double-distribution
+ * non-orthogonal MRT lattice Boltzmann method of Liu, He, Li & Li
+ * (arXiv:1510.08224): a D2Q9 MRT equation for the incompressible flow
+ * (Sec. 2.1) and a D2Q5 MRT equation for the temperature (Sec. 2.2),
+ * coupled by the Boussinesq force (Eq. 4).
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the tests, the smoke check
+ * and the CPU-baseline leg of the benchmark load this library.  It shares
+ * no code, header or table with the GPU library.
+ *
+ * It is written to be checked by eye against the paper, not to be fast:
+ *   - array-of-structures storage f[(y*nx+x)*9+i], g[(y*nx+x)*5+i];
+ *   - the collision multiplies by the full dense matrices M (Eq. 13),
+ *     M^-1 (App. A, Eq. A1), N (Eq. 26) and N^-1 (Eq. A2) exactly as
+ *     printed in the paper;
+ *   - the relaxation is the diagonal expression of Eq. 8 / Eq. 24;
+ *   - streaming is a push (Eqs. 9 and 25) into a second array;
+ *   - compiled with -O2 -ffp-contract=off (no fused multiply-add).
+ *
+ * Readings of the paper taken here (each is listed in the design notes):
+ *   R1 (Sec. 2.1, incompressible approximation after Eq. 19): the density
+ *      rho enters m_0^eq, the 2rho/3 of m_3^eq and the rho/9 of m_8^eq;
+ *      every velocity term of m^eq, every source moment and the momentum
+ *      use the reference density rho0, i.e. j = rho0*u.
+ *   R2 (Eq. 17): the printed S~_8 = (2/3) rho (ux Fy + uy Fx) is not M*S
+ *      for the Guo source; the oracle uses (2/3) rho0 (ux Fx + uy Fy),
+ *      which is.  A switch (s8_literal) keeps the printed form.
+ *   R3 (Eqs. 4, 19, 27): at a node, T = sum g (pre-collision), then
+ *      F = a + g*beta*(T - T0)*y_hat, then rho0*u = sum e_i fbar_i + rho0*F/2.
+ *   R4 (Sec. 3 uses non-equilibrium extrapolation, not given in the
+ *      text): walls are link-wise.  Flow: halfway bounce-back with the
+ *      moving-wall term 6 w_i rho0 (e_i . u_w).  Temperature, Dirichlet:
+ *      anti-bounce-back, -g*_opp + varpi*T_w/2.  Temperature, adiabatic:
+ *      bounce-back.  A link that leaves through a top/bottom wall takes
+ *      that wall's velocity, otherwise the left/right wall's.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- lattice (Eq. 5; weights after Eq. 22) -------------------------------- */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const int OPP5[5] = {0, 3, 4, 1, 2};
+static const double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+/* ---- transformation matrices as printed --------------------------------- */
+/* Eq. 13 */
+static const double M9[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 1, 1, 1, 1, 2, 2, 2, 2},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, 0, 0, 0, 1, 1, -1, -1},
+    {0, 0, 0, 0, 0, 1, -1, -1, 1},
+    {0, 0, 0, 0, 0, 1, 1, 1, 1}};
+/* Appendix A, Eq. A1 */
+static const double MI9[9][9] = {
+    {1, 0, 0, -1, 0, 0, 0, 0, 1},
+    {0, 0.5, 0, 0.25, 0.25, 0, 0, -0.5, -0.5},
+    {0, 0, 0.5, 0.25, -0.25, 0, -0.5, 0, -0.5},
+    {0, -0.5, 0, 0.25, 0.25, 0, 0, 0.5, -0.5},
+    {0, 0, -0.5, 0.25, -0.25, 0, 0.5, 0, -0.5},
+    {0, 0, 0, 0, 0, 0.25, 0.25, 0.25, 0.25},
+    {0, 0, 0, 0, 0, -0.25, 0.25, -0.25, 0.25},
+    {0, 0, 0, 0, 0, 0.25, -0.25, -0.25, 0.25},
+    {0, 0, 0, 0, 0, -0.25, -0.25, 0.25, 0.25}};
+/* Eq. 26 */
+static const double N5[5][5] = {
+    {1, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0},
+    {0, 0, 1, 0, -1},
+    {0, 1, 1, 1, 1},
+    {0, 1, -1, 1, -1}};
+/* Appendix A, Eq. A2 */
+static const double NI5[5][5] = {
+    {1, 0, 0, -1, 0},
+    {0, 0.5, 0, 0.25, 0.25},
+    {0, 0, 0.5, 0.25, -0.25},
+    {0, -0.5, 0, 0.25, 0.25},
+    {0, 0, -0.5, 0.25, -0.25}};
+
+enum { SIDE_LEFT = 0, SIDE_RIGHT = 1, SIDE_BOTTOM = 2, SIDE_TOP = 3 };
+enum { FLOW_PERIODIC = 0, FLOW_WALL = 1 };
+enum { TEMP_PERIODIC = 0, TEMP_DIRICHLET = 1, TEMP_ADIABATIC = 2 };
+
+typedef struct {
+    int32_t nx, ny;
+    double s[9];       /* Lambda = diag(s_0..s_8), Eq. 20 */
+    double q[5];       /* Q = diag(zeta_0..zeta_4), Eq. 29 */
+    double varpi;      /* Eq. 28 */
+    double rho0;       /* reference density */
+    double gbeta;      /* g*beta of Eq. 4 */
+    double T0;         /* reference temperature of Eq. 4 */
+    double ax, ay;     /* external acceleration a of Eq. 4 */
+    int32_t bc_flow[4];
+    int32_t bc_temp[4];
+    double wall_T[4];
+    double wall_u[4][2];
+    int32_t s8_literal;
+} orc_params;
+
+typedef struct {
+    orc_params p;
+    double *f, *g;       /* pre-collision state at time t, AoS */
+    double *fn, *gn;     /* streaming target */
+    double *fp, *gp;     /* post-collision state (scratch) */
+    int64_t t;
+} orc_lattice;
+
+/* ------------------------------------------------------------------------- */
+/* Single-node collision: Eqs. 4, 8, 15-20 for f; Eqs. 24, 27-29 for g.      */
+/* ------------------------------------------------------------------------- */
+static void macroscopic(const orc_params* p, const double f[9], const double g[5],
+                        double* rho, double* ux, double* uy, double* T,
+                        double* Fx, double* Fy) {
+    /* Eq. 27: T = n_0 = sum g */
+    double t = 0.0;
+    for (int i = 0; i < 5; ++i) t += g[i];
+    /* Eq. 4: F = g beta (T - T0) j + a */
+    double fx = p->ax;
+    double fy = p->ay + p->gbeta * (t - p->T0);
+    /* Eq. 18 */
+    double r = 0.0;
+    for (int i = 0; i < 9; ++i) r += f[i];
+    /* Eq. 19 with j = rho0 u (reading R1) */
+    double jx = 0.0, jy = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        jx += EX[i] * f[i];
+        jy += EY[i] * f[i];
+    }
+    jx += 0.5 * p->rho0 * fx;
+    jy += 0.5 * p->rho0 * fy;
+    *rho = r;
+    *ux = jx / p->rho0;
+    *uy = jy / p->rho0;
+    *T = t;
+    *Fx = fx;
+    *Fy = fy;
+}
+
+void orc_collide_node(const orc_params* p, const double f[9], const double g[5],
+                      double fo[9], double go[5]) {
+    double rho, ux, uy, T, Fx, Fy;
+    macroscopic(p, f, g, &rho, &ux, &uy, &T, &Fx, &Fy);
+    const double r0 = p->rho0;
+
+    /* m_bar = M fbar (Eq. 10, dense product) */
+    double m[9];
+    for (int k = 0; k < 9; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < 9; ++i) acc += M9[k][i] * f[i];
+        m[k] = acc;
+    }
+    /* Eq. 16 under reading R1 */
+    const double usq = ux * ux + uy * uy;
+    double meq[9];
+    meq[0] = rho;
+    meq[1] = r0 * ux;
+    meq[2] = r0 * uy;
+    meq[3] = 2.0 / 3.0 * rho + r0 * usq;
+    meq[4] = r0 * (ux * ux - uy * uy);
+    meq[5] = r0 * ux * uy;
+    meq[6] = 1.0 / 3.0 * r0 * uy;
+    meq[7] = 1.0 / 3.0 * r0 * ux;
+    meq[8] = 1.0 / 9.0 * rho + 1.0 / 3.0 * r0 * usq;
+    /* Eq. 17 under readings R1, R2 */
+    double S[9];
+    S[0] = 0.0;
+    S[1] = r0 * Fx;
+    S[2] = r0 * Fy;
+    S[3] = 2.0 * r0 * (ux * Fx + uy * Fy);
+    S[4] = 2.0 * r0 * (ux * Fx - uy * Fy);
+    S[5] = r0 * (ux * Fy + uy * Fx);
+    S[6] = 1.0 / 3.0 * r0 * Fy;
+    S[7] = 1.0 / 3.0 * r0 * Fx;
+    S[8] = p->s8_literal ? 2.0 / 3.0 * r0 * (ux * Fy + uy * Fx)
+                         : 2.0 / 3.0 * r0 * (ux * Fx + uy * Fy);
+    /* Eq. 8 with diagonal Lambda (Eq. 20), delta_t = 1 */
+    double ms[9];
+    for (int k = 0; k < 9; ++k)
+        ms[k] = m[k] - p->s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * p->s[k]) * S[k];
+    /* fbar* = M^-1 m_bar* (dense product with Eq. A1) */
+    for (int i = 0; i < 9; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < 9; ++k) acc += MI9[i][k] * ms[k];
+        fo[i] = acc;
+    }
+
+    /* n = N g (dense, Eq. 26) */
+    double n[5];
+    for (int k = 0; k < 5; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < 5; ++i) acc += N5[k][i] * g[i];
+        n[k] = acc;
+    }
+    /* Eq. 28 */
+    double neq[5];
+    neq[0] = T;
+    neq[1] = ux * T;
+    neq[2] = uy * T;
+    neq[3] = p->varpi * T;
+    neq[4] = 0.0;
+    /* Eq. 24 with diagonal Q (Eq. 29) */
+    double ns[5];
+    for (int k = 0; k < 5; ++k) ns[k] = n[k] - p->q[k] * (n[k] - neq[k]);
+    /* g* = N^-1 n* (dense, Eq. A2) */
+    for (int i = 0; i < 5; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < 5; ++k) acc += NI5[i][k] * ns[k];
+        go[i] = acc;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Lattice                                                                    */
+/* ------------------------------------------------------------------------- */
+static int axis_periodic_x(const orc_params* p) { return p->bc_flow[SIDE_LEFT] == FLOW_PERIODIC; }
+static int axis_periodic_y(const orc_params* p) { return p->bc_flow[SIDE_BOTTOM] == FLOW_PERIODIC; }
+
+/* Returns 0 if the parameters describe a consistent lattice. */
+int orc_check_params(const orc_params* p) {
+    if (p->nx < 1 || p->ny < 1) return -1;
+    for (int a = 0; a < 2; ++a) {
+        int s0 = 2 * a, s1 = 2 * a + 1;
+        int fp0 = p->bc_flow[s0] == FLOW_PERIODIC, fp1 = p->bc_flow[s1] == FLOW_PERIODIC;
+        int tp0 = p->bc_temp[s0] == TEMP_PERIODIC, tp1 = p->bc_temp[s1] == TEMP_PERIODIC;
+        if (fp0 != fp1 || tp0 != tp1 || fp0 != tp0) return -2;
+    }
+    for (int s = 0; s < 4; ++s) {
+        if (p->bc_flow[s] < 0 || p->bc_flow[s] > 1) return -3;
+        if (p->bc_temp[s] < 0 || p->bc_temp[s] > 2) return -3;
+    }
+    if (!(p->rho0 > 0.0)) return -4;
+    return 0;
+}
+
+orc_lattice* orc_create(const orc_params* p) {
+    if (orc_check_params(p) != 0) return NULL;
+    orc_lattice* L = (orc_lattice*)calloc(1, sizeof(orc_lattice));
+    if (!L) return NULL;
+    L->p = *p;
+    size_t n = (size_t)p->nx * (size_t)p->ny;
+    L->f = (double*)calloc(n * 9, sizeof(double));
+    L->fn = (double*)calloc(n * 9, sizeof(double));
+    L->fp = (double*)calloc(n * 9, sizeof(double));
+    L->g = (double*)calloc(n * 5, sizeof(double));
+    L->gn = (double*)calloc(n * 5, sizeof(double));
+    L->gp = (double*)calloc(n * 5, sizeof(double));
+    if (!L->f || !L->fn || !L->fp || !L->g || !L->gn || !L->gp) {
+        free(L->f); free(L->fn); free(L->fp); free(L->g); free(L->gn); free(L->gp);
+        free(L);
+        return NULL;
+    }
+    return L;
+}
+
+void orc_destroy(orc_lattice* L) {
+    if (!L) return;
+    free(L->f); free(L->fn); free(L->fp); free(L->g); free(L->gn); free(L->gp);
+    free(L);
+}
+
+/* Rest state: fbar_i = f_i^eq(rho0, u=0) (Eq. 22) and g_i = g_i^eq(T, u=0)
+ * (Eq. 30).  T is nx*ny values in [y][x] order, or NULL for T = T0. */
+void orc_init_equilibrium(orc_lattice* L, const double* T) {
+    const orc_params* p = &L->p;
+    size_t n = (size_t)p->nx * (size_t)p->ny;
+    for (size_t c = 0; c < n; ++c) {
+        double t = T ? T[c] : p->T0;
+        for (int i = 0; i < 9; ++i) L->f[c * 9 + i] = W9[i] * p->rho0;
+        L->g[c * 5 + 0] = (1.0 - p->varpi) * t;
+        for (int i = 1; i < 5; ++i) L->g[c * 5 + i] = 0.25 * p->varpi * t;
+    }
+    L->t = 0;
+}
+
+/* State exchange in plane order [i][y][x] (pre-collision at time t). */
+void orc_set_state(orc_lattice* L, const double* f, const double* g) {
+    size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    for (size_t c = 0; c < n; ++c) {
+        for (int i = 0; i < 9; ++i) L->f[c * 9 + i] = f[(size_t)i * n + c];
+        for (int i = 0; i < 5; ++i) L->g[c * 5 + i] = g[(size_t)i * n + c];
+    }
+}
+
+void orc_get_state(const orc_lattice* L, double* f, double* g) {
+    size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    for (size_t c = 0; c < n; ++c) {
+        for (int i = 0; i < 9; ++i) f[(size_t)i * n + c] = L->f[c * 9 + i];
+        for (int i = 0; i < 5; ++i) g[(size_t)i * n + c] = L->g[c * 5 + i];
+    }
+}
+
+int64_t orc_time(const orc_lattice* L) { return L->t; }
+
+/* Push streaming (Eqs. 9, 25) from fp/gp into fn/gn, with link-wise walls
+ * (reading R4).  Every (node, direction) slot of the target is written
+ * exactly once: either by the neighbour upstream or by the wall rule. */
+static void stream_push(orc_lattice* L) {
+    const orc_params* p = &L->p;
+    const int nx = p->nx, ny = p->ny;
+    const int px = axis_periodic_x(p), py = axis_periodic_y(p);
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            size_t c = (size_t)y * nx + x;
+            for (int i = 0; i < 9; ++i) {
+                int tx = x + EX[i], ty = y + EY[i];
+                int outx = (tx < 0 || tx >= nx), outy = (ty < 0 || ty >= ny);
+                if (outx && px) tx = (tx + nx) % nx;
+                if (outy && py) ty = (ty + ny) % ny;
+                int wallx = outx && !px, wally = outy && !py;
+                if (!wallx && !wally) {
+                    L->fn[((size_t)ty * nx + tx) * 9 + i] = L->fp[c * 9 + i];
+                } else {
+                    int side = wally ? (ty < 0 ? SIDE_BOTTOM : SIDE_TOP)
+                                     : (tx < 0 ? SIDE_LEFT : SIDE_RIGHT);
+                    double eu = EX[i] * p->wall_u[side][0] + EY[i] * p->wall_u[side][1];
+                    L->fn[c * 9 + OPP9[i]] = L->fp[c * 9 + i] - 6.0 * W9[i] * p->rho0 * eu;
+                }
+            }
+            for (int i = 0; i < 5; ++i) {
+                int tx = x + EX[i], ty = y + EY[i];
+                int outx = (tx < 0 || tx >= nx), outy = (ty < 0 || ty >= ny);
+                if (outx && px) tx = (tx + nx) % nx;
+                if (outy && py) ty = (ty + ny) % ny;
+                int wallx = outx && !px, wally = outy && !py;
+                if (!wallx && !wally) {
+                    L->gn[((size_t)ty * nx + tx) * 5 + i] = L->gp[c * 5 + i];
+                } else {
+                    int side = wally ? (ty < 0 ? SIDE_BOTTOM : SIDE_TOP)
+                                     : (tx < 0 ? SIDE_LEFT : SIDE_RIGHT);
+                    if (p->bc_temp[side] == TEMP_DIRICHLET)
+                        L->gn[c * 5 + OPP5[i]] = -L->gp[c * 5 + i] + 0.5 * p->varpi * p->wall_T[side];
+                    else
+                        L->gn[c * 5 + OPP5[i]] = L->gp[c * 5 + i];
+                }
+            }
+        }
+    }
+}
+
+static void collide_all(orc_lattice* L) {
+    size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    for (size_t c = 0; c < n; ++c)
+        orc_collide_node(&L->p, L->f + c * 9, L->g + c * 5, L->fp + c * 9, L->gp + c * 5);
+}
+
+/* Advance n time steps: collide every node, then push-stream. */
+void orc_step(orc_lattice* L, int64_t nsteps) {
+    for (int64_t s = 0; s < nsteps; ++s) {
+        collide_all(L);
+        stream_push(L);
+        double* t;
+        t = L->f; L->f = L->fn; L->fn = t;
+        t = L->g; L->g = L->gn; L->gn = t;
+        L->t += 1;
+    }
+}
+
+/* Post-collision state of the current time level, plane order, without
+ * advancing the lattice. */
+void orc_post_collision(orc_lattice* L, double* f, double* g) {
+    collide_all(L);
+    size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    for (size_t c = 0; c < n; ++c) {
+        for (int i = 0; i < 9; ++i) f[(size_t)i * n + c] = L->fp[c * 9 + i];
+        for (int i = 0; i < 5; ++i) g[(size_t)i * n + c] = L->gp[c * 5 + i];
+    }
+}
+
+/* rho, ux, uy, T at time t (Eqs. 18, 19, 27), [y][x] order; NULL skips. */
+void orc_moments(const orc_lattice* L, double* rho, double* ux, double* uy, double* T) {
+    size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    for (size_t c = 0; c < n; ++c) {
+        double r, u, v, t, fx, fy;
+        macroscopic(&L->p, L->f + c * 9, L->g + c * 5, &r, &u, &v, &t, &fx, &fy);
+        if (rho) rho[c] = r;
+        if (ux) ux[c] = u;
+        if (uy) uy[c] = v;
+        if (T) T[c] = t;
+    }
+}
+
+/* Local Nusselt number along one Dirichlet wall (Eq. 39 and the local
+ * definition before it): Nu = -L (dT/dx_normal-axis)_wall / dT, with the
+ * wall half a spacing outside the first node, and the wall-normal gradient
+ * from a second-order one-sided fit through T_wall, T(1/2), T(3/2):
+ *     dT/dn = (9 T1 - T2 - 8 Tw) / 3       (n into the fluid).
+ * On the left/bottom wall d/dx (d/dy) = d/dn; on the right/top it is -d/dn.
+ * nu_local gets one value per wall node (ny for left/right, nx for
+ * bottom/top) and may be NULL.  Returns 0, or -1 for a bad side. */
+int orc_nusselt(const orc_lattice* L, int side, double length, double dT,
+                double* nu_local, double* nu_mean, double* nu_max, int32_t* i_max) {
+    const orc_params* p = &L->p;
+    const int nx = p->nx, ny = p->ny;
+    if (side < 0 || side > 3) return -1;
+    if (p->bc_temp[side] != TEMP_DIRICHLET) return -1;
+    int vertical = (side == SIDE_LEFT || side == SIDE_RIGHT);
+    int count = vertical ? ny : nx;
+    int depth = vertical ? nx : ny;
+    if (depth < 2) return -1;
+    double tw = p->wall_T[side];
+    double sign = (side == SIDE_LEFT || side == SIDE_BOTTOM) ? 1.0 : -1.0;
+    double sum = 0.0, best = -INFINITY;
+    int ibest = -1;
+    for (int k = 0; k < count; ++k) {
+        int x1, y1, x2, y2;
+        if (side == SIDE_LEFT)   { x1 = 0;      y1 = k; x2 = 1;      y2 = k; }
+        else if (side == SIDE_RIGHT) { x1 = nx - 1; y1 = k; x2 = nx - 2; y2 = k; }
+        else if (side == SIDE_BOTTOM) { x1 = k; y1 = 0;      x2 = k; y2 = 1; }
+        else { x1 = k; y1 = ny - 1; x2 = k; y2 = ny - 2; }
+        const double* g1 = L->g + ((size_t)y1 * nx + x1) * 5;
+        const double* g2 = L->g + ((size_t)y2 * nx + x2) * 5;
+        double t1 = 0.0, t2 = 0.0;
+        for (int i = 0; i < 5; ++i) { t1 += g1[i]; t2 += g2[i]; }
+        double dtdn = (9.0 * t1 - t2 - 8.0 * tw) / 3.0;
+        double nu = -length * (sign * dtdn) / dT;
+        if (nu_local) nu_local[k] = nu;
+        sum += nu;
+        if (nu > best) { best = nu; ibest = k; }
+    }
+    if (nu_mean) *nu_mean = sum / count;
+    if (nu_max) *nu_max = best;
+    if (i_max) *i_max = ibest;
+    return 0;
+}
+
+/* The oracle's own tables, exported so that the tests can compare them
+ * with the printed matrices and with the basis construction of Eq. 12. */
+void orc_tables(double* m9, double* mi9, double* n5, double* ni5, double* w9,
+                int32_t* ex, int32_t* ey) {
+    if (m9) memcpy(m9, M9, sizeof(M9));
+    if (mi9) memcpy(mi9, MI9, sizeof(MI9));
+    if (n5) memcpy(n5, N5, sizeof(N5));
+    if (ni5) memcpy(ni5, NI5, sizeof(NI5));
+    if (w9) memcpy(w9, W9, sizeof(W9));
+    if (ex) for (int i = 0; i < 9; ++i) ex[i] = EX[i];
+    if (ey) for (int i = 0; i < 9; ++i) ey[i] = EY[i];
+}
+
+size_t orc_params_size(void) { return sizeof(orc_params); }

@@ -1,0 +1,125 @@
+"""Exact (rational) single-node reference for the collision, used to pin the
+oracle.  It follows a route independent of the oracle's:
+
+* velocities are evaluated from the trigonometric definition of Eq. 5;
+* M and N are built from their basis definitions (Eq. 12: products
+  e_x^p e_y^q; Eq. 26: 1, e_x, e_y, e_x^2+e_y^2, e_x^2-e_y^2) and inverted
+  by exact Gauss-Jordan elimination, not taken from the printed tables;
+* the update is the velocity-space form, Eq. 7,
+      fbar* = fbar - Lt (fbar - f^eq) + (S - Lt S / 2),  Lt = M^-1 Lambda M,
+  with f^eq from Eq. 22 and S the Guo forcing term in velocity space, whose
+  moments Eq. 10 defines as S~ = M S;
+* the thermal update is Eq. 23 with g^eq from Eq. 30.
+
+All arithmetic is in Fractions, so the only rounding is the final
+conversion.  The incompressible reading is the one the build uses: rho only
+in the rest part of f^eq, rho0 on every velocity term and in the force.
+"""
+from fractions import Fraction as Fr
+import math
+
+
+def velocities_eq5():
+    """Eq. 5 with c = 1, rounded to the integer lattice."""
+    e = [(0, 0)]
+    for i in range(1, 5):
+        a = (i - 1) * math.pi / 2
+        e.append((round(math.cos(a)), round(math.sin(a))))
+    for i in range(5, 9):
+        a = (2 * i - 9) * math.pi / 4
+        e.append((round(math.sqrt(2) * math.cos(a)), round(math.sqrt(2) * math.sin(a))))
+    return e
+
+
+E9 = velocities_eq5()
+E5 = E9[:5]
+W9 = [Fr(4, 9)] + [Fr(1, 9)] * 4 + [Fr(1, 36)] * 4   # weights stated after Eq. 22
+
+
+def basis_m9():
+    """Rows |M_0>..|M_8> of Eq. 12 from their definitions."""
+    defs = [lambda x, y: 1, lambda x, y: x, lambda x, y: y,
+            lambda x, y: x * x + y * y, lambda x, y: x * x - y * y, lambda x, y: x * y,
+            lambda x, y: x * x * y, lambda x, y: x * y * y, lambda x, y: x * x * y * y]
+    return [[Fr(d(ex, ey)) for (ex, ey) in E9] for d in defs]
+
+
+def basis_n5():
+    """Rows of N (Eq. 26) from their definitions."""
+    defs = [lambda x, y: 1, lambda x, y: x, lambda x, y: y,
+            lambda x, y: x * x + y * y, lambda x, y: x * x - y * y]
+    return [[Fr(d(ex, ey)) for (ex, ey) in E5] for d in defs]
+
+
+def inverse(a):
+    n = len(a)
+    m = [list(row) + [Fr(int(i == j)) for j in range(n)] for i, row in enumerate(a)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if m[r][c] != 0)
+        m[c], m[p] = m[p], m[c]
+        piv = m[c][c]
+        m[c] = [v / piv for v in m[c]]
+        for r in range(n):
+            if r != c and m[r][c] != 0:
+                fac = m[r][c]
+                m[r] = [vr - fac * vc for vr, vc in zip(m[r], m[c])]
+    return [row[n:] for row in m]
+
+
+def matmul(a, b):
+    return [[sum(a[i][k] * b[k][j] for k in range(len(b))) for j in range(len(b[0]))]
+            for i in range(len(a))]
+
+
+def matvec(a, v):
+    return [sum(a[i][k] * v[k] for k in range(len(v))) for i in range(len(a))]
+
+
+def diag(d):
+    n = len(d)
+    return [[d[i] if i == j else Fr(0) for j in range(n)] for i in range(n)]
+
+
+M9 = basis_m9()
+M9I = inverse(M9)
+N5 = basis_n5()
+N5I = inverse(N5)
+
+
+def collide(f, g, s, q, varpi, gbeta, T0, ax, ay, rho0=Fr(1)):
+    """Exact post-collision (fbar*, g*) at one node.  Every argument is a
+    Fraction (or a list of them); s and q are the full diagonals."""
+    T = sum(g)                                       # Eq. 27
+    Fx = ax
+    Fy = ay + gbeta * (T - T0)                       # Eq. 4
+    rho = sum(f)                                     # Eq. 18
+    ux = (sum(e[0] * fi for e, fi in zip(E9, f)) + rho0 * Fx / 2) / rho0   # Eq. 19
+    uy = (sum(e[1] * fi for e, fi in zip(E9, f)) + rho0 * Fy / 2) / rho0
+    usq = ux * ux + uy * uy
+    feq, S = [], []
+    for (ex, ey), w in zip(E9, W9):
+        eu = ex * ux + ey * uy
+        eF = ex * Fx + ey * Fy
+        uF = ux * Fx + uy * Fy
+        feq.append(w * (rho + rho0 * (3 * eu + Fr(9, 2) * eu * eu - Fr(3, 2) * usq)))  # Eq. 22
+        S.append(w * rho0 * (3 * eF - 3 * uF + 9 * eu * eF))       # Guo source
+    Lt = matmul(M9I, matmul(diag(s), M9))            # Lambda~ = M^-1 Lambda M
+    neq = [fi - fe for fi, fe in zip(f, feq)]
+    c1 = matvec(Lt, neq)
+    c2 = matvec(Lt, S)
+    fo = [fi - a + si - b / 2 for fi, a, si, b in zip(f, c1, S, c2)]   # Eq. 7
+    geq = [(1 - varpi) * T] + [varpi * T / 4 + (ex * ux + ey * uy) * T / 2 for (ex, ey) in E5[1:]]  # Eq. 30
+    Qt = matmul(N5I, matmul(diag(q), N5))
+    d = matvec(Qt, [gi - ge for gi, ge in zip(g, geq)])
+    go = [gi - di for gi, di in zip(g, d)]           # Eq. 23
+    return fo, go
+
+
+def guo_moments(ux, uy, Fx, Fy, rho0=Fr(1)):
+    """M S for the Guo source: the moment-space source that Eq. 10 defines."""
+    S = []
+    for (ex, ey), w in zip(E9, W9):
+        eu = ex * ux + ey * uy
+        eF = ex * Fx + ey * Fy
+        S.append(w * rho0 * (3 * eF - 3 * (ux * Fx + uy * Fy) + 9 * eu * eF))
+    return matvec(M9, S)

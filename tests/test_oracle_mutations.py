@@ -1,0 +1,132 @@
+"""The pins must catch plausible mistakes in the oracle.  Each case copies
+oracle/orc_lbm.c to a temporary directory, plants one mistake by text
+substitution (a dropped term, a wrong sign, a transposed operand, a wrong
+index), builds it with the same flags, and runs a quick battery of the
+pins from the other oracle tests against the copy.  At least one pin must
+fail for every planted mistake; the unmodified copy must pass them all."""
+import ctypes
+import os
+import shutil
+import subprocess
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle
+import exact_ref as X
+from paper_1510_08224_amd import workloads as W
+
+MUTANTS = {
+    "none": None,
+    "dropped_half_force": ("jx += 0.5 * p->rho0 * fx;", "jx += 0.0 * p->rho0 * fx;"),
+    "minv_sign": ("{1, 0, 0, -1, 0, 0, 0, 0, 1},", "{1, 0, 0, 1, 0, 0, 0, 0, 1},"),
+    "m_transposed": ("acc += M9[k][i] * f[i];", "acc += M9[i][k] * f[i];"),
+    "s7_wrong_component": ("S[7] = 1.0 / 3.0 * r0 * Fx;", "S[7] = 1.0 / 3.0 * r0 * Fy;"),
+    "s8_printed": ("S[8] = p->s8_literal ?", "S[8] = !p->s8_literal ?"),
+    "meq3_coefficient": ("meq[3] = 2.0 / 3.0 * rho + r0 * usq;", "meq[3] = 1.0 / 3.0 * rho + r0 * usq;"),
+    "neq3_no_varpi": ("neq[3] = p->varpi * T;", "neq[3] = T;"),
+    "neq1_wrong_u": ("neq[1] = ux * T;", "neq[1] = uy * T;"),
+    "opposite_table": ("{0, 3, 4, 1, 2, 7, 8, 5, 6}", "{0, 3, 4, 1, 2, 8, 7, 6, 5}"),
+    "antibounce_sign": ("= -L->gp[c * 5 + i] + 0.5 * p->varpi", "= L->gp[c * 5 + i] + 0.5 * p->varpi"),
+    "moving_wall_sign": ("L->fp[c * 9 + i] - 6.0 * W9[i]", "L->fp[c * 9 + i] + 6.0 * W9[i]"),
+    "buoyancy_sign": ("p->ay + p->gbeta * (t - p->T0)", "p->ay - p->gbeta * (t - p->T0)"),
+    "nusselt_first_order": ("(9.0 * t1 - t2 - 8.0 * tw) / 3.0", "2.0 * (t1 - tw)"),
+    "stream_index": ("L->fn[((size_t)ty * nx + tx) * 9 + i]", "L->fn[((size_t)ty * nx + tx) * 9 + OPP9[i]]"),
+}
+
+
+def _build(tmp, name, mut):
+    src = open(oracle._SRC).read()
+    if mut is not None:
+        assert src.count(mut[0]) >= 1, name
+        src = src.replace(mut[0], mut[1], 1)
+    c = os.path.join(tmp, f"{name}.c")
+    so = os.path.join(tmp, f"lib{name}.so")
+    open(c, "w").write(src)
+    subprocess.run(["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", so, c, "-lm"],
+                   check=True)
+    return oracle.load(so)
+
+
+def _p(lib_s, s, q, **kw):
+    p = oracle.OrcParams()
+    p.nx = p.ny = 1
+    for k in range(9):
+        p.s[k] = s[k]
+    for k in range(5):
+        p.q[k] = q[k]
+    p.varpi, p.rho0 = kw.get("varpi", 0.5), 1.0
+    p.gbeta, p.T0, p.ax, p.ay = kw.get("gbeta", 0.0), kw.get("T0", 0.5), kw.get("ax", 0.0), kw.get("ay", 0.0)
+    return p
+
+
+def _battery(lib):
+    """Return the names of the pins that fail for this oracle build."""
+    failed = []
+    # exact single-node collision (Eq. 7 in rationals)
+    rng = np.random.default_rng(0)
+    for seed in range(3):
+        s = [1, 1, 1, 1.6, 1.3, 1.3, 1.1, 1.1, 1.8]
+        q = [1, 1.2, 1.2, 1.9, 1.7]
+        p = _p(lib, s, q, gbeta=0.03, T0=0.4, ax=2e-3, ay=-1e-3, varpi=0.45)
+        w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+        f = w * (1 + 0.4 * rng.uniform(-1, 1, 9))
+        g = np.array([0.5] + [0.125] * 4) * (1 + 0.4 * rng.uniform(-1, 1, 5))
+        fo, go = oracle.collide_node(p, f, g, library=lib)
+        fe, ge = X.collide([Fr(v) for v in f], [Fr(v) for v in g], [Fr(v) for v in p.s],
+                           [Fr(v) for v in p.q], Fr(p.varpi), Fr(p.gbeta), Fr(p.T0), Fr(p.ax), Fr(p.ay))
+        if (np.max(np.abs(fo - np.array([float(v) for v in fe]))) > 1e-14
+                or np.max(np.abs(go - np.array([float(v) for v in ge]))) > 1e-14):
+            failed.append("collision_exact")
+            break
+    # Couette exact (moving wall, Dirichlet walls)
+    L = oracle.Lattice(W.channel(3, 16, s_nu=1.3, zeta_alpha=1.1, u_top=(0.05, 0.0)), library=lib)
+    L.step(12000)
+    _, ux, uy, T = L.moments()
+    y = (np.arange(16) + 0.5) / 16
+    if not (np.max(np.abs(ux - 0.05 * y[:, None])) < 1e-13 and np.max(np.abs(T - y[:, None])) < 1e-13):
+        failed.append("couette_exact")
+    # mass conservation and the centro-symmetry of the heated cavity
+    L = oracle.Lattice(W.cavity(12, 1e5, t_hot=0.5, t_cold=-0.5), library=lib)
+    r0 = L.moments()[0].sum()
+    L.step(300)
+    rho, ux, uy, T = L.moments()
+    if abs(rho.sum() - r0) / r0 > 1e-13 or not np.all(np.isfinite(rho)):
+        failed.append("mass")
+    if np.max(np.abs(ux + ux[::-1, ::-1])) > 1e-14 or np.max(np.abs(T + T[::-1, ::-1])) > 1e-14:
+        failed.append("centro_symmetry")
+    # the hot wall must drive an upward flow next to it (buoyancy sign, Eq. 4)
+    if not uy[6, 0] > 0:
+        failed.append("buoyancy_direction")
+    # Nusselt stencil on a quadratic profile
+    pb = W.cavity(6, 1e4).replace(u_c=0.0, s_nu=1.0, zeta_alpha=1.0)
+    xx = np.arange(6) + 0.5
+    Tq = 1.0 - 0.1 * xx + 0.004 * xx ** 2
+    L = oracle.Lattice(pb, T_init=np.tile(Tq, (6, 1)), library=lib)
+    if abs(L.nusselt(W.LEFT)[0] - 6 * 0.1) > 1e-12:
+        failed.append("nusselt_quadratic")
+    # mirror symmetry of a Rayleigh-Benard cell with a symmetric start
+    T = W.rb_initial_temperature(12, 6, amp=1e-2, seed=9)
+    T = 0.5 * (T + T[:, ::-1])
+    L = oracle.Lattice(W.rayleigh_benard(12, 6, 5e4), T_init=T, library=lib)
+    L.step(200)
+    _, ux, uy, T1 = L.moments()
+    if np.max(np.abs(ux + ux[:, ::-1])) > 1e-14 or np.max(np.abs(T1 - T1[:, ::-1])) > 1e-14:
+        failed.append("rb_mirror")
+    return failed
+
+
+@pytest.fixture(scope="module")
+def tmpdir_mod(tmp_path_factory):
+    return str(tmp_path_factory.mktemp("mutants"))
+
+
+@pytest.mark.parametrize("name", list(MUTANTS))
+def test_planted_mistake_is_caught(name, tmpdir_mod):
+    lib = _build(tmpdir_mod, name, MUTANTS[name])
+    failed = _battery(lib)
+    if name == "none":
+        assert failed == []
+    else:
+        assert failed, f"mutant {name} passed every pin"
