@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D2Q9 + D2Q5 non-orthogonal MRT step on one MI355X.
+
+Workload: the differentially heated square cavity, 2048 x 2048 nodes,
+Ra = 1e6, Pr = 0.71, u_c = 0.1, from rest at T = 0.5, synthetic (the
+paper's problem of Sec. 3.4 at a production size).  One benchmark "step" is
+one time step of the whole lattice; every 1000 steps the run also takes the
+wall Nusselt numbers (both walls) and the steady-state residual, as a real
+solve does.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS for FP64 storage (the plain method) with the
+roofline of the step kernel measured with HIP events on the solver's
+stream, the same figures for FP32 and FP16 deviation storage, and the CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--storage f64] [--variants f32,f16]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0              # MI355X HBM3E, published peak
+BYTES = {"f64": 8, "f32": 4, "f16": 2}
+VALUES_PER_NODE = 28               # 9 + 5 populations read, 9 + 5 written
+REDUCE_EVERY = 1000
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1510_08224_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str, nodes: int):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter runs, if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec.get("kernels", {}).get(storage)
+    if not ent or rec.get("source_hash") != kernel_source_hash() or ent.get("nodes") != nodes:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_storage(storage: str, pb, steps: int, warmup: int, launch=None) -> dict:
+    import torch
+    from paper_1510_08224_amd import lbm
+
+    S = lbm.Solver(pb.nx, pb.ny, storage, torch_memory=True)
+    S.set_params(pb)
+    if launch:
+        S.set_launch(*launch)
+    st = torch.cuda.ExternalStream(S.stream)
+    S.step(warmup)
+    S.residual()
+    S.synchronize()
+    torch.cuda.synchronize()
+    nodes = pb.nx * pb.ny
+    segs = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(REDUCE_EVERY, steps - done)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        S.step(k)
+        e1.record(st)
+        segs.append((e0, e1, k))
+        done += k
+        if done % REDUCE_EVERY == 0 or done == steps:
+            S.nusselt(0)
+            S.nusselt(1)
+            r, bad = S.residual(raise_unstable=False)
+    S.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in segs)
+    nu = S.nusselt(1)[0]
+    S.close()
+    avg_launch_s = sweep_ms / 1e3 / steps
+    alg_bytes = VALUES_PER_NODE * BYTES[storage] * nodes
+    achieved = alg_bytes / avg_launch_s / 1e9
+    traffic = measured_traffic(storage, nodes)
+    return {
+        "storage": storage,
+        "mlups": nodes * steps / wall / 1e6,
+        "ms_per_step": wall * 1e3 / steps,
+        "sweep_us_per_launch": avg_launch_s * 1e6,
+        "sweep_mlups": nodes / avg_launch_s / 1e6,
+        "residual_last": r,
+        "nonfinite": bad,
+        "nu_right_mean": nu,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes},
+    }
+
+
+def cpu_baseline(pb, steps: int) -> dict:
+    import oracle
+
+    L = oracle.Lattice(pb)
+    t0 = time.perf_counter()
+    L.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(pb.nx * pb.ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{pb.nx}x{pb.ny} cavity Ra={pb.ra:g}, {steps} steps from rest, FP64, "
+                      f"single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--storage", default="f64", choices=list(BYTES))
+    ap.add_argument("--variants", default="f32,f16", help="other storages to time ('none' for none)")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n", type=int, default=2048, help="cavity side")
+    ap.add_argument("--launch", default="", help="block_x,block_y,rows")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a single lattice would shard as y-slabs with a halo exchange, not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1510_08224_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    pb = W.cavity(args.n, 1e6, 0.71, 0.1)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    main_res = time_storage(args.storage, pb, args.steps, args.warmup, launch)
+    variants = {}
+    if args.variants != "none":
+        for s in args.variants.split(","):
+            if s and s != args.storage:
+                variants[s] = time_storage(s, pb, args.steps, args.warmup, launch)
+    cpu = None if args.no_cpu else cpu_baseline(pb, args.cpu_steps)
+    out = {
+        "metric": "MLUPS & %HBM roofline, FP64 vs FP32/FP16 store; served p50/p99 latency",
+        "value": round(main_res["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": f"cavity{args.n}_ra1e6_pr0.71_uc0.1", "nx": args.n, "ny": args.n,
+                   "storage": args.storage, "reduce_every": REDUCE_EVERY,
+                   "device": torch.cuda.get_device_name(0)},
+        "roofline": main_res["roofline"],
+        "cpu_baseline": cpu,
+        "sweep_mlups": round(main_res["sweep_mlups"], 1),
+        "sweep_us_per_launch": round(main_res["sweep_us_per_launch"], 3),
+        "nu_right_mean": main_res["nu_right_mean"],
+        "storage_variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
+                                 "sweep_mlups": round(v["sweep_mlups"], 1), "roofline": v["roofline"],
+                                 "nu_right_mean": v["nu_right_mean"]}
+                             for k, v in variants.items()},
+        "source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the double-distribution
+ * non-orthogonal multiple-relaxation-time lattice Boltzmann method of
+ * Liu, He, Li & Li, "Non-orthogonal multiple-relaxation-time lattice
+ * Boltzmann method for incompressible thermal flows" (arXiv:1510.08224).
+ *
+ * One solver advances, on one GPU, a 2-D lattice with
+ *   - a D2Q9 flow population fbar (Sec. 2.1): collision in the raw-moment
+ *     space of the non-orthogonal matrix M (Eqs. 8, 13, 16, 17, 20), with
+ *     the transformed populations fbar = f - S/2 (Eq. 7);
+ *   - a D2Q5 temperature population g (Sec. 2.2): collision in the moment
+ *     space of N (Eqs. 24, 26, 28, 29);
+ *   - the Boussinesq force F = g beta (T - T0) y_hat + a (Eq. 4);
+ *   - streaming in velocity space (Eqs. 9, 25) with link-wise walls.
+ *
+ * Conventions for every entry point:
+ *   - lattice units: delta_x = delta_t = c = 1, rho0 = 1 (Sec. 3);
+ *   - every call returns LBM_OK (0) or a negative lbm_status; nothing aborts
+ *     and no C++ exception crosses the ABI; lbm_last_error() explains a
+ *     failure;
+ *   - host arrays are caller-owned, row-major [y][x] (x fastest) for fields
+ *     and [i][y][x] for populations, FP64;
+ *   - device pointers are caller-owned device memory on the solver's GPU;
+ *   - the library owns every allocation it makes and frees it in
+ *     lbm_destroy; a buffer handed to lbm_create_ext stays the caller's
+ *     and must outlive the solver;
+ *   - lbm_step is asynchronous on the solver's stream; readouts that fill
+ *     host memory synchronize that stream before returning;
+ *   - a solver handle is not thread-safe; use one per host thread.
+ *
+ * State and time.  The library holds, for time t, the populations that
+ * streaming (with the wall rules) turns into the pre-collision populations
+ * fbar(x, t), g(x, t).  "Populations at time t" always means those
+ * pre-collision populations (the state after streaming, before collision);
+ * moments, Nusselt numbers and residuals are computed from them.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+typedef struct lbm_solver lbm_solver; /* opaque, library-owned */
+
+/* Return codes. */
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,         /* invalid argument (sizes, rates, sides, NULL) */
+    LBM_ERR_NOMEM = -2,       /* device or host allocation failed / buffer too small */
+    LBM_ERR_DEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+    LBM_ERR_STATE = -4,       /* call out of order (e.g. step before set_params) */
+    LBM_ERR_UNSTABLE = -5,    /* non-finite values found by a reduction */
+    LBM_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+};
+
+/* Population storage in device memory.  LBM_F64 stores the populations
+ * themselves and collides in FP64.  LBM_F32 and LBM_F16 store deviations
+ * from the rest equilibrium (fbar_i - w_i rho0 and g_i - g_i^eq(T0, 0), the
+ * latter scaled by a power of two for FP16) rounded to nearest even, and
+ * collide in FP32; the conserved sums (rho, rho0 u, T) are accumulated in
+ * FP64 in every mode. */
+enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
+
+enum lbm_side { LBM_LEFT = 0, LBM_RIGHT = 1, LBM_BOTTOM = 2, LBM_TOP = 3 };
+
+/* Flow boundary per side.  LBM_BC_WALL is halfway bounce-back with the
+ * moving-wall term: a population leaving node x through the wall returns
+ * to x in the opposite direction j with 6 w_j rho0 (e_j . u_w) added.
+ * Periodicity is per axis: both sides of an axis must be periodic, for
+ * flow and temperature alike, or neither. */
+enum lbm_bc_flow { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 };
+
+/* Temperature boundary per side.  LBM_T_DIRICHLET is anti-bounce-back,
+ * g_j(x) = -g*_opp(j)(x) + varpi T_w / 2; LBM_T_ADIABATIC is bounce-back,
+ * g_j(x) = g*_opp(j)(x) (zero normal flux). */
+enum lbm_bc_temp { LBM_T_PERIODIC = 0, LBM_T_DIRICHLET = 1, LBM_T_ADIABATIC = 2 };
+
+/* Problem statement (Secs. 2-3 of the paper).  Fill with
+ * lbm_params_default() first; struct_size versions the layout. */
+typedef struct {
+    uint32_t struct_size;  /* = sizeof(lbm_params) */
+    uint32_t reserved0;
+    double ra, pr;         /* Rayleigh and Prandtl numbers (Eq. 40) */
+    double u_c;            /* characteristic velocity sqrt(g beta dT L); Ma = sqrt(3) u_c (Eq. 40) */
+    double length;         /* L in Eq. 40 and in the Nusselt number; 0 => ny */
+    double t_hot, t_cold;  /* dT = t_hot - t_cold, T0 = (t_hot + t_cold)/2 (Sec. 3.4) */
+    double s_e, s_q, s_eps;        /* free D2Q9 rates (Eq. 20); defaults 1.6, 1.2, 1.8 */
+    double zeta_e, zeta_nu, varpi; /* free D2Q5 rates (Eq. 29) and varpi (Eq. 28); 1.9, 1.9, 0.5 */
+    double s_nu, zeta_alpha;       /* 0 => from Eq. 40; > 0 => used as given */
+    double ax, ay;                 /* external acceleration a (Eq. 4) */
+    int32_t bc_flow[4];            /* enum lbm_bc_flow, indexed by enum lbm_side */
+    int32_t bc_temp[4];            /* enum lbm_bc_temp */
+    double wall_T[4];              /* Dirichlet wall temperatures */
+    double wall_u[4][2];           /* wall velocities (ux, uy) */
+} lbm_params;
+
+/* Defaults: the cavity of Sec. 3.4 with Pr = 0.71, rates of Sec. 3.4,
+ * varpi = 1/2, walls everywhere, left hot (1) / right cold (0), top and
+ * bottom adiabatic; ra = u_c = 0 (must be set, or s_nu/zeta_alpha given).
+ * NULL is ignored. */
+void lbm_params_default(lbm_params* p);
+
+/* Library ABI version (LBM_ABI_VERSION) and a build description string. */
+int32_t lbm_abi_version(void);
+const char* lbm_build_info(void);
+
+/* Device bytes a solver of this size and storage needs (both population
+ * buffers with row and plane padding).  *bytes receives the size. */
+int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, uint64_t* bytes);
+
+/* Create a solver for an nx x ny lattice (nx, ny >= 1) on the current HIP
+ * device.  hip_stream: a hipStream_t to launch on, or NULL for a stream the
+ * library creates and owns.  Allocates lbm_required_bytes() of device
+ * memory.  *out is set to NULL on failure. */
+int lbm_create(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* hip_stream);
+
+/* As lbm_create, but the population buffers live in caller-owned device
+ * memory [device_buffer, device_buffer + bytes), 256-byte aligned, at least
+ * lbm_required_bytes(); the caller keeps it alive until lbm_destroy. */
+int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage,
+                   void* device_buffer, uint64_t bytes, void* hip_stream);
+
+/* Validate and apply a problem, derive the rates, and reset the state to
+ * rest at T = T0: fbar_i = w_i rho0 (Eq. 22 at u = 0) and
+ * g_i = g_i^eq(T0, 0) (Eq. 30), time t = 0.
+ * Derived (unless given explicitly, Eq. 40):
+ *   1/s_nu = 1/2 + Ma L sqrt(3 Pr)/sqrt(Ra),  Ma = sqrt(3) u_c,
+ *   1/zeta_alpha = 1/2 + c_s^2 (1/s_nu - 1/2)/(c_sT^2 Pr),
+ *   c_s^2 = 1/3, c_sT^2 = varpi/2, g beta = u_c^2/(dT L) (0 if u_c = 0).
+ * Errors: LBM_ERR_ARG for rates outside (0, 2), varpi outside (0, 1),
+ * inconsistent periodicity, unknown boundary codes, or missing data to
+ * derive a rate. */
+int lbm_set_params(lbm_solver* h, const lbm_params* p);
+
+/* Rates and constants in use: s9 = diag(Lambda) (Eq. 20), q5 = diag(Q)
+ * (Eq. 29), g beta, T0, L, dT.  Any pointer may be NULL. */
+int lbm_get_derived(const lbm_solver* h, double* s9, double* q5, double* gbeta,
+                    double* T0, double* length, double* dT);
+
+/* Reset to rest with a temperature field: fbar_i = w_i rho0,
+ * g_i = g_i^eq(T(x), 0) (Eq. 30); t = 0.  T is host [y][x], nx*ny values;
+ * NULL means T = T0 everywhere. */
+int lbm_init_temperature(lbm_solver* h, const double* T);
+
+/* Advance nsteps >= 0 time steps: per node, stream (Eqs. 9, 25) with the
+ * wall rules, then collide (Eqs. 8, 24).  Asynchronous. */
+int lbm_step(lbm_solver* h, int64_t nsteps);
+
+/* Time level t (number of steps taken since the last reset). */
+int lbm_time(const lbm_solver* h, int64_t* t);
+
+/* Wait for all work queued on the solver's stream. */
+int lbm_synchronize(lbm_solver* h);
+
+/* Macroscopic fields at time t (Eqs. 18, 19, 27): rho = sum fbar,
+ * u = (sum e fbar + rho0 F/2)/rho0, T = sum g.  Host arrays of nx*ny
+ * doubles, [y][x]; any may be NULL.  Synchronizes. */
+int lbm_moments(lbm_solver* h, double* rho, double* ux, double* uy, double* T);
+
+/* As lbm_moments into caller-owned device arrays; asynchronous on the
+ * solver's stream. */
+int lbm_moments_device(lbm_solver* h, double* rho, double* ux, double* uy, double* T);
+
+/* Wall Nusselt number on a Dirichlet side (Eq. 39 and the local
+ * definition before it): Nu(s) = -L (dT/dx_n)/dT along the wall, with the
+ * wall half a spacing outside the first fluid node and the gradient from
+ * the second-order one-sided fit dT/dn = (9 T1 - T2 - 8 T_w)/3 (n into the
+ * fluid; dT/dx_n = dT/dn on the left/bottom wall, -dT/dn on the
+ * right/top).  Mean over the wall nodes (midpoint rule), maximum and the
+ * index of the first maximum.  Reduced in FP64 in a fixed order.
+ * LBM_ERR_ARG if the side is not Dirichlet or the lattice is one node
+ * deep.  Synchronizes. */
+int lbm_nusselt(lbm_solver* h, int32_t side, double* nu_mean, double* nu_max, int32_t* i_max);
+
+/* Local Nusselt numbers along a Dirichlet side into a host array of ny
+ * (left/right) or nx (bottom/top) doubles.  Synchronizes. */
+int lbm_nusselt_local(lbm_solver* h, int32_t side, double* nu_local);
+
+/* Steady-state residual: r = max over nodes of max(|ux - ux'|, |uy - uy'|,
+ * |T - T'|) against the snapshot taken by the previous call, then the
+ * snapshot is replaced by the current fields.  The first call after a
+ * reset, a state load or lbm_set_populations only takes the snapshot and
+ * reports r = +infinity.
+ * *nonfinite = number of nodes whose rho, u or T is not finite; if it is
+ * nonzero the call returns LBM_ERR_UNSTABLE (outputs still written).
+ * FP64.  Synchronizes. */
+int lbm_residual(lbm_solver* h, double* r, int64_t* nonfinite);
+
+/* Pre-collision populations at time t in FP64, host arrays
+ * f9[9][ny][nx] and g5[5][ny][nx] (either may be NULL).  For deviation
+ * storage the rest equilibrium is added back.  Synchronizes. */
+int lbm_get_populations(lbm_solver* h, double* f9, double* g5);
+
+/* Replace the state by the given pre-collision populations at time t
+ * (same layout; both required), keeping t.  For deviation storage the
+ * values are rounded to the storage type.  Synchronizes. */
+int lbm_set_populations(lbm_solver* h, const double* f9, const double* g5);
+
+/* Raw state in storage format (bitwise checkpoint): copies both the
+ * population buffer and the time level.  lbm_state_bytes() gives the size;
+ * lbm_save_state writes to host memory, lbm_load_state restores a state
+ * saved from a solver of the same size, storage and parameters.
+ * Synchronizes. */
+int lbm_state_bytes(const lbm_solver* h, uint64_t* bytes);
+int lbm_save_state(lbm_solver* h, void* host, uint64_t bytes);
+int lbm_load_state(lbm_solver* h, const void* host, uint64_t bytes);
+
+/* The solver's stream (hipStream_t) and storage mode. */
+void* lbm_stream(const lbm_solver* h);
+int32_t lbm_storage_of(const lbm_solver* h);
+
+/* Launch shape of the step kernel: block_x threads along x (64, 128 or
+ * 256), block_y rows of threads (block_x * block_y <= 256) and
+ * rows_per_thread (1, 2 or 4) consecutive rows handled by each thread.
+ * 0 keeps the current value.  Results do not depend on the shape. */
+int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread);
+int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread);
+
+/* Message for the last failure on this handle (or of the last failed
+ * create when h is NULL).  Library-owned; valid until the next call. */
+const char* lbm_last_error(const lbm_solver* h);
+
+/* Free the solver and everything it allocated.  NULL-safe. */
+void lbm_destroy(lbm_solver* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,598 @@
+// lbm_api.hip -- host runtime behind include/lbm.h: solver lifetime,
+// parameter validation and derivation (Eqs. 20, 29, 40), device memory,
+// launches on the solver's stream, and readouts.
+#include "lbm_internal.hpp"
+#include "lbm.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lbm;
+
+struct lbm_solver {
+    int nx = 0, ny = 0, storage = 0;
+    Geom G{};
+    Coeffs C{};
+    Launch L{};
+    size_t buf_bytes = 0;        // bytes of one population buffer (14 planes)
+    void* base = nullptr;        // both buffers, contiguous
+    bool own_base = false;
+    void* buf[2] = {nullptr, nullptr};
+    int cur = 0;                 // buffer holding the state of time t
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool params_set = false;
+    lbm_params params{};
+    double s_nu = 0, zeta_alpha = 0, gbeta = 0, T0 = 0, length = 0, dT = 0;
+    int64_t t = 0;
+    // lazily allocated device scratch
+    double* snap = nullptr;      // 3 * nx * ny: residual snapshot (ux, uy, T)
+    bool snap_valid = false;
+    double* rpart = nullptr;     // residual partial maxima
+    unsigned long long* rbad = nullptr;
+    double* fields = nullptr;    // 4 * nx * ny: host-bound moments staging
+    double* small = nullptr;     // device outputs of reductions (8 doubles)
+    double* nu_local = nullptr;  // max(nx, ny)
+    double* host_small = nullptr;  // pinned host copy of `small`
+    std::string err;
+};
+
+static thread_local std::string g_create_error;
+
+static int fail(lbm_solver* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+static int hip_fail(lbm_solver* h, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return fail(h, LBM_ERR_DEVICE, m);
+}
+
+#define LBM_HIP(h, call, what)                                  \
+    do {                                                        \
+        hipError_t _e = (call);                                 \
+        if (_e != hipSuccess) return hip_fail((h), _e, (what)); \
+    } while (0)
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Row pitch: whole 256-byte segments; planes start on 4 KiB boundaries.
+static void layout(int nx, int ny, int storage, int* pitch, long long* plane, size_t* buf_bytes) {
+    const size_t b = storage_bytes(storage);
+    const size_t p = align_up((size_t)nx, 256 / b);
+    const size_t pl = align_up(p * (size_t)ny, 4096 / b);
+    *pitch = (int)p;
+    *plane = (long long)pl;
+    *buf_bytes = 14 * pl * b;
+}
+
+extern "C" {
+
+void lbm_params_default(lbm_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(lbm_params);
+    p->pr = 0.71;
+    p->t_hot = 1.0;
+    p->t_cold = 0.0;
+    p->s_e = 1.6;
+    p->s_q = 1.2;
+    p->s_eps = 1.8;
+    p->zeta_e = 1.9;
+    p->zeta_nu = 1.9;
+    p->varpi = 0.5;
+    for (int s = 0; s < 4; ++s) p->bc_flow[s] = LBM_BC_WALL;
+    p->bc_temp[LBM_LEFT] = LBM_T_DIRICHLET;
+    p->bc_temp[LBM_RIGHT] = LBM_T_DIRICHLET;
+    p->bc_temp[LBM_BOTTOM] = LBM_T_ADIABATIC;
+    p->bc_temp[LBM_TOP] = LBM_T_ADIABATIC;
+    p->wall_T[LBM_LEFT] = 1.0;
+    p->wall_T[LBM_RIGHT] = 0.0;
+}
+
+int32_t lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+const char* lbm_build_info(void) {
+    return "lbm non-orthogonal MRT D2Q9+D2Q5, HIP gfx950, storage f64/f32/f16";
+}
+
+int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, uint64_t* bytes) {
+    if (!bytes || nx < 1 || ny < 1 || storage < LBM_F64 || storage > LBM_F16)
+        return fail(nullptr, LBM_ERR_ARG, "lbm_required_bytes: bad size, storage or NULL output");
+    int pitch;
+    long long plane;
+    size_t bb;
+    layout(nx, ny, storage, &pitch, &plane, &bb);
+    *bytes = 2 * (uint64_t)bb;
+    return LBM_OK;
+}
+
+static void default_launch(lbm_solver* h) {
+    int bx = 64;
+    while (bx < 256 && bx < h->nx) bx *= 2;
+    h->L.bx = bx;
+    h->L.by = 256 / bx;
+    h->L.rows = 1;
+}
+
+static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* dev_buf,
+                         uint64_t bytes, void* stream) {
+    if (!out) return fail(nullptr, LBM_ERR_ARG, "lbm_create: NULL output handle");
+    *out = nullptr;
+    if (nx < 1 || ny < 1) return fail(nullptr, LBM_ERR_ARG, "lbm_create: nx and ny must be >= 1");
+    if ((long long)nx * ny > (1ll << 31))
+        return fail(nullptr, LBM_ERR_ARG, "lbm_create: more than 2^31 nodes");
+    if (storage < LBM_F64 || storage > LBM_F16)
+        return fail(nullptr, LBM_ERR_ARG, "lbm_create: storage must be LBM_F64, LBM_F32 or LBM_F16");
+    lbm_solver* h = new (std::nothrow) lbm_solver();
+    if (!h) return fail(nullptr, LBM_ERR_NOMEM, "lbm_create: host allocation failed");
+    h->nx = nx;
+    h->ny = ny;
+    h->storage = storage;
+    layout(nx, ny, storage, &h->G.pitch, &h->G.plane, &h->buf_bytes);
+    h->G.nx = nx;
+    h->G.ny = ny;
+    const uint64_t need = 2 * (uint64_t)h->buf_bytes;
+    if (dev_buf) {
+        if (bytes < need) {
+            delete h;
+            return fail(nullptr, LBM_ERR_NOMEM, "lbm_create_ext: buffer smaller than lbm_required_bytes()");
+        }
+        if (((uintptr_t)dev_buf & 255) != 0) {
+            delete h;
+            return fail(nullptr, LBM_ERR_ARG, "lbm_create_ext: buffer not 256-byte aligned");
+        }
+        h->base = dev_buf;
+        h->own_base = false;
+    } else {
+        hipError_t e = hipMalloc(&h->base, need);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(nullptr, LBM_ERR_NOMEM, std::string("lbm_create: hipMalloc failed: ") + hipGetErrorString(e));
+        }
+        h->own_base = true;
+    }
+    h->buf[0] = h->base;
+    h->buf[1] = static_cast<char*>(h->base) + h->buf_bytes;
+    if (stream) {
+        h->stream = static_cast<hipStream_t>(stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            if (h->own_base) (void)hipFree(h->base);
+            delete h;
+            return fail(nullptr, LBM_ERR_DEVICE, std::string("lbm_create: stream creation failed: ") + hipGetErrorString(e));
+        }
+        h->own_stream = true;
+    }
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->host_small), 8 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->small), 8 * sizeof(double));
+    if (e != hipSuccess) {
+        lbm_destroy(h);
+        return fail(nullptr, LBM_ERR_NOMEM, "lbm_create: small buffers");
+    }
+    default_launch(h);
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_create(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* hip_stream) {
+    return create_common(out, nx, ny, storage, nullptr, 0, hip_stream);
+}
+
+int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* device_buffer,
+                   uint64_t bytes, void* hip_stream) {
+    if (!device_buffer) return fail(nullptr, LBM_ERR_ARG, "lbm_create_ext: NULL device buffer");
+    return create_common(out, nx, ny, storage, device_buffer, bytes, hip_stream);
+}
+
+void lbm_destroy(lbm_solver* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->own_base && h->base) (void)hipFree(h->base);
+    if (h->snap) (void)hipFree(h->snap);
+    if (h->rpart) (void)hipFree(h->rpart);
+    if (h->rbad) (void)hipFree(h->rbad);
+    if (h->fields) (void)hipFree(h->fields);
+    if (h->small) (void)hipFree(h->small);
+    if (h->nu_local) (void)hipFree(h->nu_local);
+    if (h->host_small) (void)hipHostFree(h->host_small);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+const char* lbm_last_error(const lbm_solver* h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+void* lbm_stream(const lbm_solver* h) { return h ? static_cast<void*>(h->stream) : nullptr; }
+int32_t lbm_storage_of(const lbm_solver* h) { return h ? h->storage : -1; }
+
+static bool rate_ok(double s) { return isfinite(s) && s > 0.0 && s < 2.0; }
+
+// D2Q9 weights (after Eq. 22) for the moving-wall term.
+static const double kW9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+static int derive(lbm_solver* h, const lbm_params* p) {
+    for (int s = 0; s < 4; ++s) {
+        if (p->bc_flow[s] != LBM_BC_PERIODIC && p->bc_flow[s] != LBM_BC_WALL)
+            return fail(h, LBM_ERR_ARG, "lbm_set_params: unknown bc_flow code");
+        if (p->bc_temp[s] < LBM_T_PERIODIC || p->bc_temp[s] > LBM_T_ADIABATIC)
+            return fail(h, LBM_ERR_ARG, "lbm_set_params: unknown bc_temp code");
+    }
+    for (int a = 0; a < 2; ++a) {
+        const int s0 = 2 * a, s1 = 2 * a + 1;
+        const bool f0 = p->bc_flow[s0] == LBM_BC_PERIODIC, f1 = p->bc_flow[s1] == LBM_BC_PERIODIC;
+        const bool t0 = p->bc_temp[s0] == LBM_T_PERIODIC, t1 = p->bc_temp[s1] == LBM_T_PERIODIC;
+        if (f0 != f1 || t0 != t1 || f0 != t0)
+            return fail(h, LBM_ERR_ARG, "lbm_set_params: an axis must be periodic on both sides, for flow and temperature, or on neither");
+    }
+    if (!(isfinite(p->varpi) && p->varpi > 0.0 && p->varpi < 1.0))
+        return fail(h, LBM_ERR_ARG, "lbm_set_params: varpi must lie in (0, 1)");
+    if (!isfinite(p->t_hot) || !isfinite(p->t_cold) || !isfinite(p->ax) || !isfinite(p->ay))
+        return fail(h, LBM_ERR_ARG, "lbm_set_params: non-finite temperature or force");
+    for (int s = 0; s < 4; ++s)
+        if (!isfinite(p->wall_T[s]) || !isfinite(p->wall_u[s][0]) || !isfinite(p->wall_u[s][1]))
+            return fail(h, LBM_ERR_ARG, "lbm_set_params: non-finite wall value");
+    const double length = p->length > 0 ? p->length : (double)h->ny;
+    const double dT = p->t_hot - p->t_cold;
+    const double cs2 = 1.0 / 3.0, csT2 = p->varpi / 2.0;
+    double s_nu = p->s_nu, z_a = p->zeta_alpha;
+    if (!(s_nu > 0)) {
+        if (!(p->u_c > 0 && p->ra > 0 && p->pr > 0))
+            return fail(h, LBM_ERR_ARG, "lbm_set_params: s_nu needs ra, pr and u_c > 0 (Eq. 40) or an explicit value");
+        const double ma = sqrt(3.0) * p->u_c;
+        s_nu = 1.0 / (0.5 + ma * length * sqrt(3.0 * p->pr) / sqrt(p->ra));
+    }
+    if (!(z_a > 0)) {
+        if (!(p->pr > 0)) return fail(h, LBM_ERR_ARG, "lbm_set_params: zeta_alpha needs pr > 0 (Eq. 40) or an explicit value");
+        z_a = 1.0 / (0.5 + cs2 * (1.0 / s_nu - 0.5) / (csT2 * p->pr));
+    }
+    const double rates[7] = {p->s_e, s_nu, p->s_q, p->s_eps, z_a, p->zeta_e, p->zeta_nu};
+    for (double r : rates)
+        if (!rate_ok(r)) return fail(h, LBM_ERR_ARG, "lbm_set_params: every relaxation rate must lie in (0, 2)");
+    const double gbeta = (p->u_c > 0 && dT != 0) ? p->u_c * p->u_c / (dT * length) : 0.0;
+    const double T0 = 0.5 * (p->t_hot + p->t_cold);
+    const bool dev = h->storage != LBM_F64;
+
+    Coeffs C{};
+    C.s3 = p->s_e;
+    C.s4 = s_nu;
+    C.s6 = p->s_q;
+    C.s8 = p->s_eps;
+    C.z1 = z_a;
+    C.z3 = p->zeta_e;
+    C.z4 = p->zeta_nu;
+    C.varpi = p->varpi;
+    C.gbeta = gbeta;
+    C.ax = p->ax;
+    C.ay = p->ay;
+    C.tshift = dev ? 0.0 : -T0;
+    C.toff = dev ? T0 : 0.0;
+    for (int s = 0; s < 4; ++s) {
+        for (int i = 0; i < 9; ++i) {
+            const double eu = ex(i) * p->wall_u[s][0] + ey(i) * p->wall_u[s][1];
+            C.bbf[s][i] = p->bc_flow[s] == LBM_BC_WALL ? 6.0 * kW9[i] * eu : 0.0;
+        }
+        if (p->bc_temp[s] == LBM_T_DIRICHLET) {
+            C.gsign[s] = -1.0;
+            C.gconst[s] = dev ? 0.5 * p->varpi * (p->wall_T[s] - T0) : 0.5 * p->varpi * p->wall_T[s];
+        } else {
+            C.gsign[s] = 1.0;
+            C.gconst[s] = 0.0;
+        }
+    }
+    C.fscale = C.finv = C.gscale = C.ginv = 1.0f;
+    if (h->storage == LBM_F16) {
+        // Powers of two: deviations of O(0.1) for fbar and of O(|T - T0|)
+        // for g land near 2^9..2^10, far above the FP16 subnormal range and
+        // far below its maximum.
+        C.fscale = 4096.0f;
+        double tr = fabs(p->t_hot - T0);
+        for (int s = 0; s < 4; ++s)
+            if (p->bc_temp[s] == LBM_T_DIRICHLET) tr = fmax(tr, fabs(p->wall_T[s] - T0));
+        if (!(tr > 0)) tr = 1.0;
+        const int k = (int)floor(log2(1024.0 / tr));
+        C.gscale = (float)ldexp(1.0, k < -14 ? -14 : (k > 20 ? 20 : k));
+        C.finv = 1.0f / C.fscale;
+        C.ginv = 1.0f / C.gscale;
+    }
+    h->G.px = p->bc_flow[LBM_LEFT] == LBM_BC_PERIODIC;
+    h->G.py = p->bc_flow[LBM_BOTTOM] == LBM_BC_PERIODIC;
+    h->C = C;
+    h->s_nu = s_nu;
+    h->zeta_alpha = z_a;
+    h->gbeta = gbeta;
+    h->T0 = T0;
+    h->length = length;
+    h->dT = dT;
+    h->params = *p;
+    return LBM_OK;
+}
+
+static int reset_rest(lbm_solver* h, const double* T_host) {
+    double* dT = nullptr;
+    const size_t n = (size_t)h->nx * h->ny;
+    if (T_host) {
+        LBM_HIP(h, hipMallocAsync(reinterpret_cast<void**>(&dT), n * sizeof(double), h->stream), "hipMallocAsync(T)");
+        hipError_t e = hipMemcpyAsync(dT, T_host, n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(dT, h->stream);
+            return hip_fail(h, e, "copy of the temperature field");
+        }
+    }
+    hipError_t e = launch_unstream(h->storage, h->G, h->C, h->buf[0], nullptr, nullptr, dT, h->T0, true, h->stream);
+    if (dT) (void)hipFreeAsync(dT, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "initial-state kernel");
+    h->cur = 0;
+    h->t = 0;
+    h->snap_valid = false;
+    if (T_host) LBM_HIP(h, hipStreamSynchronize(h->stream), "synchronize after initial state");
+    return LBM_OK;
+}
+
+int lbm_set_params(lbm_solver* h, const lbm_params* p) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_set_params: NULL handle");
+    if (!p) return fail(h, LBM_ERR_ARG, "lbm_set_params: NULL params");
+    if (p->struct_size != sizeof(lbm_params))
+        return fail(h, LBM_ERR_ARG, "lbm_set_params: struct_size does not match this library's lbm_params");
+    int rc = derive(h, p);
+    if (rc != LBM_OK) return rc;
+    h->params_set = true;
+    return reset_rest(h, nullptr);
+}
+
+int lbm_get_derived(const lbm_solver* h, double* s9, double* q5, double* gbeta, double* T0,
+                    double* length, double* dT) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_get_derived: NULL handle");
+    if (!h->params_set) return LBM_ERR_STATE;
+    if (s9) {
+        const double s[9] = {1, 1, 1, h->C.s3, h->C.s4, h->C.s4, h->C.s6, h->C.s6, h->C.s8};
+        memcpy(s9, s, sizeof(s));
+    }
+    if (q5) {
+        const double q[5] = {1, h->C.z1, h->C.z1, h->C.z3, h->C.z4};
+        memcpy(q5, q, sizeof(q));
+    }
+    if (gbeta) *gbeta = h->gbeta;
+    if (T0) *T0 = h->T0;
+    if (length) *length = h->length;
+    if (dT) *dT = h->dT;
+    return LBM_OK;
+}
+
+int lbm_init_temperature(lbm_solver* h, const double* T) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_init_temperature: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_init_temperature: call lbm_set_params first");
+    return reset_rest(h, T);
+}
+
+int lbm_step(lbm_solver* h, int64_t nsteps) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_step: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_step: call lbm_set_params first");
+    if (nsteps < 0) return fail(h, LBM_ERR_ARG, "lbm_step: nsteps < 0");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        hipError_t e = launch_sweep(h->storage, h->L, h->G, h->C, h->buf[h->cur], h->buf[h->cur ^ 1], h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "sweep launch");
+        h->cur ^= 1;
+        h->t += 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_time(const lbm_solver* h, int64_t* t) {
+    if (!h || !t) return fail(nullptr, LBM_ERR_ARG, "lbm_time: NULL argument");
+    *t = h->t;
+    return LBM_OK;
+}
+
+int lbm_synchronize(lbm_solver* h) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_synchronize: NULL handle");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return LBM_OK;
+}
+
+int lbm_moments_device(lbm_solver* h, double* rho, double* ux, double* uy, double* T) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_moments_device: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_moments_device: call lbm_set_params first");
+    hipError_t e = launch_moments(h->storage, h->G, h->C, h->buf[h->cur], rho, ux, uy, T, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "moments kernel");
+    return LBM_OK;
+}
+
+static int ensure(lbm_solver* h, void** p, size_t bytes, const char* what) {
+    if (*p) return LBM_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(h, LBM_ERR_NOMEM, std::string("allocation of ") + what + " failed: " + hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_solver* h, double* rho, double* ux, double* uy, double* T) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_moments: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_moments: call lbm_set_params first");
+    const size_t n = (size_t)h->nx * h->ny;
+    int rc = ensure(h, reinterpret_cast<void**>(&h->fields), 4 * n * sizeof(double), "moment staging");
+    if (rc != LBM_OK) return rc;
+    double* d[4] = {h->fields, h->fields + n, h->fields + 2 * n, h->fields + 3 * n};
+    double* o[4] = {rho, ux, uy, T};
+    hipError_t e = launch_moments(h->storage, h->G, h->C, h->buf[h->cur], rho ? d[0] : nullptr,
+                                  ux ? d[1] : nullptr, uy ? d[2] : nullptr, T ? d[3] : nullptr, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "moments kernel");
+    for (int k = 0; k < 4; ++k)
+        if (o[k]) LBM_HIP(h, hipMemcpyAsync(o[k], d[k], n * sizeof(double), hipMemcpyDeviceToHost, h->stream), "moments copy");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "moments synchronize");
+    return LBM_OK;
+}
+
+static int nusselt_common(lbm_solver* h, int32_t side, double* host_local, double* out3) {
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_nusselt: call lbm_set_params first");
+    if (side < LBM_LEFT || side > LBM_TOP) return fail(h, LBM_ERR_ARG, "lbm_nusselt: side out of range");
+    if (h->params.bc_temp[side] != LBM_T_DIRICHLET)
+        return fail(h, LBM_ERR_ARG, "lbm_nusselt: the side is not a Dirichlet wall");
+    const int depth = (side == LBM_LEFT || side == LBM_RIGHT) ? h->nx : h->ny;
+    const int count = (side == LBM_LEFT || side == LBM_RIGHT) ? h->ny : h->nx;
+    if (depth < 2) return fail(h, LBM_ERR_ARG, "lbm_nusselt: the lattice is one node deep at this wall");
+    if (!(h->dT != 0)) return fail(h, LBM_ERR_ARG, "lbm_nusselt: t_hot == t_cold");
+    int rc = ensure(h, reinterpret_cast<void**>(&h->nu_local),
+                    (size_t)(h->nx > h->ny ? h->nx : h->ny) * sizeof(double), "Nusselt staging");
+    if (rc != LBM_OK) return rc;
+    hipError_t e = launch_nusselt(h->storage, h->G, h->C, h->buf[h->cur], side, h->params.wall_T[side],
+                                  h->length, h->dT, h->nu_local, h->small, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "Nusselt kernel");
+    LBM_HIP(h, hipMemcpyAsync(h->host_small, h->small, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "Nusselt copy");
+    if (host_local)
+        LBM_HIP(h, hipMemcpyAsync(host_local, h->nu_local, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, h->stream), "Nusselt copy");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "Nusselt synchronize");
+    memcpy(out3, h->host_small, 3 * sizeof(double));
+    return LBM_OK;
+}
+
+int lbm_nusselt(lbm_solver* h, int32_t side, double* nu_mean, double* nu_max, int32_t* i_max) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_nusselt: NULL handle");
+    double o[3];
+    int rc = nusselt_common(h, side, nullptr, o);
+    if (rc != LBM_OK) return rc;
+    if (nu_mean) *nu_mean = o[0];
+    if (nu_max) *nu_max = o[1];
+    if (i_max) *i_max = (int32_t)o[2];
+    return LBM_OK;
+}
+
+int lbm_nusselt_local(lbm_solver* h, int32_t side, double* nu_local) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_nusselt_local: NULL handle");
+    if (!nu_local) return fail(h, LBM_ERR_ARG, "lbm_nusselt_local: NULL output");
+    double o[3];
+    return nusselt_common(h, side, nu_local, o);
+}
+
+int lbm_residual(lbm_solver* h, double* r, int64_t* nonfinite) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_residual: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_residual: call lbm_set_params first");
+    const size_t n = (size_t)h->nx * h->ny;
+    int rc = ensure(h, reinterpret_cast<void**>(&h->snap), 3 * n * sizeof(double), "residual snapshot");
+    if (rc == LBM_OK) rc = ensure(h, reinterpret_cast<void**>(&h->rpart), residual_parts(h->G) * sizeof(double), "residual partials");
+    if (rc == LBM_OK) rc = ensure(h, reinterpret_cast<void**>(&h->rbad), residual_parts(h->G) * sizeof(unsigned long long), "residual partials");
+    if (rc != LBM_OK) return rc;
+    const bool first = !h->snap_valid;
+    hipError_t e = launch_residual(h->storage, h->G, h->C, h->buf[h->cur], h->snap, first, h->rpart, h->rbad,
+                                   h->small + 4, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "residual kernels");
+    LBM_HIP(h, hipMemcpyAsync(h->host_small + 4, h->small + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "residual copy");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "residual synchronize");
+    h->snap_valid = true;
+    const double rv = first ? INFINITY : h->host_small[4];
+    const int64_t bad = (int64_t)h->host_small[5];
+    if (r) *r = rv;
+    if (nonfinite) *nonfinite = bad;
+    if (bad) return fail(h, LBM_ERR_UNSTABLE, "lbm_residual: non-finite values in the lattice");
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_solver* h, double* f9, double* g5) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_get_populations: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_get_populations: call lbm_set_params first");
+    const size_t n = (size_t)h->nx * h->ny;
+    double* d = nullptr;
+    LBM_HIP(h, hipMallocAsync(reinterpret_cast<void**>(&d), 14 * n * sizeof(double), h->stream), "hipMallocAsync(populations)");
+    hipError_t e = launch_gather(h->storage, h->G, h->C, h->buf[h->cur], d, d + 9 * n, h->T0, h->stream);
+    if (e == hipSuccess && f9) e = hipMemcpyAsync(f9, d, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && g5) e = hipMemcpyAsync(g5, d + 9 * n, 5 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    (void)hipFreeAsync(d, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "lbm_get_populations");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "populations synchronize");
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_solver* h, const double* f9, const double* g5) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_set_populations: NULL handle");
+    if (!f9 || !g5) return fail(h, LBM_ERR_ARG, "lbm_set_populations: NULL input");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_set_populations: call lbm_set_params first");
+    const size_t n = (size_t)h->nx * h->ny;
+    double* d = nullptr;
+    LBM_HIP(h, hipMallocAsync(reinterpret_cast<void**>(&d), 14 * n * sizeof(double), h->stream), "hipMallocAsync(populations)");
+    hipError_t e = hipMemcpyAsync(d, f9, 9 * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + 9 * n, g5, 5 * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = launch_unstream(h->storage, h->G, h->C, h->buf[h->cur], d, d + 9 * n, nullptr, h->T0, false, h->stream);
+    (void)hipFreeAsync(d, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "lbm_set_populations");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "populations synchronize");
+    h->snap_valid = false;
+    return LBM_OK;
+}
+
+// Saved state: a header, then the current population buffer.
+struct StateHeader {
+    uint64_t magic;
+    int32_t nx, ny, storage, pitch;
+    int64_t plane, t;
+    uint64_t buf_bytes;
+};
+static const uint64_t kStateMagic = 0x4c424d5354415431ull;  // "LBMSTAT1"
+
+int lbm_state_bytes(const lbm_solver* h, uint64_t* bytes) {
+    if (!h || !bytes) return fail(nullptr, LBM_ERR_ARG, "lbm_state_bytes: NULL argument");
+    *bytes = sizeof(StateHeader) + h->buf_bytes;
+    return LBM_OK;
+}
+
+int lbm_save_state(lbm_solver* h, void* host, uint64_t bytes) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_save_state: NULL handle");
+    if (!host || bytes < sizeof(StateHeader) + h->buf_bytes) return fail(h, LBM_ERR_ARG, "lbm_save_state: buffer too small");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_save_state: call lbm_set_params first");
+    StateHeader hd{kStateMagic, h->nx, h->ny, h->storage, h->G.pitch, h->G.plane, h->t, h->buf_bytes};
+    memcpy(host, &hd, sizeof(hd));
+    LBM_HIP(h, hipMemcpyAsync(static_cast<char*>(host) + sizeof(hd), h->buf[h->cur], h->buf_bytes, hipMemcpyDeviceToHost, h->stream), "state copy");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "state synchronize");
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_solver* h, const void* host, uint64_t bytes) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_load_state: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_load_state: call lbm_set_params first");
+    if (!host || bytes < sizeof(StateHeader)) return fail(h, LBM_ERR_ARG, "lbm_load_state: buffer too small");
+    StateHeader hd;
+    memcpy(&hd, host, sizeof(hd));
+    if (hd.magic != kStateMagic || hd.nx != h->nx || hd.ny != h->ny || hd.storage != h->storage ||
+        hd.pitch != h->G.pitch || hd.plane != h->G.plane || hd.buf_bytes != h->buf_bytes ||
+        bytes < sizeof(hd) + h->buf_bytes)
+        return fail(h, LBM_ERR_ARG, "lbm_load_state: the state was saved from a different lattice or storage");
+    LBM_HIP(h, hipMemcpyAsync(h->buf[h->cur], static_cast<const char*>(host) + sizeof(hd), h->buf_bytes, hipMemcpyHostToDevice, h->stream), "state copy");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "state synchronize");
+    h->t = hd.t;
+    h->snap_valid = false;
+    return LBM_OK;
+}
+
+int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_set_launch: NULL handle");
+    Launch L = h->L;
+    if (block_x) L.bx = block_x;
+    if (block_y) L.by = block_y;
+    if (rows_per_thread) L.rows = rows_per_thread;
+    if (!(L.bx == 64 || L.bx == 128 || L.bx == 256) || L.by < 1 || L.bx * L.by > 256 ||
+        !(L.rows == 1 || L.rows == 2 || L.rows == 4))
+        return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2,4}");
+    h->L = L;
+    return LBM_OK;
+}
+
+int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_get_launch: NULL handle");
+    if (block_x) *block_x = h->L.bx;
+    if (block_y) *block_y = h->L.by;
+    if (rows_per_thread) *rows_per_thread = h->L.rows;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// lbm_device.hpp -- device-side core of the D2Q9 + D2Q5 non-orthogonal MRT
+// lattice Boltzmann step (Liu, He, Li & Li, arXiv:1510.08224): lattice
+// constants, storage codecs, the pull of one node with link-wise walls, and
+// the collision in the raw-moment spaces of M (Eq. 13) and N (Eq. 26),
+// unrolled with the zeros of M, M^-1 (Eq. A1), N and N^-1 (Eq. A2) removed.
+//
+// Layout in HBM: structure of arrays.  Plane i of a population buffer holds
+// population i of every node, rows of `pitch` elements, x fastest:
+//   element (i, x, y) at i * plane + y * pitch + x.
+// A buffer holds the 9 flow planes followed by the 5 temperature planes.
+// The buffer read by a step holds, for time t, the values that streaming
+// turns into the pre-collision populations at t (the post-collision values
+// of t - 1 for every link that stays inside the lattice).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum Side { kLeft = 0, kRight = 1, kBottom = 2, kTop = 3 };
+
+// D2Q9 velocities (Eq. 5, c = 1), their opposites, and the D2Q5 subset.
+__host__ __device__ constexpr int ex(int i) {
+    return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int ey(int i) {
+    return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) {
+    return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp");
+
+// Lattice geometry of one solver.
+struct Geom {
+    int nx, ny;
+    int pitch;          // elements per row
+    int px, py;         // 1 if the axis is periodic
+    long long plane;    // elements per plane
+};
+
+// Per-problem constants of the step (all derived on the host).
+struct Coeffs {
+    // D2Q9 rates (Eq. 20): s3 = s_e, s4 = s5 = s_nu, s6 = s7 = s_q, s8 = s_eps.
+    double s3, s4, s6, s8;
+    // D2Q5 rates (Eq. 29): z1 = z2 = zeta_alpha, z3 = zeta_e, z4 = zeta_nu.
+    double z1, z3, z4;
+    double varpi;       // Eq. 28
+    double gbeta;       // g beta (Eq. 4)
+    double ax, ay;      // external acceleration a (Eq. 4)
+    double tshift;      // sum(g) + tshift = T - T0
+    double toff;        // sum(g) + toff  = T
+    // Walls, per side.  Flow: a population pulled through a wall in
+    // direction i is the stored opposite population plus bbf[side][i]
+    // (= 6 w_i rho0 e_i . u_w).  Temperature: gsign[side] * stored opposite
+    // + gconst[side] (anti-bounce-back -1, varpi T_w/2 for full values or
+    // varpi (T_w - T0)/2 for deviations; bounce-back +1, 0).
+    double bbf[4][9];
+    double gsign[4], gconst[4];
+    // Deviation storage scales (FP16): stored = value * scale.
+    float fscale, finv, gscale, ginv;
+};
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  FP64 holds full populations; FP32 and FP16 hold
+// deviations from the rest equilibrium.
+// ---------------------------------------------------------------------------
+template <class S> struct Codec;
+
+template <> struct Codec<double> {
+    using R = double;
+    static constexpr bool kDev = false;
+    __device__ static __forceinline__ double load(const double* p, float) { return *p; }
+    __device__ static __forceinline__ void store(double* p, double v, float) {
+        __builtin_nontemporal_store(v, p);
+    }
+};
+
+template <> struct Codec<float> {
+    using R = float;
+    static constexpr bool kDev = true;
+    __device__ static __forceinline__ float load(const float* p, float) { return *p; }
+    __device__ static __forceinline__ void store(float* p, float v, float) {
+        __builtin_nontemporal_store(v, p);
+    }
+};
+
+template <> struct Codec<__half> {
+    using R = float;
+    static constexpr bool kDev = true;
+    __device__ static __forceinline__ float load(const __half* p, float inv) {
+        return __half2float(*p) * inv;
+    }
+    __device__ static __forceinline__ void store(__half* p, float v, float scale) {
+        __half h = __float2half_rn(v * scale);
+        __builtin_nontemporal_store(*reinterpret_cast<unsigned short*>(&h),
+                                    reinterpret_cast<unsigned short*>(p));
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Pull of one population with link-wise walls (Eqs. 9 and 25).
+// The source of direction I at (x, y) is (x - e_I, y - e_I).  If that node
+// lies outside a periodic axis it wraps; if it lies outside a wall the
+// population is the stored opposite one at (x, y) with the wall rule.  A
+// link that leaves through a top/bottom wall takes that wall's rule,
+// otherwise the left/right wall's.
+// ---------------------------------------------------------------------------
+struct Src {
+    long long off;  // element offset of the plane entry to read
+    int side;       // wall side, or -1 for an interior / periodic link
+};
+
+template <int I, int PLANE0>
+__device__ __forceinline__ Src source(const Geom& G, int x, int y) {
+    constexpr int dx = ex(I), dy = ey(I);
+    int sx = x - dx, sy = y - dy;
+    int side = -1;
+    if (dy != 0 && (sy < 0 || sy >= G.ny)) {
+        if (G.py) sy = sy < 0 ? sy + G.ny : sy - G.ny;
+        else side = sy < 0 ? kBottom : kTop;
+    }
+    if (dx != 0 && (sx < 0 || sx >= G.nx)) {
+        if (G.px) sx = sx < 0 ? sx + G.nx : sx - G.nx;
+        else if (side < 0) side = sx < 0 ? kLeft : kRight;
+    }
+    Src s;
+    if (side < 0) {
+        s.off = (long long)(PLANE0 + I) * G.plane + (long long)sy * G.pitch + sx;
+    } else {
+        s.off = (long long)(PLANE0 + opp(I)) * G.plane + (long long)y * G.pitch + x;
+    }
+    s.side = side;
+    return s;
+}
+
+template <class S>
+__device__ __forceinline__ void pull_node(const S* __restrict__ src, const Geom& G, const Coeffs& C,
+                                          int x, int y, typename Codec<S>::R f[9],
+                                          typename Codec<S>::R g[5]) {
+    using R = typename Codec<S>::R;
+#define LBM_PULL_F(I)                                                          \
+    {                                                                          \
+        Src s = source<I, 0>(G, x, y);                                         \
+        R v = Codec<S>::load(src + s.off, C.finv);                             \
+        if (s.side >= 0) v += (R)C.bbf[s.side][I];                             \
+        f[I] = v;                                                              \
+    }
+#define LBM_PULL_G(I)                                                          \
+    {                                                                          \
+        Src s = source<I, 9>(G, x, y);                                         \
+        R v = Codec<S>::load(src + s.off, C.ginv);                             \
+        if (s.side >= 0) v = (R)C.gsign[s.side] * v + (R)C.gconst[s.side];     \
+        g[I] = v;                                                              \
+    }
+    f[0] = Codec<S>::load(src + (long long)y * G.pitch + x, C.finv);
+    LBM_PULL_F(1) LBM_PULL_F(2) LBM_PULL_F(3) LBM_PULL_F(4)
+    LBM_PULL_F(5) LBM_PULL_F(6) LBM_PULL_F(7) LBM_PULL_F(8)
+    g[0] = Codec<S>::load(src + 9 * G.plane + (long long)y * G.pitch + x, C.ginv);
+    LBM_PULL_G(1) LBM_PULL_G(2) LBM_PULL_G(3) LBM_PULL_G(4)
+#undef LBM_PULL_F
+#undef LBM_PULL_G
+}
+
+// ---------------------------------------------------------------------------
+// Macroscopic values at a node (Eqs. 4, 18, 19, 27), conserved sums in FP64.
+// `rho` and `Tsum` are sum(fbar) and sum(g) of the stored representation:
+// full values for FP64 storage, deviations otherwise.
+// ---------------------------------------------------------------------------
+struct Macro {
+    double rho;    // sum fbar (full: density; deviation: rho - rho0)
+    double ux, uy; // velocity (rho0 = 1)
+    double Tsum;   // sum g (full: T; deviation: T - T0)
+    double T;      // temperature
+    double Fx, Fy; // force per unit mass
+};
+
+template <class R>
+__device__ __forceinline__ Macro macro(const R f[9], const R g[5], const Coeffs& C) {
+    Macro m;
+    const double g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3], g4 = g[4];
+    m.Tsum = ((g0 + g1) + (g2 + g3)) + g4;
+    m.T = m.Tsum + C.toff;
+    m.Fx = C.ax;
+    m.Fy = C.ay + C.gbeta * (m.Tsum + C.tshift);
+    const double f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4];
+    const double f5 = f[5], f6 = f[6], f7 = f[7], f8 = f[8];
+    m.rho = (((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7))) + f8;
+    const double d57 = f5 - f7, d68 = f6 - f8;
+    const double jx = (f1 - f3) + (d57 - d68);
+    const double jy = (f2 - f4) + (d57 + d68);
+    m.ux = jx + 0.5 * m.Fx;
+    m.uy = jy + 0.5 * m.Fy;
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one node in place (Eq. 8 for fbar, Eq. 24 for g), given its
+// macroscopic values.  Readings: rho0 = 1 multiplies every velocity term of
+// m^eq and every source moment; the density enters only m_0^eq, the 2/3 of
+// m_3^eq and the 1/9 of m_8^eq; S~_8 = (2/3) rho0 (ux Fx + uy Fy), the
+// moment of the Guo source (the printed form pairs ux with Fy).
+// In deviation storage the same expressions act on deviations: the rest
+// state is a fixed point and every map here is affine in rho and T with
+// the rest parts cancelling.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void collide(R f[9], R g[5], const Macro& mc, const Coeffs& C) {
+    const R rho = (R)mc.rho;
+    const R ux = (R)mc.ux, uy = (R)mc.uy;
+    const R Fx = (R)mc.Fx, Fy = (R)mc.Fy;
+    const R usq = ux * ux + uy * uy;
+    const R uF = ux * Fx + uy * Fy;
+    const R third = (R)(1.0 / 3.0);
+
+    // m_bar = M fbar: rows 3..8 of Eq. 13 (rows 0..2 are the conserved sums).
+    const R a13 = f[1] + f[3], a24 = f[2] + f[4];
+    const R c57 = f[5] + f[7], c68 = f[6] + f[8];
+    const R d57 = f[5] - f[7], d68 = f[6] - f[8];
+    const R m8 = c57 + c68;
+    const R m3 = (a13 + a24) + (R)2 * m8;
+    const R m4 = a13 - a24;
+    const R m5 = c57 - c68;
+    const R m6 = d57 + d68;
+    const R m7 = d57 - d68;
+
+    // Relaxation toward m^eq (Eq. 16) with the source of Eq. 17.
+    const R s3 = (R)C.s3, s4 = (R)C.s4, s6 = (R)C.s6, s8 = (R)C.s8;
+    const R e3 = (R)(2.0 / 3.0) * rho + usq;
+    const R e4 = ux * ux - uy * uy;
+    const R e5 = ux * uy;
+    const R e6 = third * uy;
+    const R e7 = third * ux;
+    const R e8 = (R)(1.0 / 9.0) * rho + third * usq;
+    const R S3 = (R)2 * uF;
+    const R S4 = (R)2 * (ux * Fx - uy * Fy);
+    const R S5 = ux * Fy + uy * Fx;
+    const R S6 = third * Fy;
+    const R S7 = third * Fx;
+    const R S8 = (R)(2.0 / 3.0) * uF;
+    const R n3 = m3 - s3 * (m3 - e3) + ((R)1 - (R)0.5 * s3) * S3;
+    const R n4 = m4 - s4 * (m4 - e4) + ((R)1 - (R)0.5 * s4) * S4;
+    const R n5 = m5 - s4 * (m5 - e5) + ((R)1 - (R)0.5 * s4) * S5;
+    const R n6 = m6 - s6 * (m6 - e6) + ((R)1 - (R)0.5 * s6) * S6;
+    const R n7 = m7 - s6 * (m7 - e7) + ((R)1 - (R)0.5 * s6) * S7;
+    const R n8 = m8 - s8 * (m8 - e8) + ((R)1 - (R)0.5 * s8) * S8;
+    // Conserved moments after collision: m0* = rho, m1* = jx + Fx,
+    // m2* = jy + Fy (rates 1 in Eq. 20; Eq. 15 puts -F/2 in m_bar).
+    const R n0 = rho;
+    const R n1 = (R)(mc.ux + 0.5 * mc.Fx);
+    const R n2 = (R)(mc.uy + 0.5 * mc.Fy);
+
+    // fbar* = M^-1 m_bar* (Eq. A1).
+    const R q = (R)0.25 * n3 - (R)0.5 * n8;
+    const R h4 = (R)0.25 * n4;
+    const R bx = (R)0.5 * (n1 - n7);
+    const R by = (R)0.5 * (n2 - n6);
+    f[0] = (n0 - n3) + n8;
+    f[1] = (q + h4) + bx;
+    f[3] = (q + h4) - bx;
+    f[2] = (q - h4) + by;
+    f[4] = (q - h4) - by;
+    const R p86 = n8 + n6, p57 = n5 + n7;
+    const R r86 = n8 - n6, r57 = n5 - n7;
+    f[5] = (R)0.25 * (p86 + p57);
+    f[6] = (R)0.25 * (p86 - p57);
+    f[7] = (R)0.25 * (r86 + r57);
+    f[8] = (R)0.25 * (r86 - r57);
+
+    // Temperature: n = N g (Eq. 26), n^eq (Eq. 28), Eq. 24, g* = N^-1 n*.
+    const R T = (R)mc.T;
+    const R t0 = (R)mc.Tsum;
+    const R t1 = g[1] - g[3];
+    const R t2 = g[2] - g[4];
+    const R t3 = (g[1] + g[3]) + (g[2] + g[4]);
+    const R t4 = (g[1] + g[3]) - (g[2] + g[4]);
+    const R z1 = (R)C.z1, z3 = (R)C.z3, z4 = (R)C.z4;
+    const R k1 = t1 - z1 * (t1 - ux * T);
+    const R k2 = t2 - z1 * (t2 - uy * T);
+    const R k3 = t3 - z3 * (t3 - (R)C.varpi * t0);
+    const R k4 = t4 - z4 * t4;
+    const R w3 = (R)0.25 * k3, w4 = (R)0.25 * k4;
+    g[0] = t0 - k3;
+    g[1] = (R)0.5 * k1 + (w3 + w4);
+    g[3] = (R)(-0.5) * k1 + (w3 + w4);
+    g[2] = (R)0.5 * k2 + (w3 - w4);
+    g[4] = (R)(-0.5) * k2 + (w3 - w4);
+}
+
+}  // namespace lbm

@@ -1,0 +1,35 @@
+// lbm_internal.hpp -- declarations shared by the kernels and the host runtime.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+enum Storage { kF64 = 0, kF32 = 1, kF16 = 2 };
+
+// Launch shape of the sweep: block of bx x by threads, each thread owning
+// `rows` consecutive rows of one column.
+struct Launch {
+    int bx = 256, by = 1, rows = 1;
+};
+
+inline int storage_bytes(int storage) { return storage == kF64 ? 8 : (storage == kF32 ? 4 : 2); }
+
+hipError_t launch_sweep(int storage, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
+                        void* dst, hipStream_t st);
+hipError_t launch_moments(int storage, const Geom& G, const Coeffs& C, const void* src, double* rho,
+                          double* ux, double* uy, double* T, hipStream_t st);
+hipError_t launch_gather(int storage, const Geom& G, const Coeffs& C, const void* src, double* pf,
+                         double* pg, double T0, hipStream_t st);
+hipError_t launch_unstream(int storage, const Geom& G, const Coeffs& C, void* dst, const double* pf,
+                           const double* pg, const double* Tf, double T0, bool from_temperature,
+                           hipStream_t st);
+hipError_t launch_nusselt(int storage, const Geom& G, const Coeffs& C, const void* src, int side,
+                          double tw, double length, double dT, double* local, double* out3,
+                          hipStream_t st);
+int residual_parts(const Geom& G);
+hipError_t launch_residual(int storage, const Geom& G, const Coeffs& C, const void* src, double* snap,
+                           bool update_only, double* pmax, unsigned long long* pbad, double* out2,
+                           hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,419 @@
+// lbm_kernels.hip -- gfx950 kernels of the D2Q9 + D2Q5 non-orthogonal MRT
+// lattice Boltzmann step and its readouts.
+//
+//   k_sweep      fused pull-stream + walls + Boussinesq force + D2Q9 and
+//                D2Q5 collision + store (one time step, Eqs. 4, 8, 9, 24, 25)
+//   k_moments    rho, u, T at time t (Eqs. 18, 19, 27)
+//   k_gather     pre-collision populations at time t, FP64
+//   k_unstream   write a buffer whose pull yields given pre-collision
+//                populations (state restore and initial equilibrium)
+//   k_nusselt    wall Nusselt number (Eq. 39), one block, fixed-order FP64
+//   k_residual   steady-state residual and non-finite count, FP64
+//
+// All kernels read the state through pull_node / source (lbm_device.hpp),
+// so the wall rules exist in one place.
+#include "lbm_internal.hpp"
+
+#include <float.h>
+#include <math.h>
+
+namespace lbm {
+
+// Workgroup b runs on XCD b % 8 of the MI355X.  Remap so that each XCD
+// walks a contiguous range of tiles (neighbouring tiles share cache lines of
+// the x-shifted pulls; keeping them on one XCD keeps those lines in one L2).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+template <class S>
+__device__ __forceinline__ void store_node(S* __restrict__ dst, const Geom& G, const Coeffs& C,
+                                           int x, int y, const typename Codec<S>::R f[9],
+                                           const typename Codec<S>::R g[5]) {
+    const long long o = (long long)y * G.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Codec<S>::store(dst + i * G.plane + o, f[i], C.fscale);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) Codec<S>::store(dst + (9 + i) * G.plane + o, g[i], C.gscale);
+}
+
+// One time step.  Each thread owns ROWS consecutive rows of one column;
+// all ROWS x 14 loads are issued before any arithmetic.
+template <class S, int ROWS>
+__global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
+                                               S* __restrict__ dst, int tiles_x) {
+    using R = typename Codec<S>::R;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
+    if (x >= G.nx) return;
+    R f[ROWS][9], g[ROWS][5];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+        if (y0 + r < G.ny) pull_node<S>(src, G, C, x, y0 + r, f[r], g[r]);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        if (y0 + r < G.ny) {
+            const Macro m = macro<R>(f[r], g[r], C);
+            collide<R>(f[r], g[r], m, C);
+            store_node<S>(dst, G, C, x, y0 + r, f[r], g[r]);
+        }
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_moments(Geom G, Coeffs C, const S* __restrict__ src,
+                                                 double* rho, double* ux, double* uy, double* T) {
+    using R = typename Codec<S>::R;
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int x = (int)(k % G.nx), y = (int)(k / G.nx);
+    R f[9], g[5];
+    pull_node<S>(src, G, C, x, y, f, g);
+    const Macro m = macro<R>(f, g, C);
+    if (rho) rho[k] = Codec<S>::kDev ? 1.0 + m.rho : m.rho;
+    if (ux) ux[k] = m.ux;
+    if (uy) uy[k] = m.uy;
+    if (T) T[k] = m.T;
+}
+
+// Rest populations that deviation storage subtracts: w_i rho0 for fbar,
+// g_i^eq(T0, 0) (Eq. 30) for g.
+__device__ __forceinline__ double rest_f(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+__device__ __forceinline__ double rest_g(int i, double T0, double varpi) {
+    return i == 0 ? (1.0 - varpi) * T0 : 0.25 * varpi * T0;
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_gather(Geom G, Coeffs C, const S* __restrict__ src,
+                                                double* pf, double* pg, double T0) {
+    using R = typename Codec<S>::R;
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int x = (int)(k % G.nx), y = (int)(k / G.nx);
+    R f[9], g[5];
+    pull_node<S>(src, G, C, x, y, f, g);
+    constexpr bool dev = Codec<S>::kDev;
+    if (pf)
+        for (int i = 0; i < 9; ++i) pf[i * n + k] = dev ? rest_f(i) + (double)f[i] : (double)f[i];
+    if (pg)
+        for (int i = 0; i < 5; ++i)
+            pg[i * n + k] = dev ? rest_g(i, T0, C.varpi) + (double)g[i] : (double)g[i];
+}
+
+// Destination of the stored entry (i, x, y) under the pull: the node
+// (x + e_i, y + e_i) if the link stays inside (after periodic wrap), else
+// the wall it crosses (y walls first, as in source()).
+template <int I>
+__device__ __forceinline__ int target(const Geom& G, int x, int y, int& tx, int& ty) {
+    int sx = x + ex(I), sy = y + ey(I), side = -1;
+    if (ey(I) != 0 && (sy < 0 || sy >= G.ny)) {
+        if (G.py) sy = sy < 0 ? sy + G.ny : sy - G.ny;
+        else side = sy < 0 ? kBottom : kTop;
+    }
+    if (ex(I) != 0 && (sx < 0 || sx >= G.nx)) {
+        if (G.px) sx = sx < 0 ? sx + G.nx : sx - G.nx;
+        else if (side < 0) side = sx < 0 ? kLeft : kRight;
+    }
+    tx = sx;
+    ty = sy;
+    return side;
+}
+
+// Pre-collision value of population i at node k, in the stored
+// representation (full for FP64, deviation otherwise).
+// MODE 0: from FP64 arrays pf/pg ([i][node]); MODE 1: rest equilibrium
+// with the temperature field Tf (or T0 if Tf is null), Eqs. 22 and 30.
+template <bool DEV, int MODE>
+struct PreValue {
+    const double *pf, *pg, *Tf;
+    long long n;
+    double T0, varpi;
+    __device__ double f(int i, long long k) const {
+        if (MODE == 0) return DEV ? pf[i * n + k] - rest_f(i) : pf[i * n + k];
+        return DEV ? 0.0 : rest_f(i);
+    }
+    __device__ double g(int i, long long k) const {
+        if (MODE == 0) return DEV ? pg[i * n + k] - rest_g(i, T0, varpi) : pg[i * n + k];
+        const double T = Tf ? Tf[k] : T0;
+        const double v = DEV ? T - T0 : T;
+        return i == 0 ? (1.0 - varpi) * v : 0.25 * varpi * v;
+    }
+};
+
+template <class S, int MODE>
+__global__ __launch_bounds__(256) void k_unstream(Geom G, Coeffs C, S* __restrict__ dst,
+                                                  const double* pf, const double* pg,
+                                                  const double* Tf, double T0) {
+    using R = typename Codec<S>::R;
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int x = (int)(k % G.nx), y = (int)(k / G.nx);
+    const long long o = (long long)y * G.pitch + x;
+    PreValue<Codec<S>::kDev, MODE> pv{pf, pg, Tf, n, T0, C.varpi};
+    Codec<S>::store(dst + o, (R)pv.f(0, k), C.fscale);
+#define LBM_UNSTREAM_F(I)                                                          \
+    {                                                                              \
+        int tx, ty;                                                                \
+        const int side = target<I>(G, x, y, tx, ty);                              \
+        double v = side < 0 ? pv.f(I, (long long)ty * G.nx + tx)                   \
+                            : pv.f(opp(I), k) - C.bbf[side][opp(I)];               \
+        Codec<S>::store(dst + (long long)I * G.plane + o, (R)v, C.fscale);         \
+    }
+#define LBM_UNSTREAM_G(I)                                                          \
+    {                                                                              \
+        int tx, ty;                                                                \
+        const int side = target<I>(G, x, y, tx, ty);                              \
+        double v = side < 0 ? pv.g(I, (long long)ty * G.nx + tx)                   \
+                            : (pv.g(opp(I), k) - C.gconst[side]) * C.gsign[side];  \
+        Codec<S>::store(dst + (long long)(9 + I) * G.plane + o, (R)v, C.gscale);   \
+    }
+    LBM_UNSTREAM_F(1) LBM_UNSTREAM_F(2) LBM_UNSTREAM_F(3) LBM_UNSTREAM_F(4)
+    LBM_UNSTREAM_F(5) LBM_UNSTREAM_F(6) LBM_UNSTREAM_F(7) LBM_UNSTREAM_F(8)
+    Codec<S>::store(dst + 9 * G.plane + o, (R)pv.g(0, k), C.gscale);
+    LBM_UNSTREAM_G(1) LBM_UNSTREAM_G(2) LBM_UNSTREAM_G(3) LBM_UNSTREAM_G(4)
+#undef LBM_UNSTREAM_F
+#undef LBM_UNSTREAM_G
+}
+
+// Temperature at a node from its pulled D2Q5 populations.
+template <class S>
+__device__ __forceinline__ double node_T(const S* __restrict__ src, const Geom& G, const Coeffs& C,
+                                         int x, int y) {
+    using R = typename Codec<S>::R;
+    R f[9], g[5];
+    pull_node<S>(src, G, C, x, y, f, g);
+    const double s = (((double)g[0] + (double)g[1]) + ((double)g[2] + (double)g[3])) + (double)g[4];
+    return s + C.toff;
+}
+
+// Fixed-order block reductions (wave64 shuffles, then LDS in wave order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void wave_maxloc(double& v, int& i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_down(v, o, 64);
+        const int oi = __shfl_down(i, o, 64);
+        if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __restrict__ src,
+                                                 int side, double tw, double length, double dT,
+                                                 double* local, double* out) {
+    __shared__ double s_sum[4], s_max[4];
+    __shared__ int s_idx[4];
+    const int count = (side == kLeft || side == kRight) ? G.ny : G.nx;
+    const double sign = (side == kLeft || side == kBottom) ? 1.0 : -1.0;
+    double sum = 0.0, best = -DBL_MAX;
+    int ibest = 0x7fffffff;
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        int x1, y1, x2, y2;
+        if (side == kLeft) { x1 = 0; x2 = 1; y1 = y2 = k; }
+        else if (side == kRight) { x1 = G.nx - 1; x2 = G.nx - 2; y1 = y2 = k; }
+        else if (side == kBottom) { y1 = 0; y2 = 1; x1 = x2 = k; }
+        else { y1 = G.ny - 1; y2 = G.ny - 2; x1 = x2 = k; }
+        const double t1 = node_T<S>(src, G, C, x1, y1);
+        const double t2 = node_T<S>(src, G, C, x2, y2);
+        const double dtdn = (9.0 * t1 - t2 - 8.0 * tw) / 3.0;
+        const double nu = -length * (sign * dtdn) / dT;
+        if (local) local[k] = nu;
+        sum += nu;
+        if (nu > best) { best = nu; ibest = k; }
+    }
+    sum = wave_sum(sum);
+    wave_maxloc(best, ibest);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_sum[wave] = sum; s_max[wave] = best; s_idx[wave] = ibest; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0, b = -DBL_MAX;
+        int bi = 0x7fffffff;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) {
+            t += s_sum[w];
+            if (s_max[w] > b || (s_max[w] == b && s_idx[w] < bi)) { b = s_max[w]; bi = s_idx[w]; }
+        }
+        out[0] = t / count;
+        out[1] = b;
+        out[2] = (double)bi;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_residual(Geom G, Coeffs C, const S* __restrict__ src,
+                                                  double* snap, int update_only, double* pmax,
+                                                  unsigned long long* pbad) {
+    using R = typename Codec<S>::R;
+    __shared__ double s_max[4];
+    __shared__ unsigned long long s_bad[4];
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double d = 0.0;
+    unsigned long long bad = 0;
+    if (k < n) {
+        const int x = (int)(k % G.nx), y = (int)(k / G.nx);
+        R f[9], g[5];
+        pull_node<S>(src, G, C, x, y, f, g);
+        const Macro m = macro<R>(f, g, C);
+        const bool fin = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.T);
+        bad = fin ? 0ull : 1ull;
+        if (!update_only && fin)
+            d = fmax(fmax(fabs(m.ux - snap[k]), fabs(m.uy - snap[n + k])), fabs(m.T - snap[2 * n + k]));
+        snap[k] = m.ux;
+        snap[n + k] = m.uy;
+        snap[2 * n + k] = m.T;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        d = fmax(d, __shfl_down(d, o, 64));
+        bad += __shfl_down(bad, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_max[wave] = d; s_bad[wave] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        unsigned long long b = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) { t = fmax(t, s_max[w]); b += s_bad[w]; }
+        pmax[blockIdx.x] = t;
+        pbad[blockIdx.x] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* pmax, const unsigned long long* pbad,
+                                                      int nparts, double* out) {
+    __shared__ double s_max[4];
+    __shared__ unsigned long long s_bad[4];
+    double d = 0.0;
+    unsigned long long b = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) { d = fmax(d, pmax[i]); b += pbad[i]; }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        d = fmax(d, __shfl_down(d, o, 64));
+        b += __shfl_down(b, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_max[wave] = d; s_bad[wave] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        unsigned long long bb = 0;
+        for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) { t = fmax(t, s_max[w]); bb += s_bad[w]; }
+        out[0] = t;
+        out[1] = (double)bb;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (internal; the C ABI is in lbm_api.hip).
+// ---------------------------------------------------------------------------
+static inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+template <class S>
+static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const void* src, void* dst,
+                          hipStream_t st) {
+    const int rows = L.rows;
+    const int tiles_x = (G.nx + L.bx - 1) / L.bx;
+    const int tiles_y = (G.ny + L.by * rows - 1) / (L.by * rows);
+    const int nt = tiles_x * tiles_y;
+    dim3 block(L.bx, L.by);
+    const S* s = static_cast<const S*>(src);
+    S* d = static_cast<S*>(dst);
+    switch (rows) {
+        case 1: hipLaunchKernelGGL((k_sweep<S, 1>), dim3(nt), block, 0, st, G, C, s, d, tiles_x); break;
+        case 2: hipLaunchKernelGGL((k_sweep<S, 2>), dim3(nt), block, 0, st, G, C, s, d, tiles_x); break;
+        case 4: hipLaunchKernelGGL((k_sweep<S, 4>), dim3(nt), block, 0, st, G, C, s, d, tiles_x); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(int storage, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
+                        void* dst, hipStream_t st) {
+    switch (storage) {
+        case kF64: return sweep_t<double>(L, G, C, src, dst, st);
+        case kF32: return sweep_t<float>(L, G, C, src, dst, st);
+        case kF16: return sweep_t<__half>(L, G, C, src, dst, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+#define LBM_DISPATCH(storage, CALL)                                  \
+    switch (storage) {                                              \
+        case kF64: { using S = double; CALL; } break;               \
+        case kF32: { using S = float; CALL; } break;                \
+        case kF16: { using S = __half; CALL; } break;               \
+        default: return hipErrorInvalidValue;                       \
+    }
+
+hipError_t launch_moments(int storage, const Geom& G, const Coeffs& C, const void* src, double* rho,
+                          double* ux, double* uy, double* T, hipStream_t st) {
+    const long long n = (long long)G.nx * G.ny;
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_moments<S>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                                             G, C, static_cast<const S*>(src), rho, ux, uy, T));
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int storage, const Geom& G, const Coeffs& C, const void* src, double* pf,
+                         double* pg, double T0, hipStream_t st) {
+    const long long n = (long long)G.nx * G.ny;
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_gather<S>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                                             G, C, static_cast<const S*>(src), pf, pg, T0));
+    return hipGetLastError();
+}
+
+hipError_t launch_unstream(int storage, const Geom& G, const Coeffs& C, void* dst, const double* pf,
+                           const double* pg, const double* Tf, double T0, bool from_temperature,
+                           hipStream_t st) {
+    const long long n = (long long)G.nx * G.ny;
+    if (from_temperature) {
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_unstream<S, 1>), dim3(blocks_for(n, 256)), dim3(256),
+                                                 0, st, G, C, static_cast<S*>(dst), pf, pg, Tf, T0));
+    } else {
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_unstream<S, 0>), dim3(blocks_for(n, 256)), dim3(256),
+                                                 0, st, G, C, static_cast<S*>(dst), pf, pg, Tf, T0));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_nusselt(int storage, const Geom& G, const Coeffs& C, const void* src, int side,
+                          double tw, double length, double dT, double* local, double* out3,
+                          hipStream_t st) {
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_nusselt<S>), dim3(1), dim3(256), 0, st, G, C,
+                                             static_cast<const S*>(src), side, tw, length, dT, local,
+                                             out3));
+    return hipGetLastError();
+}
+
+int residual_parts(const Geom& G) { return blocks_for((long long)G.nx * G.ny, 256); }
+
+hipError_t launch_residual(int storage, const Geom& G, const Coeffs& C, const void* src, double* snap,
+                           bool update_only, double* pmax, unsigned long long* pbad, double* out2,
+                           hipStream_t st) {
+    const int nb = residual_parts(G);
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_residual<S>), dim3(nb), dim3(256), 0, st, G, C,
+                                             static_cast<const S*>(src), snap, update_only ? 1 : 0,
+                                             pmax, pbad));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, pmax, pbad, nb, out2);
+    return hipGetLastError();
+}
+
+}  // namespace lbm
