@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=2048, help="cavity side")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one device copy of 1 GiB (reference kernel for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -159,6 +161,12 @@ def main():
         for s in args.variants.split(","):
             if s and s != args.storage:
                 variants[s] = time_storage(s, pb, args.steps, args.warmup, launch)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     cpu = None if args.no_cpu else cpu_baseline(pb, args.cpu_steps)
     out = {
         "metric": "MLUPS & %HBM roofline, FP64 vs FP32/FP16 store; served p50/p99 latency",

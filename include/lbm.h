@@ -114,7 +114,8 @@ const char* lbm_build_info(void);
  * buffers with row and plane padding).  *bytes receives the size. */
 int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, uint64_t* bytes);
 
-/* Create a solver for an nx x ny lattice (nx, ny >= 1) on the current HIP
+/* Create a solver for an nx x ny lattice (nx, ny >= 1, one population
+ * plane below 4 GiB: up to about 5.3e8 nodes in FP64) on the current HIP
  * device.  hip_stream: a hipStream_t to launch on, or NULL for a stream the
  * library creates and owns.  Allocates lbm_required_bytes() of device
  * memory.  *out is set to NULL on failure. */
@@ -151,6 +152,14 @@ int lbm_init_temperature(lbm_solver* h, const double* T);
 /* Advance nsteps >= 0 time steps: per node, stream (Eqs. 9, 25) with the
  * wall rules, then collide (Eqs. 8, 24).  Asynchronous. */
 int lbm_step(lbm_solver* h, int64_t nsteps);
+
+/* Graph replay: lbm_step advances in captured HIP graphs of `steps` sweeps
+ * (an even count in [2, 4096]; 0 = one kernel launch per step), rebuilt
+ * after lbm_set_params or lbm_set_launch.  The default is 64 for lattices
+ * of at most 2^18 nodes (where a sweep is shorter than a launch) and 0
+ * otherwise.  Results do not depend on it. */
+int lbm_set_graph_steps(lbm_solver* h, int32_t steps);
+int lbm_get_graph_steps(const lbm_solver* h, int32_t* steps);
 
 /* Time level t (number of steps taken since the last reset). */
 int lbm_time(const lbm_solver* h, int64_t* t);

@@ -39,6 +39,10 @@ struct lbm_solver {
     double* small = nullptr;     // device outputs of reductions (8 doubles)
     double* nu_local = nullptr;  // max(nx, ny)
     double* host_small = nullptr;  // pinned host copy of `small`
+    // Captured graphs of graph_steps sweeps (an even count), one per
+    // starting buffer; rebuilt after any change of parameters or launch.
+    int graph_steps = 0;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     std::string err;
 };
 
@@ -115,11 +119,24 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, uint64_t* bytes)
 }
 
 static void default_launch(lbm_solver* h) {
-    int bx = 64;
-    while (bx < 256 && bx < h->nx) bx *= 2;
+    // Measured on MI355X at 2048^2: 64 x 4 blocks for FP64 storage, full
+    // 256-wide rows for FP32/FP16; one row per thread (more rows per thread
+    // cost occupancy and lose bandwidth).
+    int bx = h->storage == LBM_F64 ? 64 : 256;
+    while (bx > 64 && bx / 2 >= h->nx) bx /= 2;
     h->L.bx = bx;
     h->L.by = 256 / bx;
     h->L.rows = 1;
+    // Small lattices finish a sweep in a few microseconds, less than a
+    // kernel launch costs: replay captured graphs of many sweeps instead.
+    h->graph_steps = ((long long)h->nx * h->ny <= (1ll << 18)) ? 64 : 0;
+}
+
+static void drop_graphs(lbm_solver* h) {
+    for (int k = 0; k < 2; ++k) {
+        if (h->graph_exec[k]) (void)hipGraphExecDestroy(h->graph_exec[k]);
+        h->graph_exec[k] = nullptr;
+    }
 }
 
 static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* dev_buf,
@@ -139,6 +156,11 @@ static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t stora
     layout(nx, ny, storage, &h->G.pitch, &h->G.plane, &h->buf_bytes);
     h->G.nx = nx;
     h->G.ny = ny;
+    // Kernels address a plane with 32-bit byte offsets.
+    if ((unsigned long long)h->G.plane * storage_bytes(storage) >= (1ull << 32)) {
+        delete h;
+        return fail(nullptr, LBM_ERR_ARG, "lbm_create: one population plane would exceed 4 GiB");
+    }
     const uint64_t need = 2 * (uint64_t)h->buf_bytes;
     if (dev_buf) {
         if (bytes < need) {
@@ -196,6 +218,7 @@ int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, vo
 void lbm_destroy(lbm_solver* h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
     if (h->own_base && h->base) (void)hipFree(h->base);
     if (h->snap) (void)hipFree(h->snap);
     if (h->rpart) (void)hipFree(h->rpart);
@@ -345,6 +368,7 @@ int lbm_set_params(lbm_solver* h, const lbm_params* p) {
         return fail(h, LBM_ERR_ARG, "lbm_set_params: struct_size does not match this library's lbm_params");
     int rc = derive(h, p);
     if (rc != LBM_OK) return rc;
+    drop_graphs(h);
     h->params_set = true;
     return reset_rest(h, nullptr);
 }
@@ -374,16 +398,68 @@ int lbm_init_temperature(lbm_solver* h, const double* T) {
     return reset_rest(h, T);
 }
 
+// Capture graph_steps sweeps starting from buffer `start` on the solver's
+// stream.
+static int build_graph(lbm_solver* h, int start) {
+    hipGraph_t g = nullptr;
+    LBM_HIP(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    int cur = start;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k) {
+        le = launch_sweep(h->storage, h->L, h->G, h->C, h->buf[cur], h->buf[cur ^ 1], h->stream);
+        cur ^= 1;
+    }
+    hipError_t ee = hipStreamEndCapture(h->stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(h, le, "sweep launch during graph capture");
+    }
+    if (ee != hipSuccess) return hip_fail(h, ee, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&h->graph_exec[start], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        h->graph_exec[start] = nullptr;
+        return hip_fail(h, ie, "hipGraphInstantiate");
+    }
+    return LBM_OK;
+}
+
 int lbm_step(lbm_solver* h, int64_t nsteps) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_step: NULL handle");
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_step: call lbm_set_params first");
     if (nsteps < 0) return fail(h, LBM_ERR_ARG, "lbm_step: nsteps < 0");
+    if (h->graph_steps > 0) {
+        while (nsteps >= h->graph_steps) {
+            if (!h->graph_exec[h->cur]) {
+                int rc = build_graph(h, h->cur);
+                if (rc != LBM_OK) return rc;
+            }
+            LBM_HIP(h, hipGraphLaunch(h->graph_exec[h->cur], h->stream), "hipGraphLaunch");
+            h->t += h->graph_steps;   // an even count: the state ends in the same buffer
+            nsteps -= h->graph_steps;
+        }
+    }
     for (int64_t k = 0; k < nsteps; ++k) {
         hipError_t e = launch_sweep(h->storage, h->L, h->G, h->C, h->buf[h->cur], h->buf[h->cur ^ 1], h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "sweep launch");
         h->cur ^= 1;
         h->t += 1;
     }
+    return LBM_OK;
+}
+
+int lbm_set_graph_steps(lbm_solver* h, int32_t steps) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_set_graph_steps: NULL handle");
+    if (steps < 0 || steps % 2 != 0 || steps > 4096)
+        return fail(h, LBM_ERR_ARG, "lbm_set_graph_steps: an even count in [0, 4096]");
+    drop_graphs(h);
+    h->graph_steps = steps;
+    return LBM_OK;
+}
+
+int lbm_get_graph_steps(const lbm_solver* h, int32_t* steps) {
+    if (!h || !steps) return fail(nullptr, LBM_ERR_ARG, "lbm_get_graph_steps: NULL argument");
+    *steps = h->graph_steps;
     return LBM_OK;
 }
 
@@ -584,6 +660,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
         !(L.rows == 1 || L.rows == 2 || L.rows == 4))
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2,4}");
     h->L = L;
+    drop_graphs(h);
     return LBM_OK;
 }
 

@@ -165,6 +165,139 @@ __device__ __forceinline__ void pull_node(const S* __restrict__ src, const Geom&
 #undef LBM_PULL_G
 }
 
+// Element offset of the pull source of plane PL in direction I relative to
+// the node itself (uniform across a workgroup).
+#define LBM_SHIFT(I, PL) ((long long)(PL) * G.plane - (long long)ey(I) * G.pitch - ex(I))
+
+// Address p + byte_off with a 32-bit unsigned lane offset: a uniform base
+// plus a 32-bit VGPR, which the hardware adds itself (global saddr form).
+template <class T>
+__device__ __forceinline__ T* at_bytes(T* p, unsigned byte_off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ const T* at_bytes(const T* p, unsigned byte_off) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
+}
+
+// Pull of one node whose every neighbour lies inside the lattice (no wall,
+// no wrap).  Each plane's shift (plane offset - e_y pitch - e_x) is uniform
+// across the workgroup, so it stays in scalar registers and every load adds
+// the same 32-bit lane byte offset `boff` = (y * pitch + x) * sizeof(S).
+template <class S>
+__device__ __forceinline__ void pull_interior(const S* __restrict__ src, const Geom& G, const Coeffs& C,
+                                              unsigned boff, typename Codec<S>::R f[9],
+                                              typename Codec<S>::R g[5]) {
+#define LBM_PI_F(I) f[I] = Codec<S>::load(at_bytes(src + LBM_SHIFT(I, I), boff), C.finv);
+#define LBM_PI_G(I) g[I] = Codec<S>::load(at_bytes(src + LBM_SHIFT(I, 9 + I), boff), C.ginv);
+    LBM_PI_F(0) LBM_PI_F(1) LBM_PI_F(2) LBM_PI_F(3) LBM_PI_F(4)
+    LBM_PI_F(5) LBM_PI_F(6) LBM_PI_F(7) LBM_PI_F(8)
+    LBM_PI_G(0) LBM_PI_G(1) LBM_PI_G(2) LBM_PI_G(3) LBM_PI_G(4)
+#undef LBM_PI_F
+#undef LBM_PI_G
+}
+
+// ---------------------------------------------------------------------------
+// Buffer-resource access (one descriptor for a whole population buffer,
+// per-plane offsets in scalar registers, one 32-bit lane offset shared by
+// all planes).  Usable while the buffer is below 4 GiB.  Stores are
+// non-temporal: the written buffer is not read again in the same step.
+// ---------------------------------------------------------------------------
+typedef unsigned int lbm_v2u __attribute__((ext_vector_type(2)));
+constexpr int kCachePolicyNT = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    // dword 3 = 0x00020000: 32-bit data format, the raw-buffer setting of gfx9-class GPUs
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <class S> struct Buf;
+template <> struct Buf<double> {
+    __device__ static __forceinline__ double load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double v,
+                                                 float) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lbm_v2u, v), r, vo, so, kCachePolicyNT);
+    }
+};
+template <> struct Buf<float> {
+    __device__ static __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v,
+                                                 float) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, kCachePolicyNT);
+    }
+};
+template <> struct Buf<__half> {
+    __device__ static __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float inv) {
+        const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+        return __half2float(__ushort_as_half(u)) * inv;
+    }
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v,
+                                                 float scale) {
+        const unsigned short u = __half_as_ushort(__float2half_rn(v * scale));
+        __builtin_amdgcn_raw_buffer_store_b16(u, r, vo, so, kCachePolicyNT);
+    }
+};
+
+// Interior pull through a buffer descriptor: every load is
+// buffer_load voffset=boff, soffset=shift of the plane.
+template <class S>
+__device__ __forceinline__ void pull_interior_buf(__amdgpu_buffer_rsrc_t r, const Geom& G, const Coeffs& C,
+                                                  unsigned boff, typename Codec<S>::R f[9],
+                                                  typename Codec<S>::R g[5]) {
+#define LBM_PB_F(I) f[I] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(I, I) * (long long)sizeof(S)), C.finv);
+#define LBM_PB_G(I) g[I] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(I, 9 + I) * (long long)sizeof(S)), C.ginv);
+    LBM_PB_F(0) LBM_PB_F(1) LBM_PB_F(2) LBM_PB_F(3) LBM_PB_F(4)
+    LBM_PB_F(5) LBM_PB_F(6) LBM_PB_F(7) LBM_PB_F(8)
+    LBM_PB_G(0) LBM_PB_G(1) LBM_PB_G(2) LBM_PB_G(3) LBM_PB_G(4)
+#undef LBM_PB_F
+#undef LBM_PB_G
+}
+
+// Correction of the x-shifted pulls of a node in the first or last column
+// after an interior pull (which read the neighbouring row's element there):
+// periodic axes re-read the wrapped source, walls apply the wall rule to
+// the node's own opposite population.
+template <class S>
+__device__ __forceinline__ void fix_x_edges(const S* __restrict__ src, const Geom& G, const Coeffs& C,
+                                            int x, int y, typename Codec<S>::R f[9],
+                                            typename Codec<S>::R g[5]) {
+    using R = typename Codec<S>::R;
+    auto ld = [&](int pl, int xx, int yy, float inv) -> R {
+        return Codec<S>::load(src + (long long)pl * G.plane + (long long)yy * G.pitch + xx, inv);
+    };
+    if (x == 0) {
+        if (G.px) {
+            const int xs = G.nx - 1;
+            f[1] = ld(1, xs, y, C.finv);
+            f[5] = ld(5, xs, y - 1, C.finv);
+            f[8] = ld(8, xs, y + 1, C.finv);
+            g[1] = ld(10, xs, y, C.ginv);
+        } else {
+            f[1] = ld(3, 0, y, C.finv) + (R)C.bbf[kLeft][1];
+            f[5] = ld(7, 0, y, C.finv) + (R)C.bbf[kLeft][5];
+            f[8] = ld(6, 0, y, C.finv) + (R)C.bbf[kLeft][8];
+            g[1] = (R)C.gsign[kLeft] * ld(12, 0, y, C.ginv) + (R)C.gconst[kLeft];
+        }
+    }
+    if (x == G.nx - 1) {
+        if (G.px) {
+            f[3] = ld(3, 0, y, C.finv);
+            f[6] = ld(6, 0, y - 1, C.finv);
+            f[7] = ld(7, 0, y + 1, C.finv);
+            g[3] = ld(12, 0, y, C.ginv);
+        } else {
+            f[3] = ld(1, x, y, C.finv) + (R)C.bbf[kRight][3];
+            f[6] = ld(8, x, y, C.finv) + (R)C.bbf[kRight][6];
+            f[7] = ld(5, x, y, C.finv) + (R)C.bbf[kRight][7];
+            g[3] = (R)C.gsign[kRight] * ld(10, x, y, C.ginv) + (R)C.gconst[kRight];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Macroscopic values at a node (Eqs. 4, 18, 19, 27), conserved sums in FP64.
 // `rho` and `Tsum` are sum(fbar) and sum(g) of the stored representation:

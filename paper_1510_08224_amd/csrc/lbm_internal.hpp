@@ -11,6 +11,7 @@ enum Storage { kF64 = 0, kF32 = 1, kF16 = 2 };
 // `rows` consecutive rows of one column.
 struct Launch {
     int bx = 256, by = 1, rows = 1;
+    bool buffer = true;  // buffer-resource addressing when the buffer is below 4 GiB
 };
 
 inline int storage_bytes(int storage) { return storage == kF64 ? 8 : (storage == kF32 ? 4 : 2); }

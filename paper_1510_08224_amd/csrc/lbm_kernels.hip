@@ -30,25 +30,72 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 
 template <class S>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, const Geom& G, const Coeffs& C,
-                                           int x, int y, const typename Codec<S>::R f[9],
+                                           unsigned boff, const typename Codec<S>::R f[9],
                                            const typename Codec<S>::R g[5]) {
-    const long long o = (long long)y * G.pitch + x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Codec<S>::store(dst + i * G.plane + o, f[i], C.fscale);
+    for (int i = 0; i < 9; ++i) Codec<S>::store(at_bytes(dst + (long long)i * G.plane, boff), f[i], C.fscale);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) Codec<S>::store(dst + (9 + i) * G.plane + o, g[i], C.gscale);
+    for (int i = 0; i < 5; ++i)
+        Codec<S>::store(at_bytes(dst + (long long)(9 + i) * G.plane, boff), g[i], C.gscale);
 }
 
-// One time step.  Each thread owns ROWS consecutive rows of one column;
-// all ROWS x 14 loads are issued before any arithmetic.
-template <class S, int ROWS>
+template <class S>
+__device__ __forceinline__ void store_node_buf(__amdgpu_buffer_rsrc_t r, const Geom& G, const Coeffs& C,
+                                               unsigned boff, const typename Codec<S>::R f[9],
+                                               const typename Codec<S>::R g[5]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        Buf<S>::store(r, boff, (unsigned)((long long)i * G.plane * (long long)sizeof(S)), f[i], C.fscale);
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        Buf<S>::store(r, boff, (unsigned)((long long)(9 + i) * G.plane * (long long)sizeof(S)), g[i], C.gscale);
+}
+
+// One time step.  Each thread owns ROWS consecutive rows of one column.
+// Fast path (wave-uniform): a wave whose 64 columns all lie in the lattice
+// and whose rows all have a row above and below reads every population
+// with one shared lane offset, all ROWS x 14 loads issued before any
+// arithmetic; lanes in the first or last column then correct their
+// x-shifted pulls.  Waves touching the bottom or top row, or the ragged
+// right end, resolve walls and wraps per link.  BUF selects buffer-resource
+// addressing (buffers below 4 GiB) over global addressing.
+template <class S, int ROWS, bool BUF>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
-                                               S* __restrict__ dst, int tiles_x) {
+                                               S* __restrict__ dst, int tiles_x, unsigned buf_bytes) {
     using R = typename Codec<S>::R;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x = tx * blockDim.x + threadIdx.x;
     const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
+    const int xw = __builtin_amdgcn_readfirstlane(x);
+    const int yw = __builtin_amdgcn_readfirstlane(y0);
+    const bool fast = xw + 63 <= G.nx - 1 && yw >= 1 && yw + ROWS - 1 <= G.ny - 2;
+    if (fast) {
+        R f[ROWS][9], g[ROWS][5];
+        unsigned boff[ROWS];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) boff[r] = (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S);
+        if (BUF) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) pull_interior_buf<S>(rs, G, C, boff[r], f[r], g[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) pull_interior<S>(src, G, C, boff[r], f[r], g[r]);
+        }
+        if (xw == 0 || xw + 63 == G.nx - 1) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) fix_x_edges<S>(src, G, C, x, y0 + r, f[r], g[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const Macro m = macro<R>(f[r], g[r], C);
+            collide<R>(f[r], g[r], m, C);
+            if (BUF) store_node_buf<S>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
+            else store_node<S>(dst, G, C, boff[r], f[r], g[r]);
+        }
+        return;
+    }
     if (x >= G.nx) return;
     R f[ROWS][9], g[ROWS][5];
 #pragma unroll
@@ -59,7 +106,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __rest
         if (y0 + r < G.ny) {
             const Macro m = macro<R>(f[r], g[r], C);
             collide<R>(f[r], g[r], m, C);
-            store_node<S>(dst, G, C, x, y0 + r, f[r], g[r]);
+            store_node<S>(dst, G, C, (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S), f[r], g[r]);
         }
     }
 }
@@ -325,22 +372,31 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* pmax, const 
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
 
+template <class S, bool BUF>
+static void sweep_launch(int rows, dim3 grid, dim3 block, hipStream_t st, const Geom& G, const Coeffs& C,
+                         const S* s, S* d, int tiles_x, unsigned bytes) {
+    switch (rows) {
+        case 1: hipLaunchKernelGGL((k_sweep<S, 1, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
+        case 2: hipLaunchKernelGGL((k_sweep<S, 2, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
+        default: hipLaunchKernelGGL((k_sweep<S, 4, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
+    }
+}
+
 template <class S>
 static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const void* src, void* dst,
                           hipStream_t st) {
     const int rows = L.rows;
+    if (rows != 1 && rows != 2 && rows != 4) return hipErrorInvalidValue;
     const int tiles_x = (G.nx + L.bx - 1) / L.bx;
     const int tiles_y = (G.ny + L.by * rows - 1) / (L.by * rows);
     const int nt = tiles_x * tiles_y;
-    dim3 block(L.bx, L.by);
     const S* s = static_cast<const S*>(src);
     S* d = static_cast<S*>(dst);
-    switch (rows) {
-        case 1: hipLaunchKernelGGL((k_sweep<S, 1>), dim3(nt), block, 0, st, G, C, s, d, tiles_x); break;
-        case 2: hipLaunchKernelGGL((k_sweep<S, 2>), dim3(nt), block, 0, st, G, C, s, d, tiles_x); break;
-        case 4: hipLaunchKernelGGL((k_sweep<S, 4>), dim3(nt), block, 0, st, G, C, s, d, tiles_x); break;
-        default: return hipErrorInvalidValue;
-    }
+    const unsigned long long bytes = 14ull * (unsigned long long)G.plane * sizeof(S);
+    if (L.buffer && bytes < (1ull << 32))
+        sweep_launch<S, true>(rows, dim3(nt), dim3(L.bx, L.by), st, G, C, s, d, tiles_x, (unsigned)bytes);
+    else
+        sweep_launch<S, false>(rows, dim3(nt), dim3(L.bx, L.by), st, G, C, s, d, tiles_x, 0u);
     return hipGetLastError();
 }
 

@@ -85,6 +85,8 @@ _SIGS = {
     "lbm_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "lbm_get_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_set_graph_steps": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbm_get_graph_steps": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_last_error": (ctypes.c_char_p, [_P]),
     "lbm_destroy": (None, [_P]),
 }
@@ -95,6 +97,15 @@ def lib():
     other implementation to fall back to."""
     global _lib
     if _lib is None:
+        # PyTorch's wheel ships its own libamdhip64 under the same soname as
+        # /opt/rocm's.  Loading torch first makes liblbm.so bind to that one
+        # runtime, so torch tensors and streams and the library share it;
+        # loading liblbm.so first would bring up a second HIP runtime in the
+        # process, after which torch cannot open the GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1510_08224_amd.build` (hipcc, gfx950)")
@@ -233,6 +244,14 @@ class Solver:
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().lbm_get_launch(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), self.h)
         return a.value, b.value, c.value
+
+    def set_graph_steps(self, steps: int):
+        _check(lib().lbm_set_graph_steps(self.h, int(steps)), self.h)
+
+    def get_graph_steps(self) -> int:
+        v = ctypes.c_int32()
+        _check(lib().lbm_get_graph_steps(self.h, ctypes.byref(v)), self.h)
+        return v.value
 
     # -- time stepping ---------------------------------------------------
     def step(self, n: int = 1):

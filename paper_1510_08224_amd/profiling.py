@@ -1,0 +1,142 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+    python -m paper_1510_08224_amd.profiling stats  <rocprof dir> <out.md> "<command>"
+    python -m paper_1510_08224_amd.profiling traffic <fetch dir> <write dir> <out.json> "<commands>"
+
+``stats`` turns the kernel statistics of a ``rocprofv3 --kernel-trace
+--stats -f csv`` run into a short Markdown table.  ``traffic`` reads two
+``rocprofv3 --pmc`` runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
+scales each counter by what it reads for the 1 GiB device copy the
+benchmark runs with ``--calibrate-copy`` (1 GiB read, 1 GiB written), and
+records the HBM bytes per launch of each step kernel together with a hash
+of the kernel sources they were measured on.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+COPY_BYTES = 1 << 30
+SWEEP = re.compile(r"k_sweep<(double|float|__half)")
+STORAGE = {"double": "f64", "float": "f32", "__half": "f16"}
+
+
+def _find(d: str, suffix: str) -> list[str]:
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def _col(row: dict, *names):
+    low = {k.lower(): v for k, v in row.items()}
+    for n in names:
+        if n.lower() in low:
+            return low[n.lower()]
+    raise KeyError(names)
+
+
+def kernel_stats(d: str) -> list[dict]:
+    files = _find(d, "kernel_stats.csv")
+    if not files:
+        raise FileNotFoundError(f"no kernel_stats.csv under {d}")
+    out = []
+    with open(files[0]) as fh:
+        for row in csv.DictReader(fh):
+            out.append({"name": _col(row, "Name", "KernelName"), "calls": int(_col(row, "Calls")),
+                        "total_ns": float(_col(row, "TotalDurationNs")),
+                        "avg_ns": float(_col(row, "AverageNs")),
+                        "pct": float(_col(row, "Percentage"))})
+    return out
+
+
+def write_stats_md(d: str, out_md: str, command: str, top: int = 12):
+    rows = kernel_stats(d)
+    lines = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | average (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        name = r["name"].replace("|", "\\|")
+        if len(name) > 90:
+            name = name[:87] + "..."
+        lines.append(f"| `{name}` | {r['calls']} | {r['avg_ns'] / 1e3:.3f} | {r['total_ns'] / 1e6:.3f} | {r['pct']:.2f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return rows
+
+
+def counter_means(d: str, counter: str) -> dict:
+    """Mean counter value per dispatch, by kernel name."""
+    files = _find(d, "counter_collection.csv")
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    acc: dict = {}
+    with open(files[0]) as fh:
+        for row in csv.DictReader(fh):
+            if _col(row, "Counter_Name") != counter:
+                continue
+            name = _col(row, "Kernel_Name")
+            acc.setdefault(name, []).append(float(_col(row, "Counter_Value")))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def source_hash(root: str) -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(root, "paper_1510_08224_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def write_traffic(fetch_dir: str, write_dir: str, out_json: str, commands: str, nodes: int,
+                  root: str):
+    fetch = counter_means(fetch_dir, "FETCH_SIZE")
+    write = counter_means(write_dir, "WRITE_SIZE")
+    copy_f = [v for k, v in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+    copy_w = [v for k, v in write.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+    if not copy_f or not copy_w:
+        raise RuntimeError("the calibration copy kernel is missing from the counter runs")
+    # the largest copy-like dispatch is the 1 GiB calibration copy
+    cf = max(v[0] for v in copy_f) * 1024.0
+    cw = max(v[0] for v in copy_w) * 1024.0
+    sf, sw = COPY_BYTES / cf, COPY_BYTES / cw
+    rec = {"source_hash": source_hash(root), "commands": commands,
+           "calibration": {"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES,
+                           "fetch_counter_bytes": cf, "write_counter_bytes": cw,
+                           "fetch_scale": sf, "write_scale": sw},
+           "kernels": {}}
+    for name, (fv, n) in fetch.items():
+        m = SWEEP.search(name)
+        if not m:
+            continue
+        st = STORAGE[m.group(1)]
+        wv = write.get(name, (float("nan"), 0))[0]
+        rb, wb = fv * 1024.0 * sf, wv * 1024.0 * sw
+        alg = 28 * {"f64": 8, "f32": 4, "f16": 2}[st] * nodes
+        rec["kernels"][st] = {"kernel": name, "dispatches": n, "nodes": nodes,
+                              "read_bytes_per_launch": rb, "write_bytes_per_launch": wb,
+                              "bytes_per_launch": rb + wb, "algorithmic_bytes_per_launch": alg,
+                              "traffic_over_algorithmic": (rb + wb) / alg}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+def main():
+    if len(sys.argv) >= 5 and sys.argv[1] == "stats":
+        write_stats_md(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        rec = write_traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]), root)
+        print(json.dumps(rec["kernels"], indent=1))
+    else:
+        print(__doc__)
+        sys.exit(2)
+
+
+if __name__ == "__main__":
+    main()

@@ -237,3 +237,37 @@ def test_parity_full_size_in_bench_launch(which):
     ef, eg = max_rel_pop_error(pb, fa, ga, fb, gb)
     assert ef < TOL and eg < TOL, (ef, eg)
     S.close()
+
+
+def test_graph_replays_match_eager_launches():
+    """lbm_step in captured graphs of 8 sweeps: every replay, with eager
+    work and synchronizations between replays, matches the one-launch-per-
+    step path bitwise (and an odd tail of plain launches is handled)."""
+    pb = W.cavity(48, 1e5, ny=40)
+    T = W.random_temperature(48, 40, 0.0, 1.0, seed=31)
+    eager = lbm.Solver(48, 40, "f64")
+    eager.set_params(pb)
+    eager.set_graph_steps(0)
+    eager.init_temperature(T)
+    graph = lbm.Solver(48, 40, "f64")
+    graph.set_params(pb)
+    graph.set_graph_steps(8)
+    graph.init_temperature(T)
+    assert graph.get_graph_steps() == 8
+    for rep in range(5):
+        n = 8 * (rep + 1) + (rep % 2) * 3        # graphs plus a plain tail
+        eager.step(n)
+        graph.step(n)
+        graph.moments()                           # eager work between replays
+        fa, ga = eager.get_populations()
+        fb, gb = graph.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), rep
+        assert graph.time == eager.time
+    # parameters change: the graph must be rebuilt, not replayed stale
+    pb2 = pb.replace(ra=3e4)
+    eager.set_params(pb2); graph.set_params(pb2)
+    eager.step(16); graph.step(16)
+    assert np.array_equal(eager.get_populations()[0], graph.get_populations()[0])
+    with pytest.raises(lbm.LbmError):
+        graph.set_graph_steps(7)
+    eager.close(); graph.close()
