@@ -37,7 +37,7 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1510_08224_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
+        if name.startswith("lbm_") and name.endswith((".hip", ".hpp")):
             with open(os.path.join(csrc, name), "rb") as fh:
                 h.update(name.encode())
                 h.update(fh.read())
@@ -138,7 +138,7 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="cavity side")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one device copy of 1 GiB (reference kernel for counter runs)")
+                    help="also run one elementwise pass over 1 GiB (reference kernel for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -162,9 +162,10 @@ def main():
             if s and s != args.storage:
                 variants[s] = time_storage(s, pb, args.steps, args.warmup, launch)
     if args.calibrate_copy:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        # reference for counter runs: one dispatch reading and writing 1 GiB
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
     cpu = None if args.no_cpu else cpu_baseline(pb, args.cpu_steps)

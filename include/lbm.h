@@ -231,6 +231,62 @@ int32_t lbm_storage_of(const lbm_solver* h);
 int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread);
 int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread);
 
+/* ------------------------------------------------------------------------
+ * Batches.  A batch advances many independent solvers (each with its own
+ * size, parameters and state) with one kernel launch per time step: a
+ * device table lists, for every workgroup, a member lattice and a tile of
+ * block_x x (256 / block_x) nodes (block_x from the member's
+ * lbm_set_launch), and every member runs exactly the step of lbm_step.
+ * Results of a member are bitwise the same alone and in a batch.
+ * Members must share the batch's storage and stream (create them with
+ * lbm_batch_stream()).  A solver belongs to at most one batch; lbm_destroy
+ * removes it.  Stepping, resetting or reconfiguring a member on its own is
+ * allowed and only makes the next lbm_batch_step rebuild the table.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+/* Create an empty batch for `storage` on hip_stream (NULL: own stream). */
+int lbm_batch_create(lbm_batch** out, int32_t storage, void* hip_stream);
+
+/* Add a solver (params set, same storage and stream); *slot receives its
+ * slot index (the lowest free one). */
+int lbm_batch_add(lbm_batch* b, lbm_solver* s, int32_t* slot);
+
+/* Remove the solver in `slot` (it stays valid and owned by the caller).
+ * Waits for the batch's queued work. */
+int lbm_batch_remove(lbm_batch* b, int32_t slot);
+
+/* Number of members and of slots (members plus free slots). */
+int lbm_batch_size(const lbm_batch* b, int32_t* active, int32_t* slots);
+
+/* The solver in a slot, or NULL. */
+lbm_solver* lbm_batch_member(const lbm_batch* b, int32_t slot);
+
+/* Advance every member nsteps steps (asynchronous). */
+int lbm_batch_step(lbm_batch* b, int64_t nsteps);
+
+/* Replay captured graphs of `steps` batched launches (even, <= 4096;
+ * 0 = one launch per step, the default). */
+int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
+
+/* Wait for the batch's stream. */
+int lbm_batch_synchronize(lbm_batch* b);
+
+/* lbm_residual of every member: r[slot] and nonfinite[slot] for each slot
+ * (NaN and -1 for free slots).  Returns LBM_ERR_UNSTABLE if any member has
+ * non-finite values (all outputs still written).  Synchronizes. */
+int lbm_batch_residual(lbm_batch* b, double* r, int64_t* nonfinite);
+
+/* The batch's stream (hipStream_t). */
+void* lbm_batch_stream(const lbm_batch* b);
+
+/* Message for the last failure on this batch (or of the last failed
+ * create when b is NULL). */
+const char* lbm_batch_last_error(const lbm_batch* b);
+
+/* Free the batch (members are released, not destroyed).  NULL-safe. */
+void lbm_batch_destroy(lbm_batch* b);
+
 /* Message for the last failure on this handle (or of the last failed
  * create when h is NULL).  Library-owned; valid until the next call. */
 const char* lbm_last_error(const lbm_solver* h);

@@ -1,0 +1,192 @@
+"""Batched solves and the tile autotuner.
+
+    python -m paper_1510_08224_amd.batching [--count 256 --seed 3 --steps 2000]
+
+Builds the batch workload (independent differentially heated cavities,
+side uniform over {64, 96, 128, 192, 256}, Ra log-uniform in [1e3, 1e6],
+Pr in {0.71, 7.0}, u_c = 0.1, FP32 storage), tunes the tile width of every
+size class, and reports aggregate MLUPS of the batched step (one launch per
+time step for all members, replayed from captured graphs) against one
+launch per instance per step on the same GPU.
+
+Autotuner: for each size class (lattice shape) the tile width block_x in
+{64, 128, 256} (never wider than the lattice) is chosen by coordinate
+descent on the measured time of the whole batched step, other classes held
+fixed.  Results are cached in a JSON file keyed by GPU architecture,
+storage and size class; a cached class is not re-measured.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+from . import lbm
+from . import workloads as W
+
+DEFAULT_CACHE = os.environ.get("LBM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lbm_tiles.json"))
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_batch(B: lbm.Batch, steps: int) -> float:
+    """Seconds per batched step, from HIP events on the batch's stream."""
+    import torch
+    st = torch.cuda.ExternalStream(B.stream)
+    B.step(2)
+    B.synchronize()
+    e0, e1 = _events()
+    e0.record(st)
+    B.step(steps)
+    e1.record(st)
+    B.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def time_per_instance(solvers, steps: int) -> float:
+    """Seconds per time step when every instance gets its own launch."""
+    import torch
+    for S in solvers:
+        S.set_graph_steps(0)
+    st = torch.cuda.ExternalStream(solvers[0].stream)
+    for S in solvers:
+        S.step(1)
+    solvers[0].synchronize()
+    e0, e1 = _events()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        for S in solvers:
+            S.step(1)
+    e1.record(st)
+    solvers[0].synchronize()
+    wall = time.perf_counter() - t0
+    return max(e0.elapsed_time(e1) / 1e3, wall) / steps
+
+
+def build(problems, storage: str = "f32", graph_steps: int = 50):
+    B = lbm.Batch(storage)
+    B.set_graph_steps(graph_steps)
+    solvers = []
+    for pb in problems:
+        S = B.new_solver(pb.nx, pb.ny)
+        S.set_params(pb)
+        B.add(S)
+        solvers.append(S)
+    return B, solvers
+
+
+def size_classes(solvers) -> dict:
+    cls: dict = {}
+    for S in solvers:
+        cls.setdefault(f"{S.nx}x{S.ny}", []).append(S)
+    return cls
+
+
+def _arch() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", "gpu").split(":")[0]
+
+
+def autotune(B: lbm.Batch, solvers, candidates=(64, 128, 256), steps: int = 60, cache_path: str | None = None,
+             passes: int = 1) -> dict:
+    """Choose block_x per size class; returns {class: block_x} and applies it."""
+    cache_path = cache_path or DEFAULT_CACHE
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    key = f"{_arch()}/{B.storage_name}"
+    known = cache.get(key, {})
+    classes = size_classes(solvers)
+    choice = {}
+
+    def apply(c, bx):
+        for S in classes[c]:
+            S.set_launch(bx, 256 // bx, 1)
+
+    for c, members in classes.items():
+        bx = known.get(c)
+        if bx is None:
+            nx = members[0].nx
+            bx = 64
+            while bx < 256 and bx < nx:
+                bx *= 2
+        choice[c] = bx
+        apply(c, bx)
+    trials = []
+    for _ in range(passes):
+        for c, members in sorted(classes.items()):
+            if c in known:
+                continue
+            nx = members[0].nx
+            best_bx, best_t = choice[c], None
+            for bx in candidates:
+                if bx > 64 and bx // 2 >= nx:      # half the tile would be off the lattice
+                    continue
+                apply(c, bx)
+                t = time_batch(B, steps)
+                trials.append({"class": c, "block_x": bx, "us_per_step": round(t * 1e6, 2)})
+                if best_t is None or t < best_t:
+                    best_t, best_bx = t, bx
+            choice[c] = best_bx
+            apply(c, best_bx)
+    if cache_path:
+        cache.setdefault(key, {}).update(choice)
+        os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return {"choice": choice, "trials": trials, "cache_key": key}
+
+
+def report(count: int = 256, seed: int = 3, steps: int = 2000, base_steps: int = 200,
+           storage: str = "f32", tune: bool = True, cache_path: str | None = None) -> dict:
+    problems = W.batch_mix(count, seed)
+    nodes = sum(p.nx * p.ny for p in problems)
+    B, solvers = build(problems, storage)
+    tuned = autotune(B, solvers, cache_path=cache_path) if tune else {"choice": {}, "trials": []}
+    t_batch = time_batch(B, steps)
+    t_inst = time_per_instance(solvers, base_steps)
+    r, bad = B.residual()
+    out = {
+        "workload": f"batch{count}_cavities_seed{seed}",
+        "storage": storage,
+        "members": count,
+        "nodes": nodes,
+        "size_classes": {c: len(v) for c, v in size_classes(solvers).items()},
+        "batched": {"us_per_step": round(t_batch * 1e6, 2), "mlups": round(nodes / t_batch / 1e6, 1),
+                    "steps": steps, "graph_steps": 50},
+        "one_launch_per_instance": {"us_per_step": round(t_inst * 1e6, 2), "mlups": round(nodes / t_inst / 1e6, 1),
+                                    "steps": base_steps},
+        "speedup": round(t_inst / t_batch, 2),
+        "hbm_GBs_batched": round(28 * {"f64": 8, "f32": 4, "f16": 2}[storage] * nodes / t_batch / 1e9, 1),
+        "nonfinite_members": int((bad > 0).sum()),
+        "autotune": tuned,
+    }
+    B.close()
+    for S in solvers:
+        S.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--count", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--base-steps", type=int, default=200)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--cache", default=None)
+    args = ap.parse_args()
+    print(json.dumps(report(args.count, args.seed, args.steps, args.base_steps, args.storage,
+                            not args.no_tune, args.cache)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -16,6 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["lbm_kernels.hip", "lbm_api.hip"]
+PROBE_LIB = os.path.join(HERE, "libbwprobe.so")
+PROBE_SOURCES = ["bw_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -27,11 +29,11 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def _link(srcs, lib, verbose):
     objs = []
     procs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in SOURCES:
+    for src in srcs:
         obj = os.path.join(HERE, "_build", src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -41,13 +43,19 @@ def build(verbose: bool = False) -> str:
     for p, cmd in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed: " + " ".join(cmd))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Build liblbm.so (the product) and libbwprobe.so (bandwidth ceilings)."""
+    _link(PROBE_SOURCES, PROBE_LIB, verbose)
+    return _link(SOURCES, LIB, verbose)
 
 
 if __name__ == "__main__":

@@ -43,8 +43,28 @@ struct lbm_solver {
     // starting buffer; rebuilt after any change of parameters or launch.
     int graph_steps = 0;
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    lbm_batch* batch = nullptr;  // batch this solver belongs to, if any
     std::string err;
 };
+
+struct lbm_batch {
+    int storage = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<lbm_solver*> slots;   // nullptr = free slot
+    bool dirty = true;                // tile table must be rebuilt
+    int parity = 0;                   // steps since the table was built, mod 2
+    bool buffer = true;
+    BatchMember* d_members = nullptr;
+    BatchTile* d_tiles = nullptr;
+    size_t cap_members = 0, cap_tiles = 0;
+    int ntiles = 0;
+    int graph_steps = 0;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+static void batch_invalidate(lbm_batch* b);
 
 static thread_local std::string g_create_error;
 
@@ -217,6 +237,12 @@ int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, vo
 
 void lbm_destroy(lbm_solver* h) {
     if (!h) return;
+    if (h->batch) {
+        for (auto& m : h->batch->slots)
+            if (m == h) m = nullptr;
+        batch_invalidate(h->batch);
+        h->batch = nullptr;
+    }
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     drop_graphs(h);
     if (h->own_base && h->base) (void)hipFree(h->base);
@@ -357,6 +383,7 @@ static int reset_rest(lbm_solver* h, const double* T_host) {
     h->cur = 0;
     h->t = 0;
     h->snap_valid = false;
+    if (h->batch) batch_invalidate(h->batch);
     if (T_host) LBM_HIP(h, hipStreamSynchronize(h->stream), "synchronize after initial state");
     return LBM_OK;
 }
@@ -370,6 +397,7 @@ int lbm_set_params(lbm_solver* h, const lbm_params* p) {
     if (rc != LBM_OK) return rc;
     drop_graphs(h);
     h->params_set = true;
+    if (h->batch) batch_invalidate(h->batch);
     return reset_rest(h, nullptr);
 }
 
@@ -428,6 +456,7 @@ int lbm_step(lbm_solver* h, int64_t nsteps) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_step: NULL handle");
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_step: call lbm_set_params first");
     if (nsteps < 0) return fail(h, LBM_ERR_ARG, "lbm_step: nsteps < 0");
+    if (h->batch && nsteps > 0) batch_invalidate(h->batch);
     if (h->graph_steps > 0) {
         while (nsteps >= h->graph_steps) {
             if (!h->graph_exec[h->cur]) {
@@ -645,6 +674,7 @@ int lbm_load_state(lbm_solver* h, const void* host, uint64_t bytes) {
         return fail(h, LBM_ERR_ARG, "lbm_load_state: the state was saved from a different lattice or storage");
     LBM_HIP(h, hipMemcpyAsync(h->buf[h->cur], static_cast<const char*>(host) + sizeof(hd), h->buf_bytes, hipMemcpyHostToDevice, h->stream), "state copy");
     LBM_HIP(h, hipStreamSynchronize(h->stream), "state synchronize");
+    if (h->batch) batch_invalidate(h->batch);
     h->t = hd.t;
     h->snap_valid = false;
     return LBM_OK;
@@ -661,6 +691,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2,4}");
     h->L = L;
     drop_graphs(h);
+    if (h->batch) batch_invalidate(h->batch);
     return LBM_OK;
 }
 
@@ -670,6 +701,246 @@ int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int3
     if (block_y) *block_y = h->L.by;
     if (rows_per_thread) *rows_per_thread = h->L.rows;
     return LBM_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batches: many independent lattices advanced by one launch per step.
+// ---------------------------------------------------------------------------
+static int bfail(lbm_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+static void batch_drop_graphs(lbm_batch* b) {
+    for (int k = 0; k < 2; ++k) {
+        if (b->graph_exec[k]) (void)hipGraphExecDestroy(b->graph_exec[k]);
+        b->graph_exec[k] = nullptr;
+    }
+}
+
+static void batch_invalidate(lbm_batch* b) {
+    b->dirty = true;
+    batch_drop_graphs(b);
+}
+
+int lbm_batch_create(lbm_batch** out, int32_t storage, void* hip_stream) {
+    if (!out) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_create: NULL output handle");
+    *out = nullptr;
+    if (storage < LBM_F64 || storage > LBM_F16) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_create: bad storage");
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return bfail(nullptr, LBM_ERR_NOMEM, "lbm_batch_create: host allocation failed");
+    b->storage = storage;
+    if (hip_stream) {
+        b->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete b;
+            return bfail(nullptr, LBM_ERR_DEVICE, std::string("lbm_batch_create: stream: ") + hipGetErrorString(e));
+        }
+        b->own_stream = true;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto* m : b->slots)
+        if (m) m->batch = nullptr;
+    batch_drop_graphs(b);
+    if (b->d_members) (void)hipFree(b->d_members);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+void* lbm_batch_stream(const lbm_batch* b) { return b ? static_cast<void*>(b->stream) : nullptr; }
+
+int lbm_batch_add(lbm_batch* b, lbm_solver* h, int32_t* slot) {
+    if (!b || !h) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: NULL argument");
+    if (h->batch) return bfail(b, LBM_ERR_STATE, "lbm_batch_add: the solver already belongs to a batch");
+    if (h->storage != b->storage) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: storage differs from the batch's");
+    if (h->stream != b->stream) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: the solver must use the batch's stream");
+    if (!h->params_set) return bfail(b, LBM_ERR_STATE, "lbm_batch_add: call lbm_set_params on the solver first");
+    int k = 0;
+    while (k < (int)b->slots.size() && b->slots[k]) ++k;
+    if (k == (int)b->slots.size()) b->slots.push_back(nullptr);
+    b->slots[k] = h;
+    h->batch = b;
+    batch_invalidate(b);
+    if (slot) *slot = k;
+    return LBM_OK;
+}
+
+int lbm_batch_remove(lbm_batch* b, int32_t slot) {
+    if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_remove: NULL batch");
+    if (slot < 0 || slot >= (int)b->slots.size() || !b->slots[slot])
+        return bfail(b, LBM_ERR_ARG, "lbm_batch_remove: empty or invalid slot");
+    // work queued for this member must finish before the caller may free it
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("lbm_batch_remove: synchronize: ") + hipGetErrorString(e));
+    b->slots[slot]->batch = nullptr;
+    b->slots[slot] = nullptr;
+    batch_invalidate(b);
+    return LBM_OK;
+}
+
+int lbm_batch_size(const lbm_batch* b, int32_t* active, int32_t* slots) {
+    if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_size: NULL batch");
+    int a = 0;
+    for (auto* m : b->slots) a += m != nullptr;
+    if (active) *active = a;
+    if (slots) *slots = (int32_t)b->slots.size();
+    return LBM_OK;
+}
+
+lbm_solver* lbm_batch_member(const lbm_batch* b, int32_t slot) {
+    if (!b || slot < 0 || slot >= (int)b->slots.size()) return nullptr;
+    return b->slots[slot];
+}
+
+static int batch_build(lbm_batch* b) {
+    std::vector<BatchMember> mem;
+    std::vector<BatchTile> tiles;
+    std::vector<int> index(b->slots.size(), -1);
+    b->buffer = true;
+    for (size_t k = 0; k < b->slots.size(); ++k) {
+        lbm_solver* h = b->slots[k];
+        if (!h) continue;
+        BatchMember M{};
+        M.G = h->G;
+        M.C = h->C;
+        M.buf[0] = h->buf[0];
+        M.buf[1] = h->buf[1];
+        M.buf_bytes = h->buf_bytes < (1ull << 32) ? (unsigned)h->buf_bytes : 0u;
+        if (h->buf_bytes >= (1ull << 32)) b->buffer = false;
+        M.cur0 = h->cur;
+        const int id = (int)mem.size();
+        mem.push_back(M);
+        const int bx = h->L.bx, by = 256 / h->L.bx;
+        for (int y0 = 0; y0 < h->ny; y0 += by)
+            for (int x0 = 0; x0 < h->nx; x0 += bx) tiles.push_back(BatchTile{id, x0, y0, bx});
+    }
+    if (mem.size() > b->cap_members) {
+        if (b->d_members) (void)hipFree(b->d_members);
+        b->d_members = nullptr;
+        b->cap_members = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_members), mem.size() * sizeof(BatchMember));
+        if (e != hipSuccess) return bfail(b, LBM_ERR_NOMEM, "batch member table allocation");
+        b->cap_members = mem.size();
+    }
+    if (tiles.size() > b->cap_tiles) {
+        if (b->d_tiles) (void)hipFree(b->d_tiles);
+        b->d_tiles = nullptr;
+        b->cap_tiles = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_tiles), tiles.size() * sizeof(BatchTile));
+        if (e != hipSuccess) return bfail(b, LBM_ERR_NOMEM, "batch tile table allocation");
+        b->cap_tiles = tiles.size();
+    }
+    if (!mem.empty()) {
+        hipError_t e = hipMemcpyAsync(b->d_members, mem.data(), mem.size() * sizeof(BatchMember), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // host vectors die on return
+        if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("batch table upload: ") + hipGetErrorString(e));
+    }
+    b->ntiles = (int)tiles.size();
+    b->parity = 0;
+    b->dirty = false;
+    return LBM_OK;
+}
+
+static int batch_build_graph(lbm_batch* b, int start) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, "batch graph capture begin");
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k)
+        le = launch_sweep_batch(b->storage, b->buffer, b->d_members, b->d_tiles, b->ntiles, (start + k) & 1, b->stream);
+    e = hipStreamEndCapture(b->stream, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(b, LBM_ERR_DEVICE, "batch graph capture");
+    }
+    e = hipGraphInstantiate(&b->graph_exec[start], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph_exec[start] = nullptr;
+        return bfail(b, LBM_ERR_DEVICE, "batch graph instantiate");
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+    if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_step: NULL batch");
+    if (nsteps < 0) return bfail(b, LBM_ERR_ARG, "lbm_batch_step: nsteps < 0");
+    if (b->dirty) {
+        int rc = batch_build(b);
+        if (rc != LBM_OK) return rc;
+    }
+    int64_t left = nsteps;
+    if (b->graph_steps > 0 && b->ntiles > 0) {
+        while (left >= b->graph_steps) {
+            if (!b->graph_exec[b->parity]) {
+                int rc = batch_build_graph(b, b->parity);
+                if (rc != LBM_OK) return rc;
+            }
+            hipError_t e = hipGraphLaunch(b->graph_exec[b->parity], b->stream);
+            if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, "batch graph launch");
+            left -= b->graph_steps;   // even: parity unchanged
+        }
+    }
+    for (int64_t k = 0; k < left; ++k) {
+        hipError_t e = launch_sweep_batch(b->storage, b->buffer, b->d_members, b->d_tiles, b->ntiles, b->parity, b->stream);
+        if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("batched sweep launch: ") + hipGetErrorString(e));
+        b->parity ^= 1;
+    }
+    for (auto* h : b->slots) {
+        if (!h) continue;
+        h->t += nsteps;
+        h->cur ^= (int)(nsteps & 1);
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps) {
+    if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_set_graph_steps: NULL batch");
+    if (steps < 0 || steps % 2 != 0 || steps > 4096)
+        return bfail(b, LBM_ERR_ARG, "lbm_batch_set_graph_steps: an even count in [0, 4096]");
+    batch_drop_graphs(b);
+    b->graph_steps = steps;
+    return LBM_OK;
+}
+
+int lbm_batch_synchronize(lbm_batch* b) {
+    if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_synchronize: NULL batch");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("batch synchronize: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_batch_residual(lbm_batch* b, double* r, int64_t* nonfinite) {
+    if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_residual: NULL batch");
+    int worst = LBM_OK;
+    for (size_t k = 0; k < b->slots.size(); ++k) {
+        lbm_solver* h = b->slots[k];
+        double rv = NAN;
+        int64_t bad = -1;
+        if (h) {
+            int rc = lbm_residual(h, &rv, &bad);
+            if (rc != LBM_OK && rc != LBM_ERR_UNSTABLE) return bfail(b, rc, h->err);
+            if (rc == LBM_ERR_UNSTABLE) worst = LBM_ERR_UNSTABLE;
+        }
+        if (r) r[k] = rv;
+        if (nonfinite) nonfinite[k] = bad;
+    }
+    if (worst != LBM_OK) b->err = "lbm_batch_residual: non-finite values in at least one member";
+    return worst;
 }
 
 }  // extern "C"

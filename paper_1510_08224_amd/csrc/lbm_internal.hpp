@@ -14,10 +14,27 @@ struct Launch {
     bool buffer = true;  // buffer-resource addressing when the buffer is below 4 GiB
 };
 
+// A lattice of a batch as the batched step kernel sees it.
+struct BatchMember {
+    Geom G;
+    Coeffs C;
+    void* buf[2];
+    unsigned buf_bytes;  // bytes of one population buffer
+    int cur0;            // buffer holding the state when the tile table was built
+};
+
+// One workgroup's work in a batched step: bx x (256 / bx) nodes of member
+// `member` starting at (x0, y0).
+struct BatchTile {
+    int member, x0, y0, bx;
+};
+
 inline int storage_bytes(int storage) { return storage == kF64 ? 8 : (storage == kF32 ? 4 : 2); }
 
 hipError_t launch_sweep(int storage, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
                         void* dst, hipStream_t st);
+hipError_t launch_sweep_batch(int storage, bool buffer, const BatchMember* members, const BatchTile* tiles,
+                              int ntiles, int parity, hipStream_t st);
 hipError_t launch_moments(int storage, const Geom& G, const Coeffs& C, const void* src, double* rho,
                           double* ux, double* uy, double* T, hipStream_t st);
 hipError_t launch_gather(int storage, const Geom& G, const Coeffs& C, const void* src, double* pf,

@@ -51,7 +51,7 @@ __device__ __forceinline__ void store_node_buf(__amdgpu_buffer_rsrc_t r, const G
         Buf<S>::store(r, boff, (unsigned)((long long)(9 + i) * G.plane * (long long)sizeof(S)), g[i], C.gscale);
 }
 
-// One time step.  Each thread owns ROWS consecutive rows of one column.
+// One time step of the nodes (x, y0 .. y0 + ROWS - 1) of one lattice.
 // Fast path (wave-uniform): a wave whose 64 columns all lie in the lattice
 // and whose rows all have a row above and below reads every population
 // with one shared lane offset, all ROWS x 14 loads issued before any
@@ -60,13 +60,9 @@ __device__ __forceinline__ void store_node_buf(__amdgpu_buffer_rsrc_t r, const G
 // right end, resolve walls and wraps per link.  BUF selects buffer-resource
 // addressing (buffers below 4 GiB) over global addressing.
 template <class S, int ROWS, bool BUF>
-__global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
-                                               S* __restrict__ dst, int tiles_x, unsigned buf_bytes) {
+__device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, const S* __restrict__ src,
+                                            S* __restrict__ dst, int x, int y0, unsigned buf_bytes) {
     using R = typename Codec<S>::R;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int x = tx * blockDim.x + threadIdx.x;
-    const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
     const int xw = __builtin_amdgcn_readfirstlane(x);
     const int yw = __builtin_amdgcn_readfirstlane(y0);
     const bool fast = xw + 63 <= G.nx - 1 && yw >= 1 && yw + ROWS - 1 <= G.ny - 2;
@@ -109,6 +105,35 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __rest
             store_node<S>(dst, G, C, (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S), f[r], g[r]);
         }
     }
+}
+
+// One time step of one lattice: tiles of blockDim.x x (blockDim.y * ROWS)
+// nodes, walked XCD by XCD.
+template <class S, int ROWS, bool BUF>
+__global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
+                                               S* __restrict__ dst, int tiles_x, unsigned buf_bytes) {
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
+    sweep_nodes<S, ROWS, BUF>(G, C, src, dst, x, y0, buf_bytes);
+}
+
+// One time step of every lattice of a batch.  Each workgroup of 256
+// threads takes one entry of the tile table: a member lattice and a tile
+// of bx x (256 / bx) nodes at (x0, y0).  Member m reads buffer
+// (cur0 + parity) & 1 and writes the other one.
+template <class S, bool BUF>
+__global__ __launch_bounds__(256) void k_sweep_batch(const BatchMember* __restrict__ members,
+                                                     const BatchTile* __restrict__ tiles, int parity) {
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const BatchMember& M = members[t.member];
+    const int sel = (M.cur0 + parity) & 1;
+    const S* src = static_cast<const S*>(M.buf[sel]);
+    S* dst = static_cast<S*>(M.buf[sel ^ 1]);
+    const int x = t.x0 + (int)(threadIdx.x % (unsigned)t.bx);
+    const int y = t.y0 + (int)(threadIdx.x / (unsigned)t.bx);
+    sweep_nodes<S, 1, BUF>(M.G, M.C, src, dst, x, y, M.buf_bytes);
 }
 
 template <class S>
@@ -417,6 +442,27 @@ hipError_t launch_sweep(int storage, const Launch& L, const Geom& G, const Coeff
         case kF16: { using S = __half; CALL; } break;               \
         default: return hipErrorInvalidValue;                       \
     }
+
+hipError_t launch_sweep_batch(int storage, bool buffer, const BatchMember* members, const BatchTile* tiles,
+                              int ntiles, int parity, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (storage) {
+        case kF64:
+            if (buffer) hipLaunchKernelGGL((k_sweep_batch<double, true>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            else hipLaunchKernelGGL((k_sweep_batch<double, false>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            break;
+        case kF32:
+            if (buffer) hipLaunchKernelGGL((k_sweep_batch<float, true>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            else hipLaunchKernelGGL((k_sweep_batch<float, false>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            break;
+        case kF16:
+            if (buffer) hipLaunchKernelGGL((k_sweep_batch<__half, true>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            else hipLaunchKernelGGL((k_sweep_batch<__half, false>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_moments(int storage, const Geom& G, const Coeffs& C, const void* src, double* rho,
                           double* ux, double* uy, double* T, hipStream_t st) {

@@ -87,6 +87,18 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_int32)]),
     "lbm_set_graph_steps": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lbm_get_graph_steps": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, _P]),
+    "lbm_batch_add": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbm_batch_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_member": (_P, [_P, ctypes.c_int32]),
+    "lbm_batch_step": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "lbm_batch_set_graph_steps": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbm_batch_synchronize": (ctypes.c_int, [_P]),
+    "lbm_batch_residual": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
+    "lbm_batch_stream": (_P, [_P]),
+    "lbm_batch_last_error": (ctypes.c_char_p, [_P]),
+    "lbm_batch_destroy": (None, [_P]),
     "lbm_last_error": (ctypes.c_char_p, [_P]),
     "lbm_destroy": (None, [_P]),
 }
@@ -322,3 +334,75 @@ class Solver:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(lib().lbm_load_state(self.h, ctypes.cast(buf, _P), len(blob)), self.h)
+
+
+def _bcheck(rc: int, b=None):
+    if rc != LBM_OK:
+        msg = lib().lbm_batch_last_error(b)
+        raise LbmError(rc, msg.decode() if msg else "")
+    return rc
+
+
+class Batch:
+    """A set of solvers advanced together (one launch per step for all).
+    Solvers for a batch are created with :meth:`new_solver` so that they
+    share its storage and stream."""
+
+    def __init__(self, storage: str = "f32", stream=None):
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.storage_name = {v: k for k, v in STORAGE.items()}[self.storage]
+        h = _P()
+        _bcheck(lib().lbm_batch_create(ctypes.byref(h), self.storage, stream))
+        self.h = h
+        self.members: dict[int, Solver] = {}
+
+    @property
+    def stream(self):
+        return lib().lbm_batch_stream(self.h)
+
+    def new_solver(self, nx: int, ny: int, torch_memory: bool = False) -> Solver:
+        return Solver(nx, ny, self.storage, torch_memory=torch_memory, stream=self.stream)
+
+    def add(self, solver: Solver) -> int:
+        slot = ctypes.c_int32()
+        _bcheck(lib().lbm_batch_add(self.h, solver.h, ctypes.byref(slot)), self.h)
+        self.members[slot.value] = solver
+        return slot.value
+
+    def remove(self, slot: int) -> Solver:
+        _bcheck(lib().lbm_batch_remove(self.h, int(slot)), self.h)
+        return self.members.pop(slot)
+
+    def size(self):
+        a, s = ctypes.c_int32(), ctypes.c_int32()
+        _bcheck(lib().lbm_batch_size(self.h, ctypes.byref(a), ctypes.byref(s)), self.h)
+        return a.value, s.value
+
+    def step(self, n: int = 1):
+        _bcheck(lib().lbm_batch_step(self.h, int(n)), self.h)
+
+    def set_graph_steps(self, steps: int):
+        _bcheck(lib().lbm_batch_set_graph_steps(self.h, int(steps)), self.h)
+
+    def synchronize(self):
+        _bcheck(lib().lbm_batch_synchronize(self.h), self.h)
+
+    def residual(self):
+        """Per-slot residuals and non-finite counts (NaN / -1 for free slots)."""
+        _, slots = self.size()
+        r = np.zeros(max(slots, 1)); bad = np.zeros(max(slots, 1), dtype=np.int64)
+        rc = lib().lbm_batch_residual(self.h, _dp(r), bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        if rc not in (LBM_OK, LBM_ERR_UNSTABLE):
+            _bcheck(rc, self.h)
+        return r[:slots], bad[:slots]
+
+    def close(self):
+        if self.h:
+            lib().lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,10 +6,11 @@
 ``stats`` turns the kernel statistics of a ``rocprofv3 --kernel-trace
 --stats -f csv`` run into a short Markdown table.  ``traffic`` reads two
 ``rocprofv3 --pmc`` runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
-scales each counter by what it reads for the 1 GiB device copy the
-benchmark runs with ``--calibrate-copy`` (1 GiB read, 1 GiB written), and
-records the HBM bytes per launch of each step kernel together with a hash
-of the kernel sources they were measured on.
+scales each counter by what it reads for the reference kernel the
+benchmark runs with ``--calibrate-copy`` (one elementwise pass over 2^28
+floats: 1 GiB read, 1 GiB written, in one dispatch), and records the HBM
+bytes per launch of each step kernel together with a hash of the kernel
+sources they were measured on.
 """
 from __future__ import annotations
 
@@ -67,7 +68,7 @@ def write_stats_md(d: str, out_md: str, command: str, top: int = 12):
 
 
 def counter_means(d: str, counter: str) -> dict:
-    """Mean counter value per dispatch, by kernel name."""
+    """Mean counter value per dispatch and dispatch count, by kernel name."""
     files = _find(d, "counter_collection.csv")
     if not files:
         raise FileNotFoundError(f"no counter_collection.csv under {d}")
@@ -85,7 +86,7 @@ def source_hash(root: str) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(root, "paper_1510_08224_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
+        if name.startswith("lbm_") and name.endswith((".hip", ".hpp")):
             with open(os.path.join(csrc, name), "rb") as fh:
                 h.update(name.encode())
                 h.update(fh.read())
@@ -96,13 +97,13 @@ def write_traffic(fetch_dir: str, write_dir: str, out_json: str, commands: str, 
                   root: str):
     fetch = counter_means(fetch_dir, "FETCH_SIZE")
     write = counter_means(write_dir, "WRITE_SIZE")
-    copy_f = [v for k, v in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-    copy_w = [v for k, v in write.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-    if not copy_f or not copy_w:
-        raise RuntimeError("the calibration copy kernel is missing from the counter runs")
-    # the largest copy-like dispatch is the 1 GiB calibration copy
-    cf = max(v[0] for v in copy_f) * 1024.0
-    cw = max(v[0] for v in copy_w) * 1024.0
+    ref_f = [v for k, v in fetch.items() if "MulFunctor" in k]
+    ref_w = [v for k, v in write.items() if "MulFunctor" in k]
+    if not ref_f or not ref_w:
+        raise RuntimeError("the calibration kernel (elementwise multiply of 2^28 floats) is missing")
+    # one dispatch reading 1 GiB and writing 1 GiB
+    cf = max(v[0] for v in ref_f) * 1024.0
+    cw = max(v[0] for v in ref_w) * 1024.0
     sf, sw = COPY_BYTES / cf, COPY_BYTES / cw
     rec = {"source_hash": source_hash(root), "commands": commands,
            "calibration": {"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES,
