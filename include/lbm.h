@@ -70,16 +70,26 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
 enum lbm_side { LBM_LEFT = 0, LBM_RIGHT = 1, LBM_BOTTOM = 2, LBM_TOP = 3 };
 
 /* Flow boundary per side.  LBM_BC_WALL is halfway bounce-back with the
- * moving-wall term: a population leaving node x through the wall returns
- * to x in the opposite direction j with 6 w_j rho0 (e_j . u_w) added.
- * Periodicity is per axis: both sides of an axis must be periodic, for
- * flow and temperature alike, or neither. */
-enum lbm_bc_flow { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 };
+ * moving-wall term: the wall lies half a spacing outside the last node,
+ * and a population leaving node x through it returns to x in the opposite
+ * direction j with 6 w_j rho0 (e_j . u_w) added.  LBM_BC_NEE is
+ * non-equilibrium extrapolation (the wall scheme of the paper's Sec. 3):
+ * the wall passes through the last node row/column, whose populations are
+ * rebuilt every step from the inward neighbour x_f as
+ * f^eq(rho(x_f), u_w) + fbar(x_f) - f^eq(rho(x_f), u(x_f)) (Eq. 22), and
+ * likewise for g with g^eq (Eq. 30) at the wall temperature.  Periodicity
+ * is per axis: both sides of an axis must be periodic, for flow and
+ * temperature alike, or neither.  NEE and link-wise walls are not mixed on
+ * one lattice, and an NEE flow wall takes an NEE temperature wall. */
+enum lbm_bc_flow { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1, LBM_BC_NEE = 2 };
 
 /* Temperature boundary per side.  LBM_T_DIRICHLET is anti-bounce-back,
  * g_j(x) = -g*_opp(j)(x) + varpi T_w / 2; LBM_T_ADIABATIC is bounce-back,
- * g_j(x) = g*_opp(j)(x) (zero normal flux). */
-enum lbm_bc_temp { LBM_T_PERIODIC = 0, LBM_T_DIRICHLET = 1, LBM_T_ADIABATIC = 2 };
+ * g_j(x) = g*_opp(j)(x) (zero normal flux).  LBM_T_NEE_DIRICHLET and
+ * LBM_T_NEE_ADIABATIC pair with LBM_BC_NEE: the wall node's temperature is
+ * T_w, or that of its inward neighbour. */
+enum lbm_bc_temp { LBM_T_PERIODIC = 0, LBM_T_DIRICHLET = 1, LBM_T_ADIABATIC = 2,
+                   LBM_T_NEE_DIRICHLET = 3, LBM_T_NEE_ADIABATIC = 4 };
 
 /* Problem statement (Secs. 2-3 of the paper).  Fill with
  * lbm_params_default() first; struct_size versions the layout. */
@@ -88,7 +98,8 @@ typedef struct {
     uint32_t reserved0;
     double ra, pr;         /* Rayleigh and Prandtl numbers (Eq. 40) */
     double u_c;            /* characteristic velocity sqrt(g beta dT L); Ma = sqrt(3) u_c (Eq. 40) */
-    double length;         /* L in Eq. 40 and in the Nusselt number; 0 => ny */
+    double length;         /* L in Eq. 40 and in the Nusselt number; 0 => the distance
+                              between the bottom and top walls (ny, or ny - 1 with NEE walls) */
     double t_hot, t_cold;  /* dT = t_hot - t_cold, T0 = (t_hot + t_cold)/2 (Sec. 3.4) */
     double s_e, s_q, s_eps;        /* free D2Q9 rates (Eq. 20); defaults 1.6, 1.2, 1.8 */
     double zeta_e, zeta_nu, varpi; /* free D2Q5 rates (Eq. 29) and varpi (Eq. 28); 1.9, 1.9, 0.5 */

@@ -34,8 +34,8 @@ _LIB = os.path.join(_HERE, "liborc_lbm.so")
 
 # Interface constants (the same values the C library header uses).
 LEFT, RIGHT, BOTTOM, TOP = 0, 1, 2, 3
-FLOW_PERIODIC, FLOW_WALL = 0, 1
-TEMP_PERIODIC, TEMP_DIRICHLET, TEMP_ADIABATIC = 0, 1, 2
+FLOW_PERIODIC, FLOW_WALL, FLOW_NEE = 0, 1, 2
+TEMP_PERIODIC, TEMP_DIRICHLET, TEMP_ADIABATIC, TEMP_NEE_DIRICHLET, TEMP_NEE_ADIABATIC = 0, 1, 2, 3, 4
 
 CS2 = 1.0 / 3.0  # D2Q9 lattice sound speed squared (Sec. 2.1, after Eq. 19)
 
@@ -130,9 +130,11 @@ def derive(pb) -> dict:
         1/zeta_alpha = 1/2 + c_s^2 (1/s_nu - 1/2) / (c_sT^2 Pr),
     with c_s^2 = 1/3 and c_sT^2 = varpi/2 (Sec. 2.2).  g*beta follows from
     u_c = sqrt(g beta dT L) (text after Eq. 40); T0 = (T_h + T_c)/2.
-    L defaults to ny.
+    L defaults to the distance between the bottom and top walls: ny for
+    link-wise walls (half a spacing outside the nodes), ny - 1 for NEE walls.
     """
-    length = pb.length if pb.length > 0 else float(pb.ny)
+    length = pb.length if pb.length > 0 else (float(pb.ny - 1) if pb.bc_flow[BOTTOM] == FLOW_NEE
+                                               else float(pb.ny))
     dT = pb.t_hot - pb.t_cold
     csT2 = pb.varpi / 2.0
     if pb.s_nu > 0:

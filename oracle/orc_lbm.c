@@ -28,8 +28,20 @@
  *      which is.  A switch (s8_literal) keeps the printed form.
  *   R3 (Eqs. 4, 19, 27): at a node, T = sum g (pre-collision), then
  *      F = a + g*beta*(T - T0)*y_hat, then rho0*u = sum e_i fbar_i + rho0*F/2.
+ *   R5 (Sec. 3, non-equilibrium extrapolation, the scheme of Guo, Zheng
+ *      and Shi that the paper cites for its walls): with the NEE wall type
+ *      the wall passes through the first/last node row or column.  After
+ *      streaming, every population of a wall node x_b is rebuilt from its
+ *      inward neighbour x_f:
+ *        fbar_i(x_b) = f_i^eq(rho(x_f), u_w) + [fbar_i(x_f) - f_i^eq(rho(x_f), u(x_f))],
+ *        g_i(x_b)    = g_i^eq(T_b, u_w)      + [g_i(x_f)    - g_i^eq(T(x_f), u(x_f))],
+ *      with f^eq of Eq. 22 (reading R1), g^eq of Eq. 30, T_b = T_w for a
+ *      Dirichlet wall and T(x_f) for an adiabatic one.  A corner node takes
+ *      the diagonal inward neighbour, the velocity of its top/bottom wall,
+ *      and a Dirichlet temperature if either of its walls has one (the
+ *      top/bottom wall's first).
  *   R4 (Sec. 3 uses non-equilibrium extrapolation, not given in the
- *      text): walls are link-wise.  Flow: halfway bounce-back with the
+ *      text): the default walls are link-wise.  Flow: halfway bounce-back with the
  *      moving-wall term 6 w_i rho0 (e_i . u_w).  Temperature, Dirichlet:
  *      anti-bounce-back, -g*_opp + varpi*T_w/2.  Temperature, adiabatic:
  *      bounce-back.  A link that leaves through a top/bottom wall takes
@@ -87,8 +99,9 @@ static const double NI5[5][5] = {
     {0, 0, -0.5, 0.25, -0.25}};
 
 enum { SIDE_LEFT = 0, SIDE_RIGHT = 1, SIDE_BOTTOM = 2, SIDE_TOP = 3 };
-enum { FLOW_PERIODIC = 0, FLOW_WALL = 1 };
-enum { TEMP_PERIODIC = 0, TEMP_DIRICHLET = 1, TEMP_ADIABATIC = 2 };
+enum { FLOW_PERIODIC = 0, FLOW_WALL = 1, FLOW_NEE = 2 };
+enum { TEMP_PERIODIC = 0, TEMP_DIRICHLET = 1, TEMP_ADIABATIC = 2, TEMP_NEE_DIRICHLET = 3,
+       TEMP_NEE_ADIABATIC = 4 };
 
 typedef struct {
     int32_t nx, ny;
@@ -233,13 +246,24 @@ int orc_check_params(const orc_params* p) {
         int tp0 = p->bc_temp[s0] == TEMP_PERIODIC, tp1 = p->bc_temp[s1] == TEMP_PERIODIC;
         if (fp0 != fp1 || tp0 != tp1 || fp0 != tp0) return -2;
     }
+    int nee = 0, linkwise = 0;
     for (int s = 0; s < 4; ++s) {
-        if (p->bc_flow[s] < 0 || p->bc_flow[s] > 1) return -3;
-        if (p->bc_temp[s] < 0 || p->bc_temp[s] > 2) return -3;
+        if (p->bc_flow[s] < 0 || p->bc_flow[s] > 2) return -3;
+        if (p->bc_temp[s] < 0 || p->bc_temp[s] > 4) return -3;
+        int fn = p->bc_flow[s] == FLOW_NEE;
+        int tn = p->bc_temp[s] == TEMP_NEE_DIRICHLET || p->bc_temp[s] == TEMP_NEE_ADIABATIC;
+        if (fn != tn) return -5;
+        nee += fn;
+        linkwise += p->bc_flow[s] == FLOW_WALL;
     }
+    if (nee && linkwise) return -6;   /* one wall family per lattice */
+    if (nee && ((p->bc_flow[SIDE_LEFT] == FLOW_NEE && p->nx < 3) ||
+                (p->bc_flow[SIDE_BOTTOM] == FLOW_NEE && p->ny < 3))) return -7;
     if (!(p->rho0 > 0.0)) return -4;
     return 0;
 }
+
+static void apply_nee_to(orc_lattice* L, double* F, double* G);
 
 orc_lattice* orc_create(const orc_params* p) {
     if (orc_check_params(p) != 0) return NULL;
@@ -278,6 +302,7 @@ void orc_init_equilibrium(orc_lattice* L, const double* T) {
         L->g[c * 5 + 0] = (1.0 - p->varpi) * t;
         for (int i = 1; i < 5; ++i) L->g[c * 5 + i] = 0.25 * p->varpi * t;
     }
+    apply_nee_to(L, L->f, L->g);   /* NEE wall nodes are always extrapolated */
     L->t = 0;
 }
 
@@ -288,6 +313,7 @@ void orc_set_state(orc_lattice* L, const double* f, const double* g) {
         for (int i = 0; i < 9; ++i) L->f[c * 9 + i] = f[(size_t)i * n + c];
         for (int i = 0; i < 5; ++i) L->g[c * 5 + i] = g[(size_t)i * n + c];
     }
+    apply_nee_to(L, L->f, L->g);
 }
 
 void orc_get_state(const orc_lattice* L, double* f, double* g) {
@@ -299,6 +325,53 @@ void orc_get_state(const orc_lattice* L, double* f, double* g) {
 }
 
 int64_t orc_time(const orc_lattice* L) { return L->t; }
+
+/* f_i^eq of Eq. 22 under reading R1 and g_i^eq of Eq. 30. */
+static double feq_i(const orc_params* p, int i, double rho, double ux, double uy) {
+    double eu = EX[i] * ux + EY[i] * uy;
+    double usq = ux * ux + uy * uy;
+    return W9[i] * (rho + p->rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+}
+
+static double geq_i(const orc_params* p, int i, double T, double ux, double uy) {
+    if (i == 0) return (1.0 - p->varpi) * T;
+    return 0.25 * p->varpi * T + 0.5 * (EX[i] * ux + EY[i] * uy) * T;
+}
+
+static int is_nee(const orc_params* p, int side) { return p->bc_flow[side] == FLOW_NEE; }
+
+/* Non-equilibrium extrapolation (reading R5) on a pre-collision state. */
+static void apply_nee_to(orc_lattice* L, double* F, double* G) {
+    const orc_params* p = &L->p;
+    const int nx = p->nx, ny = p->ny;
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            int onL = is_nee(p, SIDE_LEFT) && x == 0, onR = is_nee(p, SIDE_RIGHT) && x == nx - 1;
+            int onB = is_nee(p, SIDE_BOTTOM) && y == 0, onT = is_nee(p, SIDE_TOP) && y == ny - 1;
+            if (!(onL || onR || onB || onT)) continue;
+            int fx = x + (onL ? 1 : (onR ? -1 : 0));
+            int fy = y + (onB ? 1 : (onT ? -1 : 0));
+            int sx = onL ? SIDE_LEFT : (onR ? SIDE_RIGHT : -1);
+            int sy = onB ? SIDE_BOTTOM : (onT ? SIDE_TOP : -1);
+            int vside = sy >= 0 ? sy : sx;
+            int tside = -1;
+            if (sy >= 0 && p->bc_temp[sy] == TEMP_NEE_DIRICHLET) tside = sy;
+            else if (sx >= 0 && p->bc_temp[sx] == TEMP_NEE_DIRICHLET) tside = sx;
+            const double* ff = F + ((size_t)fy * nx + fx) * 9;
+            const double* gf = G + ((size_t)fy * nx + fx) * 5;
+            double rho, ux, uy, T, Fx, Fy;
+            macroscopic(p, ff, gf, &rho, &ux, &uy, &T, &Fx, &Fy);
+            double uwx = p->wall_u[vside][0], uwy = p->wall_u[vside][1];
+            double Tb = tside >= 0 ? p->wall_T[tside] : T;
+            double* fb = F + ((size_t)y * nx + x) * 9;
+            double* gb = G + ((size_t)y * nx + x) * 5;
+            for (int i = 0; i < 9; ++i)
+                fb[i] = feq_i(p, i, rho, uwx, uwy) + (ff[i] - feq_i(p, i, rho, ux, uy));
+            for (int i = 0; i < 5; ++i)
+                gb[i] = geq_i(p, i, Tb, uwx, uwy) + (gf[i] - geq_i(p, i, T, ux, uy));
+        }
+    }
+}
 
 /* Push streaming (Eqs. 9, 25) from fp/gp into fn/gn, with link-wise walls
  * (reading R4).  Every (node, direction) slot of the target is written
@@ -321,6 +394,7 @@ static void stream_push(orc_lattice* L) {
                 } else {
                     int side = wally ? (ty < 0 ? SIDE_BOTTOM : SIDE_TOP)
                                      : (tx < 0 ? SIDE_LEFT : SIDE_RIGHT);
+                    if (p->bc_flow[side] == FLOW_NEE) continue;   /* rebuilt by apply_nee */
                     double eu = EX[i] * p->wall_u[side][0] + EY[i] * p->wall_u[side][1];
                     L->fn[c * 9 + OPP9[i]] = L->fp[c * 9 + i] - 6.0 * W9[i] * p->rho0 * eu;
                 }
@@ -336,6 +410,7 @@ static void stream_push(orc_lattice* L) {
                 } else {
                     int side = wally ? (ty < 0 ? SIDE_BOTTOM : SIDE_TOP)
                                      : (tx < 0 ? SIDE_LEFT : SIDE_RIGHT);
+                    if (p->bc_flow[side] == FLOW_NEE) continue;   /* rebuilt by apply_nee */
                     if (p->bc_temp[side] == TEMP_DIRICHLET)
                         L->gn[c * 5 + OPP5[i]] = -L->gp[c * 5 + i] + 0.5 * p->varpi * p->wall_T[side];
                     else
@@ -357,6 +432,7 @@ void orc_step(orc_lattice* L, int64_t nsteps) {
     for (int64_t s = 0; s < nsteps; ++s) {
         collide_all(L);
         stream_push(L);
+        apply_nee_to(L, L->fn, L->gn);
         double* t;
         t = L->f; L->f = L->fn; L->fn = t;
         t = L->g; L->g = L->gn; L->gn = t;
@@ -389,44 +465,53 @@ void orc_moments(const orc_lattice* L, double* rho, double* ux, double* uy, doub
 }
 
 /* Local Nusselt number along one Dirichlet wall (Eq. 39 and the local
- * definition before it): Nu = -L (dT/dx_normal-axis)_wall / dT, with the
- * wall half a spacing outside the first node, and the wall-normal gradient
- * from a second-order one-sided fit through T_wall, T(1/2), T(3/2):
- *     dT/dn = (9 T1 - T2 - 8 Tw) / 3       (n into the fluid).
- * On the left/bottom wall d/dx (d/dy) = d/dn; on the right/top it is -d/dn.
+ * definition before it): Nu = -L (dT/dx_normal-axis)_wall / dT.
+ * Link-wise walls sit half a spacing outside the first node; the wall-
+ * normal gradient comes from a second-order one-sided fit through T_wall,
+ * T(1/2), T(3/2):  dT/dn = (9 T1 - T2 - 8 Tw) / 3  (n into the fluid), and
+ * the mean is the midpoint rule over the wall nodes.  NEE walls pass
+ * through the first node: dT/dn = (-3 T0 + 4 T1 - T2) / 2 with T0, T1, T2
+ * the first three nodes, and the mean is the trapezoidal rule.  On the
+ * left/bottom wall d/dx (d/dy) = d/dn; on the right/top it is -d/dn.
  * nu_local gets one value per wall node (ny for left/right, nx for
  * bottom/top) and may be NULL.  Returns 0, or -1 for a bad side. */
+static double node_T(const orc_lattice* L, int x, int y) {
+    const double* g = L->g + ((size_t)y * L->p.nx + x) * 5;
+    double t = 0.0;
+    for (int i = 0; i < 5; ++i) t += g[i];
+    return t;
+}
+
 int orc_nusselt(const orc_lattice* L, int side, double length, double dT,
                 double* nu_local, double* nu_mean, double* nu_max, int32_t* i_max) {
     const orc_params* p = &L->p;
     const int nx = p->nx, ny = p->ny;
     if (side < 0 || side > 3) return -1;
-    if (p->bc_temp[side] != TEMP_DIRICHLET) return -1;
+    const int nee = p->bc_temp[side] == TEMP_NEE_DIRICHLET;
+    if (p->bc_temp[side] != TEMP_DIRICHLET && !nee) return -1;
     int vertical = (side == SIDE_LEFT || side == SIDE_RIGHT);
     int count = vertical ? ny : nx;
     int depth = vertical ? nx : ny;
-    if (depth < 2) return -1;
+    if (depth < (nee ? 3 : 2)) return -1;
     double tw = p->wall_T[side];
     double sign = (side == SIDE_LEFT || side == SIDE_BOTTOM) ? 1.0 : -1.0;
     double sum = 0.0, best = -INFINITY;
     int ibest = -1;
     for (int k = 0; k < count; ++k) {
-        int x1, y1, x2, y2;
-        if (side == SIDE_LEFT)   { x1 = 0;      y1 = k; x2 = 1;      y2 = k; }
-        else if (side == SIDE_RIGHT) { x1 = nx - 1; y1 = k; x2 = nx - 2; y2 = k; }
-        else if (side == SIDE_BOTTOM) { x1 = k; y1 = 0;      x2 = k; y2 = 1; }
-        else { x1 = k; y1 = ny - 1; x2 = k; y2 = ny - 2; }
-        const double* g1 = L->g + ((size_t)y1 * nx + x1) * 5;
-        const double* g2 = L->g + ((size_t)y2 * nx + x2) * 5;
-        double t1 = 0.0, t2 = 0.0;
-        for (int i = 0; i < 5; ++i) { t1 += g1[i]; t2 += g2[i]; }
-        double dtdn = (9.0 * t1 - t2 - 8.0 * tw) / 3.0;
+        double t[3];
+        for (int d = 0; d < 3 && d < depth; ++d) {
+            int x = vertical ? (side == SIDE_LEFT ? d : nx - 1 - d) : k;
+            int y = vertical ? k : (side == SIDE_BOTTOM ? d : ny - 1 - d);
+            t[d] = node_T(L, x, y);
+        }
+        double dtdn = nee ? (-3.0 * t[0] + 4.0 * t[1] - t[2]) / 2.0
+                          : (9.0 * t[0] - t[1] - 8.0 * tw) / 3.0;
         double nu = -length * (sign * dtdn) / dT;
         if (nu_local) nu_local[k] = nu;
-        sum += nu;
+        sum += (nee && (k == 0 || k == count - 1)) ? 0.5 * nu : nu;
         if (nu > best) { best = nu; ibest = k; }
     }
-    if (nu_mean) *nu_mean = sum / count;
+    if (nu_mean) *nu_mean = nee ? sum / (count - 1) : sum / count;
     if (nu_max) *nu_max = best;
     if (i_max) *i_max = ibest;
     return 0;

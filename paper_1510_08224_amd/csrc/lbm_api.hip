@@ -59,6 +59,12 @@ struct lbm_batch {
     BatchTile* d_tiles = nullptr;
     size_t cap_members = 0, cap_tiles = 0;
     int ntiles = 0;
+    std::vector<int> member_slot;     // tile-table member index -> slot
+    double* d_tile_max = nullptr;     // batched residual scratch
+    unsigned long long* d_tile_bad = nullptr;
+    double* d_rout = nullptr;
+    double* h_rout = nullptr;
+    size_t cap_rtiles = 0, cap_rout = 0;
     int graph_steps = 0;
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     std::string err;
@@ -270,12 +276,23 @@ static bool rate_ok(double s) { return isfinite(s) && s > 0.0 && s < 2.0; }
 static const double kW9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
 static int derive(lbm_solver* h, const lbm_params* p) {
+    int nee = 0, linkwise = 0;
     for (int s = 0; s < 4; ++s) {
-        if (p->bc_flow[s] != LBM_BC_PERIODIC && p->bc_flow[s] != LBM_BC_WALL)
+        if (p->bc_flow[s] < LBM_BC_PERIODIC || p->bc_flow[s] > LBM_BC_NEE)
             return fail(h, LBM_ERR_ARG, "lbm_set_params: unknown bc_flow code");
-        if (p->bc_temp[s] < LBM_T_PERIODIC || p->bc_temp[s] > LBM_T_ADIABATIC)
+        if (p->bc_temp[s] < LBM_T_PERIODIC || p->bc_temp[s] > LBM_T_NEE_ADIABATIC)
             return fail(h, LBM_ERR_ARG, "lbm_set_params: unknown bc_temp code");
+        const bool fn = p->bc_flow[s] == LBM_BC_NEE;
+        const bool tn = p->bc_temp[s] == LBM_T_NEE_DIRICHLET || p->bc_temp[s] == LBM_T_NEE_ADIABATIC;
+        if (fn != tn)
+            return fail(h, LBM_ERR_ARG, "lbm_set_params: an NEE flow wall needs an NEE temperature wall and vice versa");
+        nee += fn;
+        linkwise += p->bc_flow[s] == LBM_BC_WALL;
     }
+    if (nee && linkwise)
+        return fail(h, LBM_ERR_ARG, "lbm_set_params: NEE and link-wise walls cannot be mixed on one lattice");
+    if ((p->bc_flow[LBM_LEFT] == LBM_BC_NEE && h->nx < 3) || (p->bc_flow[LBM_BOTTOM] == LBM_BC_NEE && h->ny < 3))
+        return fail(h, LBM_ERR_ARG, "lbm_set_params: NEE walls need at least 3 nodes across");
     for (int a = 0; a < 2; ++a) {
         const int s0 = 2 * a, s1 = 2 * a + 1;
         const bool f0 = p->bc_flow[s0] == LBM_BC_PERIODIC, f1 = p->bc_flow[s1] == LBM_BC_PERIODIC;
@@ -290,7 +307,9 @@ static int derive(lbm_solver* h, const lbm_params* p) {
     for (int s = 0; s < 4; ++s)
         if (!isfinite(p->wall_T[s]) || !isfinite(p->wall_u[s][0]) || !isfinite(p->wall_u[s][1]))
             return fail(h, LBM_ERR_ARG, "lbm_set_params: non-finite wall value");
-    const double length = p->length > 0 ? p->length : (double)h->ny;
+    // default L: the distance between the bottom and top walls
+    const double length = p->length > 0 ? p->length
+                                        : (p->bc_flow[LBM_BOTTOM] == LBM_BC_NEE ? (double)(h->ny - 1) : (double)h->ny);
     const double dT = p->t_hot - p->t_cold;
     const double cs2 = 1.0 / 3.0, csT2 = p->varpi / 2.0;
     double s_nu = p->s_nu, z_a = p->zeta_alpha;
@@ -338,6 +357,14 @@ static int derive(lbm_solver* h, const lbm_params* p) {
             C.gconst[s] = 0.0;
         }
     }
+    C.any_nee = nee > 0;
+    for (int s = 0; s < 4; ++s) {
+        C.nee[s] = p->bc_flow[s] == LBM_BC_NEE;
+        C.tdir[s] = p->bc_temp[s] == LBM_T_NEE_DIRICHLET;
+        C.uw[s][0] = p->wall_u[s][0];
+        C.uw[s][1] = p->wall_u[s][1];
+        C.wT[s] = p->wall_T[s];
+    }
     C.fscale = C.finv = C.gscale = C.ginv = 1.0f;
     if (h->storage == LBM_F16) {
         // Powers of two: deviations of O(0.1) for fbar and of O(|T - T0|)
@@ -346,7 +373,8 @@ static int derive(lbm_solver* h, const lbm_params* p) {
         C.fscale = 4096.0f;
         double tr = fabs(p->t_hot - T0);
         for (int s = 0; s < 4; ++s)
-            if (p->bc_temp[s] == LBM_T_DIRICHLET) tr = fmax(tr, fabs(p->wall_T[s] - T0));
+            if (p->bc_temp[s] == LBM_T_DIRICHLET || p->bc_temp[s] == LBM_T_NEE_DIRICHLET)
+                tr = fmax(tr, fabs(p->wall_T[s] - T0));
         if (!(tr > 0)) tr = 1.0;
         const int k = (int)floor(log2(1024.0 / tr));
         C.gscale = (float)ldexp(1.0, k < -14 ? -14 : (k > 20 ? 20 : k));
@@ -542,17 +570,18 @@ int lbm_moments(lbm_solver* h, double* rho, double* ux, double* uy, double* T) {
 static int nusselt_common(lbm_solver* h, int32_t side, double* host_local, double* out3) {
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_nusselt: call lbm_set_params first");
     if (side < LBM_LEFT || side > LBM_TOP) return fail(h, LBM_ERR_ARG, "lbm_nusselt: side out of range");
-    if (h->params.bc_temp[side] != LBM_T_DIRICHLET)
+    const int nee = h->params.bc_temp[side] == LBM_T_NEE_DIRICHLET;
+    if (h->params.bc_temp[side] != LBM_T_DIRICHLET && !nee)
         return fail(h, LBM_ERR_ARG, "lbm_nusselt: the side is not a Dirichlet wall");
     const int depth = (side == LBM_LEFT || side == LBM_RIGHT) ? h->nx : h->ny;
     const int count = (side == LBM_LEFT || side == LBM_RIGHT) ? h->ny : h->nx;
-    if (depth < 2) return fail(h, LBM_ERR_ARG, "lbm_nusselt: the lattice is one node deep at this wall");
+    if (depth < 2 + nee) return fail(h, LBM_ERR_ARG, "lbm_nusselt: the lattice is too shallow at this wall");
     if (!(h->dT != 0)) return fail(h, LBM_ERR_ARG, "lbm_nusselt: t_hot == t_cold");
     int rc = ensure(h, reinterpret_cast<void**>(&h->nu_local),
                     (size_t)(h->nx > h->ny ? h->nx : h->ny) * sizeof(double), "Nusselt staging");
     if (rc != LBM_OK) return rc;
     hipError_t e = launch_nusselt(h->storage, h->G, h->C, h->buf[h->cur], side, h->params.wall_T[side],
-                                  h->length, h->dT, h->nu_local, h->small, h->stream);
+                                  h->length, h->dT, nee, h->nu_local, h->small, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "Nusselt kernel");
     LBM_HIP(h, hipMemcpyAsync(h->host_small, h->small, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "Nusselt copy");
     if (host_local)
@@ -754,6 +783,10 @@ void lbm_batch_destroy(lbm_batch* b) {
     batch_drop_graphs(b);
     if (b->d_members) (void)hipFree(b->d_members);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_tile_max) (void)hipFree(b->d_tile_max);
+    if (b->d_tile_bad) (void)hipFree(b->d_tile_bad);
+    if (b->d_rout) (void)hipFree(b->d_rout);
+    if (b->h_rout) (void)hipHostFree(b->h_rout);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -767,6 +800,11 @@ int lbm_batch_add(lbm_batch* b, lbm_solver* h, int32_t* slot) {
     if (h->storage != b->storage) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: storage differs from the batch's");
     if (h->stream != b->stream) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: the solver must use the batch's stream");
     if (!h->params_set) return bfail(b, LBM_ERR_STATE, "lbm_batch_add: call lbm_set_params on the solver first");
+    // members keep a residual snapshot so that the batch can take every
+    // member's residual in one launch
+    if (ensure(h, reinterpret_cast<void**>(&h->snap), 3 * (size_t)h->nx * h->ny * sizeof(double),
+               "residual snapshot") != LBM_OK)
+        return bfail(b, LBM_ERR_NOMEM, h->err);
     int k = 0;
     while (k < (int)b->slots.size() && b->slots[k]) ++k;
     if (k == (int)b->slots.size()) b->slots.push_back(nullptr);
@@ -807,7 +845,7 @@ lbm_solver* lbm_batch_member(const lbm_batch* b, int32_t slot) {
 static int batch_build(lbm_batch* b) {
     std::vector<BatchMember> mem;
     std::vector<BatchTile> tiles;
-    std::vector<int> index(b->slots.size(), -1);
+    b->member_slot.clear();
     b->buffer = true;
     for (size_t k = 0; k < b->slots.size(); ++k) {
         lbm_solver* h = b->slots[k];
@@ -820,11 +858,15 @@ static int batch_build(lbm_batch* b) {
         M.buf_bytes = h->buf_bytes < (1ull << 32) ? (unsigned)h->buf_bytes : 0u;
         if (h->buf_bytes >= (1ull << 32)) b->buffer = false;
         M.cur0 = h->cur;
+        M.snap = h->snap;
         const int id = (int)mem.size();
-        mem.push_back(M);
+        M.tile0 = (int)tiles.size();
         const int bx = h->L.bx, by = 256 / h->L.bx;
         for (int y0 = 0; y0 < h->ny; y0 += by)
             for (int x0 = 0; x0 < h->nx; x0 += bx) tiles.push_back(BatchTile{id, x0, y0, bx});
+        M.ntiles = (int)tiles.size() - M.tile0;
+        mem.push_back(M);
+        b->member_slot.push_back((int)k);
     }
     if (mem.size() > b->cap_members) {
         if (b->d_members) (void)hipFree(b->d_members);
@@ -926,18 +968,54 @@ int lbm_batch_synchronize(lbm_batch* b) {
 
 int lbm_batch_residual(lbm_batch* b, double* r, int64_t* nonfinite) {
     if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_residual: NULL batch");
-    int worst = LBM_OK;
+    if (b->dirty) {
+        int rc = batch_build(b);
+        if (rc != LBM_OK) return rc;
+    }
+    const size_t nm = b->member_slot.size();
+    if (b->cap_rtiles < (size_t)b->ntiles) {
+        if (b->d_tile_max) (void)hipFree(b->d_tile_max);
+        if (b->d_tile_bad) (void)hipFree(b->d_tile_bad);
+        b->d_tile_max = nullptr;
+        b->d_tile_bad = nullptr;
+        b->cap_rtiles = 0;
+        if (hipMalloc(reinterpret_cast<void**>(&b->d_tile_max), b->ntiles * sizeof(double)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&b->d_tile_bad), b->ntiles * sizeof(unsigned long long)) != hipSuccess)
+            return bfail(b, LBM_ERR_NOMEM, "batch residual scratch");
+        b->cap_rtiles = b->ntiles;
+    }
+    if (b->cap_rout < nm) {
+        if (b->d_rout) (void)hipFree(b->d_rout);
+        if (b->h_rout) (void)hipHostFree(b->h_rout);
+        b->d_rout = nullptr;
+        b->h_rout = nullptr;
+        b->cap_rout = 0;
+        if (hipMalloc(reinterpret_cast<void**>(&b->d_rout), 2 * nm * sizeof(double)) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_rout), 2 * nm * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return bfail(b, LBM_ERR_NOMEM, "batch residual output");
+        b->cap_rout = nm;
+    }
+    if (nm) {
+        hipError_t e = launch_residual_batch(b->storage, b->d_members, (int)nm, b->d_tiles, b->ntiles, b->parity,
+                                             b->d_tile_max, b->d_tile_bad, b->d_rout, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->h_rout, b->d_rout, 2 * nm * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("batch residual: ") + hipGetErrorString(e));
+    }
     for (size_t k = 0; k < b->slots.size(); ++k) {
+        if (r) r[k] = NAN;
+        if (nonfinite) nonfinite[k] = -1;
+    }
+    int worst = LBM_OK;
+    for (size_t m = 0; m < nm; ++m) {
+        const int k = b->member_slot[m];
         lbm_solver* h = b->slots[k];
-        double rv = NAN;
-        int64_t bad = -1;
-        if (h) {
-            int rc = lbm_residual(h, &rv, &bad);
-            if (rc != LBM_OK && rc != LBM_ERR_UNSTABLE) return bfail(b, rc, h->err);
-            if (rc == LBM_ERR_UNSTABLE) worst = LBM_ERR_UNSTABLE;
-        }
-        if (r) r[k] = rv;
+        const int64_t bad = (int64_t)b->h_rout[2 * m + 1];
+        if (r) r[k] = h->snap_valid ? b->h_rout[2 * m] : INFINITY;
         if (nonfinite) nonfinite[k] = bad;
+        h->snap_valid = true;
+        if (bad) worst = LBM_ERR_UNSTABLE;
     }
     if (worst != LBM_OK) b->err = "lbm_batch_residual: non-finite values in at least one member";
     return worst;

@@ -60,6 +60,12 @@ struct Coeffs {
     // varpi (T_w - T0)/2 for deviations; bounce-back +1, 0).
     double bbf[4][9];
     double gsign[4], gconst[4];
+    // Non-equilibrium extrapolation walls (the wall passes through the
+    // first/last node row or column): nee[side] = 1 for such a side,
+    // tdir[side] = 1 if its temperature is Dirichlet, uw the wall velocity,
+    // wT the wall temperature.  any_nee = any side.
+    int nee[4], tdir[4], any_nee;
+    double uw[4][2], wT[4];
     // Deviation storage scales (FP16): stored = value * scale.
     float fscale, finv, gscale, ginv;
 };
@@ -198,6 +204,53 @@ __device__ __forceinline__ void pull_interior(const S* __restrict__ src, const G
 }
 
 // ---------------------------------------------------------------------------
+// Non-equilibrium extrapolation walls (the scheme the paper's Sec. 3 uses;
+// reading: Guo-Zheng-Shi extrapolation of the non-equilibrium part).  A
+// wall node x_b takes its pre-collision populations from its inward
+// neighbour x_f:
+//   fbar_i(x_b) = f_i^eq(rho(x_f), u_w) + [fbar_i(x_f) - f_i^eq(rho(x_f), u(x_f))]
+//   g_i(x_b)    = g_i^eq(T_b, u_w)      + [g_i(x_f)    - g_i^eq(T(x_f), u(x_f))]
+// with f^eq of Eq. 22 (rho only in the rest term, rho0 = 1 on the velocity
+// terms), g^eq of Eq. 30, T_b the wall temperature (Dirichlet) or T(x_f)
+// (adiabatic).  Corner nodes use the diagonal neighbour, the velocity of
+// their top/bottom wall and a Dirichlet temperature if either wall has one
+// (top/bottom first).  In deviation storage both equilibria are taken
+// relative to the rest state, which cancels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double w9(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+__device__ __forceinline__ double feq_rep(int i, double rho, double ux, double uy) {
+    const double eu = ex(i) * ux + ey(i) * uy, usq = ux * ux + uy * uy;
+    return w9(i) * (rho + 1.0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+}
+
+// g^eq(T, u) minus the stored rest part g^eq(Trest, 0) (Trest = 0 for full
+// values, T0 for deviations).
+__device__ __forceinline__ double geq_rep(int i, double T, double ux, double uy, double varpi, double Trest) {
+    if (i == 0) return (1.0 - varpi) * (T - Trest);
+    return 0.25 * varpi * (T - Trest) + 0.5 * (ex(i) * ux + ey(i) * uy) * T;
+}
+
+__device__ __forceinline__ bool nee_node_at(const Geom& G, const Coeffs& C, int x, int y) {
+    return (C.nee[kLeft] && x == 0) || (C.nee[kRight] && x == G.nx - 1) || (C.nee[kBottom] && y == 0) ||
+           (C.nee[kTop] && y == G.ny - 1);
+}
+
+// Defined below (needs macro()).
+template <class S>
+__device__ void nee_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
+                         typename Codec<S>::R f[9], typename Codec<S>::R g[5]);
+
+// Pre-collision populations of any node: extrapolated on NEE walls,
+// pulled everywhere else.
+template <class S>
+__device__ __forceinline__ void load_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x,
+                                          int y, typename Codec<S>::R f[9], typename Codec<S>::R g[5]) {
+    if (C.any_nee && nee_node_at(G, C, x, y)) nee_node<S>(src, G, C, x, y, f, g);
+    else pull_node<S>(src, G, C, x, y, f, g);
+}
+
+// ---------------------------------------------------------------------------
 // Buffer-resource access (one descriptor for a whole population buffer,
 // per-plane offsets in scalar registers, one 32-bit lane offset shared by
 // all planes).  Usable while the buffer is below 4 GiB.  Stores are
@@ -269,6 +322,10 @@ __device__ __forceinline__ void fix_x_edges(const S* __restrict__ src, const Geo
     auto ld = [&](int pl, int xx, int yy, float inv) -> R {
         return Codec<S>::load(src + (long long)pl * G.plane + (long long)yy * G.pitch + xx, inv);
     };
+    if ((x == 0 && C.nee[kLeft]) || (x == G.nx - 1 && C.nee[kRight])) {
+        nee_node<S>(src, G, C, x, y, f, g);
+        return;
+    }
     if (x == 0) {
         if (G.px) {
             const int xs = G.nx - 1;
@@ -421,6 +478,30 @@ __device__ __forceinline__ void collide(R f[9], R g[5], const Macro& mc, const C
     g[3] = (R)(-0.5) * k1 + (w3 + w4);
     g[2] = (R)0.5 * k2 + (w3 - w4);
     g[4] = (R)(-0.5) * k2 + (w3 - w4);
+}
+
+template <class S>
+__device__ void nee_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
+                         typename Codec<S>::R f[9], typename Codec<S>::R g[5]) {
+    using R = typename Codec<S>::R;
+    const bool onL = C.nee[kLeft] && x == 0, onR = C.nee[kRight] && x == G.nx - 1;
+    const bool onB = C.nee[kBottom] && y == 0, onT = C.nee[kTop] && y == G.ny - 1;
+    const int fx = x + (onL ? 1 : (onR ? -1 : 0));
+    const int fy = y + (onB ? 1 : (onT ? -1 : 0));
+    const int sx = onL ? kLeft : (onR ? kRight : -1);
+    const int sy = onB ? kBottom : (onT ? kTop : -1);
+    const int vs = sy >= 0 ? sy : sx;
+    const int ts = (sy >= 0 && C.tdir[sy]) ? sy : ((sx >= 0 && C.tdir[sx]) ? sx : -1);
+    R ff[9], gf[5];
+    pull_node<S>(src, G, C, fx, fy, ff, gf);
+    const Macro m = macro<R>(ff, gf, C);
+    const double uwx = C.uw[vs][0], uwy = C.uw[vs][1];
+    const double Tb = ts >= 0 ? C.wT[ts] : m.T;
+    for (int i = 0; i < 9; ++i)
+        f[i] = (R)(feq_rep(i, m.rho, uwx, uwy) + ((double)ff[i] - feq_rep(i, m.rho, m.ux, m.uy)));
+    for (int i = 0; i < 5; ++i)
+        g[i] = (R)(geq_rep(i, Tb, uwx, uwy, C.varpi, C.toff) +
+                   ((double)gf[i] - geq_rep(i, m.T, m.ux, m.uy, C.varpi, C.toff)));
 }
 
 }  // namespace lbm

@@ -21,6 +21,8 @@ struct BatchMember {
     void* buf[2];
     unsigned buf_bytes;  // bytes of one population buffer
     int cur0;            // buffer holding the state when the tile table was built
+    double* snap;        // residual snapshot (3 * nx * ny), or null
+    int tile0, ntiles;   // this member's range of the tile table
 };
 
 // One workgroup's work in a batched step: bx x (256 / bx) nodes of member
@@ -35,6 +37,9 @@ hipError_t launch_sweep(int storage, const Launch& L, const Geom& G, const Coeff
                         void* dst, hipStream_t st);
 hipError_t launch_sweep_batch(int storage, bool buffer, const BatchMember* members, const BatchTile* tiles,
                               int ntiles, int parity, hipStream_t st);
+hipError_t launch_residual_batch(int storage, const BatchMember* members, int nmembers, const BatchTile* tiles,
+                                 int ntiles, int parity, double* tile_max, unsigned long long* tile_bad,
+                                 double* out2, hipStream_t st);
 hipError_t launch_moments(int storage, const Geom& G, const Coeffs& C, const void* src, double* rho,
                           double* ux, double* uy, double* T, hipStream_t st);
 hipError_t launch_gather(int storage, const Geom& G, const Coeffs& C, const void* src, double* pf,
@@ -43,7 +48,7 @@ hipError_t launch_unstream(int storage, const Geom& G, const Coeffs& C, void* ds
                            const double* pg, const double* Tf, double T0, bool from_temperature,
                            hipStream_t st);
 hipError_t launch_nusselt(int storage, const Geom& G, const Coeffs& C, const void* src, int side,
-                          double tw, double length, double dT, double* local, double* out3,
+                          double tw, double length, double dT, int nee, double* local, double* out3,
                           hipStream_t st);
 int residual_parts(const Geom& G);
 hipError_t launch_residual(int storage, const Geom& G, const Coeffs& C, const void* src, double* snap,

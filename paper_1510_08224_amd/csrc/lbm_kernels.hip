@@ -96,7 +96,7 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
     R f[ROWS][9], g[ROWS][5];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r)
-        if (y0 + r < G.ny) pull_node<S>(src, G, C, x, y0 + r, f[r], g[r]);
+        if (y0 + r < G.ny) load_node<S>(src, G, C, x, y0 + r, f[r], g[r]);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         if (y0 + r < G.ny) {
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_moments(Geom G, Coeffs C, const S* __re
     if (k >= n) return;
     const int x = (int)(k % G.nx), y = (int)(k / G.nx);
     R f[9], g[5];
-    pull_node<S>(src, G, C, x, y, f, g);
+    load_node<S>(src, G, C, x, y, f, g);
     const Macro m = macro<R>(f, g, C);
     if (rho) rho[k] = Codec<S>::kDev ? 1.0 + m.rho : m.rho;
     if (ux) ux[k] = m.ux;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_gather(Geom G, Coeffs C, const S* __res
     if (k >= n) return;
     const int x = (int)(k % G.nx), y = (int)(k / G.nx);
     R f[9], g[5];
-    pull_node<S>(src, G, C, x, y, f, g);
+    load_node<S>(src, G, C, x, y, f, g);
     constexpr bool dev = Codec<S>::kDev;
     if (pf)
         for (int i = 0; i < 9; ++i) pf[i * n + k] = dev ? rest_f(i) + (double)f[i] : (double)f[i];
@@ -262,7 +262,7 @@ __device__ __forceinline__ double node_T(const S* __restrict__ src, const Geom& 
                                          int x, int y) {
     using R = typename Codec<S>::R;
     R f[9], g[5];
-    pull_node<S>(src, G, C, x, y, f, g);
+    load_node<S>(src, G, C, x, y, f, g);
     const double s = (((double)g[0] + (double)g[1]) + ((double)g[2] + (double)g[3])) + (double)g[4];
     return s + C.toff;
 }
@@ -283,10 +283,13 @@ __device__ __forceinline__ void wave_maxloc(double& v, int& i) {
     }
 }
 
+// Link-wise walls: wall half a spacing outside node 1, dT/dn from
+// (9 T1 - T2 - 8 Tw) / 3, midpoint mean.  NEE walls (nee = 1): wall through
+// node 0, dT/dn from (-3 T0 + 4 T1 - T2) / 2, trapezoidal mean.
 template <class S>
 __global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __restrict__ src,
                                                  int side, double tw, double length, double dT,
-                                                 double* local, double* out) {
+                                                 int nee, double* local, double* out) {
     __shared__ double s_sum[4], s_max[4];
     __shared__ int s_idx[4];
     const int count = (side == kLeft || side == kRight) ? G.ny : G.nx;
@@ -294,17 +297,19 @@ __global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __re
     double sum = 0.0, best = -DBL_MAX;
     int ibest = 0x7fffffff;
     for (int k = threadIdx.x; k < count; k += blockDim.x) {
-        int x1, y1, x2, y2;
-        if (side == kLeft) { x1 = 0; x2 = 1; y1 = y2 = k; }
-        else if (side == kRight) { x1 = G.nx - 1; x2 = G.nx - 2; y1 = y2 = k; }
-        else if (side == kBottom) { y1 = 0; y2 = 1; x1 = x2 = k; }
-        else { y1 = G.ny - 1; y2 = G.ny - 2; x1 = x2 = k; }
-        const double t1 = node_T<S>(src, G, C, x1, y1);
-        const double t2 = node_T<S>(src, G, C, x2, y2);
-        const double dtdn = (9.0 * t1 - t2 - 8.0 * tw) / 3.0;
+        double t[3];
+        for (int d = 0; d < 2 + nee; ++d) {
+            int x, y;
+            if (side == kLeft) { x = d; y = k; }
+            else if (side == kRight) { x = G.nx - 1 - d; y = k; }
+            else if (side == kBottom) { x = k; y = d; }
+            else { x = k; y = G.ny - 1 - d; }
+            t[d] = node_T<S>(src, G, C, x, y);
+        }
+        const double dtdn = nee ? (-3.0 * t[0] + 4.0 * t[1] - t[2]) / 2.0 : (9.0 * t[0] - t[1] - 8.0 * tw) / 3.0;
         const double nu = -length * (sign * dtdn) / dT;
         if (local) local[k] = nu;
-        sum += nu;
+        sum += (nee && (k == 0 || k == count - 1)) ? 0.5 * nu : nu;
         if (nu > best) { best = nu; ibest = k; }
     }
     sum = wave_sum(sum);
@@ -320,7 +325,7 @@ __global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __re
             t += s_sum[w];
             if (s_max[w] > b || (s_max[w] == b && s_idx[w] < bi)) { b = s_max[w]; bi = s_idx[w]; }
         }
-        out[0] = t / count;
+        out[0] = nee ? t / (count - 1) : t / count;
         out[1] = b;
         out[2] = (double)bi;
     }
@@ -340,7 +345,7 @@ __global__ __launch_bounds__(256) void k_residual(Geom G, Coeffs C, const S* __r
     if (k < n) {
         const int x = (int)(k % G.nx), y = (int)(k / G.nx);
         R f[9], g[5];
-        pull_node<S>(src, G, C, x, y, f, g);
+        load_node<S>(src, G, C, x, y, f, g);
         const Macro m = macro<R>(f, g, C);
         const bool fin = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.T);
         bad = fin ? 0ull : 1ull;
@@ -389,6 +394,85 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* pmax, const 
         for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) { t = fmax(t, s_max[w]); bb += s_bad[w]; }
         out[0] = t;
         out[1] = (double)bb;
+    }
+}
+
+// Residual of every member of a batch: one workgroup per tile, partial
+// maxima and non-finite counts per tile, then one workgroup per member
+// reduces its contiguous range of tiles (fixed order) into out2[2 m],
+// out2[2 m + 1].
+template <class S>
+__global__ __launch_bounds__(256) void k_residual_batch(const BatchMember* __restrict__ members,
+                                                        const BatchTile* __restrict__ tiles, int parity,
+                                                        double* tile_max, unsigned long long* tile_bad) {
+    using R = typename Codec<S>::R;
+    __shared__ double s_max[4];
+    __shared__ unsigned long long s_bad[4];
+    const int ti = blockIdx.x;
+    const BatchTile t = tiles[ti];
+    const BatchMember& M = members[t.member];
+    const S* src = static_cast<const S*>(M.buf[(M.cur0 + parity) & 1]);
+    const int x = t.x0 + (int)(threadIdx.x % (unsigned)t.bx);
+    const int y = t.y0 + (int)(threadIdx.x / (unsigned)t.bx);
+    double d = 0.0;
+    unsigned long long bad = 0;
+    if (x < M.G.nx && y < M.G.ny) {
+        const long long n = (long long)M.G.nx * M.G.ny, k = (long long)y * M.G.nx + x;
+        R f[9], g[5];
+        load_node<S>(src, M.G, M.C, x, y, f, g);
+        const Macro m = macro<R>(f, g, M.C);
+        const bool fin = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.T);
+        bad = fin ? 0ull : 1ull;
+        double* snap = M.snap;
+        if (fin)
+            d = fmax(fmax(fabs(m.ux - snap[k]), fabs(m.uy - snap[n + k])), fabs(m.T - snap[2 * n + k]));
+        snap[k] = m.ux;
+        snap[n + k] = m.uy;
+        snap[2 * n + k] = m.T;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        d = fmax(d, __shfl_down(d, o, 64));
+        bad += __shfl_down(bad, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_max[wave] = d; s_bad[wave] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tm = 0.0;
+        unsigned long long b = 0;
+        for (int w = 0; w < 4; ++w) { tm = fmax(tm, s_max[w]); b += s_bad[w]; }
+        tile_max[ti] = tm;
+        tile_bad[ti] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_members(const BatchMember* __restrict__ members,
+                                                        const double* tile_max,
+                                                        const unsigned long long* tile_bad, double* out2) {
+    __shared__ double s_max[4];
+    __shared__ unsigned long long s_bad[4];
+    const BatchMember& M = members[blockIdx.x];
+    double d = 0.0;
+    unsigned long long b = 0;
+    for (int i = threadIdx.x; i < M.ntiles; i += blockDim.x) {
+        d = fmax(d, tile_max[M.tile0 + i]);
+        b += tile_bad[M.tile0 + i];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        d = fmax(d, __shfl_down(d, o, 64));
+        b += __shfl_down(b, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_max[wave] = d; s_bad[wave] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tm = 0.0;
+        unsigned long long bb = 0;
+        for (int w = 0; w < 4; ++w) { tm = fmax(tm, s_max[w]); bb += s_bad[w]; }
+        out2[2 * blockIdx.x] = tm;
+        out2[2 * blockIdx.x + 1] = (double)bb;
     }
 }
 
@@ -464,6 +548,18 @@ hipError_t launch_sweep_batch(int storage, bool buffer, const BatchMember* membe
     return hipGetLastError();
 }
 
+hipError_t launch_residual_batch(int storage, const BatchMember* members, int nmembers, const BatchTile* tiles,
+                                 int ntiles, int parity, double* tile_max, unsigned long long* tile_bad,
+                                 double* out2, hipStream_t st) {
+    if (ntiles <= 0 || nmembers <= 0) return hipSuccess;
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_residual_batch<S>), dim3(ntiles), dim3(256), 0, st, members, tiles,
+                                             parity, tile_max, tile_bad));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_members, dim3(nmembers), dim3(256), 0, st, members, tile_max, tile_bad, out2);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments(int storage, const Geom& G, const Coeffs& C, const void* src, double* rho,
                           double* ux, double* uy, double* T, hipStream_t st) {
     const long long n = (long long)G.nx * G.ny;
@@ -495,10 +591,10 @@ hipError_t launch_unstream(int storage, const Geom& G, const Coeffs& C, void* ds
 }
 
 hipError_t launch_nusselt(int storage, const Geom& G, const Coeffs& C, const void* src, int side,
-                          double tw, double length, double dT, double* local, double* out3,
+                          double tw, double length, double dT, int nee, double* local, double* out3,
                           hipStream_t st) {
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_nusselt<S>), dim3(1), dim3(256), 0, st, G, C,
-                                             static_cast<const S*>(src), side, tw, length, dT, local,
+                                             static_cast<const S*>(src), side, tw, length, dT, nee, local,
                                              out3));
     return hipGetLastError();
 }

@@ -24,8 +24,8 @@ LBM_OK, LBM_ERR_ARG, LBM_ERR_NOMEM, LBM_ERR_DEVICE = 0, -1, -2, -3
 LBM_ERR_STATE, LBM_ERR_UNSTABLE, LBM_ERR_UNSUPPORTED = -4, -5, -6
 LBM_F64, LBM_F32, LBM_F16 = 0, 1, 2
 LBM_LEFT, LBM_RIGHT, LBM_BOTTOM, LBM_TOP = 0, 1, 2, 3
-LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
-LBM_T_PERIODIC, LBM_T_DIRICHLET, LBM_T_ADIABATIC = 0, 1, 2
+LBM_BC_PERIODIC, LBM_BC_WALL, LBM_BC_NEE = 0, 1, 2
+LBM_T_PERIODIC, LBM_T_DIRICHLET, LBM_T_ADIABATIC, LBM_T_NEE_DIRICHLET, LBM_T_NEE_ADIABATIC = 0, 1, 2, 3, 4
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16}
 _CODES = {-1: "LBM_ERR_ARG", -2: "LBM_ERR_NOMEM", -3: "LBM_ERR_DEVICE", -4: "LBM_ERR_STATE",

@@ -1,6 +1,6 @@
 """Continuous-batching solve server.
 
-    python -m paper_1510_08224_amd.serving [--count 48 --rates 0.25,0.5,1,2]
+    python -m paper_1510_08224_amd.serving [--count 32 --rates 0.5,1,2,4 --cap 100000]
 
 Requests (cavity and Rayleigh-Benard solves of different sizes, Poisson
 arrivals) are admitted as slots in one :class:`lbm.Batch` while an HBM
@@ -236,9 +236,9 @@ def summarize(results, wall, lup) -> dict:
             "status": {s: sum(r.status == s for r in results) for s in sorted({r.status for r in results})}}
 
 
-def benchmark(count: int = 48, rates=(0.25, 0.5, 1.0, 2.0), seed: int = 4, cap: int = 30000,
+def benchmark(count: int = 32, rates=(0.5, 1.0, 2.0, 4.0), seed: int = 4, cap: int = 100000,
               tol: float = 1e-7, check_every: int = 1000, budget_gib: float = 2.0, max_slots: int = 64,
-              n_range=(64, 1024)) -> dict:
+              n_range=(64, 1024), live_serial_rate: float | None = 1.0) -> dict:
     base = W.request_stream(count, 1.0, seed=seed, n_range=n_range)
     # service time of each request alone (the plain method), measured once
     service, lup_serial, serial_results = {}, 0, {}
@@ -271,18 +271,25 @@ def benchmark(count: int = 48, rates=(0.25, 0.5, 1.0, 2.0), seed: int = 4, cap: 
         # equality of stopping: the server's steps per request match the plain method's
         same = sum(r.steps == serial_results[r.rid].steps and r.status == serial_results[r.rid].status
                    for r in run["results"])
-        out["rates"].append({"rate_factor": f, "arrival_rate_per_s": round(lam, 4), "batched": batched,
-                             "serial": serial, "same_steps_as_alone": f"{same}/{len(run['results'])}"})
+        entry = {"rate_factor": f, "arrival_rate_per_s": round(lam, 4), "batched": batched,
+                 "serial": serial, "same_steps_as_alone": f"{same}/{len(run['results'])}"}
+        if live_serial_rate is not None and abs(f - live_serial_rate) < 1e-12:
+            # the plain method run live at this rate, to check the FIFO model
+            live = serve_serial(reqs, tol, check_every, cap)
+            wall = max(r.finish for r in live)
+            lup = sum(r.nx * r.ny * r.steps for r in live)
+            entry["serial_live"] = summarize(live, wall, lup)
+        out["rates"].append(entry)
         print(json.dumps(out["rates"][-1]), flush=True)
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--count", type=int, default=48)
-    ap.add_argument("--rates", default="0.25,0.5,1,2")
+    ap.add_argument("--count", type=int, default=32)
+    ap.add_argument("--rates", default="0.5,1,2,4")
     ap.add_argument("--seed", type=int, default=4)
-    ap.add_argument("--cap", type=int, default=30000)
+    ap.add_argument("--cap", type=int, default=100000)
     ap.add_argument("--budget-gib", type=float, default=2.0)
     ap.add_argument("--max-slots", type=int, default=64)
     ap.add_argument("--nmax", type=int, default=1024)

@@ -20,8 +20,17 @@ from dataclasses import dataclass, field
 import numpy as np
 
 LEFT, RIGHT, BOTTOM, TOP = 0, 1, 2, 3
-FLOW_PERIODIC, FLOW_WALL = 0, 1
-TEMP_PERIODIC, TEMP_DIRICHLET, TEMP_ADIABATIC = 0, 1, 2
+FLOW_PERIODIC, FLOW_WALL, FLOW_NEE = 0, 1, 2
+TEMP_PERIODIC, TEMP_DIRICHLET, TEMP_ADIABATIC, TEMP_NEE_DIRICHLET, TEMP_NEE_ADIABATIC = 0, 1, 2, 3, 4
+
+
+def with_nee_walls(pb: "Problem") -> "Problem":
+    """The same problem with non-equilibrium-extrapolation walls in place of
+    link-wise walls (walls through the first/last node row or column)."""
+    tmap = {TEMP_DIRICHLET: TEMP_NEE_DIRICHLET, TEMP_ADIABATIC: TEMP_NEE_ADIABATIC}
+    flow = tuple(FLOW_NEE if f == FLOW_WALL else f for f in pb.bc_flow)
+    temp = tuple(tmap.get(t, t) for t in pb.bc_temp)
+    return dataclasses.replace(pb, bc_flow=flow, bc_temp=temp, name=pb.name + "_nee")
 
 
 @dataclass

@@ -33,10 +33,10 @@ def _check(pb, S, L, tol=TOL, nusselt=True):
     assert np.max(np.abs(mg[3] - mo[3])) < tol * ts
     if nusselt:
         for side in range(4):
-            if pb.bc_temp[side] != W.TEMP_DIRICHLET:
+            if pb.bc_temp[side] not in (W.TEMP_DIRICHLET, W.TEMP_NEE_DIRICHLET):
                 continue
             depth = pb.nx if side in (W.LEFT, W.RIGHT) else pb.ny
-            if depth < 2 or pb.t_hot == pb.t_cold:
+            if depth < 3 or pb.t_hot == pb.t_cold:
                 continue
             a = S.nusselt(side)
             b = L.nusselt(side)
@@ -82,6 +82,16 @@ CASES = {
     "lid_cavity_moving_walls_30x30": (lambda: W.cavity(30, 1e5).replace(
         wall_u=((0.0, 0.003), (0.0, 0.0), (0.01, 0.0), (0.05, 0.0))), None, None),
     "cavity_paper_temperatures_24": (lambda: W.cavity(24, 1e4, t_hot=21.0, t_cold=1.0), None, None),
+    # non-equilibrium extrapolation walls (walls through the edge nodes)
+    "nee_cavity40x30_randT": (lambda: W.with_nee_walls(W.cavity(40, 1e5, ny=30)),
+                              lambda pb: W.random_temperature(40, 30, 0.0, 1.0, seed=13), None),
+    "nee_cavity130x70_fastpath": (lambda: W.with_nee_walls(W.cavity(130, 3e5, ny=70)), None, None),
+    "nee_rb70x17_noise": (lambda: W.with_nee_walls(W.rayleigh_benard(70, 17, 2e4)),
+                          lambda pb: W.rb_initial_temperature(70, 17, amp=1e-2, seed=7), None),
+    "nee_injection_channel13x21": (lambda: W.with_nee_walls(W.channel(13, 21, s_nu=0.8, zeta_alpha=0.9,
+                                   u_top=(0.02, 0.01), u_bottom=(0.0, 0.01))), None, None),
+    "nee_cavity_random_pops_24x20": (lambda: W.with_nee_walls(W.cavity(24, 1e4, ny=20)), None,
+                                     lambda pb: W.random_populations(24, 20, 17)),
 }
 
 

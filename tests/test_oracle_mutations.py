@@ -31,7 +31,12 @@ MUTANTS = {
     "antibounce_sign": ("= -L->gp[c * 5 + i] + 0.5 * p->varpi", "= L->gp[c * 5 + i] + 0.5 * p->varpi"),
     "moving_wall_sign": ("L->fp[c * 9 + i] - 6.0 * W9[i]", "L->fp[c * 9 + i] + 6.0 * W9[i]"),
     "buoyancy_sign": ("p->ay + p->gbeta * (t - p->T0)", "p->ay - p->gbeta * (t - p->T0)"),
-    "nusselt_first_order": ("(9.0 * t1 - t2 - 8.0 * tw) / 3.0", "2.0 * (t1 - tw)"),
+    "nusselt_first_order": ("(9.0 * t[0] - t[1] - 8.0 * tw) / 3.0", "2.0 * (t[0] - tw)"),
+    "nee_neq_sign": ("fb[i] = feq_i(p, i, rho, uwx, uwy) + (ff[i] - feq_i(p, i, rho, ux, uy));",
+                     "fb[i] = feq_i(p, i, rho, uwx, uwy) - (ff[i] - feq_i(p, i, rho, ux, uy));"),
+    "nee_wall_temperature": ("double Tb = tside >= 0 ? p->wall_T[tside] : T;", "double Tb = T;"),
+    "nee_wall_velocity": ("double uwx = p->wall_u[vside][0], uwy = p->wall_u[vside][1];",
+                          "double uwx = ux, uwy = uy;"),
     "stream_index": ("L->fn[((size_t)ty * nx + tx) * 9 + i]", "L->fn[((size_t)ty * nx + tx) * 9 + OPP9[i]]"),
 }
 
@@ -106,6 +111,15 @@ def _battery(lib):
     L = oracle.Lattice(pb, T_init=np.tile(Tq, (6, 1)), library=lib)
     if abs(L.nusselt(W.LEFT)[0] - 6 * 0.1) > 1e-12:
         failed.append("nusselt_quadratic")
+    # non-equilibrium extrapolation walls: Couette exact with the walls on the nodes
+    pb = W.channel(3, 12, s_nu=1.2, zeta_alpha=0.9, u_top=(0.04, 0.0)).replace(
+        bc_flow=(0, 0, 2, 2), bc_temp=(0, 0, 3, 3))
+    L = oracle.Lattice(pb, library=lib)
+    L.step(8000)
+    _, ux, uy, T = L.moments()
+    yy = np.arange(12) / 11.0
+    if not (np.max(np.abs(ux - 0.04 * yy[:, None])) < 1e-12 and np.max(np.abs(T - yy[:, None])) < 1e-12):
+        failed.append("nee_couette_exact")
     # mirror symmetry of a Rayleigh-Benard cell with a symmetric start
     T = W.rb_initial_temperature(12, 6, amp=1e-2, seed=9)
     T = 0.5 * (T + T[:, ::-1])
