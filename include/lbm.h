@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 typedef struct lbm_solver lbm_solver; /* opaque, library-owned */
 
@@ -68,6 +68,16 @@ enum lbm_status {
 enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
 
 enum lbm_side { LBM_LEFT = 0, LBM_RIGHT = 1, LBM_BOTTOM = 2, LBM_TOP = 3 };
+
+/* Thermal model, fixed at creation (it sets the number of populations).
+ * LBM_MODEL_D2Q5: the paper's D2Q5 temperature equation (Sec. 2.2).
+ * LBM_MODEL_D2Q9T: its D2Q9 variant (Eqs. 31-33): equilibrium of Eq. 31
+ *   with theta in {0, 1}, collided with the non-orthogonal M of Eq. 13 and
+ *   Q = diag(1, zeta_alpha, zeta_alpha, zeta_e, zeta_nu, zeta_nu, zeta_q,
+ *   zeta_q, zeta_eps) (Eq. 32); c_sT^2 = 1/3.
+ * LBM_MODEL_ISOTHERMAL: no temperature field (Secs. 3.1-3.2); the force
+ *   is the external acceleration a only. */
+enum lbm_model { LBM_MODEL_D2Q5 = 0, LBM_MODEL_D2Q9T = 1, LBM_MODEL_ISOTHERMAL = 2 };
 
 /* Flow boundary per side.  LBM_BC_WALL is halfway bounce-back with the
  * moving-wall term: the wall lies half a spacing outside the last node,
@@ -103,6 +113,8 @@ typedef struct {
     double t_hot, t_cold;  /* dT = t_hot - t_cold, T0 = (t_hot + t_cold)/2 (Sec. 3.4) */
     double s_e, s_q, s_eps;        /* free D2Q9 rates (Eq. 20); defaults 1.6, 1.2, 1.8 */
     double zeta_e, zeta_nu, varpi; /* free D2Q5 rates (Eq. 29) and varpi (Eq. 28); 1.9, 1.9, 0.5 */
+    double zeta_q, zeta_eps;       /* further D2Q9 thermal rates (Eq. 32); 1.9, 1.9 */
+    double theta;                  /* D2Q9 thermal equilibrium switch of Eq. 31, 0 or 1; 1 */
     double s_nu, zeta_alpha;       /* 0 => from Eq. 40; > 0 => used as given */
     double ax, ay;                 /* external acceleration a (Eq. 4) */
     int32_t bc_flow[4];            /* enum lbm_bc_flow, indexed by enum lbm_side */
@@ -121,43 +133,48 @@ void lbm_params_default(lbm_params* p);
 int32_t lbm_abi_version(void);
 const char* lbm_build_info(void);
 
-/* Device bytes a solver of this size and storage needs (both population
- * buffers with row and plane padding).  *bytes receives the size. */
-int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, uint64_t* bytes);
+/* Device bytes a solver of this size, storage and thermal model needs
+ * (both population buffers with row and plane padding). */
+int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, uint64_t* bytes);
 
 /* Create a solver for an nx x ny lattice (nx, ny >= 1, one population
  * plane below 4 GiB: up to about 5.3e8 nodes in FP64) on the current HIP
  * device.  hip_stream: a hipStream_t to launch on, or NULL for a stream the
  * library creates and owns.  Allocates lbm_required_bytes() of device
  * memory.  *out is set to NULL on failure. */
-int lbm_create(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* hip_stream);
+int lbm_create(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, int32_t model, void* hip_stream);
 
 /* As lbm_create, but the population buffers live in caller-owned device
  * memory [device_buffer, device_buffer + bytes), 256-byte aligned, at least
  * lbm_required_bytes(); the caller keeps it alive until lbm_destroy. */
-int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage,
+int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, int32_t model,
                    void* device_buffer, uint64_t bytes, void* hip_stream);
 
 /* Validate and apply a problem, derive the rates, and reset the state to
  * rest at T = T0: fbar_i = w_i rho0 (Eq. 22 at u = 0) and
- * g_i = g_i^eq(T0, 0) (Eq. 30), time t = 0.
+ * g_i = g_i^eq(T0, 0) (Eq. 30 or 31), time t = 0.
  * Derived (unless given explicitly, Eq. 40):
  *   1/s_nu = 1/2 + Ma L sqrt(3 Pr)/sqrt(Ra),  Ma = sqrt(3) u_c,
  *   1/zeta_alpha = 1/2 + c_s^2 (1/s_nu - 1/2)/(c_sT^2 Pr),
- *   c_s^2 = 1/3, c_sT^2 = varpi/2, g beta = u_c^2/(dT L) (0 if u_c = 0).
+ *   c_s^2 = 1/3, c_sT^2 = varpi/2 (D2Q5) or 1/3 (D2Q9 thermal),
+ *   g beta = u_c^2/(dT L) (0 if u_c = 0 or without a temperature field).
  * Errors: LBM_ERR_ARG for rates outside (0, 2), varpi outside (0, 1),
- * inconsistent periodicity, unknown boundary codes, or missing data to
- * derive a rate. */
+ * theta other than 0 or 1 (D2Q9 thermal), inconsistent periodicity,
+ * unknown boundary codes, or missing data to derive a rate.  The
+ * temperature boundary codes are checked for every model. */
 int lbm_set_params(lbm_solver* h, const lbm_params* p);
 
-/* Rates and constants in use: s9 = diag(Lambda) (Eq. 20), q5 = diag(Q)
- * (Eq. 29), g beta, T0, L, dT.  Any pointer may be NULL. */
-int lbm_get_derived(const lbm_solver* h, double* s9, double* q5, double* gbeta,
+/* Rates and constants in use: s9 = diag(Lambda) (Eq. 20); q9 = diag(Q),
+ * 9 values: Eq. 29 in the first 5 and zeros (D2Q5), Eq. 32 (D2Q9 thermal),
+ * all zero (no temperature field); g beta, T0, L, dT.  Any pointer may be
+ * NULL.  LBM_ERR_STATE before lbm_set_params. */
+int lbm_get_derived(const lbm_solver* h, double* s9, double* q9, double* gbeta,
                     double* T0, double* length, double* dT);
 
 /* Reset to rest with a temperature field: fbar_i = w_i rho0,
- * g_i = g_i^eq(T(x), 0) (Eq. 30); t = 0.  T is host [y][x], nx*ny values;
- * NULL means T = T0 everywhere. */
+ * g_i = g_i^eq(T(x), 0) (Eq. 30 or 31); t = 0.  T is host [y][x], nx*ny
+ * values; NULL means T = T0 everywhere.  A non-NULL T without a
+ * temperature field is LBM_ERR_UNSUPPORTED. */
 int lbm_init_temperature(lbm_solver* h, const double* T);
 
 /* Advance nsteps >= 0 time steps: per node, stream (Eqs. 9, 25) with the
@@ -198,6 +215,9 @@ int lbm_moments_device(lbm_solver* h, double* rho, double* ux, double* uy, doubl
  * deep.  Synchronizes. */
 int lbm_nusselt(lbm_solver* h, int32_t side, double* nu_mean, double* nu_max, int32_t* i_max);
 
+/* (Nusselt numbers need a temperature field: LBM_ERR_UNSUPPORTED for the
+ * isothermal model.) */
+
 /* Local Nusselt numbers along a Dirichlet side into a host array of ny
  * (left/right) or nx (bottom/top) doubles.  Synchronizes. */
 int lbm_nusselt_local(lbm_solver* h, int32_t side, double* nu_local);
@@ -213,7 +233,8 @@ int lbm_nusselt_local(lbm_solver* h, int32_t side, double* nu_local);
 int lbm_residual(lbm_solver* h, double* r, int64_t* nonfinite);
 
 /* Pre-collision populations at time t in FP64, host arrays
- * f9[9][ny][nx] and g5[5][ny][nx] (either may be NULL).  For deviation
+ * f9[9][ny][nx] and g5[NG][ny][nx] with NG = 5, 9 or 0 by thermal model
+ * (either may be NULL).  For deviation
  * storage the rest equilibrium is added back.  Synchronizes. */
 int lbm_get_populations(lbm_solver* h, double* f9, double* g5);
 
@@ -231,9 +252,10 @@ int lbm_state_bytes(const lbm_solver* h, uint64_t* bytes);
 int lbm_save_state(lbm_solver* h, void* host, uint64_t bytes);
 int lbm_load_state(lbm_solver* h, const void* host, uint64_t bytes);
 
-/* The solver's stream (hipStream_t) and storage mode. */
+/* The solver's stream (hipStream_t), storage mode and thermal model. */
 void* lbm_stream(const lbm_solver* h);
 int32_t lbm_storage_of(const lbm_solver* h);
+int32_t lbm_model_of(const lbm_solver* h);
 
 /* Launch shape of the step kernel: block_x threads along x (64, 128 or
  * 256), block_y rows of threads (block_x * block_y <= 256) and
@@ -256,7 +278,8 @@ int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int3
  * ------------------------------------------------------------------------ */
 typedef struct lbm_batch lbm_batch;
 
-/* Create an empty batch for `storage` on hip_stream (NULL: own stream). */
+/* Create an empty batch for `storage` on hip_stream (NULL: own stream).
+ * All members share one thermal model (that of the first member). */
 int lbm_batch_create(lbm_batch** out, int32_t storage, void* hip_stream);
 
 /* Add a solver (params set, same storage and stream); *slot receives its

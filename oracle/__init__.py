@@ -10,7 +10,7 @@ The arithmetic of a time step lives in ``orc_lbm.c`` (plain C, dense matrix
 products, push streaming, ``-ffp-contract=off``).  This module adds, in
 plain Python:
 
-* the parameter map of Eq. 40 and the rate diagonals of Eqs. 20 and 29;
+* the parameter map of Eq. 40 and the rate diagonals of Eqs. 20, 29 and 32;
 * the closed-form profiles of Eqs. 34, 36 and 37 and the error norms of
   Eqs. 35 and 38, used to pin the oracle against the paper;
 * a ``Lattice`` wrapper around the C oracle.
@@ -36,6 +36,9 @@ _LIB = os.path.join(_HERE, "liborc_lbm.so")
 LEFT, RIGHT, BOTTOM, TOP = 0, 1, 2, 3
 FLOW_PERIODIC, FLOW_WALL, FLOW_NEE = 0, 1, 2
 TEMP_PERIODIC, TEMP_DIRICHLET, TEMP_ADIABATIC, TEMP_NEE_DIRICHLET, TEMP_NEE_ADIABATIC = 0, 1, 2, 3, 4
+MODEL_D2Q5, MODEL_D2Q9T, MODEL_ISOTHERMAL = 0, 1, 2
+MODELS = {"d2q5": MODEL_D2Q5, "d2q9t": MODEL_D2Q9T, "isothermal": MODEL_ISOTHERMAL}
+MODEL_NG = {MODEL_D2Q5: 5, MODEL_D2Q9T: 9, MODEL_ISOTHERMAL: 0}
 
 CS2 = 1.0 / 3.0  # D2Q9 lattice sound speed squared (Sec. 2.1, after Eq. 19)
 
@@ -51,9 +54,9 @@ def build(force: bool = True) -> str:
 
 class OrcParams(ctypes.Structure):
     _fields_ = [
-        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-        ("s", ctypes.c_double * 9), ("q", ctypes.c_double * 5),
-        ("varpi", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("model", ctypes.c_int32),
+        ("s", ctypes.c_double * 9), ("q", ctypes.c_double * 9),
+        ("varpi", ctypes.c_double), ("theta", ctypes.c_double), ("rho0", ctypes.c_double),
         ("gbeta", ctypes.c_double), ("T0", ctypes.c_double),
         ("ax", ctypes.c_double), ("ay", ctypes.c_double),
         ("bc_flow", ctypes.c_int32 * 4), ("bc_temp", ctypes.c_int32 * 4),
@@ -122,21 +125,29 @@ def tables(library=None) -> dict:
 # ---------------------------------------------------------------------------
 # Parameter map (Eqs. 20, 29, 40; Sec. 3 global settings)
 # ---------------------------------------------------------------------------
-def derive(pb) -> dict:
+def _model(model) -> int:
+    return MODELS[model] if isinstance(model, str) else int(model)
+
+
+def derive(pb, model=MODEL_D2Q5) -> dict:
     """Relaxation diagonals and forcing constants for a problem.
 
     s_nu and zeta_alpha come from Eq. 40 unless given explicitly (> 0):
         1/s_nu = 1/2 + Ma L sqrt(3 Pr) / sqrt(Ra),  Ma = sqrt(3) u_c,
         1/zeta_alpha = 1/2 + c_s^2 (1/s_nu - 1/2) / (c_sT^2 Pr),
-    with c_s^2 = 1/3 and c_sT^2 = varpi/2 (Sec. 2.2).  g*beta follows from
-    u_c = sqrt(g beta dT L) (text after Eq. 40); T0 = (T_h + T_c)/2.
+    with c_s^2 = 1/3 and c_sT^2 = varpi/2 for the D2Q5 model (Sec. 2.2),
+    c_sT^2 = c_s^2 for the D2Q9 thermal model (the diffusivity stated after
+    Eq. 32).  g*beta follows from u_c = sqrt(g beta dT L) (text after
+    Eq. 40), and is 0 without a temperature field; T0 = (T_h + T_c)/2.
     L defaults to the distance between the bottom and top walls: ny for
     link-wise walls (half a spacing outside the nodes), ny - 1 for NEE walls.
+    The thermal diagonal is Eq. 29 (D2Q5, 5 entries) or Eq. 32 (D2Q9, 9).
     """
+    model = _model(model)
     length = pb.length if pb.length > 0 else (float(pb.ny - 1) if pb.bc_flow[BOTTOM] == FLOW_NEE
                                                else float(pb.ny))
     dT = pb.t_hot - pb.t_cold
-    csT2 = pb.varpi / 2.0
+    csT2 = CS2 if model == MODEL_D2Q9T else pb.varpi / 2.0
     if pb.s_nu > 0:
         s_nu = pb.s_nu
     else:
@@ -150,25 +161,38 @@ def derive(pb) -> dict:
         if not pb.pr > 0:
             raise ValueError("zeta_alpha needs either an explicit value or Pr")
         z_a = 1.0 / (0.5 + CS2 * (1.0 / s_nu - 0.5) / (csT2 * pb.pr))
-    gbeta = pb.u_c ** 2 / (dT * length) if (pb.u_c > 0 and dT != 0) else 0.0
+    gbeta = (pb.u_c ** 2 / (dT * length)
+             if (model != MODEL_ISOTHERMAL and pb.u_c > 0 and dT != 0) else 0.0)
     s = [1.0, 1.0, 1.0, pb.s_e, s_nu, s_nu, pb.s_q, pb.s_q, pb.s_eps]       # Eq. 20
-    q = [1.0, z_a, z_a, pb.zeta_e, pb.zeta_nu]                              # Eq. 29
-    return {"s": s, "q": q, "s_nu": s_nu, "zeta_alpha": z_a, "gbeta": gbeta,
+    if model == MODEL_D2Q9T:                                                # Eq. 32
+        q = [1.0, z_a, z_a, pb.zeta_e, pb.zeta_nu, pb.zeta_nu, pb.zeta_q, pb.zeta_q, pb.zeta_eps]
+    else:                                                                   # Eq. 29
+        q = [1.0, z_a, z_a, pb.zeta_e, pb.zeta_nu]
+    return {"model": model, "s": s, "q": q, "s_nu": s_nu, "zeta_alpha": z_a, "gbeta": gbeta,
             "T0": 0.5 * (pb.t_hot + pb.t_cold), "length": length, "dT": dT,
             "nu": CS2 * (1.0 / s_nu - 0.5), "alpha": csT2 * (1.0 / z_a - 0.5)}
 
 
-def make_params(pb, s8_literal: bool = False, overrides: dict | None = None) -> OrcParams:
-    d = derive(pb)
+def rate_for_reynolds(re: float, length: float, u: float) -> float:
+    """s_nu for a Reynolds number Re = L u / nu (Sec. 3.2):
+    1/s_nu = 1/2 + L u / (c_s^2 Re)."""
+    return 1.0 / (0.5 + length * u / (CS2 * re))
+
+
+def make_params(pb, s8_literal: bool = False, overrides: dict | None = None,
+                model=MODEL_D2Q5) -> OrcParams:
+    d = derive(pb, model)
     if overrides:
         d.update(overrides)
     p = OrcParams()
     p.nx, p.ny = int(pb.nx), int(pb.ny)
+    p.model = d["model"]
     for k in range(9):
         p.s[k] = d["s"][k]
-    for k in range(5):
+    for k in range(len(d["q"])):
         p.q[k] = d["q"][k]
     p.varpi = pb.varpi
+    p.theta = getattr(pb, "theta", 1.0)
     p.rho0 = 1.0
     p.gbeta = d["gbeta"]
     p.T0 = d["T0"]
@@ -185,22 +209,26 @@ def make_params(pb, s8_literal: bool = False, overrides: dict | None = None) -> 
 
 def collide_node(params: OrcParams, f, g, library=None):
     """One-node collision (Eqs. 8 and 24 followed by M^-1 and N^-1)."""
+    ng = MODEL_NG[params.model]
     f = np.ascontiguousarray(f, dtype=np.float64)
-    g = np.ascontiguousarray(g, dtype=np.float64)
-    fo = np.zeros(9); go = np.zeros(5)
+    g = np.ascontiguousarray(g if ng else np.zeros(1), dtype=np.float64)
+    fo = np.zeros(9); go = np.zeros(max(ng, 1))
     (library or lib()).orc_collide_node(ctypes.byref(params), _dp(f), _dp(g), _dp(fo), _dp(go))
-    return fo, go
+    return fo, go[:ng]
 
 
 class Lattice:
     """An nx x ny lattice advanced by the C oracle.  State = pre-collision
     populations at time t, exchanged in plane order [i][y][x]."""
 
-    def __init__(self, pb, s8_literal: bool = False, T_init=None, overrides=None, library=None):
+    def __init__(self, pb, s8_literal: bool = False, T_init=None, overrides=None, library=None,
+                 model=MODEL_D2Q5):
         self._lib = library or lib()
         self.pb = pb
-        self.params = make_params(pb, s8_literal, overrides)
-        self.derived = derive(pb)
+        self.model = _model(model)
+        self.ng = MODEL_NG[self.model]
+        self.params = make_params(pb, s8_literal, overrides, self.model)
+        self.derived = derive(pb, self.model)
         if overrides:
             self.derived.update(overrides)
         self._h = self._lib.orc_create(ctypes.byref(self.params))
@@ -229,20 +257,26 @@ class Lattice:
     def step(self, n: int = 1):
         self._lib.orc_step(self._h, int(n))
 
+    def _gbuf(self):
+        return np.zeros((max(self.ng, 1), self.ny, self.nx))
+
     def get_state(self):
-        f = np.zeros((9, self.ny, self.nx)); g = np.zeros((5, self.ny, self.nx))
+        f = np.zeros((9, self.ny, self.nx)); g = self._gbuf()
         self._lib.orc_get_state(self._h, _dp(f), _dp(g))
-        return f, g
+        return f, g[:self.ng]
 
     def set_state(self, f, g):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, self.ny, self.nx)
-        g = np.ascontiguousarray(g, dtype=np.float64).reshape(5, self.ny, self.nx)
+        if self.ng:
+            g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.ng, self.ny, self.nx)
+        else:
+            g = self._gbuf()
         self._lib.orc_set_state(self._h, _dp(f), _dp(g))
 
     def post_collision(self):
-        f = np.zeros((9, self.ny, self.nx)); g = np.zeros((5, self.ny, self.nx))
+        f = np.zeros((9, self.ny, self.nx)); g = self._gbuf()
         self._lib.orc_post_collision(self._h, _dp(f), _dp(g))
-        return f, g
+        return f, g[:self.ng]
 
     def moments(self):
         shp = (self.ny, self.nx)

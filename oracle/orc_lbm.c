@@ -2,8 +2,12 @@
  * orc_lbm.c -- plain, slow, FP64 CPU oracle for the double-distribution
  * non-orthogonal MRT lattice Boltzmann method of Liu, He, Li & Li
  * (arXiv:1510.08224): a D2Q9 MRT equation for the incompressible flow
- * (Sec. 2.1) and a D2Q5 MRT equation for the temperature (Sec. 2.2),
- * coupled by the Boussinesq force (Eq. 4).
+ * (Sec. 2.1) and an MRT equation for the temperature (Sec. 2.2), coupled
+ * by the Boussinesq force (Eq. 4).  The temperature lattice is one of
+ *   MODEL_D2Q5      the D2Q5 model (Eqs. 23-30), the paper's main one;
+ *   MODEL_D2Q9T     the D2Q9 thermal model (Eqs. 31-32);
+ *   MODEL_ISOTHERMAL no temperature field: the flow alone, driven by the
+ *                   acceleration a and the walls (Secs. 3.1, 3.2).
  *
  * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the tests, the smoke check
  * and the CPU-baseline leg of the benchmark load this library.  It shares
@@ -14,6 +18,8 @@
  *   - the collision multiplies by the full dense matrices M (Eq. 13),
  *     M^-1 (App. A, Eq. A1), N (Eq. 26) and N^-1 (Eq. A2) exactly as
  *     printed in the paper;
+ *   - the D2Q9 thermal equilibrium moments are the dense product M g^eq
+ *     with g^eq of Eq. 31 (the definition n^eq = N g^eq);
  *   - the relaxation is the diagonal expression of Eq. 8 / Eq. 24;
  *   - streaming is a push (Eqs. 9 and 25) into a second array;
  *   - compiled with -O2 -ffp-contract=off (no fused multiply-add).
@@ -40,6 +46,11 @@
  *      the diagonal inward neighbour, the velocity of its top/bottom wall,
  *      and a Dirichlet temperature if either of its walls has one (the
  *      top/bottom wall's first).
+ *   R6 (Eqs. 31-32): the D2Q9 thermal model's N is the non-orthogonal
+ *      D2Q9 matrix M of Eq. 13 (built from the same basis, Eq. 12), its
+ *      relaxation diagonal is Eq. 32 and c_s^2 = 1/3; its Dirichlet
+ *      anti-bounce-back adds twice the even part of Eq. 31 at the wall,
+ *      2 w_i T_w [1 + theta (4.5 (e_i.u_w)^2 - 1.5 |u_w|^2)].
  *   R4 (Sec. 3 uses non-equilibrium extrapolation, not given in the
  *      text): the default walls are link-wise.  Flow: halfway bounce-back with the
  *      moving-wall term 6 w_i rho0 (e_i . u_w).  Temperature, Dirichlet:
@@ -56,7 +67,6 @@
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 static const int OPP9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-static const int OPP5[5] = {0, 3, 4, 1, 2};
 static const double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                              1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
@@ -98,6 +108,7 @@ static const double NI5[5][5] = {
     {0, -0.5, 0, 0.25, 0.25},
     {0, 0, -0.5, 0.25, -0.25}};
 
+enum { MODEL_D2Q5 = 0, MODEL_D2Q9T = 1, MODEL_ISOTHERMAL = 2 };
 enum { SIDE_LEFT = 0, SIDE_RIGHT = 1, SIDE_BOTTOM = 2, SIDE_TOP = 3 };
 enum { FLOW_PERIODIC = 0, FLOW_WALL = 1, FLOW_NEE = 2 };
 enum { TEMP_PERIODIC = 0, TEMP_DIRICHLET = 1, TEMP_ADIABATIC = 2, TEMP_NEE_DIRICHLET = 3,
@@ -105,9 +116,11 @@ enum { TEMP_PERIODIC = 0, TEMP_DIRICHLET = 1, TEMP_ADIABATIC = 2, TEMP_NEE_DIRIC
 
 typedef struct {
     int32_t nx, ny;
+    int32_t model;     /* MODEL_* */
     double s[9];       /* Lambda = diag(s_0..s_8), Eq. 20 */
-    double q[5];       /* Q = diag(zeta_0..zeta_4), Eq. 29 */
-    double varpi;      /* Eq. 28 */
+    double q[9];       /* Q = diag(zeta_0..), Eq. 29 (5 used) or Eq. 32 (9) */
+    double varpi;      /* Eq. 28 (D2Q5) */
+    double theta;      /* Eq. 31 (D2Q9 thermal), 0 or 1 */
     double rho0;       /* reference density */
     double gbeta;      /* g*beta of Eq. 4 */
     double T0;         /* reference temperature of Eq. 4 */
@@ -121,6 +134,7 @@ typedef struct {
 
 typedef struct {
     orc_params p;
+    int ng;              /* temperature populations per node: 5, 9 or 0 */
     double *f, *g;       /* pre-collision state at time t, AoS */
     double *fn, *gn;     /* streaming target */
     double *fp, *gp;     /* post-collision state (scratch) */
@@ -130,12 +144,28 @@ typedef struct {
 /* ------------------------------------------------------------------------- */
 /* Single-node collision: Eqs. 4, 8, 15-20 for f; Eqs. 24, 27-29 for g.      */
 /* ------------------------------------------------------------------------- */
-static void macroscopic(const orc_params* p, const double f[9], const double g[5],
+static int model_ng(const orc_params* p) {
+    return p->model == MODEL_D2Q5 ? 5 : (p->model == MODEL_D2Q9T ? 9 : 0);
+}
+
+/* g_i^eq: Eq. 30 (D2Q5) or Eq. 31 (D2Q9 thermal, c_s^2 = 1/3). */
+static double geq_i(const orc_params* p, int i, double T, double ux, double uy) {
+    double eu = EX[i] * ux + EY[i] * uy;
+    if (p->model == MODEL_D2Q9T) {
+        double usq = ux * ux + uy * uy;
+        return W9[i] * T * (1.0 + 3.0 * eu + p->theta * (4.5 * eu * eu - 1.5 * usq));
+    }
+    if (i == 0) return (1.0 - p->varpi) * T;
+    return 0.25 * p->varpi * T + 0.5 * eu * T;
+}
+
+static void macroscopic(const orc_params* p, const double f[9], const double* g,
                         double* rho, double* ux, double* uy, double* T,
                         double* Fx, double* Fy) {
-    /* Eq. 27: T = n_0 = sum g */
-    double t = 0.0;
-    for (int i = 0; i < 5; ++i) t += g[i];
+    /* Eq. 27: T = n_0 = sum g (no temperature field: T = T0, no buoyancy) */
+    const int ng = model_ng(p);
+    double t = ng ? 0.0 : p->T0;
+    for (int i = 0; i < ng; ++i) t += g[i];
     /* Eq. 4: F = g beta (T - T0) j + a */
     double fx = p->ax;
     double fy = p->ay + p->gbeta * (t - p->T0);
@@ -158,8 +188,8 @@ static void macroscopic(const orc_params* p, const double f[9], const double g[5
     *Fy = fy;
 }
 
-void orc_collide_node(const orc_params* p, const double f[9], const double g[5],
-                      double fo[9], double go[5]) {
+void orc_collide_node(const orc_params* p, const double f[9], const double* g,
+                      double fo[9], double* go) {
     double rho, ux, uy, T, Fx, Fy;
     macroscopic(p, f, g, &rho, &ux, &uy, &T, &Fx, &Fy);
     const double r0 = p->rho0;
@@ -206,6 +236,28 @@ void orc_collide_node(const orc_params* p, const double f[9], const double g[5],
         fo[i] = acc;
     }
 
+    if (p->model == MODEL_ISOTHERMAL) return;
+    if (p->model == MODEL_D2Q9T) {
+        /* n = M g, n^eq = M g^eq (Eq. 31, reading R6), Q of Eq. 32 */
+        double n9[9], ne9[9], geq[9], ns9[9];
+        for (int i = 0; i < 9; ++i) geq[i] = geq_i(p, i, T, ux, uy);
+        for (int k = 0; k < 9; ++k) {
+            double acc = 0.0, acce = 0.0;
+            for (int i = 0; i < 9; ++i) {
+                acc += M9[k][i] * g[i];
+                acce += M9[k][i] * geq[i];
+            }
+            n9[k] = acc;
+            ne9[k] = acce;
+        }
+        for (int k = 0; k < 9; ++k) ns9[k] = n9[k] - p->q[k] * (n9[k] - ne9[k]);
+        for (int i = 0; i < 9; ++i) {
+            double acc = 0.0;
+            for (int k = 0; k < 9; ++k) acc += MI9[i][k] * ns9[k];
+            go[i] = acc;
+        }
+        return;
+    }
     /* n = N g (dense, Eq. 26) */
     double n[5];
     for (int k = 0; k < 5; ++k) {
@@ -260,6 +312,8 @@ int orc_check_params(const orc_params* p) {
     if (nee && ((p->bc_flow[SIDE_LEFT] == FLOW_NEE && p->nx < 3) ||
                 (p->bc_flow[SIDE_BOTTOM] == FLOW_NEE && p->ny < 3))) return -7;
     if (!(p->rho0 > 0.0)) return -4;
+    if (p->model < MODEL_D2Q5 || p->model > MODEL_ISOTHERMAL) return -8;
+    if (p->model == MODEL_D2Q9T && !(p->theta == 0.0 || p->theta == 1.0)) return -9;
     return 0;
 }
 
@@ -270,13 +324,15 @@ orc_lattice* orc_create(const orc_params* p) {
     orc_lattice* L = (orc_lattice*)calloc(1, sizeof(orc_lattice));
     if (!L) return NULL;
     L->p = *p;
+    L->ng = model_ng(p);
     size_t n = (size_t)p->nx * (size_t)p->ny;
+    size_t ng = L->ng ? (size_t)L->ng : 1;
     L->f = (double*)calloc(n * 9, sizeof(double));
     L->fn = (double*)calloc(n * 9, sizeof(double));
     L->fp = (double*)calloc(n * 9, sizeof(double));
-    L->g = (double*)calloc(n * 5, sizeof(double));
-    L->gn = (double*)calloc(n * 5, sizeof(double));
-    L->gp = (double*)calloc(n * 5, sizeof(double));
+    L->g = (double*)calloc(n * ng, sizeof(double));
+    L->gn = (double*)calloc(n * ng, sizeof(double));
+    L->gp = (double*)calloc(n * ng, sizeof(double));
     if (!L->f || !L->fn || !L->fp || !L->g || !L->gn || !L->gp) {
         free(L->f); free(L->fn); free(L->fp); free(L->g); free(L->gn); free(L->gp);
         free(L);
@@ -292,15 +348,15 @@ void orc_destroy(orc_lattice* L) {
 }
 
 /* Rest state: fbar_i = f_i^eq(rho0, u=0) (Eq. 22) and g_i = g_i^eq(T, u=0)
- * (Eq. 30).  T is nx*ny values in [y][x] order, or NULL for T = T0. */
+ * (Eq. 30 or 31).  T is nx*ny values in [y][x] order, or NULL for T = T0. */
 void orc_init_equilibrium(orc_lattice* L, const double* T) {
     const orc_params* p = &L->p;
+    const int ng = L->ng;
     size_t n = (size_t)p->nx * (size_t)p->ny;
     for (size_t c = 0; c < n; ++c) {
         double t = T ? T[c] : p->T0;
         for (int i = 0; i < 9; ++i) L->f[c * 9 + i] = W9[i] * p->rho0;
-        L->g[c * 5 + 0] = (1.0 - p->varpi) * t;
-        for (int i = 1; i < 5; ++i) L->g[c * 5 + i] = 0.25 * p->varpi * t;
+        for (int i = 0; i < ng; ++i) L->g[c * ng + i] = geq_i(p, i, t, 0.0, 0.0);
     }
     apply_nee_to(L, L->f, L->g);   /* NEE wall nodes are always extrapolated */
     L->t = 0;
@@ -309,33 +365,30 @@ void orc_init_equilibrium(orc_lattice* L, const double* T) {
 /* State exchange in plane order [i][y][x] (pre-collision at time t). */
 void orc_set_state(orc_lattice* L, const double* f, const double* g) {
     size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    const int ng = L->ng;
     for (size_t c = 0; c < n; ++c) {
         for (int i = 0; i < 9; ++i) L->f[c * 9 + i] = f[(size_t)i * n + c];
-        for (int i = 0; i < 5; ++i) L->g[c * 5 + i] = g[(size_t)i * n + c];
+        for (int i = 0; i < ng; ++i) L->g[c * ng + i] = g[(size_t)i * n + c];
     }
     apply_nee_to(L, L->f, L->g);
 }
 
 void orc_get_state(const orc_lattice* L, double* f, double* g) {
     size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    const int ng = L->ng;
     for (size_t c = 0; c < n; ++c) {
         for (int i = 0; i < 9; ++i) f[(size_t)i * n + c] = L->f[c * 9 + i];
-        for (int i = 0; i < 5; ++i) g[(size_t)i * n + c] = L->g[c * 5 + i];
+        for (int i = 0; i < ng; ++i) g[(size_t)i * n + c] = L->g[c * ng + i];
     }
 }
 
 int64_t orc_time(const orc_lattice* L) { return L->t; }
 
-/* f_i^eq of Eq. 22 under reading R1 and g_i^eq of Eq. 30. */
+/* f_i^eq of Eq. 22 under reading R1. */
 static double feq_i(const orc_params* p, int i, double rho, double ux, double uy) {
     double eu = EX[i] * ux + EY[i] * uy;
     double usq = ux * ux + uy * uy;
     return W9[i] * (rho + p->rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
-}
-
-static double geq_i(const orc_params* p, int i, double T, double ux, double uy) {
-    if (i == 0) return (1.0 - p->varpi) * T;
-    return 0.25 * p->varpi * T + 0.5 * (EX[i] * ux + EY[i] * uy) * T;
 }
 
 static int is_nee(const orc_params* p, int side) { return p->bc_flow[side] == FLOW_NEE; }
@@ -343,7 +396,7 @@ static int is_nee(const orc_params* p, int side) { return p->bc_flow[side] == FL
 /* Non-equilibrium extrapolation (reading R5) on a pre-collision state. */
 static void apply_nee_to(orc_lattice* L, double* F, double* G) {
     const orc_params* p = &L->p;
-    const int nx = p->nx, ny = p->ny;
+    const int nx = p->nx, ny = p->ny, ng = L->ng;
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             int onL = is_nee(p, SIDE_LEFT) && x == 0, onR = is_nee(p, SIDE_RIGHT) && x == nx - 1;
@@ -358,16 +411,16 @@ static void apply_nee_to(orc_lattice* L, double* F, double* G) {
             if (sy >= 0 && p->bc_temp[sy] == TEMP_NEE_DIRICHLET) tside = sy;
             else if (sx >= 0 && p->bc_temp[sx] == TEMP_NEE_DIRICHLET) tside = sx;
             const double* ff = F + ((size_t)fy * nx + fx) * 9;
-            const double* gf = G + ((size_t)fy * nx + fx) * 5;
+            const double* gf = G + ((size_t)fy * nx + fx) * ng;
             double rho, ux, uy, T, Fx, Fy;
             macroscopic(p, ff, gf, &rho, &ux, &uy, &T, &Fx, &Fy);
             double uwx = p->wall_u[vside][0], uwy = p->wall_u[vside][1];
             double Tb = tside >= 0 ? p->wall_T[tside] : T;
             double* fb = F + ((size_t)y * nx + x) * 9;
-            double* gb = G + ((size_t)y * nx + x) * 5;
+            double* gb = G + ((size_t)y * nx + x) * ng;
             for (int i = 0; i < 9; ++i)
                 fb[i] = feq_i(p, i, rho, uwx, uwy) + (ff[i] - feq_i(p, i, rho, ux, uy));
-            for (int i = 0; i < 5; ++i)
+            for (int i = 0; i < ng; ++i)
                 gb[i] = geq_i(p, i, Tb, uwx, uwy) + (gf[i] - geq_i(p, i, T, ux, uy));
         }
     }
@@ -378,7 +431,7 @@ static void apply_nee_to(orc_lattice* L, double* F, double* G) {
  * exactly once: either by the neighbour upstream or by the wall rule. */
 static void stream_push(orc_lattice* L) {
     const orc_params* p = &L->p;
-    const int nx = p->nx, ny = p->ny;
+    const int nx = p->nx, ny = p->ny, ng = L->ng;
     const int px = axis_periodic_x(p), py = axis_periodic_y(p);
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
@@ -399,22 +452,34 @@ static void stream_push(orc_lattice* L) {
                     L->fn[c * 9 + OPP9[i]] = L->fp[c * 9 + i] - 6.0 * W9[i] * p->rho0 * eu;
                 }
             }
-            for (int i = 0; i < 5; ++i) {
+            for (int i = 0; i < ng; ++i) {
                 int tx = x + EX[i], ty = y + EY[i];
                 int outx = (tx < 0 || tx >= nx), outy = (ty < 0 || ty >= ny);
                 if (outx && px) tx = (tx + nx) % nx;
                 if (outy && py) ty = (ty + ny) % ny;
                 int wallx = outx && !px, wally = outy && !py;
                 if (!wallx && !wally) {
-                    L->gn[((size_t)ty * nx + tx) * 5 + i] = L->gp[c * 5 + i];
+                    L->gn[((size_t)ty * nx + tx) * ng + i] = L->gp[c * ng + i];
                 } else {
                     int side = wally ? (ty < 0 ? SIDE_BOTTOM : SIDE_TOP)
                                      : (tx < 0 ? SIDE_LEFT : SIDE_RIGHT);
                     if (p->bc_flow[side] == FLOW_NEE) continue;   /* rebuilt by apply_nee */
+                    /* anti-bounce-back adds twice the even part of g^eq at
+                     * the wall: varpi T_w / 4 per link (Eq. 30) or
+                     * w_i T_w [1 + theta (4.5 (e.u_w)^2 - 1.5 u_w^2)] (Eq. 31) */
+                    double even;
+                    if (p->model == MODEL_D2Q9T) {
+                        double eu = EX[i] * p->wall_u[side][0] + EY[i] * p->wall_u[side][1];
+                        double usq = p->wall_u[side][0] * p->wall_u[side][0] +
+                                     p->wall_u[side][1] * p->wall_u[side][1];
+                        even = W9[i] * p->wall_T[side] * (1.0 + p->theta * (4.5 * eu * eu - 1.5 * usq));
+                    } else {
+                        even = 0.25 * p->varpi * p->wall_T[side];
+                    }
                     if (p->bc_temp[side] == TEMP_DIRICHLET)
-                        L->gn[c * 5 + OPP5[i]] = -L->gp[c * 5 + i] + 0.5 * p->varpi * p->wall_T[side];
+                        L->gn[c * ng + OPP9[i]] = -L->gp[c * ng + i] + 2.0 * even;
                     else
-                        L->gn[c * 5 + OPP5[i]] = L->gp[c * 5 + i];
+                        L->gn[c * ng + OPP9[i]] = L->gp[c * ng + i];
                 }
             }
         }
@@ -423,8 +488,9 @@ static void stream_push(orc_lattice* L) {
 
 static void collide_all(orc_lattice* L) {
     size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    const int ng = L->ng;
     for (size_t c = 0; c < n; ++c)
-        orc_collide_node(&L->p, L->f + c * 9, L->g + c * 5, L->fp + c * 9, L->gp + c * 5);
+        orc_collide_node(&L->p, L->f + c * 9, L->g + c * ng, L->fp + c * 9, L->gp + c * ng);
 }
 
 /* Advance n time steps: collide every node, then push-stream. */
@@ -445,9 +511,10 @@ void orc_step(orc_lattice* L, int64_t nsteps) {
 void orc_post_collision(orc_lattice* L, double* f, double* g) {
     collide_all(L);
     size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
+    const int ng = L->ng;
     for (size_t c = 0; c < n; ++c) {
         for (int i = 0; i < 9; ++i) f[(size_t)i * n + c] = L->fp[c * 9 + i];
-        for (int i = 0; i < 5; ++i) g[(size_t)i * n + c] = L->gp[c * 5 + i];
+        for (int i = 0; i < ng; ++i) g[(size_t)i * n + c] = L->gp[c * ng + i];
     }
 }
 
@@ -456,7 +523,7 @@ void orc_moments(const orc_lattice* L, double* rho, double* ux, double* uy, doub
     size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
     for (size_t c = 0; c < n; ++c) {
         double r, u, v, t, fx, fy;
-        macroscopic(&L->p, L->f + c * 9, L->g + c * 5, &r, &u, &v, &t, &fx, &fy);
+        macroscopic(&L->p, L->f + c * 9, L->g + c * L->ng, &r, &u, &v, &t, &fx, &fy);
         if (rho) rho[c] = r;
         if (ux) ux[c] = u;
         if (uy) uy[c] = v;
@@ -476,9 +543,9 @@ void orc_moments(const orc_lattice* L, double* rho, double* ux, double* uy, doub
  * nu_local gets one value per wall node (ny for left/right, nx for
  * bottom/top) and may be NULL.  Returns 0, or -1 for a bad side. */
 static double node_T(const orc_lattice* L, int x, int y) {
-    const double* g = L->g + ((size_t)y * L->p.nx + x) * 5;
+    const double* g = L->g + ((size_t)y * L->p.nx + x) * L->ng;
     double t = 0.0;
-    for (int i = 0; i < 5; ++i) t += g[i];
+    for (int i = 0; i < L->ng; ++i) t += g[i];
     return t;
 }
 
@@ -486,7 +553,7 @@ int orc_nusselt(const orc_lattice* L, int side, double length, double dT,
                 double* nu_local, double* nu_mean, double* nu_max, int32_t* i_max) {
     const orc_params* p = &L->p;
     const int nx = p->nx, ny = p->ny;
-    if (side < 0 || side > 3) return -1;
+    if (side < 0 || side > 3 || L->ng == 0) return -1;
     const int nee = p->bc_temp[side] == TEMP_NEE_DIRICHLET;
     if (p->bc_temp[side] != TEMP_DIRICHLET && !nee) return -1;
     int vertical = (side == SIDE_LEFT || side == SIDE_RIGHT);

@@ -16,6 +16,7 @@ using namespace lbm;
 
 struct lbm_solver {
     int nx = 0, ny = 0, storage = 0;
+    int model = LBM_MODEL_D2Q5, ng = 5;  // thermal model and its population count
     Geom G{};
     Coeffs C{};
     Launch L{};
@@ -49,6 +50,7 @@ struct lbm_solver {
 
 struct lbm_batch {
     int storage = 0;
+    int ng = -1;                      // thermal populations of the members (set by the first)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::vector<lbm_solver*> slots;   // nullptr = free slot
@@ -93,14 +95,19 @@ static int hip_fail(lbm_solver* h, hipError_t e, const char* what) {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Row pitch: whole 256-byte segments; planes start on 4 KiB boundaries.
-static void layout(int nx, int ny, int storage, int* pitch, long long* plane, size_t* buf_bytes) {
+// Temperature populations per node of a thermal model.
+static int model_ng(int model) { return model == LBM_MODEL_D2Q5 ? 5 : (model == LBM_MODEL_D2Q9T ? 9 : 0); }
+static bool model_ok(int model) { return model >= LBM_MODEL_D2Q5 && model <= LBM_MODEL_ISOTHERMAL; }
+
+// Row pitch: whole 256-byte segments; planes start on 4 KiB boundaries;
+// 9 + NG planes per buffer.
+static void layout(int nx, int ny, int storage, int ng, int* pitch, long long* plane, size_t* buf_bytes) {
     const size_t b = storage_bytes(storage);
     const size_t p = align_up((size_t)nx, 256 / b);
     const size_t pl = align_up(p * (size_t)ny, 4096 / b);
     *pitch = (int)p;
     *plane = (long long)pl;
-    *buf_bytes = 14 * pl * b;
+    *buf_bytes = (size_t)(9 + ng) * pl * b;
 }
 
 extern "C" {
@@ -117,7 +124,10 @@ void lbm_params_default(lbm_params* p) {
     p->s_eps = 1.8;
     p->zeta_e = 1.9;
     p->zeta_nu = 1.9;
+    p->zeta_q = 1.9;
+    p->zeta_eps = 1.9;
     p->varpi = 0.5;
+    p->theta = 1.0;
     for (int s = 0; s < 4; ++s) p->bc_flow[s] = LBM_BC_WALL;
     p->bc_temp[LBM_LEFT] = LBM_T_DIRICHLET;
     p->bc_temp[LBM_RIGHT] = LBM_T_DIRICHLET;
@@ -133,13 +143,13 @@ const char* lbm_build_info(void) {
     return "lbm non-orthogonal MRT D2Q9+D2Q5, HIP gfx950, storage f64/f32/f16";
 }
 
-int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, uint64_t* bytes) {
-    if (!bytes || nx < 1 || ny < 1 || storage < LBM_F64 || storage > LBM_F16)
-        return fail(nullptr, LBM_ERR_ARG, "lbm_required_bytes: bad size, storage or NULL output");
+int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, uint64_t* bytes) {
+    if (!bytes || nx < 1 || ny < 1 || storage < LBM_F64 || storage > LBM_F16 || !model_ok(model))
+        return fail(nullptr, LBM_ERR_ARG, "lbm_required_bytes: bad size, storage, model or NULL output");
     int pitch;
     long long plane;
     size_t bb;
-    layout(nx, ny, storage, &pitch, &plane, &bb);
+    layout(nx, ny, storage, model_ng(model), &pitch, &plane, &bb);
     *bytes = 2 * (uint64_t)bb;
     return LBM_OK;
 }
@@ -165,8 +175,8 @@ static void drop_graphs(lbm_solver* h) {
     }
 }
 
-static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* dev_buf,
-                         uint64_t bytes, void* stream) {
+static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, int32_t model,
+                         void* dev_buf, uint64_t bytes, void* stream) {
     if (!out) return fail(nullptr, LBM_ERR_ARG, "lbm_create: NULL output handle");
     *out = nullptr;
     if (nx < 1 || ny < 1) return fail(nullptr, LBM_ERR_ARG, "lbm_create: nx and ny must be >= 1");
@@ -174,12 +184,15 @@ static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t stora
         return fail(nullptr, LBM_ERR_ARG, "lbm_create: more than 2^31 nodes");
     if (storage < LBM_F64 || storage > LBM_F16)
         return fail(nullptr, LBM_ERR_ARG, "lbm_create: storage must be LBM_F64, LBM_F32 or LBM_F16");
+    if (!model_ok(model)) return fail(nullptr, LBM_ERR_ARG, "lbm_create: unknown thermal model");
     lbm_solver* h = new (std::nothrow) lbm_solver();
     if (!h) return fail(nullptr, LBM_ERR_NOMEM, "lbm_create: host allocation failed");
     h->nx = nx;
     h->ny = ny;
     h->storage = storage;
-    layout(nx, ny, storage, &h->G.pitch, &h->G.plane, &h->buf_bytes);
+    h->model = model;
+    h->ng = model_ng(model);
+    layout(nx, ny, storage, h->ng, &h->G.pitch, &h->G.plane, &h->buf_bytes);
     h->G.nx = nx;
     h->G.ny = ny;
     // Kernels address a plane with 32-bit byte offsets.
@@ -231,15 +244,17 @@ static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t stora
     return LBM_OK;
 }
 
-int lbm_create(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* hip_stream) {
-    return create_common(out, nx, ny, storage, nullptr, 0, hip_stream);
+int lbm_create(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, int32_t model, void* hip_stream) {
+    return create_common(out, nx, ny, storage, model, nullptr, 0, hip_stream);
 }
 
-int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, void* device_buffer,
-                   uint64_t bytes, void* hip_stream) {
+int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, int32_t model,
+                   void* device_buffer, uint64_t bytes, void* hip_stream) {
     if (!device_buffer) return fail(nullptr, LBM_ERR_ARG, "lbm_create_ext: NULL device buffer");
-    return create_common(out, nx, ny, storage, device_buffer, bytes, hip_stream);
+    return create_common(out, nx, ny, storage, model, device_buffer, bytes, hip_stream);
 }
+
+int32_t lbm_model_of(const lbm_solver* h) { return h ? h->model : -1; }
 
 void lbm_destroy(lbm_solver* h) {
     if (!h) return;
@@ -308,10 +323,14 @@ static int derive(lbm_solver* h, const lbm_params* p) {
         if (!isfinite(p->wall_T[s]) || !isfinite(p->wall_u[s][0]) || !isfinite(p->wall_u[s][1]))
             return fail(h, LBM_ERR_ARG, "lbm_set_params: non-finite wall value");
     // default L: the distance between the bottom and top walls
+    const bool q9 = h->ng == 9, iso = h->ng == 0;
+    if (q9 && !(p->theta == 0.0 || p->theta == 1.0))
+        return fail(h, LBM_ERR_ARG, "lbm_set_params: theta must be 0 or 1 (Eq. 31)");
     const double length = p->length > 0 ? p->length
                                         : (p->bc_flow[LBM_BOTTOM] == LBM_BC_NEE ? (double)(h->ny - 1) : (double)h->ny);
     const double dT = p->t_hot - p->t_cold;
-    const double cs2 = 1.0 / 3.0, csT2 = p->varpi / 2.0;
+    // c_sT^2 = varpi / 2 for D2Q5 (Sec. 2.2); c_s^2 = 1/3 for D2Q9 (after Eq. 32)
+    const double cs2 = 1.0 / 3.0, csT2 = q9 ? cs2 : p->varpi / 2.0;
     double s_nu = p->s_nu, z_a = p->zeta_alpha;
     if (!(s_nu > 0)) {
         if (!(p->u_c > 0 && p->ra > 0 && p->pr > 0))
@@ -323,10 +342,11 @@ static int derive(lbm_solver* h, const lbm_params* p) {
         if (!(p->pr > 0)) return fail(h, LBM_ERR_ARG, "lbm_set_params: zeta_alpha needs pr > 0 (Eq. 40) or an explicit value");
         z_a = 1.0 / (0.5 + cs2 * (1.0 / s_nu - 0.5) / (csT2 * p->pr));
     }
-    const double rates[7] = {p->s_e, s_nu, p->s_q, p->s_eps, z_a, p->zeta_e, p->zeta_nu};
+    const double rates[9] = {p->s_e, s_nu, p->s_q, p->s_eps, z_a, p->zeta_e, p->zeta_nu,
+                             q9 ? p->zeta_q : 1.0, q9 ? p->zeta_eps : 1.0};
     for (double r : rates)
         if (!rate_ok(r)) return fail(h, LBM_ERR_ARG, "lbm_set_params: every relaxation rate must lie in (0, 2)");
-    const double gbeta = (p->u_c > 0 && dT != 0) ? p->u_c * p->u_c / (dT * length) : 0.0;
+    const double gbeta = (!iso && p->u_c > 0 && dT != 0) ? p->u_c * p->u_c / (dT * length) : 0.0;
     const double T0 = 0.5 * (p->t_hot + p->t_cold);
     const bool dev = h->storage != LBM_F64;
 
@@ -338,6 +358,10 @@ static int derive(lbm_solver* h, const lbm_params* p) {
     C.z1 = z_a;
     C.z3 = p->zeta_e;
     C.z4 = p->zeta_nu;
+    C.z6 = q9 ? p->zeta_q : 1.0;
+    C.z8 = q9 ? p->zeta_eps : 1.0;
+    C.theta = q9 ? p->theta : 0.0;
+    C.T0 = T0;
     C.varpi = p->varpi;
     C.gbeta = gbeta;
     C.ax = p->ax;
@@ -349,12 +373,24 @@ static int derive(lbm_solver* h, const lbm_params* p) {
             const double eu = ex(i) * p->wall_u[s][0] + ey(i) * p->wall_u[s][1];
             C.bbf[s][i] = p->bc_flow[s] == LBM_BC_WALL ? 6.0 * kW9[i] * eu : 0.0;
         }
-        if (p->bc_temp[s] == LBM_T_DIRICHLET) {
-            C.gsign[s] = -1.0;
-            C.gconst[s] = dev ? 0.5 * p->varpi * (p->wall_T[s] - T0) : 0.5 * p->varpi * p->wall_T[s];
-        } else {
-            C.gsign[s] = 1.0;
-            C.gconst[s] = 0.0;
+        // anti-bounce-back: twice the even part of g^eq at the wall (Eq. 30:
+        // varpi T_w / 4 per link; Eq. 31: w_i T_w [1 + theta (4.5 (e.u_w)^2 - 1.5 u_w^2)]),
+        // minus twice the stored rest part for deviation storage
+        const bool dir = p->bc_temp[s] == LBM_T_DIRICHLET;
+        C.gsign[s] = dir ? -1.0 : 1.0;
+        for (int i = 0; i < 9; ++i) {
+            double c = 0.0;
+            if (dir && i > 0) {
+                const double Tw = p->wall_T[s];
+                if (q9) {
+                    const double eu = ex(i) * p->wall_u[s][0] + ey(i) * p->wall_u[s][1];
+                    const double usq = p->wall_u[s][0] * p->wall_u[s][0] + p->wall_u[s][1] * p->wall_u[s][1];
+                    c = 2.0 * kW9[i] * Tw * (1.0 + p->theta * (4.5 * eu * eu - 1.5 * usq)) - (dev ? 2.0 * kW9[i] * T0 : 0.0);
+                } else if (i <= 4) {
+                    c = dev ? 0.5 * p->varpi * (Tw - T0) : 0.5 * p->varpi * Tw;
+                }
+            }
+            C.gconst[s][i] = c;
         }
     }
     C.any_nee = nee > 0;
@@ -405,7 +441,7 @@ static int reset_rest(lbm_solver* h, const double* T_host) {
             return hip_fail(h, e, "copy of the temperature field");
         }
     }
-    hipError_t e = launch_unstream(h->storage, h->G, h->C, h->buf[0], nullptr, nullptr, dT, h->T0, true, h->stream);
+    hipError_t e = launch_unstream(h->storage, h->ng, h->G, h->C, h->buf[0], nullptr, nullptr, dT, h->T0, true, h->stream);
     if (dT) (void)hipFreeAsync(dT, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "initial-state kernel");
     h->cur = 0;
@@ -429,7 +465,7 @@ int lbm_set_params(lbm_solver* h, const lbm_params* p) {
     return reset_rest(h, nullptr);
 }
 
-int lbm_get_derived(const lbm_solver* h, double* s9, double* q5, double* gbeta, double* T0,
+int lbm_get_derived(const lbm_solver* h, double* s9, double* q9, double* gbeta, double* T0,
                     double* length, double* dT) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_get_derived: NULL handle");
     if (!h->params_set) return LBM_ERR_STATE;
@@ -437,9 +473,12 @@ int lbm_get_derived(const lbm_solver* h, double* s9, double* q5, double* gbeta, 
         const double s[9] = {1, 1, 1, h->C.s3, h->C.s4, h->C.s4, h->C.s6, h->C.s6, h->C.s8};
         memcpy(s9, s, sizeof(s));
     }
-    if (q5) {
-        const double q[5] = {1, h->C.z1, h->C.z1, h->C.z3, h->C.z4};
-        memcpy(q5, q, sizeof(q));
+    if (q9) {
+        const double C1 = h->C.z1, C3 = h->C.z3, C4 = h->C.z4, C6 = h->C.z6, C8 = h->C.z8;
+        const double q5[9] = {1, C1, C1, C3, C4, 0, 0, 0, 0};
+        const double q9v[9] = {1, C1, C1, C3, C4, C4, C6, C6, C8};
+        const double* q = h->ng == 9 ? q9v : q5;
+        for (int k = 0; k < 9; ++k) q9[k] = h->ng == 0 ? 0.0 : q[k];
     }
     if (gbeta) *gbeta = h->gbeta;
     if (T0) *T0 = h->T0;
@@ -451,6 +490,8 @@ int lbm_get_derived(const lbm_solver* h, double* s9, double* q5, double* gbeta, 
 int lbm_init_temperature(lbm_solver* h, const double* T) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_init_temperature: NULL handle");
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_init_temperature: call lbm_set_params first");
+    if (T && h->ng == 0)
+        return fail(h, LBM_ERR_UNSUPPORTED, "lbm_init_temperature: the isothermal model has no temperature");
     return reset_rest(h, T);
 }
 
@@ -462,7 +503,7 @@ static int build_graph(lbm_solver* h, int start) {
     int cur = start;
     hipError_t le = hipSuccess;
     for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k) {
-        le = launch_sweep(h->storage, h->L, h->G, h->C, h->buf[cur], h->buf[cur ^ 1], h->stream);
+        le = launch_sweep(h->storage, h->ng, h->L, h->G, h->C, h->buf[cur], h->buf[cur ^ 1], h->stream);
         cur ^= 1;
     }
     hipError_t ee = hipStreamEndCapture(h->stream, &g);
@@ -497,7 +538,7 @@ int lbm_step(lbm_solver* h, int64_t nsteps) {
         }
     }
     for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e = launch_sweep(h->storage, h->L, h->G, h->C, h->buf[h->cur], h->buf[h->cur ^ 1], h->stream);
+        hipError_t e = launch_sweep(h->storage, h->ng, h->L, h->G, h->C, h->buf[h->cur], h->buf[h->cur ^ 1], h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "sweep launch");
         h->cur ^= 1;
         h->t += 1;
@@ -535,7 +576,7 @@ int lbm_synchronize(lbm_solver* h) {
 int lbm_moments_device(lbm_solver* h, double* rho, double* ux, double* uy, double* T) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_moments_device: NULL handle");
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_moments_device: call lbm_set_params first");
-    hipError_t e = launch_moments(h->storage, h->G, h->C, h->buf[h->cur], rho, ux, uy, T, h->stream);
+    hipError_t e = launch_moments(h->storage, h->ng, h->G, h->C, h->buf[h->cur], rho, ux, uy, T, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "moments kernel");
     return LBM_OK;
 }
@@ -558,7 +599,7 @@ int lbm_moments(lbm_solver* h, double* rho, double* ux, double* uy, double* T) {
     if (rc != LBM_OK) return rc;
     double* d[4] = {h->fields, h->fields + n, h->fields + 2 * n, h->fields + 3 * n};
     double* o[4] = {rho, ux, uy, T};
-    hipError_t e = launch_moments(h->storage, h->G, h->C, h->buf[h->cur], rho ? d[0] : nullptr,
+    hipError_t e = launch_moments(h->storage, h->ng, h->G, h->C, h->buf[h->cur], rho ? d[0] : nullptr,
                                   ux ? d[1] : nullptr, uy ? d[2] : nullptr, T ? d[3] : nullptr, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "moments kernel");
     for (int k = 0; k < 4; ++k)
@@ -570,6 +611,7 @@ int lbm_moments(lbm_solver* h, double* rho, double* ux, double* uy, double* T) {
 static int nusselt_common(lbm_solver* h, int32_t side, double* host_local, double* out3) {
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_nusselt: call lbm_set_params first");
     if (side < LBM_LEFT || side > LBM_TOP) return fail(h, LBM_ERR_ARG, "lbm_nusselt: side out of range");
+    if (h->ng == 0) return fail(h, LBM_ERR_UNSUPPORTED, "lbm_nusselt: the isothermal model has no temperature");
     const int nee = h->params.bc_temp[side] == LBM_T_NEE_DIRICHLET;
     if (h->params.bc_temp[side] != LBM_T_DIRICHLET && !nee)
         return fail(h, LBM_ERR_ARG, "lbm_nusselt: the side is not a Dirichlet wall");
@@ -580,7 +622,7 @@ static int nusselt_common(lbm_solver* h, int32_t side, double* host_local, doubl
     int rc = ensure(h, reinterpret_cast<void**>(&h->nu_local),
                     (size_t)(h->nx > h->ny ? h->nx : h->ny) * sizeof(double), "Nusselt staging");
     if (rc != LBM_OK) return rc;
-    hipError_t e = launch_nusselt(h->storage, h->G, h->C, h->buf[h->cur], side, h->params.wall_T[side],
+    hipError_t e = launch_nusselt(h->storage, h->ng, h->G, h->C, h->buf[h->cur], side, h->params.wall_T[side],
                                   h->length, h->dT, nee, h->nu_local, h->small, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "Nusselt kernel");
     LBM_HIP(h, hipMemcpyAsync(h->host_small, h->small, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "Nusselt copy");
@@ -618,7 +660,7 @@ int lbm_residual(lbm_solver* h, double* r, int64_t* nonfinite) {
     if (rc == LBM_OK) rc = ensure(h, reinterpret_cast<void**>(&h->rbad), residual_parts(h->G) * sizeof(unsigned long long), "residual partials");
     if (rc != LBM_OK) return rc;
     const bool first = !h->snap_valid;
-    hipError_t e = launch_residual(h->storage, h->G, h->C, h->buf[h->cur], h->snap, first, h->rpart, h->rbad,
+    hipError_t e = launch_residual(h->storage, h->ng, h->G, h->C, h->buf[h->cur], h->snap, first, h->rpart, h->rbad,
                                    h->small + 4, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "residual kernels");
     LBM_HIP(h, hipMemcpyAsync(h->host_small + 4, h->small + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "residual copy");
@@ -637,10 +679,11 @@ int lbm_get_populations(lbm_solver* h, double* f9, double* g5) {
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_get_populations: call lbm_set_params first");
     const size_t n = (size_t)h->nx * h->ny;
     double* d = nullptr;
-    LBM_HIP(h, hipMallocAsync(reinterpret_cast<void**>(&d), 14 * n * sizeof(double), h->stream), "hipMallocAsync(populations)");
-    hipError_t e = launch_gather(h->storage, h->G, h->C, h->buf[h->cur], d, d + 9 * n, h->T0, h->stream);
+    LBM_HIP(h, hipMallocAsync(reinterpret_cast<void**>(&d), (9 + h->ng) * n * sizeof(double), h->stream), "hipMallocAsync(populations)");
+    hipError_t e = launch_gather(h->storage, h->ng, h->G, h->C, h->buf[h->cur], d, d + 9 * n, h->T0, h->stream);
     if (e == hipSuccess && f9) e = hipMemcpyAsync(f9, d, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess && g5) e = hipMemcpyAsync(g5, d + 9 * n, 5 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && g5 && h->ng)
+        e = hipMemcpyAsync(g5, d + 9 * n, h->ng * n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     (void)hipFreeAsync(d, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "lbm_get_populations");
     LBM_HIP(h, hipStreamSynchronize(h->stream), "populations synchronize");
@@ -649,15 +692,16 @@ int lbm_get_populations(lbm_solver* h, double* f9, double* g5) {
 
 int lbm_set_populations(lbm_solver* h, const double* f9, const double* g5) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_set_populations: NULL handle");
-    if (!f9 || !g5) return fail(h, LBM_ERR_ARG, "lbm_set_populations: NULL input");
+    if (!f9 || (!g5 && h->ng)) return fail(h, LBM_ERR_ARG, "lbm_set_populations: NULL input");
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_set_populations: call lbm_set_params first");
     const size_t n = (size_t)h->nx * h->ny;
     double* d = nullptr;
-    LBM_HIP(h, hipMallocAsync(reinterpret_cast<void**>(&d), 14 * n * sizeof(double), h->stream), "hipMallocAsync(populations)");
+    LBM_HIP(h, hipMallocAsync(reinterpret_cast<void**>(&d), (9 + h->ng) * n * sizeof(double), h->stream), "hipMallocAsync(populations)");
     hipError_t e = hipMemcpyAsync(d, f9, 9 * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d + 9 * n, g5, 5 * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && h->ng)
+        e = hipMemcpyAsync(d + 9 * n, g5, h->ng * n * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
-        e = launch_unstream(h->storage, h->G, h->C, h->buf[h->cur], d, d + 9 * n, nullptr, h->T0, false, h->stream);
+        e = launch_unstream(h->storage, h->ng, h->G, h->C, h->buf[h->cur], d, d + 9 * n, nullptr, h->T0, false, h->stream);
     (void)hipFreeAsync(d, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "lbm_set_populations");
     LBM_HIP(h, hipStreamSynchronize(h->stream), "populations synchronize");
@@ -798,6 +842,9 @@ int lbm_batch_add(lbm_batch* b, lbm_solver* h, int32_t* slot) {
     if (!b || !h) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: NULL argument");
     if (h->batch) return bfail(b, LBM_ERR_STATE, "lbm_batch_add: the solver already belongs to a batch");
     if (h->storage != b->storage) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: storage differs from the batch's");
+    int active = 0;
+    for (auto* m : b->slots) active += m != nullptr;
+    if (active && h->ng != b->ng) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: thermal model differs from the batch's");
     if (h->stream != b->stream) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: the solver must use the batch's stream");
     if (!h->params_set) return bfail(b, LBM_ERR_STATE, "lbm_batch_add: call lbm_set_params on the solver first");
     // members keep a residual snapshot so that the batch can take every
@@ -810,6 +857,7 @@ int lbm_batch_add(lbm_batch* b, lbm_solver* h, int32_t* slot) {
     if (k == (int)b->slots.size()) b->slots.push_back(nullptr);
     b->slots[k] = h;
     h->batch = b;
+    b->ng = h->ng;
     batch_invalidate(b);
     if (slot) *slot = k;
     return LBM_OK;
@@ -903,7 +951,7 @@ static int batch_build_graph(lbm_batch* b, int start) {
     if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, "batch graph capture begin");
     hipError_t le = hipSuccess;
     for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k)
-        le = launch_sweep_batch(b->storage, b->buffer, b->d_members, b->d_tiles, b->ntiles, (start + k) & 1, b->stream);
+        le = launch_sweep_batch(b->storage, b->ng, b->buffer, b->d_members, b->d_tiles, b->ntiles, (start + k) & 1, b->stream);
     e = hipStreamEndCapture(b->stream, &g);
     if (le != hipSuccess || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -938,7 +986,7 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps) {
         }
     }
     for (int64_t k = 0; k < left; ++k) {
-        hipError_t e = launch_sweep_batch(b->storage, b->buffer, b->d_members, b->d_tiles, b->ntiles, b->parity, b->stream);
+        hipError_t e = launch_sweep_batch(b->storage, b->ng, b->buffer, b->d_members, b->d_tiles, b->ntiles, b->parity, b->stream);
         if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("batched sweep launch: ") + hipGetErrorString(e));
         b->parity ^= 1;
     }
@@ -996,7 +1044,7 @@ int lbm_batch_residual(lbm_batch* b, double* r, int64_t* nonfinite) {
         b->cap_rout = nm;
     }
     if (nm) {
-        hipError_t e = launch_residual_batch(b->storage, b->d_members, (int)nm, b->d_tiles, b->ntiles, b->parity,
+        hipError_t e = launch_residual_batch(b->storage, b->ng, b->d_members, (int)nm, b->d_tiles, b->ntiles, b->parity,
                                              b->d_tile_max, b->d_tile_bad, b->d_rout, b->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(b->h_rout, b->d_rout, 2 * nm * sizeof(double), hipMemcpyDeviceToHost, b->stream);

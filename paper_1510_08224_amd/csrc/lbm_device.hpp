@@ -1,13 +1,20 @@
-// lbm_device.hpp -- device-side core of the D2Q9 + D2Q5 non-orthogonal MRT
-// lattice Boltzmann step (Liu, He, Li & Li, arXiv:1510.08224): lattice
-// constants, storage codecs, the pull of one node with link-wise walls, and
-// the collision in the raw-moment spaces of M (Eq. 13) and N (Eq. 26),
-// unrolled with the zeros of M, M^-1 (Eq. A1), N and N^-1 (Eq. A2) removed.
+// lbm_device.hpp -- device-side core of the double-distribution
+// non-orthogonal MRT lattice Boltzmann step (Liu, He, Li & Li,
+// arXiv:1510.08224): lattice constants, storage codecs, the pull of one node
+// with its walls, and the collisions in the raw-moment spaces of M (Eq. 13)
+// and N (Eq. 26), unrolled with the zeros of M, M^-1 (Eq. A1), N and N^-1
+// (Eq. A2) removed.
+//
+// The temperature lattice is a template parameter NG:
+//   NG = 5  the paper's D2Q5 thermal model (Sec. 2.2, Eqs. 23-30);
+//   NG = 9  its D2Q9 thermal variant (Eqs. 31-33), collided with the same
+//           non-orthogonal M as the flow, equilibrium of Eq. 31 with theta;
+//   NG = 0  no temperature field (isothermal flow, Secs. 3.1-3.2).
 //
 // Layout in HBM: structure of arrays.  Plane i of a population buffer holds
 // population i of every node, rows of `pitch` elements, x fastest:
 //   element (i, x, y) at i * plane + y * pitch + x.
-// A buffer holds the 9 flow planes followed by the 5 temperature planes.
+// A buffer holds the 9 flow planes followed by the NG temperature planes.
 // The buffer read by a step holds, for time t, the values that streaming
 // turns into the pre-collision populations at t (the post-collision values
 // of t - 1 for every link that stays inside the lattice).
@@ -21,7 +28,7 @@ namespace lbm {
 
 enum Side { kLeft = 0, kRight = 1, kBottom = 2, kTop = 3 };
 
-// D2Q9 velocities (Eq. 5, c = 1), their opposites, and the D2Q5 subset.
+// D2Q9 velocities (Eq. 5, c = 1), their opposites; D2Q5 is the subset 0..4.
 __host__ __device__ constexpr int ex(int i) {
     return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
 }
@@ -34,6 +41,9 @@ __host__ __device__ constexpr int opp(int i) {
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp");
 
+// D2Q9 weights (stated after Eq. 22).
+__host__ __device__ constexpr double w9(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
 // Lattice geometry of one solver.
 struct Geom {
     int nx, ny;
@@ -44,22 +54,27 @@ struct Geom {
 
 // Per-problem constants of the step (all derived on the host).
 struct Coeffs {
-    // D2Q9 rates (Eq. 20): s3 = s_e, s4 = s5 = s_nu, s6 = s7 = s_q, s8 = s_eps.
+    // D2Q9 flow rates (Eq. 20): s3 = s_e, s4 = s5 = s_nu, s6 = s7 = s_q, s8 = s_eps.
     double s3, s4, s6, s8;
-    // D2Q5 rates (Eq. 29): z1 = z2 = zeta_alpha, z3 = zeta_e, z4 = zeta_nu.
-    double z1, z3, z4;
-    double varpi;       // Eq. 28
+    // Thermal rates.  D2Q5 (Eq. 29): z1 = z2 = zeta_alpha, z3 = zeta_e,
+    // z4 = zeta_nu.  D2Q9 (Eq. 32): also z4 = z5 = zeta_nu, z6 = z7 = zeta_q,
+    // z8 = zeta_eps.
+    double z1, z3, z4, z6, z8;
+    double varpi;       // Eq. 28 (D2Q5)
+    double theta;       // Eq. 31 (D2Q9), 0 or 1
     double gbeta;       // g beta (Eq. 4)
     double ax, ay;      // external acceleration a (Eq. 4)
     double tshift;      // sum(g) + tshift = T - T0
-    double toff;        // sum(g) + toff  = T
-    // Walls, per side.  Flow: a population pulled through a wall in
-    // direction i is the stored opposite population plus bbf[side][i]
+    double toff;        // sum(g) + toff  = T  (also the stored rest temperature)
+    double T0;          // reference temperature
+    // Link-wise walls, per side.  Flow: a population pulled through a wall
+    // in direction i is the stored opposite population plus bbf[side][i]
     // (= 6 w_i rho0 e_i . u_w).  Temperature: gsign[side] * stored opposite
-    // + gconst[side] (anti-bounce-back -1, varpi T_w/2 for full values or
-    // varpi (T_w - T0)/2 for deviations; bounce-back +1, 0).
+    // + gconst[side][i] (anti-bounce-back: -1 and twice the even part of the
+    // equilibrium at the wall, relative to the stored rest state;
+    // bounce-back: +1, 0).
     double bbf[4][9];
-    double gsign[4], gconst[4];
+    double gsign[4], gconst[4][9];
     // Non-equilibrium extrapolation walls (the wall passes through the
     // first/last node row or column): nee[side] = 1 for such a side,
     // tdir[side] = 1 if its temperature is Dirichlet, uw the wall velocity,
@@ -143,32 +158,52 @@ __device__ __forceinline__ Src source(const Geom& G, int x, int y) {
     return s;
 }
 
-template <class S>
-__device__ __forceinline__ void pull_node(const S* __restrict__ src, const Geom& G, const Coeffs& C,
-                                          int x, int y, typename Codec<S>::R f[9],
-                                          typename Codec<S>::R g[5]) {
+template <class S, int I>
+__device__ __forceinline__ typename Codec<S>::R pull_f1(const S* __restrict__ src, const Geom& G, const Coeffs& C,
+                                                        int x, int y) {
     using R = typename Codec<S>::R;
-#define LBM_PULL_F(I)                                                          \
-    {                                                                          \
-        Src s = source<I, 0>(G, x, y);                                         \
-        R v = Codec<S>::load(src + s.off, C.finv);                             \
-        if (s.side >= 0) v += (R)C.bbf[s.side][I];                             \
-        f[I] = v;                                                              \
-    }
-#define LBM_PULL_G(I)                                                          \
-    {                                                                          \
-        Src s = source<I, 9>(G, x, y);                                         \
-        R v = Codec<S>::load(src + s.off, C.ginv);                             \
-        if (s.side >= 0) v = (R)C.gsign[s.side] * v + (R)C.gconst[s.side];     \
-        g[I] = v;                                                              \
-    }
+    const Src s = source<I, 0>(G, x, y);
+    R v = Codec<S>::load(src + s.off, C.finv);
+    if (s.side >= 0) v += (R)C.bbf[s.side][I];
+    return v;
+}
+
+template <class S, int I>
+__device__ __forceinline__ typename Codec<S>::R pull_g1(const S* __restrict__ src, const Geom& G, const Coeffs& C,
+                                                        int x, int y) {
+    using R = typename Codec<S>::R;
+    const Src s = source<I, 9>(G, x, y);
+    R v = Codec<S>::load(src + s.off, C.ginv);
+    if (s.side >= 0) v = (R)C.gsign[s.side] * v + (R)C.gconst[s.side][I];
+    return v;
+}
+
+// f[9] and g[NG] of node (x, y), link-wise walls and wraps resolved per link.
+template <class S, int NG>
+__device__ __forceinline__ void pull_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
+                                          typename Codec<S>::R f[9], typename Codec<S>::R g[NG > 0 ? NG : 1]) {
     f[0] = Codec<S>::load(src + (long long)y * G.pitch + x, C.finv);
-    LBM_PULL_F(1) LBM_PULL_F(2) LBM_PULL_F(3) LBM_PULL_F(4)
-    LBM_PULL_F(5) LBM_PULL_F(6) LBM_PULL_F(7) LBM_PULL_F(8)
-    g[0] = Codec<S>::load(src + 9 * G.plane + (long long)y * G.pitch + x, C.ginv);
-    LBM_PULL_G(1) LBM_PULL_G(2) LBM_PULL_G(3) LBM_PULL_G(4)
-#undef LBM_PULL_F
-#undef LBM_PULL_G
+    f[1] = pull_f1<S, 1>(src, G, C, x, y);
+    f[2] = pull_f1<S, 2>(src, G, C, x, y);
+    f[3] = pull_f1<S, 3>(src, G, C, x, y);
+    f[4] = pull_f1<S, 4>(src, G, C, x, y);
+    f[5] = pull_f1<S, 5>(src, G, C, x, y);
+    f[6] = pull_f1<S, 6>(src, G, C, x, y);
+    f[7] = pull_f1<S, 7>(src, G, C, x, y);
+    f[8] = pull_f1<S, 8>(src, G, C, x, y);
+    if constexpr (NG > 0) {
+        g[0] = Codec<S>::load(src + 9 * G.plane + (long long)y * G.pitch + x, C.ginv);
+        g[1] = pull_g1<S, 1>(src, G, C, x, y);
+        g[2] = pull_g1<S, 2>(src, G, C, x, y);
+        g[3] = pull_g1<S, 3>(src, G, C, x, y);
+        g[4] = pull_g1<S, 4>(src, G, C, x, y);
+    }
+    if constexpr (NG == 9) {
+        g[5] = pull_g1<S, 5>(src, G, C, x, y);
+        g[6] = pull_g1<S, 6>(src, G, C, x, y);
+        g[7] = pull_g1<S, 7>(src, G, C, x, y);
+        g[8] = pull_g1<S, 8>(src, G, C, x, y);
+    }
 }
 
 // Element offset of the pull source of plane PL in direction I relative to
@@ -190,64 +225,14 @@ __device__ __forceinline__ const T* at_bytes(const T* p, unsigned byte_off) {
 // no wrap).  Each plane's shift (plane offset - e_y pitch - e_x) is uniform
 // across the workgroup, so it stays in scalar registers and every load adds
 // the same 32-bit lane byte offset `boff` = (y * pitch + x) * sizeof(S).
-template <class S>
+template <class S, int NG>
 __device__ __forceinline__ void pull_interior(const S* __restrict__ src, const Geom& G, const Coeffs& C,
                                               unsigned boff, typename Codec<S>::R f[9],
-                                              typename Codec<S>::R g[5]) {
-#define LBM_PI_F(I) f[I] = Codec<S>::load(at_bytes(src + LBM_SHIFT(I, I), boff), C.finv);
-#define LBM_PI_G(I) g[I] = Codec<S>::load(at_bytes(src + LBM_SHIFT(I, 9 + I), boff), C.ginv);
-    LBM_PI_F(0) LBM_PI_F(1) LBM_PI_F(2) LBM_PI_F(3) LBM_PI_F(4)
-    LBM_PI_F(5) LBM_PI_F(6) LBM_PI_F(7) LBM_PI_F(8)
-    LBM_PI_G(0) LBM_PI_G(1) LBM_PI_G(2) LBM_PI_G(3) LBM_PI_G(4)
-#undef LBM_PI_F
-#undef LBM_PI_G
-}
-
-// ---------------------------------------------------------------------------
-// Non-equilibrium extrapolation walls (the scheme the paper's Sec. 3 uses;
-// reading: Guo-Zheng-Shi extrapolation of the non-equilibrium part).  A
-// wall node x_b takes its pre-collision populations from its inward
-// neighbour x_f:
-//   fbar_i(x_b) = f_i^eq(rho(x_f), u_w) + [fbar_i(x_f) - f_i^eq(rho(x_f), u(x_f))]
-//   g_i(x_b)    = g_i^eq(T_b, u_w)      + [g_i(x_f)    - g_i^eq(T(x_f), u(x_f))]
-// with f^eq of Eq. 22 (rho only in the rest term, rho0 = 1 on the velocity
-// terms), g^eq of Eq. 30, T_b the wall temperature (Dirichlet) or T(x_f)
-// (adiabatic).  Corner nodes use the diagonal neighbour, the velocity of
-// their top/bottom wall and a Dirichlet temperature if either wall has one
-// (top/bottom first).  In deviation storage both equilibria are taken
-// relative to the rest state, which cancels.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double w9(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
-
-__device__ __forceinline__ double feq_rep(int i, double rho, double ux, double uy) {
-    const double eu = ex(i) * ux + ey(i) * uy, usq = ux * ux + uy * uy;
-    return w9(i) * (rho + 1.0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
-}
-
-// g^eq(T, u) minus the stored rest part g^eq(Trest, 0) (Trest = 0 for full
-// values, T0 for deviations).
-__device__ __forceinline__ double geq_rep(int i, double T, double ux, double uy, double varpi, double Trest) {
-    if (i == 0) return (1.0 - varpi) * (T - Trest);
-    return 0.25 * varpi * (T - Trest) + 0.5 * (ex(i) * ux + ey(i) * uy) * T;
-}
-
-__device__ __forceinline__ bool nee_node_at(const Geom& G, const Coeffs& C, int x, int y) {
-    return (C.nee[kLeft] && x == 0) || (C.nee[kRight] && x == G.nx - 1) || (C.nee[kBottom] && y == 0) ||
-           (C.nee[kTop] && y == G.ny - 1);
-}
-
-// Defined below (needs macro()).
-template <class S>
-__device__ void nee_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
-                         typename Codec<S>::R f[9], typename Codec<S>::R g[5]);
-
-// Pre-collision populations of any node: extrapolated on NEE walls,
-// pulled everywhere else.
-template <class S>
-__device__ __forceinline__ void load_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x,
-                                          int y, typename Codec<S>::R f[9], typename Codec<S>::R g[5]) {
-    if (C.any_nee && nee_node_at(G, C, x, y)) nee_node<S>(src, G, C, x, y, f, g);
-    else pull_node<S>(src, G, C, x, y, f, g);
+                                              typename Codec<S>::R g[NG > 0 ? NG : 1]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = Codec<S>::load(at_bytes(src + LBM_SHIFT(i, i), boff), C.finv);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) g[i] = Codec<S>::load(at_bytes(src + LBM_SHIFT(i, 9 + i), boff), C.ginv);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,62 +282,16 @@ template <> struct Buf<__half> {
 
 // Interior pull through a buffer descriptor: every load is
 // buffer_load voffset=boff, soffset=shift of the plane.
-template <class S>
+template <class S, int NG>
 __device__ __forceinline__ void pull_interior_buf(__amdgpu_buffer_rsrc_t r, const Geom& G, const Coeffs& C,
                                                   unsigned boff, typename Codec<S>::R f[9],
-                                                  typename Codec<S>::R g[5]) {
-#define LBM_PB_F(I) f[I] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(I, I) * (long long)sizeof(S)), C.finv);
-#define LBM_PB_G(I) g[I] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(I, 9 + I) * (long long)sizeof(S)), C.ginv);
-    LBM_PB_F(0) LBM_PB_F(1) LBM_PB_F(2) LBM_PB_F(3) LBM_PB_F(4)
-    LBM_PB_F(5) LBM_PB_F(6) LBM_PB_F(7) LBM_PB_F(8)
-    LBM_PB_G(0) LBM_PB_G(1) LBM_PB_G(2) LBM_PB_G(3) LBM_PB_G(4)
-#undef LBM_PB_F
-#undef LBM_PB_G
-}
-
-// Correction of the x-shifted pulls of a node in the first or last column
-// after an interior pull (which read the neighbouring row's element there):
-// periodic axes re-read the wrapped source, walls apply the wall rule to
-// the node's own opposite population.
-template <class S>
-__device__ __forceinline__ void fix_x_edges(const S* __restrict__ src, const Geom& G, const Coeffs& C,
-                                            int x, int y, typename Codec<S>::R f[9],
-                                            typename Codec<S>::R g[5]) {
-    using R = typename Codec<S>::R;
-    auto ld = [&](int pl, int xx, int yy, float inv) -> R {
-        return Codec<S>::load(src + (long long)pl * G.plane + (long long)yy * G.pitch + xx, inv);
-    };
-    if ((x == 0 && C.nee[kLeft]) || (x == G.nx - 1 && C.nee[kRight])) {
-        nee_node<S>(src, G, C, x, y, f, g);
-        return;
-    }
-    if (x == 0) {
-        if (G.px) {
-            const int xs = G.nx - 1;
-            f[1] = ld(1, xs, y, C.finv);
-            f[5] = ld(5, xs, y - 1, C.finv);
-            f[8] = ld(8, xs, y + 1, C.finv);
-            g[1] = ld(10, xs, y, C.ginv);
-        } else {
-            f[1] = ld(3, 0, y, C.finv) + (R)C.bbf[kLeft][1];
-            f[5] = ld(7, 0, y, C.finv) + (R)C.bbf[kLeft][5];
-            f[8] = ld(6, 0, y, C.finv) + (R)C.bbf[kLeft][8];
-            g[1] = (R)C.gsign[kLeft] * ld(12, 0, y, C.ginv) + (R)C.gconst[kLeft];
-        }
-    }
-    if (x == G.nx - 1) {
-        if (G.px) {
-            f[3] = ld(3, 0, y, C.finv);
-            f[6] = ld(6, 0, y - 1, C.finv);
-            f[7] = ld(7, 0, y + 1, C.finv);
-            g[3] = ld(12, 0, y, C.ginv);
-        } else {
-            f[3] = ld(1, x, y, C.finv) + (R)C.bbf[kRight][3];
-            f[6] = ld(8, x, y, C.finv) + (R)C.bbf[kRight][6];
-            f[7] = ld(5, x, y, C.finv) + (R)C.bbf[kRight][7];
-            g[3] = (R)C.gsign[kRight] * ld(10, x, y, C.ginv) + (R)C.gconst[kRight];
-        }
-    }
+                                                  typename Codec<S>::R g[NG > 0 ? NG : 1]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(i, i) * (long long)sizeof(S)), C.finv);
+#pragma unroll
+    for (int i = 0; i < NG; ++i)
+        g[i] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(i, 9 + i) * (long long)sizeof(S)), C.ginv);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,19 +302,31 @@ __device__ __forceinline__ void fix_x_edges(const S* __restrict__ src, const Geo
 struct Macro {
     double rho;    // sum fbar (full: density; deviation: rho - rho0)
     double ux, uy; // velocity (rho0 = 1)
-    double Tsum;   // sum g (full: T; deviation: T - T0)
-    double T;      // temperature
+    double Tsum;   // sum g (full: T; deviation: T - T0); 0 without temperature
+    double T;      // temperature (T0 without temperature)
     double Fx, Fy; // force per unit mass
 };
 
-template <class R>
-__device__ __forceinline__ Macro macro(const R f[9], const R g[5], const Coeffs& C) {
+template <class R, int NG>
+__device__ __forceinline__ Macro macro(const R f[9], const R g[NG > 0 ? NG : 1], const Coeffs& C) {
     Macro m;
-    const double g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3], g4 = g[4];
-    m.Tsum = ((g0 + g1) + (g2 + g3)) + g4;
-    m.T = m.Tsum + C.toff;
+    if constexpr (NG == 0) {
+        m.Tsum = 0.0;
+        m.T = C.T0;
+        m.Fy = C.ay;
+    } else {
+        double t = ((double)g[0] + (double)g[1]) + ((double)g[2] + (double)g[3]);
+        if constexpr (NG == 5) {
+            t += (double)g[4];
+        } else {
+            t += ((double)g[4] + (double)g[5]) + ((double)g[6] + (double)g[7]);
+            t += (double)g[8];
+        }
+        m.Tsum = t;
+        m.T = t + C.toff;
+        m.Fy = C.ay + C.gbeta * (t + C.tshift);
+    }
     m.Fx = C.ax;
-    m.Fy = C.ay + C.gbeta * (m.Tsum + C.tshift);
     const double f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4];
     const double f5 = f[5], f6 = f[6], f7 = f[7], f8 = f[8];
     m.rho = (((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7))) + f8;
@@ -387,102 +338,177 @@ __device__ __forceinline__ Macro macro(const R f[9], const R g[5], const Coeffs&
     return m;
 }
 
-// ---------------------------------------------------------------------------
-// Collision of one node in place (Eq. 8 for fbar, Eq. 24 for g), given its
-// macroscopic values.  Readings: rho0 = 1 multiplies every velocity term of
-// m^eq and every source moment; the density enters only m_0^eq, the 2/3 of
-// m_3^eq and the 1/9 of m_8^eq; S~_8 = (2/3) rho0 (ux Fx + uy Fy), the
-// moment of the Guo source (the printed form pairs ux with Fy).
-// In deviation storage the same expressions act on deviations: the rest
-// state is a fixed point and every map here is affine in rho and T with
-// the rest parts cancelling.
-// ---------------------------------------------------------------------------
+// Rows 3..8 of the raw-moment transform M of Eq. 13 (rows 0..2 are the
+// conserved sums), and its inverse (Eq. A1) from the moments k0..k8.
 template <class R>
-__device__ __forceinline__ void collide(R f[9], R g[5], const Macro& mc, const Coeffs& C) {
+struct Moments9 {
+    R m3, m4, m5, m6, m7, m8, d13, d24;
+    __device__ __forceinline__ explicit Moments9(const R v[9]) {
+        const R a13 = v[1] + v[3], a24 = v[2] + v[4];
+        const R c57 = v[5] + v[7], c68 = v[6] + v[8];
+        const R d57 = v[5] - v[7], d68 = v[6] - v[8];
+        m8 = c57 + c68;
+        m3 = (a13 + a24) + (R)2 * m8;
+        m4 = a13 - a24;
+        m5 = c57 - c68;
+        m6 = d57 + d68;
+        m7 = d57 - d68;
+        d13 = v[1] - v[3];
+        d24 = v[2] - v[4];
+    }
+};
+
+template <class R>
+__device__ __forceinline__ void inverse9(R v[9], R k0, R k1, R k2, R k3, R k4, R k5, R k6, R k7, R k8) {
+    const R q = (R)0.25 * k3 - (R)0.5 * k8;
+    const R h4 = (R)0.25 * k4;
+    const R bx = (R)0.5 * (k1 - k7);
+    const R by = (R)0.5 * (k2 - k6);
+    v[0] = (k0 - k3) + k8;
+    v[1] = (q + h4) + bx;
+    v[3] = (q + h4) - bx;
+    v[2] = (q - h4) + by;
+    v[4] = (q - h4) - by;
+    const R p86 = k8 + k6, p57 = k5 + k7;
+    const R r86 = k8 - k6, r57 = k5 - k7;
+    v[5] = (R)0.25 * (p86 + p57);
+    v[6] = (R)0.25 * (p86 - p57);
+    v[7] = (R)0.25 * (r86 + r57);
+    v[8] = (R)0.25 * (r86 - r57);
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one node in place (Eq. 8 for fbar; Eq. 24, or its D2Q9
+// counterpart, for g), given its macroscopic values.  Readings: rho0 = 1
+// multiplies every velocity term of m^eq and every source moment; the
+// density enters only m_0^eq, the 2/3 of m_3^eq and the 1/9 of m_8^eq;
+// S~_8 = (2/3) rho0 (ux Fx + uy Fy), the moment of the Guo source (the
+// printed form pairs ux with Fy).  In deviation storage the same
+// expressions act on deviations: the rest state is a fixed point and every
+// map here is affine in rho and T with the rest parts cancelling.
+// ---------------------------------------------------------------------------
+template <class R, int NG>
+__device__ __forceinline__ void collide(R f[9], R g[NG > 0 ? NG : 1], const Macro& mc, const Coeffs& C) {
     const R rho = (R)mc.rho;
     const R ux = (R)mc.ux, uy = (R)mc.uy;
     const R Fx = (R)mc.Fx, Fy = (R)mc.Fy;
     const R usq = ux * ux + uy * uy;
     const R uF = ux * Fx + uy * Fy;
     const R third = (R)(1.0 / 3.0);
-
-    // m_bar = M fbar: rows 3..8 of Eq. 13 (rows 0..2 are the conserved sums).
-    const R a13 = f[1] + f[3], a24 = f[2] + f[4];
-    const R c57 = f[5] + f[7], c68 = f[6] + f[8];
-    const R d57 = f[5] - f[7], d68 = f[6] - f[8];
-    const R m8 = c57 + c68;
-    const R m3 = (a13 + a24) + (R)2 * m8;
-    const R m4 = a13 - a24;
-    const R m5 = c57 - c68;
-    const R m6 = d57 + d68;
-    const R m7 = d57 - d68;
-
-    // Relaxation toward m^eq (Eq. 16) with the source of Eq. 17.
-    const R s3 = (R)C.s3, s4 = (R)C.s4, s6 = (R)C.s6, s8 = (R)C.s8;
-    const R e3 = (R)(2.0 / 3.0) * rho + usq;
-    const R e4 = ux * ux - uy * uy;
-    const R e5 = ux * uy;
-    const R e6 = third * uy;
-    const R e7 = third * ux;
-    const R e8 = (R)(1.0 / 9.0) * rho + third * usq;
-    const R S3 = (R)2 * uF;
-    const R S4 = (R)2 * (ux * Fx - uy * Fy);
-    const R S5 = ux * Fy + uy * Fx;
-    const R S6 = third * Fy;
-    const R S7 = third * Fx;
-    const R S8 = (R)(2.0 / 3.0) * uF;
-    const R n3 = m3 - s3 * (m3 - e3) + ((R)1 - (R)0.5 * s3) * S3;
-    const R n4 = m4 - s4 * (m4 - e4) + ((R)1 - (R)0.5 * s4) * S4;
-    const R n5 = m5 - s4 * (m5 - e5) + ((R)1 - (R)0.5 * s4) * S5;
-    const R n6 = m6 - s6 * (m6 - e6) + ((R)1 - (R)0.5 * s6) * S6;
-    const R n7 = m7 - s6 * (m7 - e7) + ((R)1 - (R)0.5 * s6) * S7;
-    const R n8 = m8 - s8 * (m8 - e8) + ((R)1 - (R)0.5 * s8) * S8;
-    // Conserved moments after collision: m0* = rho, m1* = jx + Fx,
-    // m2* = jy + Fy (rates 1 in Eq. 20; Eq. 15 puts -F/2 in m_bar).
-    const R n0 = rho;
-    const R n1 = (R)(mc.ux + 0.5 * mc.Fx);
-    const R n2 = (R)(mc.uy + 0.5 * mc.Fy);
-
-    // fbar* = M^-1 m_bar* (Eq. A1).
-    const R q = (R)0.25 * n3 - (R)0.5 * n8;
-    const R h4 = (R)0.25 * n4;
-    const R bx = (R)0.5 * (n1 - n7);
-    const R by = (R)0.5 * (n2 - n6);
-    f[0] = (n0 - n3) + n8;
-    f[1] = (q + h4) + bx;
-    f[3] = (q + h4) - bx;
-    f[2] = (q - h4) + by;
-    f[4] = (q - h4) - by;
-    const R p86 = n8 + n6, p57 = n5 + n7;
-    const R r86 = n8 - n6, r57 = n5 - n7;
-    f[5] = (R)0.25 * (p86 + p57);
-    f[6] = (R)0.25 * (p86 - p57);
-    f[7] = (R)0.25 * (r86 + r57);
-    f[8] = (R)0.25 * (r86 - r57);
-
-    // Temperature: n = N g (Eq. 26), n^eq (Eq. 28), Eq. 24, g* = N^-1 n*.
-    const R T = (R)mc.T;
-    const R t0 = (R)mc.Tsum;
-    const R t1 = g[1] - g[3];
-    const R t2 = g[2] - g[4];
-    const R t3 = (g[1] + g[3]) + (g[2] + g[4]);
-    const R t4 = (g[1] + g[3]) - (g[2] + g[4]);
-    const R z1 = (R)C.z1, z3 = (R)C.z3, z4 = (R)C.z4;
-    const R k1 = t1 - z1 * (t1 - ux * T);
-    const R k2 = t2 - z1 * (t2 - uy * T);
-    const R k3 = t3 - z3 * (t3 - (R)C.varpi * t0);
-    const R k4 = t4 - z4 * t4;
-    const R w3 = (R)0.25 * k3, w4 = (R)0.25 * k4;
-    g[0] = t0 - k3;
-    g[1] = (R)0.5 * k1 + (w3 + w4);
-    g[3] = (R)(-0.5) * k1 + (w3 + w4);
-    g[2] = (R)0.5 * k2 + (w3 - w4);
-    g[4] = (R)(-0.5) * k2 + (w3 - w4);
+    {
+        const Moments9<R> m(f);
+        // Relaxation toward m^eq (Eq. 16) with the source of Eq. 17.
+        const R s3 = (R)C.s3, s4 = (R)C.s4, s6 = (R)C.s6, s8 = (R)C.s8;
+        const R e3 = (R)(2.0 / 3.0) * rho + usq;
+        const R e4 = ux * ux - uy * uy;
+        const R e5 = ux * uy;
+        const R e6 = third * uy;
+        const R e7 = third * ux;
+        const R e8 = (R)(1.0 / 9.0) * rho + third * usq;
+        const R S3 = (R)2 * uF;
+        const R S4 = (R)2 * (ux * Fx - uy * Fy);
+        const R S5 = ux * Fy + uy * Fx;
+        const R S6 = third * Fy;
+        const R S7 = third * Fx;
+        const R S8 = (R)(2.0 / 3.0) * uF;
+        const R n3 = m.m3 - s3 * (m.m3 - e3) + ((R)1 - (R)0.5 * s3) * S3;
+        const R n4 = m.m4 - s4 * (m.m4 - e4) + ((R)1 - (R)0.5 * s4) * S4;
+        const R n5 = m.m5 - s4 * (m.m5 - e5) + ((R)1 - (R)0.5 * s4) * S5;
+        const R n6 = m.m6 - s6 * (m.m6 - e6) + ((R)1 - (R)0.5 * s6) * S6;
+        const R n7 = m.m7 - s6 * (m.m7 - e7) + ((R)1 - (R)0.5 * s6) * S7;
+        const R n8 = m.m8 - s8 * (m.m8 - e8) + ((R)1 - (R)0.5 * s8) * S8;
+        // Conserved moments after collision: m0* = rho, m1* = jx + Fx,
+        // m2* = jy + Fy (rates 1 in Eq. 20; Eq. 15 puts -F/2 in m_bar).
+        const R n1 = (R)(mc.ux + 0.5 * mc.Fx);
+        const R n2 = (R)(mc.uy + 0.5 * mc.Fy);
+        inverse9<R>(f, rho, n1, n2, n3, n4, n5, n6, n7, n8);
+    }
+    if constexpr (NG == 5) {
+        // n = N g (Eq. 26), n^eq (Eq. 28), Eq. 24, g* = N^-1 n* (Eq. A2).
+        const R T = (R)mc.T;
+        const R t0 = (R)mc.Tsum;
+        const R t1 = g[1] - g[3];
+        const R t2 = g[2] - g[4];
+        const R t3 = (g[1] + g[3]) + (g[2] + g[4]);
+        const R t4 = (g[1] + g[3]) - (g[2] + g[4]);
+        const R z1 = (R)C.z1, z3 = (R)C.z3, z4 = (R)C.z4;
+        const R k1 = t1 - z1 * (t1 - ux * T);
+        const R k2 = t2 - z1 * (t2 - uy * T);
+        const R k3 = t3 - z3 * (t3 - (R)C.varpi * t0);
+        const R k4 = t4 - z4 * t4;
+        const R w3 = (R)0.25 * k3, w4 = (R)0.25 * k4;
+        g[0] = t0 - k3;
+        g[1] = (R)0.5 * k1 + (w3 + w4);
+        g[3] = (R)(-0.5) * k1 + (w3 + w4);
+        g[2] = (R)0.5 * k2 + (w3 - w4);
+        g[4] = (R)(-0.5) * k2 + (w3 - w4);
+    }
+    if constexpr (NG == 9) {
+        // n = M g (Eq. 13), n^eq = M g^eq with g^eq of Eq. 31:
+        // T (1, ux, uy, 2/3 + th |u|^2, th (ux^2 - uy^2), th ux uy, uy/3,
+        // ux/3, 1/9 + th |u|^2 / 3); relaxation with Q of Eq. 32;
+        // g* = M^-1 n*.  The rest part of the constant terms uses Tsum.
+        const Moments9<R> m(g);
+        const R T = (R)mc.T;
+        const R t0 = (R)mc.Tsum;
+        const R th = (R)C.theta;
+        const R n1 = m.d13 + m.m7;
+        const R n2 = m.d24 + m.m6;
+        const R z1 = (R)C.z1, z3 = (R)C.z3, z4 = (R)C.z4, z6 = (R)C.z6, z8 = (R)C.z8;
+        const R k1 = n1 - z1 * (n1 - ux * T);
+        const R k2 = n2 - z1 * (n2 - uy * T);
+        const R k3 = m.m3 - z3 * (m.m3 - ((R)(2.0 / 3.0) * t0 + th * usq * T));
+        const R k4 = m.m4 - z4 * (m.m4 - th * (ux * ux - uy * uy) * T);
+        const R k5 = m.m5 - z4 * (m.m5 - th * ux * uy * T);
+        const R k6 = m.m6 - z6 * (m.m6 - third * uy * T);
+        const R k7 = m.m7 - z6 * (m.m7 - third * ux * T);
+        const R k8 = m.m8 - z8 * (m.m8 - ((R)(1.0 / 9.0) * t0 + third * th * usq * T));
+        inverse9<R>(g, t0, k1, k2, k3, k4, k5, k6, k7, k8);
+    }
 }
 
-template <class S>
+// ---------------------------------------------------------------------------
+// Non-equilibrium extrapolation walls (the scheme the paper's Sec. 3 uses;
+// reading: Guo-Zheng-Shi extrapolation of the non-equilibrium part).  A
+// wall node x_b takes its pre-collision populations from its inward
+// neighbour x_f:
+//   fbar_i(x_b) = f_i^eq(rho(x_f), u_w) + [fbar_i(x_f) - f_i^eq(rho(x_f), u(x_f))]
+//   g_i(x_b)    = g_i^eq(T_b, u_w)      + [g_i(x_f)    - g_i^eq(T(x_f), u(x_f))]
+// with f^eq of Eq. 22 (rho only in the rest term, rho0 = 1 on the velocity
+// terms), g^eq of Eq. 30 (D2Q5) or Eq. 31 (D2Q9), T_b the wall temperature
+// (Dirichlet) or T(x_f) (adiabatic).  Corner nodes use the diagonal
+// neighbour, the velocity of their top/bottom wall and a Dirichlet
+// temperature if either wall has one (top/bottom first).  In deviation
+// storage both equilibria are taken relative to the rest state, which
+// cancels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double feq_rep(int i, double rho, double ux, double uy) {
+    const double eu = ex(i) * ux + ey(i) * uy, usq = ux * ux + uy * uy;
+    return w9(i) * (rho + 1.0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+}
+
+// g^eq(T, u) minus the stored rest part g^eq(Trest, 0) (Trest = 0 for full
+// values, T0 for deviations).
+template <int NG>
+__device__ __forceinline__ double geq_rep(int i, double T, double ux, double uy, const Coeffs& C) {
+    const double eu = ex(i) * ux + ey(i) * uy;
+    if constexpr (NG == 5) {
+        if (i == 0) return (1.0 - C.varpi) * (T - C.toff);
+        return 0.25 * C.varpi * (T - C.toff) + 0.5 * eu * T;
+    } else {
+        const double usq = ux * ux + uy * uy;
+        return w9(i) * ((T - C.toff) + T * (3.0 * eu + C.theta * (4.5 * eu * eu - 1.5 * usq)));
+    }
+}
+
+__device__ __forceinline__ bool nee_node_at(const Geom& G, const Coeffs& C, int x, int y) {
+    return (C.nee[kLeft] && x == 0) || (C.nee[kRight] && x == G.nx - 1) || (C.nee[kBottom] && y == 0) ||
+           (C.nee[kTop] && y == G.ny - 1);
+}
+
+template <class S, int NG>
 __device__ void nee_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
-                         typename Codec<S>::R f[9], typename Codec<S>::R g[5]) {
+                         typename Codec<S>::R f[9], typename Codec<S>::R g[NG > 0 ? NG : 1]) {
     using R = typename Codec<S>::R;
     const bool onL = C.nee[kLeft] && x == 0, onR = C.nee[kRight] && x == G.nx - 1;
     const bool onB = C.nee[kBottom] && y == 0, onT = C.nee[kTop] && y == G.ny - 1;
@@ -492,16 +518,88 @@ __device__ void nee_node(const S* __restrict__ src, const Geom& G, const Coeffs&
     const int sy = onB ? kBottom : (onT ? kTop : -1);
     const int vs = sy >= 0 ? sy : sx;
     const int ts = (sy >= 0 && C.tdir[sy]) ? sy : ((sx >= 0 && C.tdir[sx]) ? sx : -1);
-    R ff[9], gf[5];
-    pull_node<S>(src, G, C, fx, fy, ff, gf);
-    const Macro m = macro<R>(ff, gf, C);
+    R ff[9], gf[NG > 0 ? NG : 1];
+    pull_node<S, NG>(src, G, C, fx, fy, ff, gf);
+    const Macro m = macro<R, NG>(ff, gf, C);
     const double uwx = C.uw[vs][0], uwy = C.uw[vs][1];
-    const double Tb = ts >= 0 ? C.wT[ts] : m.T;
     for (int i = 0; i < 9; ++i)
         f[i] = (R)(feq_rep(i, m.rho, uwx, uwy) + ((double)ff[i] - feq_rep(i, m.rho, m.ux, m.uy)));
-    for (int i = 0; i < 5; ++i)
-        g[i] = (R)(geq_rep(i, Tb, uwx, uwy, C.varpi, C.toff) +
-                   ((double)gf[i] - geq_rep(i, m.T, m.ux, m.uy, C.varpi, C.toff)));
+    if constexpr (NG > 0) {
+        const double Tb = ts >= 0 ? C.wT[ts] : m.T;
+        for (int i = 0; i < NG; ++i)
+            g[i] = (R)(geq_rep<NG>(i, Tb, uwx, uwy, C) + ((double)gf[i] - geq_rep<NG>(i, m.T, m.ux, m.uy, C)));
+    }
+}
+
+// Pre-collision populations of any node: extrapolated on NEE walls,
+// pulled everywhere else.
+template <class S, int NG>
+__device__ __forceinline__ void load_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
+                                          typename Codec<S>::R f[9], typename Codec<S>::R g[NG > 0 ? NG : 1]) {
+    if (C.any_nee && nee_node_at(G, C, x, y)) nee_node<S, NG>(src, G, C, x, y, f, g);
+    else pull_node<S, NG>(src, G, C, x, y, f, g);
+}
+
+// Correction of the x-shifted pulls of a node in the first or last column
+// after an interior pull (which read the neighbouring row's element there):
+// NEE walls rebuild the node, periodic axes re-read the wrapped source,
+// link-wise walls apply the wall rule to the node's own opposite
+// population.
+template <class S, int NG>
+__device__ __forceinline__ void fix_x_edges(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
+                                            typename Codec<S>::R f[9], typename Codec<S>::R g[NG > 0 ? NG : 1]) {
+    using R = typename Codec<S>::R;
+    if ((x == 0 && C.nee[kLeft]) || (x == G.nx - 1 && C.nee[kRight])) {
+        nee_node<S, NG>(src, G, C, x, y, f, g);
+        return;
+    }
+    auto ld = [&](int pl, int xx, int yy, float inv) -> R {
+        return Codec<S>::load(src + (long long)pl * G.plane + (long long)yy * G.pitch + xx, inv);
+    };
+    // populations moving in +x (1, 5, 8) at x = 0 and in -x (3, 6, 7) at x = nx - 1
+    if (x == 0) {
+        if (G.px) {
+            const int xs = G.nx - 1;
+            f[1] = ld(1, xs, y, C.finv);
+            f[5] = ld(5, xs, y - 1, C.finv);
+            f[8] = ld(8, xs, y + 1, C.finv);
+            if constexpr (NG > 0) g[1] = ld(10, xs, y, C.ginv);
+            if constexpr (NG == 9) {
+                g[5] = ld(14, xs, y - 1, C.ginv);
+                g[8] = ld(17, xs, y + 1, C.ginv);
+            }
+        } else {
+            f[1] = ld(3, 0, y, C.finv) + (R)C.bbf[kLeft][1];
+            f[5] = ld(7, 0, y, C.finv) + (R)C.bbf[kLeft][5];
+            f[8] = ld(6, 0, y, C.finv) + (R)C.bbf[kLeft][8];
+            if constexpr (NG > 0) g[1] = (R)C.gsign[kLeft] * ld(12, 0, y, C.ginv) + (R)C.gconst[kLeft][1];
+            if constexpr (NG == 9) {
+                g[5] = (R)C.gsign[kLeft] * ld(16, 0, y, C.ginv) + (R)C.gconst[kLeft][5];
+                g[8] = (R)C.gsign[kLeft] * ld(15, 0, y, C.ginv) + (R)C.gconst[kLeft][8];
+            }
+        }
+    }
+    if (x == G.nx - 1) {
+        if (G.px) {
+            f[3] = ld(3, 0, y, C.finv);
+            f[6] = ld(6, 0, y - 1, C.finv);
+            f[7] = ld(7, 0, y + 1, C.finv);
+            if constexpr (NG > 0) g[3] = ld(12, 0, y, C.ginv);
+            if constexpr (NG == 9) {
+                g[6] = ld(15, 0, y - 1, C.ginv);
+                g[7] = ld(16, 0, y + 1, C.ginv);
+            }
+        } else {
+            f[3] = ld(1, x, y, C.finv) + (R)C.bbf[kRight][3];
+            f[6] = ld(8, x, y, C.finv) + (R)C.bbf[kRight][6];
+            f[7] = ld(5, x, y, C.finv) + (R)C.bbf[kRight][7];
+            if constexpr (NG > 0) g[3] = (R)C.gsign[kRight] * ld(10, x, y, C.ginv) + (R)C.gconst[kRight][3];
+            if constexpr (NG == 9) {
+                g[6] = (R)C.gsign[kRight] * ld(17, x, y, C.ginv) + (R)C.gconst[kRight][6];
+                g[7] = (R)C.gsign[kRight] * ld(14, x, y, C.ginv) + (R)C.gconst[kRight][7];
+            }
+        }
+    }
 }
 
 }  // namespace lbm

@@ -33,25 +33,25 @@ struct BatchTile {
 
 inline int storage_bytes(int storage) { return storage == kF64 ? 8 : (storage == kF32 ? 4 : 2); }
 
-hipError_t launch_sweep(int storage, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
+hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
                         void* dst, hipStream_t st);
-hipError_t launch_sweep_batch(int storage, bool buffer, const BatchMember* members, const BatchTile* tiles,
+hipError_t launch_sweep_batch(int storage, int ng, bool buffer, const BatchMember* members, const BatchTile* tiles,
                               int ntiles, int parity, hipStream_t st);
-hipError_t launch_residual_batch(int storage, const BatchMember* members, int nmembers, const BatchTile* tiles,
+hipError_t launch_residual_batch(int storage, int ng, const BatchMember* members, int nmembers, const BatchTile* tiles,
                                  int ntiles, int parity, double* tile_max, unsigned long long* tile_bad,
                                  double* out2, hipStream_t st);
-hipError_t launch_moments(int storage, const Geom& G, const Coeffs& C, const void* src, double* rho,
+hipError_t launch_moments(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, double* rho,
                           double* ux, double* uy, double* T, hipStream_t st);
-hipError_t launch_gather(int storage, const Geom& G, const Coeffs& C, const void* src, double* pf,
+hipError_t launch_gather(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, double* pf,
                          double* pg, double T0, hipStream_t st);
-hipError_t launch_unstream(int storage, const Geom& G, const Coeffs& C, void* dst, const double* pf,
+hipError_t launch_unstream(int storage, int ng, const Geom& G, const Coeffs& C, void* dst, const double* pf,
                            const double* pg, const double* Tf, double T0, bool from_temperature,
                            hipStream_t st);
-hipError_t launch_nusselt(int storage, const Geom& G, const Coeffs& C, const void* src, int side,
+hipError_t launch_nusselt(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, int side,
                           double tw, double length, double dT, int nee, double* local, double* out3,
                           hipStream_t st);
 int residual_parts(const Geom& G);
-hipError_t launch_residual(int storage, const Geom& G, const Coeffs& C, const void* src, double* snap,
+hipError_t launch_residual(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, double* snap,
                            bool update_only, double* pmax, unsigned long long* pbad, double* out2,
                            hipStream_t st);
 

@@ -1,23 +1,28 @@
-// lbm_kernels.hip -- gfx950 kernels of the D2Q9 + D2Q5 non-orthogonal MRT
-// lattice Boltzmann step and its readouts.
+// lbm_kernels.hip -- gfx950 kernels of the non-orthogonal MRT lattice
+// Boltzmann step and its readouts, for every temperature lattice NG (0, 5, 9)
+// and storage (FP64, FP32 / FP16 deviations).
 //
-//   k_sweep      fused pull-stream + walls + Boussinesq force + D2Q9 and
-//                D2Q5 collision + store (one time step, Eqs. 4, 8, 9, 24, 25)
-//   k_moments    rho, u, T at time t (Eqs. 18, 19, 27)
-//   k_gather     pre-collision populations at time t, FP64
-//   k_unstream   write a buffer whose pull yields given pre-collision
-//                populations (state restore and initial equilibrium)
-//   k_nusselt    wall Nusselt number (Eq. 39), one block, fixed-order FP64
-//   k_residual   steady-state residual and non-finite count, FP64
+//   k_sweep          fused pull-stream + walls + Boussinesq force + flow and
+//                    temperature collision + store (one time step; Eqs. 4, 8,
+//                    9, 24, 25)
+//   k_sweep_batch    the same step for every lattice of a batch
+//   k_moments        rho, u, T at time t (Eqs. 18, 19, 27)
+//   k_gather         pre-collision populations at time t, FP64
+//   k_unstream       write a buffer whose pull yields given pre-collision
+//                    populations (state restore and initial equilibrium)
+//   k_nusselt        wall Nusselt number (Eq. 39), one block, fixed-order FP64
+//   k_residual(_batch) steady-state residual and non-finite count, FP64
 //
-// All kernels read the state through pull_node / source (lbm_device.hpp),
-// so the wall rules exist in one place.
+// All kernels read the state through load_node / pull_node / source
+// (lbm_device.hpp), so the wall rules exist in one place.
 #include "lbm_internal.hpp"
 
 #include <float.h>
 #include <math.h>
 
 namespace lbm {
+
+constexpr int gdim(int NG) { return NG > 0 ? NG : 1; }
 
 // Workgroup b runs on XCD b % 8 of the MI355X.  Remap so that each XCD
 // walks a contiguous range of tiles (neighbouring tiles share cache lines of
@@ -28,38 +33,38 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-template <class S>
-__device__ __forceinline__ void store_node(S* __restrict__ dst, const Geom& G, const Coeffs& C,
-                                           unsigned boff, const typename Codec<S>::R f[9],
-                                           const typename Codec<S>::R g[5]) {
+template <class S, int NG>
+__device__ __forceinline__ void store_node(S* __restrict__ dst, const Geom& G, const Coeffs& C, unsigned boff,
+                                           const typename Codec<S>::R f[9],
+                                           const typename Codec<S>::R g[gdim(NG)]) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) Codec<S>::store(at_bytes(dst + (long long)i * G.plane, boff), f[i], C.fscale);
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < NG; ++i)
         Codec<S>::store(at_bytes(dst + (long long)(9 + i) * G.plane, boff), g[i], C.gscale);
 }
 
-template <class S>
+template <class S, int NG>
 __device__ __forceinline__ void store_node_buf(__amdgpu_buffer_rsrc_t r, const Geom& G, const Coeffs& C,
                                                unsigned boff, const typename Codec<S>::R f[9],
-                                               const typename Codec<S>::R g[5]) {
+                                               const typename Codec<S>::R g[gdim(NG)]) {
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         Buf<S>::store(r, boff, (unsigned)((long long)i * G.plane * (long long)sizeof(S)), f[i], C.fscale);
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < NG; ++i)
         Buf<S>::store(r, boff, (unsigned)((long long)(9 + i) * G.plane * (long long)sizeof(S)), g[i], C.gscale);
 }
 
 // One time step of the nodes (x, y0 .. y0 + ROWS - 1) of one lattice.
 // Fast path (wave-uniform): a wave whose 64 columns all lie in the lattice
 // and whose rows all have a row above and below reads every population
-// with one shared lane offset, all ROWS x 14 loads issued before any
+// with one shared lane offset, all ROWS x (9 + NG) loads issued before any
 // arithmetic; lanes in the first or last column then correct their
 // x-shifted pulls.  Waves touching the bottom or top row, or the ragged
 // right end, resolve walls and wraps per link.  BUF selects buffer-resource
 // addressing (buffers below 4 GiB) over global addressing.
-template <class S, int ROWS, bool BUF>
+template <class S, int NG, int ROWS, bool BUF>
 __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, const S* __restrict__ src,
                                             S* __restrict__ dst, int x, int y0, unsigned buf_bytes) {
     using R = typename Codec<S>::R;
@@ -67,63 +72,63 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
     const int yw = __builtin_amdgcn_readfirstlane(y0);
     const bool fast = xw + 63 <= G.nx - 1 && yw >= 1 && yw + ROWS - 1 <= G.ny - 2;
     if (fast) {
-        R f[ROWS][9], g[ROWS][5];
+        R f[ROWS][9], g[ROWS][gdim(NG)];
         unsigned boff[ROWS];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) boff[r] = (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S);
         if (BUF) {
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) pull_interior_buf<S>(rs, G, C, boff[r], f[r], g[r]);
+            for (int r = 0; r < ROWS; ++r) pull_interior_buf<S, NG>(rs, G, C, boff[r], f[r], g[r]);
         } else {
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) pull_interior<S>(src, G, C, boff[r], f[r], g[r]);
+            for (int r = 0; r < ROWS; ++r) pull_interior<S, NG>(src, G, C, boff[r], f[r], g[r]);
         }
         if (xw == 0 || xw + 63 == G.nx - 1) {
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) fix_x_edges<S>(src, G, C, x, y0 + r, f[r], g[r]);
+            for (int r = 0; r < ROWS; ++r) fix_x_edges<S, NG>(src, G, C, x, y0 + r, f[r], g[r]);
         }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-            const Macro m = macro<R>(f[r], g[r], C);
-            collide<R>(f[r], g[r], m, C);
-            if (BUF) store_node_buf<S>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
-            else store_node<S>(dst, G, C, boff[r], f[r], g[r]);
+            const Macro m = macro<R, NG>(f[r], g[r], C);
+            collide<R, NG>(f[r], g[r], m, C);
+            if (BUF) store_node_buf<S, NG>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
+            else store_node<S, NG>(dst, G, C, boff[r], f[r], g[r]);
         }
         return;
     }
     if (x >= G.nx) return;
-    R f[ROWS][9], g[ROWS][5];
+    R f[ROWS][9], g[ROWS][gdim(NG)];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r)
-        if (y0 + r < G.ny) load_node<S>(src, G, C, x, y0 + r, f[r], g[r]);
+        if (y0 + r < G.ny) load_node<S, NG>(src, G, C, x, y0 + r, f[r], g[r]);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         if (y0 + r < G.ny) {
-            const Macro m = macro<R>(f[r], g[r], C);
-            collide<R>(f[r], g[r], m, C);
-            store_node<S>(dst, G, C, (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S), f[r], g[r]);
+            const Macro m = macro<R, NG>(f[r], g[r], C);
+            collide<R, NG>(f[r], g[r], m, C);
+            store_node<S, NG>(dst, G, C, (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S), f[r], g[r]);
         }
     }
 }
 
 // One time step of one lattice: tiles of blockDim.x x (blockDim.y * ROWS)
 // nodes, walked XCD by XCD.
-template <class S, int ROWS, bool BUF>
+template <class S, int NG, int ROWS, bool BUF>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
                                                S* __restrict__ dst, int tiles_x, unsigned buf_bytes) {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x = tx * blockDim.x + threadIdx.x;
     const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
-    sweep_nodes<S, ROWS, BUF>(G, C, src, dst, x, y0, buf_bytes);
+    sweep_nodes<S, NG, ROWS, BUF>(G, C, src, dst, x, y0, buf_bytes);
 }
 
 // One time step of every lattice of a batch.  Each workgroup of 256
 // threads takes one entry of the tile table: a member lattice and a tile
 // of bx x (256 / bx) nodes at (x0, y0).  Member m reads buffer
 // (cur0 + parity) & 1 and writes the other one.
-template <class S, bool BUF>
+template <class S, int NG, bool BUF>
 __global__ __launch_bounds__(256) void k_sweep_batch(const BatchMember* __restrict__ members,
                                                      const BatchTile* __restrict__ tiles, int parity) {
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
@@ -133,20 +138,20 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const BatchMember* __restri
     S* dst = static_cast<S*>(M.buf[sel ^ 1]);
     const int x = t.x0 + (int)(threadIdx.x % (unsigned)t.bx);
     const int y = t.y0 + (int)(threadIdx.x / (unsigned)t.bx);
-    sweep_nodes<S, 1, BUF>(M.G, M.C, src, dst, x, y, M.buf_bytes);
+    sweep_nodes<S, NG, 1, BUF>(M.G, M.C, src, dst, x, y, M.buf_bytes);
 }
 
-template <class S>
-__global__ __launch_bounds__(256) void k_moments(Geom G, Coeffs C, const S* __restrict__ src,
-                                                 double* rho, double* ux, double* uy, double* T) {
+template <class S, int NG>
+__global__ __launch_bounds__(256) void k_moments(Geom G, Coeffs C, const S* __restrict__ src, double* rho,
+                                                 double* ux, double* uy, double* T) {
     using R = typename Codec<S>::R;
     const long long n = (long long)G.nx * G.ny;
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int x = (int)(k % G.nx), y = (int)(k / G.nx);
-    R f[9], g[5];
-    load_node<S>(src, G, C, x, y, f, g);
-    const Macro m = macro<R>(f, g, C);
+    R f[9], g[gdim(NG)];
+    load_node<S, NG>(src, G, C, x, y, f, g);
+    const Macro m = macro<R, NG>(f, g, C);
     if (rho) rho[k] = Codec<S>::kDev ? 1.0 + m.rho : m.rho;
     if (ux) ux[k] = m.ux;
     if (uy) uy[k] = m.uy;
@@ -154,30 +159,30 @@ __global__ __launch_bounds__(256) void k_moments(Geom G, Coeffs C, const S* __re
 }
 
 // Rest populations that deviation storage subtracts: w_i rho0 for fbar,
-// g_i^eq(T0, 0) (Eq. 30) for g.
-__device__ __forceinline__ double rest_f(int i) {
-    return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
-}
-__device__ __forceinline__ double rest_g(int i, double T0, double varpi) {
-    return i == 0 ? (1.0 - varpi) * T0 : 0.25 * varpi * T0;
+// g_i^eq(T0, 0) for g (Eq. 30 for D2Q5, Eq. 31 for D2Q9).
+__device__ __forceinline__ double rest_f(int i) { return w9(i); }
+template <int NG>
+__device__ __forceinline__ double rest_g(int i, double T, double varpi) {
+    if constexpr (NG == 5) return i == 0 ? (1.0 - varpi) * T : 0.25 * varpi * T;
+    else return w9(i) * T;
 }
 
-template <class S>
-__global__ __launch_bounds__(256) void k_gather(Geom G, Coeffs C, const S* __restrict__ src,
-                                                double* pf, double* pg, double T0) {
+template <class S, int NG>
+__global__ __launch_bounds__(256) void k_gather(Geom G, Coeffs C, const S* __restrict__ src, double* pf,
+                                                double* pg, double T0) {
     using R = typename Codec<S>::R;
     const long long n = (long long)G.nx * G.ny;
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int x = (int)(k % G.nx), y = (int)(k / G.nx);
-    R f[9], g[5];
-    load_node<S>(src, G, C, x, y, f, g);
+    R f[9], g[gdim(NG)];
+    load_node<S, NG>(src, G, C, x, y, f, g);
     constexpr bool dev = Codec<S>::kDev;
     if (pf)
         for (int i = 0; i < 9; ++i) pf[i * n + k] = dev ? rest_f(i) + (double)f[i] : (double)f[i];
     if (pg)
-        for (int i = 0; i < 5; ++i)
-            pg[i * n + k] = dev ? rest_g(i, T0, C.varpi) + (double)g[i] : (double)g[i];
+        for (int i = 0; i < NG; ++i)
+            pg[i * n + k] = dev ? rest_g<NG>(i, T0, C.varpi) + (double)g[i] : (double)g[i];
 }
 
 // Destination of the stored entry (i, x, y) under the pull: the node
@@ -202,8 +207,8 @@ __device__ __forceinline__ int target(const Geom& G, int x, int y, int& tx, int&
 // Pre-collision value of population i at node k, in the stored
 // representation (full for FP64, deviation otherwise).
 // MODE 0: from FP64 arrays pf/pg ([i][node]); MODE 1: rest equilibrium
-// with the temperature field Tf (or T0 if Tf is null), Eqs. 22 and 30.
-template <bool DEV, int MODE>
+// with the temperature field Tf (or T0 if Tf is null), Eqs. 22, 30, 31.
+template <bool DEV, int NG, int MODE>
 struct PreValue {
     const double *pf, *pg, *Tf;
     long long n;
@@ -213,58 +218,76 @@ struct PreValue {
         return DEV ? 0.0 : rest_f(i);
     }
     __device__ double g(int i, long long k) const {
-        if (MODE == 0) return DEV ? pg[i * n + k] - rest_g(i, T0, varpi) : pg[i * n + k];
+        if (MODE == 0) return DEV ? pg[i * n + k] - rest_g<NG>(i, T0, varpi) : pg[i * n + k];
         const double T = Tf ? Tf[k] : T0;
-        const double v = DEV ? T - T0 : T;
-        return i == 0 ? (1.0 - varpi) * v : 0.25 * varpi * v;
+        return rest_g<NG>(i, DEV ? T - T0 : T, varpi);
     }
 };
 
-template <class S, int MODE>
-__global__ __launch_bounds__(256) void k_unstream(Geom G, Coeffs C, S* __restrict__ dst,
-                                                  const double* pf, const double* pg,
-                                                  const double* Tf, double T0) {
+template <class S, int NG, int MODE, int I>
+__device__ __forceinline__ void unstream_f(S* __restrict__ dst, const Geom& G, const Coeffs& C,
+                                           const PreValue<Codec<S>::kDev, NG, MODE>& pv, int x, int y, long long k,
+                                           long long o) {
+    using R = typename Codec<S>::R;
+    int tx, ty;
+    const int side = target<I>(G, x, y, tx, ty);
+    const double v = side < 0 ? pv.f(I, (long long)ty * G.nx + tx) : pv.f(opp(I), k) - C.bbf[side][opp(I)];
+    Codec<S>::store(dst + (long long)I * G.plane + o, (R)v, C.fscale);
+}
+
+template <class S, int NG, int MODE, int I>
+__device__ __forceinline__ void unstream_g(S* __restrict__ dst, const Geom& G, const Coeffs& C,
+                                           const PreValue<Codec<S>::kDev, NG, MODE>& pv, int x, int y, long long k,
+                                           long long o) {
+    using R = typename Codec<S>::R;
+    int tx, ty;
+    const int side = target<I>(G, x, y, tx, ty);
+    const double v = side < 0 ? pv.g(I, (long long)ty * G.nx + tx)
+                              : (pv.g(opp(I), k) - C.gconst[side][opp(I)]) * C.gsign[side];
+    Codec<S>::store(dst + (long long)(9 + I) * G.plane + o, (R)v, C.gscale);
+}
+
+template <class S, int NG, int MODE>
+__global__ __launch_bounds__(256) void k_unstream(Geom G, Coeffs C, S* __restrict__ dst, const double* pf,
+                                                  const double* pg, const double* Tf, double T0) {
     using R = typename Codec<S>::R;
     const long long n = (long long)G.nx * G.ny;
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int x = (int)(k % G.nx), y = (int)(k / G.nx);
     const long long o = (long long)y * G.pitch + x;
-    PreValue<Codec<S>::kDev, MODE> pv{pf, pg, Tf, n, T0, C.varpi};
+    const PreValue<Codec<S>::kDev, NG, MODE> pv{pf, pg, Tf, n, T0, C.varpi};
     Codec<S>::store(dst + o, (R)pv.f(0, k), C.fscale);
-#define LBM_UNSTREAM_F(I)                                                          \
-    {                                                                              \
-        int tx, ty;                                                                \
-        const int side = target<I>(G, x, y, tx, ty);                              \
-        double v = side < 0 ? pv.f(I, (long long)ty * G.nx + tx)                   \
-                            : pv.f(opp(I), k) - C.bbf[side][opp(I)];               \
-        Codec<S>::store(dst + (long long)I * G.plane + o, (R)v, C.fscale);         \
+    unstream_f<S, NG, MODE, 1>(dst, G, C, pv, x, y, k, o);
+    unstream_f<S, NG, MODE, 2>(dst, G, C, pv, x, y, k, o);
+    unstream_f<S, NG, MODE, 3>(dst, G, C, pv, x, y, k, o);
+    unstream_f<S, NG, MODE, 4>(dst, G, C, pv, x, y, k, o);
+    unstream_f<S, NG, MODE, 5>(dst, G, C, pv, x, y, k, o);
+    unstream_f<S, NG, MODE, 6>(dst, G, C, pv, x, y, k, o);
+    unstream_f<S, NG, MODE, 7>(dst, G, C, pv, x, y, k, o);
+    unstream_f<S, NG, MODE, 8>(dst, G, C, pv, x, y, k, o);
+    if constexpr (NG > 0) {
+        Codec<S>::store(dst + 9 * G.plane + o, (R)pv.g(0, k), C.gscale);
+        unstream_g<S, NG, MODE, 1>(dst, G, C, pv, x, y, k, o);
+        unstream_g<S, NG, MODE, 2>(dst, G, C, pv, x, y, k, o);
+        unstream_g<S, NG, MODE, 3>(dst, G, C, pv, x, y, k, o);
+        unstream_g<S, NG, MODE, 4>(dst, G, C, pv, x, y, k, o);
     }
-#define LBM_UNSTREAM_G(I)                                                          \
-    {                                                                              \
-        int tx, ty;                                                                \
-        const int side = target<I>(G, x, y, tx, ty);                              \
-        double v = side < 0 ? pv.g(I, (long long)ty * G.nx + tx)                   \
-                            : (pv.g(opp(I), k) - C.gconst[side]) * C.gsign[side];  \
-        Codec<S>::store(dst + (long long)(9 + I) * G.plane + o, (R)v, C.gscale);   \
+    if constexpr (NG == 9) {
+        unstream_g<S, NG, MODE, 5>(dst, G, C, pv, x, y, k, o);
+        unstream_g<S, NG, MODE, 6>(dst, G, C, pv, x, y, k, o);
+        unstream_g<S, NG, MODE, 7>(dst, G, C, pv, x, y, k, o);
+        unstream_g<S, NG, MODE, 8>(dst, G, C, pv, x, y, k, o);
     }
-    LBM_UNSTREAM_F(1) LBM_UNSTREAM_F(2) LBM_UNSTREAM_F(3) LBM_UNSTREAM_F(4)
-    LBM_UNSTREAM_F(5) LBM_UNSTREAM_F(6) LBM_UNSTREAM_F(7) LBM_UNSTREAM_F(8)
-    Codec<S>::store(dst + 9 * G.plane + o, (R)pv.g(0, k), C.gscale);
-    LBM_UNSTREAM_G(1) LBM_UNSTREAM_G(2) LBM_UNSTREAM_G(3) LBM_UNSTREAM_G(4)
-#undef LBM_UNSTREAM_F
-#undef LBM_UNSTREAM_G
 }
 
-// Temperature at a node from its pulled D2Q5 populations.
-template <class S>
-__device__ __forceinline__ double node_T(const S* __restrict__ src, const Geom& G, const Coeffs& C,
-                                         int x, int y) {
+// Temperature at a node from its (pulled or extrapolated) populations.
+template <class S, int NG>
+__device__ __forceinline__ double node_T(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y) {
     using R = typename Codec<S>::R;
-    R f[9], g[5];
-    load_node<S>(src, G, C, x, y, f, g);
-    const double s = (((double)g[0] + (double)g[1]) + ((double)g[2] + (double)g[3])) + (double)g[4];
-    return s + C.toff;
+    R f[9], g[gdim(NG)];
+    load_node<S, NG>(src, G, C, x, y, f, g);
+    return macro<R, NG>(f, g, C).T;
 }
 
 // Fixed-order block reductions (wave64 shuffles, then LDS in wave order).
@@ -286,10 +309,9 @@ __device__ __forceinline__ void wave_maxloc(double& v, int& i) {
 // Link-wise walls: wall half a spacing outside node 1, dT/dn from
 // (9 T1 - T2 - 8 Tw) / 3, midpoint mean.  NEE walls (nee = 1): wall through
 // node 0, dT/dn from (-3 T0 + 4 T1 - T2) / 2, trapezoidal mean.
-template <class S>
-__global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __restrict__ src,
-                                                 int side, double tw, double length, double dT,
-                                                 int nee, double* local, double* out) {
+template <class S, int NG>
+__global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __restrict__ src, int side, double tw,
+                                                 double length, double dT, int nee, double* local, double* out) {
     __shared__ double s_sum[4], s_max[4];
     __shared__ int s_idx[4];
     const int count = (side == kLeft || side == kRight) ? G.ny : G.nx;
@@ -304,7 +326,7 @@ __global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __re
             else if (side == kRight) { x = G.nx - 1 - d; y = k; }
             else if (side == kBottom) { x = k; y = d; }
             else { x = k; y = G.ny - 1 - d; }
-            t[d] = node_T<S>(src, G, C, x, y);
+            t[d] = node_T<S, NG>(src, G, C, x, y);
         }
         const double dtdn = nee ? (-3.0 * t[0] + 4.0 * t[1] - t[2]) / 2.0 : (9.0 * t[0] - t[1] - 8.0 * tw) / 3.0;
         const double nu = -length * (sign * dtdn) / dT;
@@ -331,30 +353,31 @@ __global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __re
     }
 }
 
-template <class S>
-__global__ __launch_bounds__(256) void k_residual(Geom G, Coeffs C, const S* __restrict__ src,
-                                                  double* snap, int update_only, double* pmax,
-                                                  unsigned long long* pbad) {
+// Residual of one node against its snapshot (which it then replaces):
+// max(|ux - ux'|, |uy - uy'|, |T - T'|), and whether rho, u, T are finite.
+template <class S, int NG>
+__device__ __forceinline__ void residual_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x,
+                                              int y, double* snap, bool update_only, double& d,
+                                              unsigned long long& bad) {
     using R = typename Codec<S>::R;
+    const long long n = (long long)G.nx * G.ny, k = (long long)y * G.nx + x;
+    R f[9], g[gdim(NG)];
+    load_node<S, NG>(src, G, C, x, y, f, g);
+    const Macro m = macro<R, NG>(f, g, C);
+    const bool fin = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.T);
+    bad = fin ? 0ull : 1ull;
+    d = 0.0;
+    if (!update_only && fin)
+        d = fmax(fmax(fabs(m.ux - snap[k]), fabs(m.uy - snap[n + k])), fabs(m.T - snap[2 * n + k]));
+    snap[k] = m.ux;
+    snap[n + k] = m.uy;
+    snap[2 * n + k] = m.T;
+}
+
+// Block max / sum of (d, bad) in a fixed order; lane 0 of wave 0 returns it.
+__device__ __forceinline__ void block_maxsum(double& d, unsigned long long& bad) {
     __shared__ double s_max[4];
     __shared__ unsigned long long s_bad[4];
-    const long long n = (long long)G.nx * G.ny;
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double d = 0.0;
-    unsigned long long bad = 0;
-    if (k < n) {
-        const int x = (int)(k % G.nx), y = (int)(k / G.nx);
-        R f[9], g[5];
-        load_node<S>(src, G, C, x, y, f, g);
-        const Macro m = macro<R>(f, g, C);
-        const bool fin = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.T);
-        bad = fin ? 0ull : 1ull;
-        if (!update_only && fin)
-            d = fmax(fmax(fabs(m.ux - snap[k]), fabs(m.uy - snap[n + k])), fabs(m.T - snap[2 * n + k]));
-        snap[k] = m.ux;
-        snap[n + k] = m.uy;
-        snap[2 * n + k] = m.T;
-    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         d = fmax(d, __shfl_down(d, o, 64));
@@ -368,32 +391,35 @@ __global__ __launch_bounds__(256) void k_residual(Geom G, Coeffs C, const S* __r
         unsigned long long b = 0;
         const int nw = (blockDim.x + 63) >> 6;
         for (int w = 0; w < nw; ++w) { t = fmax(t, s_max[w]); b += s_bad[w]; }
-        pmax[blockIdx.x] = t;
-        pbad[blockIdx.x] = b;
+        d = t;
+        bad = b;
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_final(const double* pmax, const unsigned long long* pbad,
-                                                      int nparts, double* out) {
-    __shared__ double s_max[4];
-    __shared__ unsigned long long s_bad[4];
+template <class S, int NG>
+__global__ __launch_bounds__(256) void k_residual(Geom G, Coeffs C, const S* __restrict__ src, double* snap,
+                                                  int update_only, double* pmax, unsigned long long* pbad) {
+    const long long n = (long long)G.nx * G.ny;
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double d = 0.0;
+    unsigned long long bad = 0;
+    if (k < n) residual_node<S, NG>(src, G, C, (int)(k % G.nx), (int)(k / G.nx), snap, update_only != 0, d, bad);
+    block_maxsum(d, bad);
+    if (threadIdx.x == 0) {
+        pmax[blockIdx.x] = d;
+        pbad[blockIdx.x] = bad;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* pmax, const unsigned long long* pbad, int nparts,
+                                                      double* out) {
     double d = 0.0;
     unsigned long long b = 0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) { d = fmax(d, pmax[i]); b += pbad[i]; }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        d = fmax(d, __shfl_down(d, o, 64));
-        b += __shfl_down(b, o, 64);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) { s_max[wave] = d; s_bad[wave] = b; }
-    __syncthreads();
+    block_maxsum(d, b);
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        unsigned long long bb = 0;
-        for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) { t = fmax(t, s_max[w]); bb += s_bad[w]; }
-        out[0] = t;
-        out[1] = (double)bb;
+        out[0] = d;
+        out[1] = (double)b;
     }
 }
 
@@ -401,13 +427,10 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* pmax, const 
 // maxima and non-finite counts per tile, then one workgroup per member
 // reduces its contiguous range of tiles (fixed order) into out2[2 m],
 // out2[2 m + 1].
-template <class S>
+template <class S, int NG>
 __global__ __launch_bounds__(256) void k_residual_batch(const BatchMember* __restrict__ members,
                                                         const BatchTile* __restrict__ tiles, int parity,
                                                         double* tile_max, unsigned long long* tile_bad) {
-    using R = typename Codec<S>::R;
-    __shared__ double s_max[4];
-    __shared__ unsigned long long s_bad[4];
     const int ti = blockIdx.x;
     const BatchTile t = tiles[ti];
     const BatchMember& M = members[t.member];
@@ -416,42 +439,17 @@ __global__ __launch_bounds__(256) void k_residual_batch(const BatchMember* __res
     const int y = t.y0 + (int)(threadIdx.x / (unsigned)t.bx);
     double d = 0.0;
     unsigned long long bad = 0;
-    if (x < M.G.nx && y < M.G.ny) {
-        const long long n = (long long)M.G.nx * M.G.ny, k = (long long)y * M.G.nx + x;
-        R f[9], g[5];
-        load_node<S>(src, M.G, M.C, x, y, f, g);
-        const Macro m = macro<R>(f, g, M.C);
-        const bool fin = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.T);
-        bad = fin ? 0ull : 1ull;
-        double* snap = M.snap;
-        if (fin)
-            d = fmax(fmax(fabs(m.ux - snap[k]), fabs(m.uy - snap[n + k])), fabs(m.T - snap[2 * n + k]));
-        snap[k] = m.ux;
-        snap[n + k] = m.uy;
-        snap[2 * n + k] = m.T;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        d = fmax(d, __shfl_down(d, o, 64));
-        bad += __shfl_down(bad, o, 64);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) { s_max[wave] = d; s_bad[wave] = bad; }
-    __syncthreads();
+    if (x < M.G.nx && y < M.G.ny) residual_node<S, NG>(src, M.G, M.C, x, y, M.snap, false, d, bad);
+    block_maxsum(d, bad);
     if (threadIdx.x == 0) {
-        double tm = 0.0;
-        unsigned long long b = 0;
-        for (int w = 0; w < 4; ++w) { tm = fmax(tm, s_max[w]); b += s_bad[w]; }
-        tile_max[ti] = tm;
-        tile_bad[ti] = b;
+        tile_max[ti] = d;
+        tile_bad[ti] = bad;
     }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_members(const BatchMember* __restrict__ members,
-                                                        const double* tile_max,
-                                                        const unsigned long long* tile_bad, double* out2) {
-    __shared__ double s_max[4];
-    __shared__ unsigned long long s_bad[4];
+                                                        const double* tile_max, const unsigned long long* tile_bad,
+                                                        double* out2) {
     const BatchMember& M = members[blockIdx.x];
     double d = 0.0;
     unsigned long long b = 0;
@@ -459,20 +457,10 @@ __global__ __launch_bounds__(256) void k_reduce_members(const BatchMember* __res
         d = fmax(d, tile_max[M.tile0 + i]);
         b += tile_bad[M.tile0 + i];
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        d = fmax(d, __shfl_down(d, o, 64));
-        b += __shfl_down(b, o, 64);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) { s_max[wave] = d; s_bad[wave] = b; }
-    __syncthreads();
+    block_maxsum(d, b);
     if (threadIdx.x == 0) {
-        double tm = 0.0;
-        unsigned long long bb = 0;
-        for (int w = 0; w < 4; ++w) { tm = fmax(tm, s_max[w]); bb += s_bad[w]; }
-        out2[2 * blockIdx.x] = tm;
-        out2[2 * blockIdx.x + 1] = (double)bb;
+        out2[2 * blockIdx.x] = d;
+        out2[2 * blockIdx.x + 1] = (double)b;
     }
 }
 
@@ -481,17 +469,32 @@ __global__ __launch_bounds__(256) void k_reduce_members(const BatchMember* __res
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
 
-template <class S, bool BUF>
+// Runs the statement with S (storage type) and NG (temperature lattice) bound.
+#define LBM_DISPATCH(storage, ng, ...)                                                    \
+    switch ((storage) * 16 + (ng)) {                                                      \
+        case kF64 * 16 + 0: { using S = double; constexpr int NG = 0; __VA_ARGS__; } break; \
+        case kF64 * 16 + 5: { using S = double; constexpr int NG = 5; __VA_ARGS__; } break; \
+        case kF64 * 16 + 9: { using S = double; constexpr int NG = 9; __VA_ARGS__; } break; \
+        case kF32 * 16 + 0: { using S = float; constexpr int NG = 0; __VA_ARGS__; } break;  \
+        case kF32 * 16 + 5: { using S = float; constexpr int NG = 5; __VA_ARGS__; } break;  \
+        case kF32 * 16 + 9: { using S = float; constexpr int NG = 9; __VA_ARGS__; } break;  \
+        case kF16 * 16 + 0: { using S = __half; constexpr int NG = 0; __VA_ARGS__; } break; \
+        case kF16 * 16 + 5: { using S = __half; constexpr int NG = 5; __VA_ARGS__; } break; \
+        case kF16 * 16 + 9: { using S = __half; constexpr int NG = 9; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;                                             \
+    }
+
+template <class S, int NG, bool BUF>
 static void sweep_launch(int rows, dim3 grid, dim3 block, hipStream_t st, const Geom& G, const Coeffs& C,
                          const S* s, S* d, int tiles_x, unsigned bytes) {
     switch (rows) {
-        case 1: hipLaunchKernelGGL((k_sweep<S, 1, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
-        case 2: hipLaunchKernelGGL((k_sweep<S, 2, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
-        default: hipLaunchKernelGGL((k_sweep<S, 4, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
+        case 1: hipLaunchKernelGGL((k_sweep<S, NG, 1, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
+        case 2: hipLaunchKernelGGL((k_sweep<S, NG, 2, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
+        default: hipLaunchKernelGGL((k_sweep<S, NG, 4, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
     }
 }
 
-template <class S>
+template <class S, int NG>
 static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const void* src, void* dst,
                           hipStream_t st) {
     const int rows = L.rows;
@@ -501,113 +504,85 @@ static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const
     const int nt = tiles_x * tiles_y;
     const S* s = static_cast<const S*>(src);
     S* d = static_cast<S*>(dst);
-    const unsigned long long bytes = 14ull * (unsigned long long)G.plane * sizeof(S);
+    const unsigned long long bytes = (unsigned long long)(9 + NG) * (unsigned long long)G.plane * sizeof(S);
     if (L.buffer && bytes < (1ull << 32))
-        sweep_launch<S, true>(rows, dim3(nt), dim3(L.bx, L.by), st, G, C, s, d, tiles_x, (unsigned)bytes);
+        sweep_launch<S, NG, true>(rows, dim3(nt), dim3(L.bx, L.by), st, G, C, s, d, tiles_x, (unsigned)bytes);
     else
-        sweep_launch<S, false>(rows, dim3(nt), dim3(L.bx, L.by), st, G, C, s, d, tiles_x, 0u);
+        sweep_launch<S, NG, false>(rows, dim3(nt), dim3(L.bx, L.by), st, G, C, s, d, tiles_x, 0u);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int storage, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
+hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
                         void* dst, hipStream_t st) {
-    switch (storage) {
-        case kF64: return sweep_t<double>(L, G, C, src, dst, st);
-        case kF32: return sweep_t<float>(L, G, C, src, dst, st);
-        case kF16: return sweep_t<__half>(L, G, C, src, dst, st);
-    }
-    return hipErrorInvalidValue;
+    LBM_DISPATCH(storage, ng, { hipError_t e = sweep_t<S, NG>(L, G, C, src, dst, st); if (e != hipSuccess) return e; });
+    return hipSuccess;
 }
 
-#define LBM_DISPATCH(storage, CALL)                                  \
-    switch (storage) {                                              \
-        case kF64: { using S = double; CALL; } break;               \
-        case kF32: { using S = float; CALL; } break;                \
-        case kF16: { using S = __half; CALL; } break;               \
-        default: return hipErrorInvalidValue;                       \
-    }
-
-hipError_t launch_sweep_batch(int storage, bool buffer, const BatchMember* members, const BatchTile* tiles,
+hipError_t launch_sweep_batch(int storage, int ng, bool buffer, const BatchMember* members, const BatchTile* tiles,
                               int ntiles, int parity, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    switch (storage) {
-        case kF64:
-            if (buffer) hipLaunchKernelGGL((k_sweep_batch<double, true>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
-            else hipLaunchKernelGGL((k_sweep_batch<double, false>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
-            break;
-        case kF32:
-            if (buffer) hipLaunchKernelGGL((k_sweep_batch<float, true>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
-            else hipLaunchKernelGGL((k_sweep_batch<float, false>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
-            break;
-        case kF16:
-            if (buffer) hipLaunchKernelGGL((k_sweep_batch<__half, true>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
-            else hipLaunchKernelGGL((k_sweep_batch<__half, false>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
-            break;
-        default: return hipErrorInvalidValue;
-    }
+    LBM_DISPATCH(storage, ng, {
+        if (buffer) hipLaunchKernelGGL((k_sweep_batch<S, NG, true>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+        else hipLaunchKernelGGL((k_sweep_batch<S, NG, false>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+    });
     return hipGetLastError();
 }
 
-hipError_t launch_residual_batch(int storage, const BatchMember* members, int nmembers, const BatchTile* tiles,
-                                 int ntiles, int parity, double* tile_max, unsigned long long* tile_bad,
-                                 double* out2, hipStream_t st) {
+hipError_t launch_residual_batch(int storage, int ng, const BatchMember* members, int nmembers,
+                                 const BatchTile* tiles, int ntiles, int parity, double* tile_max,
+                                 unsigned long long* tile_bad, double* out2, hipStream_t st) {
     if (ntiles <= 0 || nmembers <= 0) return hipSuccess;
-    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_residual_batch<S>), dim3(ntiles), dim3(256), 0, st, members, tiles,
-                                             parity, tile_max, tile_bad));
+    LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_residual_batch<S, NG>), dim3(ntiles), dim3(256), 0, st, members,
+                                                 tiles, parity, tile_max, tile_bad));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_members, dim3(nmembers), dim3(256), 0, st, members, tile_max, tile_bad, out2);
     return hipGetLastError();
 }
 
-hipError_t launch_moments(int storage, const Geom& G, const Coeffs& C, const void* src, double* rho,
+hipError_t launch_moments(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, double* rho,
                           double* ux, double* uy, double* T, hipStream_t st) {
     const long long n = (long long)G.nx * G.ny;
-    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_moments<S>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                                             G, C, static_cast<const S*>(src), rho, ux, uy, T));
+    LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_moments<S, NG>), dim3(blocks_for(n, 256)), dim3(256), 0, st, G, C,
+                                                 static_cast<const S*>(src), rho, ux, uy, T));
     return hipGetLastError();
 }
 
-hipError_t launch_gather(int storage, const Geom& G, const Coeffs& C, const void* src, double* pf,
+hipError_t launch_gather(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, double* pf,
                          double* pg, double T0, hipStream_t st) {
     const long long n = (long long)G.nx * G.ny;
-    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_gather<S>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                                             G, C, static_cast<const S*>(src), pf, pg, T0));
+    LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_gather<S, NG>), dim3(blocks_for(n, 256)), dim3(256), 0, st, G, C,
+                                                 static_cast<const S*>(src), pf, pg, T0));
     return hipGetLastError();
 }
 
-hipError_t launch_unstream(int storage, const Geom& G, const Coeffs& C, void* dst, const double* pf,
-                           const double* pg, const double* Tf, double T0, bool from_temperature,
-                           hipStream_t st) {
+hipError_t launch_unstream(int storage, int ng, const Geom& G, const Coeffs& C, void* dst, const double* pf,
+                           const double* pg, const double* Tf, double T0, bool from_temperature, hipStream_t st) {
     const long long n = (long long)G.nx * G.ny;
     if (from_temperature) {
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_unstream<S, 1>), dim3(blocks_for(n, 256)), dim3(256),
-                                                 0, st, G, C, static_cast<S*>(dst), pf, pg, Tf, T0));
+        LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_unstream<S, NG, 1>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                                                     G, C, static_cast<S*>(dst), pf, pg, Tf, T0));
     } else {
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_unstream<S, 0>), dim3(blocks_for(n, 256)), dim3(256),
-                                                 0, st, G, C, static_cast<S*>(dst), pf, pg, Tf, T0));
+        LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_unstream<S, NG, 0>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                                                     G, C, static_cast<S*>(dst), pf, pg, Tf, T0));
     }
     return hipGetLastError();
 }
 
-hipError_t launch_nusselt(int storage, const Geom& G, const Coeffs& C, const void* src, int side,
-                          double tw, double length, double dT, int nee, double* local, double* out3,
-                          hipStream_t st) {
-    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_nusselt<S>), dim3(1), dim3(256), 0, st, G, C,
-                                             static_cast<const S*>(src), side, tw, length, dT, nee, local,
-                                             out3));
+hipError_t launch_nusselt(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, int side, double tw,
+                          double length, double dT, int nee, double* local, double* out3, hipStream_t st) {
+    LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_nusselt<S, NG>), dim3(1), dim3(256), 0, st, G, C,
+                                                 static_cast<const S*>(src), side, tw, length, dT, nee, local, out3));
     return hipGetLastError();
 }
 
 int residual_parts(const Geom& G) { return blocks_for((long long)G.nx * G.ny, 256); }
 
-hipError_t launch_residual(int storage, const Geom& G, const Coeffs& C, const void* src, double* snap,
-                           bool update_only, double* pmax, unsigned long long* pbad, double* out2,
-                           hipStream_t st) {
+hipError_t launch_residual(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, double* snap,
+                           bool update_only, double* pmax, unsigned long long* pbad, double* out2, hipStream_t st) {
     const int nb = residual_parts(G);
-    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_residual<S>), dim3(nb), dim3(256), 0, st, G, C,
-                                             static_cast<const S*>(src), snap, update_only ? 1 : 0,
-                                             pmax, pbad));
+    LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_residual<S, NG>), dim3(nb), dim3(256), 0, st, G, C,
+                                                 static_cast<const S*>(src), snap, update_only ? 1 : 0, pmax, pbad));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, pmax, pbad, nb, out2);

@@ -27,7 +27,10 @@ LBM_LEFT, LBM_RIGHT, LBM_BOTTOM, LBM_TOP = 0, 1, 2, 3
 LBM_BC_PERIODIC, LBM_BC_WALL, LBM_BC_NEE = 0, 1, 2
 LBM_T_PERIODIC, LBM_T_DIRICHLET, LBM_T_ADIABATIC, LBM_T_NEE_DIRICHLET, LBM_T_NEE_ADIABATIC = 0, 1, 2, 3, 4
 
+LBM_MODEL_D2Q5, LBM_MODEL_D2Q9T, LBM_MODEL_ISOTHERMAL = 0, 1, 2
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16}
+MODEL = {"d2q5": LBM_MODEL_D2Q5, "d2q9t": LBM_MODEL_D2Q9T, "isothermal": LBM_MODEL_ISOTHERMAL}
+MODEL_NG = {LBM_MODEL_D2Q5: 5, LBM_MODEL_D2Q9T: 9, LBM_MODEL_ISOTHERMAL: 0}
 _CODES = {-1: "LBM_ERR_ARG", -2: "LBM_ERR_NOMEM", -3: "LBM_ERR_DEVICE", -4: "LBM_ERR_STATE",
           -5: "LBM_ERR_UNSTABLE", -6: "LBM_ERR_UNSUPPORTED"}
 
@@ -45,6 +48,7 @@ class LbmParams(ctypes.Structure):
         ("length", ctypes.c_double), ("t_hot", ctypes.c_double), ("t_cold", ctypes.c_double),
         ("s_e", ctypes.c_double), ("s_q", ctypes.c_double), ("s_eps", ctypes.c_double),
         ("zeta_e", ctypes.c_double), ("zeta_nu", ctypes.c_double), ("varpi", ctypes.c_double),
+        ("zeta_q", ctypes.c_double), ("zeta_eps", ctypes.c_double), ("theta", ctypes.c_double),
         ("s_nu", ctypes.c_double), ("zeta_alpha", ctypes.c_double),
         ("ax", ctypes.c_double), ("ay", ctypes.c_double),
         ("bc_flow", ctypes.c_int32 * 4), ("bc_temp", ctypes.c_int32 * 4),
@@ -59,11 +63,12 @@ _SIGS = {
     "lbm_params_default": (None, [ctypes.POINTER(LbmParams)]),
     "lbm_abi_version": (ctypes.c_int32, []),
     "lbm_build_info": (ctypes.c_char_p, []),
-    "lbm_required_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+    "lbm_required_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_uint64)]),
-    "lbm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P]),
+    "lbm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, _P]),
     "lbm_create_ext": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                      _P, ctypes.c_uint64, _P]),
+                                      ctypes.c_int32, _P, ctypes.c_uint64, _P]),
     "lbm_set_params": (ctypes.c_int, [_P, ctypes.POINTER(LbmParams)]),
     "lbm_get_derived": (ctypes.c_int, [_P, _D, _D, _D, _D, _D, _D]),
     "lbm_init_temperature": (ctypes.c_int, [_P, _D]),
@@ -82,6 +87,7 @@ _SIGS = {
     "lbm_load_state": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
     "lbm_stream": (_P, [_P]),
     "lbm_storage_of": (ctypes.c_int32, [_P]),
+    "lbm_model_of": (ctypes.c_int32, [_P]),
     "lbm_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "lbm_get_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32)]),
@@ -158,7 +164,7 @@ def lbm_params_from_problem(pb) -> LbmParams:
     """Marshal a ``workloads.Problem`` into ``lbm_params``."""
     p = lbm_params_default()
     for k in ("ra", "pr", "u_c", "length", "t_hot", "t_cold", "s_e", "s_q", "s_eps", "zeta_e",
-              "zeta_nu", "varpi", "s_nu", "zeta_alpha", "ax", "ay"):
+              "zeta_nu", "varpi", "s_nu", "zeta_alpha", "ax", "ay", "zeta_q", "zeta_eps", "theta"):
         setattr(p, k, float(getattr(pb, k)))
     for s in range(4):
         p.bc_flow[s] = int(pb.bc_flow[s])
@@ -169,21 +175,21 @@ def lbm_params_from_problem(pb) -> LbmParams:
     return p
 
 
-def lbm_required_bytes(nx: int, ny: int, storage: int) -> int:
+def lbm_required_bytes(nx: int, ny: int, storage: int, model: int = LBM_MODEL_D2Q5) -> int:
     b = ctypes.c_uint64()
-    _check(lib().lbm_required_bytes(nx, ny, storage, ctypes.byref(b)))
+    _check(lib().lbm_required_bytes(nx, ny, storage, model, ctypes.byref(b)))
     return b.value
 
 
-def lbm_create(nx: int, ny: int, storage: int, stream=None):
+def lbm_create(nx: int, ny: int, storage: int, model: int = LBM_MODEL_D2Q5, stream=None):
     h = _P()
-    _check(lib().lbm_create(ctypes.byref(h), nx, ny, storage, stream))
+    _check(lib().lbm_create(ctypes.byref(h), nx, ny, storage, model, stream))
     return h
 
 
-def lbm_create_ext(nx: int, ny: int, storage: int, device_ptr: int, nbytes: int, stream=None):
+def lbm_create_ext(nx: int, ny: int, storage: int, model: int, device_ptr: int, nbytes: int, stream=None):
     h = _P()
-    _check(lib().lbm_create_ext(ctypes.byref(h), nx, ny, storage, _P(device_ptr), nbytes, stream))
+    _check(lib().lbm_create_ext(ctypes.byref(h), nx, ny, storage, model, _P(device_ptr), nbytes, stream))
     return h
 
 
@@ -197,22 +203,29 @@ class Solver:
     allocation (kept alive by the solver) and the solver launches on the
     current PyTorch stream."""
 
-    def __init__(self, nx: int, ny: int, storage: str = "f64", torch_memory: bool = False, stream=None):
+    def __init__(self, nx: int, ny: int, storage: str = "f64", torch_memory: bool = False, stream=None,
+                 model="d2q5"):
         self.nx, self.ny = int(nx), int(ny)
         self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.model = MODEL[model] if isinstance(model, str) else int(model)
+        self.ng = MODEL_NG[self.model]
         self._mem = None
         self.h = None
         if torch_memory:
             import torch
-            nbytes = lbm_required_bytes(self.nx, self.ny, self.storage)
+            nbytes = lbm_required_bytes(self.nx, self.ny, self.storage, self.model)
             self._mem = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
             ptr = self._mem.data_ptr()
             ptr = (ptr + 255) // 256 * 256
             if stream is None:
                 stream = torch.cuda.current_stream().cuda_stream or None
-            self.h = lbm_create_ext(self.nx, self.ny, self.storage, ptr, nbytes, stream)
+            self.h = lbm_create_ext(self.nx, self.ny, self.storage, self.model, ptr, nbytes, stream)
         else:
-            self.h = lbm_create(self.nx, self.ny, self.storage, stream)
+            self.h = lbm_create(self.nx, self.ny, self.storage, self.model, stream)
+
+    @property
+    def model_name(self) -> str:
+        return {v: k for k, v in MODEL.items()}[self.model]
 
     def close(self):
         if self.h:
@@ -238,11 +251,12 @@ class Solver:
         _check(lib().lbm_set_params(self.h, ctypes.byref(p)), self.h)
 
     def derived(self) -> dict:
-        s9 = np.zeros(9); q5 = np.zeros(5)
+        s9 = np.zeros(9); q9 = np.zeros(9)
         gb, t0, ln, dt = (ctypes.c_double() for _ in range(4))
-        _check(lib().lbm_get_derived(self.h, _dp(s9), _dp(q5), ctypes.byref(gb), ctypes.byref(t0),
+        _check(lib().lbm_get_derived(self.h, _dp(s9), _dp(q9), ctypes.byref(gb), ctypes.byref(t0),
                                      ctypes.byref(ln), ctypes.byref(dt)), self.h)
-        return {"s": s9, "q": q5, "gbeta": gb.value, "T0": t0.value, "length": ln.value, "dT": dt.value}
+        return {"s": s9, "q": q9[:self.ng], "gbeta": gb.value, "T0": t0.value, "length": ln.value,
+                "dT": dt.value}
 
     def init_temperature(self, T=None):
         if T is not None:
@@ -315,13 +329,13 @@ class Solver:
         return r.value, bad.value
 
     def get_populations(self):
-        f = np.zeros((9, self.ny, self.nx)); g = np.zeros((5, self.ny, self.nx))
+        f = np.zeros((9, self.ny, self.nx)); g = np.zeros((self.ng, self.ny, self.nx))
         _check(lib().lbm_get_populations(self.h, _dp(f), _dp(g)), self.h)
         return f, g
 
     def set_populations(self, f, g):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, self.ny, self.nx)
-        g = np.ascontiguousarray(g, dtype=np.float64).reshape(5, self.ny, self.nx)
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.ng, self.ny, self.nx) if self.ng else None
         _check(lib().lbm_set_populations(self.h, _dp(f), _dp(g)), self.h)
 
     def save_state(self) -> bytes:
@@ -360,8 +374,8 @@ class Batch:
     def stream(self):
         return lib().lbm_batch_stream(self.h)
 
-    def new_solver(self, nx: int, ny: int, torch_memory: bool = False) -> Solver:
-        return Solver(nx, ny, self.storage, torch_memory=torch_memory, stream=self.stream)
+    def new_solver(self, nx: int, ny: int, torch_memory: bool = False, model="d2q5") -> Solver:
+        return Solver(nx, ny, self.storage, torch_memory=torch_memory, stream=self.stream, model=model)
 
     def add(self, solver: Solver) -> int:
         slot = ctypes.c_int32()

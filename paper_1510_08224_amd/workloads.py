@@ -8,7 +8,7 @@ GPU path and the CPU oracle are fed from.
 Workloads follow the paper's problems (Sec. 3): the differentially heated
 square cavity (Sec. 3.4), the channel with a moving, injecting wall
 (Sec. 3.3), the body-force-driven channel (Sec. 3.1), plus the
-Rayleigh-Benard cell, the batched cavity mix and the Poisson request stream
+lid-driven cavity (Sec. 3.2), the Rayleigh-Benard cell, the batched cavity mix and the Poisson request stream
 used for precision, batching and serving measurements.
 """
 from __future__ import annotations
@@ -52,6 +52,9 @@ class Problem:
     zeta_e: float = 1.9
     zeta_nu: float = 1.9
     varpi: float = 0.5
+    zeta_q: float = 1.9
+    zeta_eps: float = 1.9
+    theta: float = 1.0
     s_nu: float = 0.0
     zeta_alpha: float = 0.0
     ax: float = 0.0
@@ -106,6 +109,17 @@ def channel(nx: int, ny: int, s_nu: float, zeta_alpha: float = 1.0, ax: float = 
                    name=f"channel{nx}x{ny}", **kw)
 
 
+def lid_cavity(n: int, s_nu: float, u0: float = 0.1) -> Problem:
+    """Lid-driven cavity (Sec. 3.2): the top wall moves in +x with u0, the
+    other walls are at rest; s_e, s_q, s_eps at the paper's 1.6, 1.2, 1.8.
+    Meant for the model without a temperature field (walls adiabatic)."""
+    return Problem(nx=n, ny=n, s_nu=s_nu, zeta_alpha=1.0,
+                   bc_flow=(FLOW_WALL,) * 4, bc_temp=(TEMP_ADIABATIC,) * 4,
+                   wall_T=(0.0, 0.0, 0.0, 0.0),
+                   wall_u=((0.0, 0.0), (0.0, 0.0), (0.0, 0.0), (u0, 0.0)),
+                   name=f"lid{n}_snu{s_nu:.4f}")
+
+
 def periodic_box(nx: int, ny: int, s_nu: float, zeta_alpha: float, **kw) -> Problem:
     """Fully periodic lattice (no walls)."""
     return Problem(nx=nx, ny=ny, s_nu=s_nu, zeta_alpha=zeta_alpha,
@@ -134,13 +148,14 @@ def random_temperature(nx: int, ny: int, lo: float, hi: float, seed: int) -> np.
 
 
 def random_populations(nx: int, ny: int, seed: int, f_scale: float = 0.1, g_scale: float = 0.2,
-                       spread: float = 0.3):
+                       spread: float = 0.3, ng: int = 5):
     """Arbitrary positive population fields in plane order [i][y][x]:
-    value = scale * (1 + spread * U(-1, 1)).  Used for collision parity on
-    states far from equilibrium."""
+    value = scale * (1 + spread * U(-1, 1)), 9 flow planes then ``ng``
+    temperature planes (5, 9 or 0).  Used for collision parity on states
+    far from equilibrium."""
     rng = np.random.Generator(np.random.PCG64(seed))
     f = f_scale * (1.0 + spread * rng.uniform(-1.0, 1.0, size=(9, ny, nx)))
-    g = g_scale * (1.0 + spread * rng.uniform(-1.0, 1.0, size=(5, ny, nx)))
+    g = g_scale * (1.0 + spread * rng.uniform(-1.0, 1.0, size=(ng, ny, nx)))
     return np.ascontiguousarray(f), np.ascontiguousarray(g)
 
 

@@ -9,7 +9,8 @@ oracle.  It follows a route independent of the oracle's:
       fbar* = fbar - Lt (fbar - f^eq) + (S - Lt S / 2),  Lt = M^-1 Lambda M,
   with f^eq from Eq. 22 and S the Guo forcing term in velocity space, whose
   moments Eq. 10 defines as S~ = M S;
-* the thermal update is Eq. 23 with g^eq from Eq. 30.
+* the thermal update is Eq. 23 with g^eq from Eq. 30 (D2Q5) or Eq. 31
+  (D2Q9, with N the D2Q9 basis matrix and Q of Eq. 32).
 
 All arithmetic is in Fractions, so the only rounding is the final
 conversion.  The incompressible reading is the one the build uses: rho only
@@ -86,12 +87,8 @@ N5 = basis_n5()
 N5I = inverse(N5)
 
 
-def collide(f, g, s, q, varpi, gbeta, T0, ax, ay, rho0=Fr(1)):
-    """Exact post-collision (fbar*, g*) at one node.  Every argument is a
-    Fraction (or a list of them); s and q are the full diagonals."""
-    T = sum(g)                                       # Eq. 27
-    Fx = ax
-    Fy = ay + gbeta * (T - T0)                       # Eq. 4
+def _flow(f, s, Fx, Fy, rho0):
+    """Exact fbar* of Eq. 7 for given force; returns (fbar*, ux, uy)."""
     rho = sum(f)                                     # Eq. 18
     ux = (sum(e[0] * fi for e, fi in zip(E9, f)) + rho0 * Fx / 2) / rho0   # Eq. 19
     uy = (sum(e[1] * fi for e, fi in zip(E9, f)) + rho0 * Fy / 2) / rho0
@@ -108,11 +105,54 @@ def collide(f, g, s, q, varpi, gbeta, T0, ax, ay, rho0=Fr(1)):
     c1 = matvec(Lt, neq)
     c2 = matvec(Lt, S)
     fo = [fi - a + si - b / 2 for fi, a, si, b in zip(f, c1, S, c2)]   # Eq. 7
+    return fo, ux, uy
+
+
+def collide(f, g, s, q, varpi, gbeta, T0, ax, ay, rho0=Fr(1)):
+    """Exact post-collision (fbar*, g*) at one node, D2Q5 temperature model.
+    Every argument is a Fraction (or a list of them); s and q are the full
+    diagonals."""
+    T = sum(g)                                       # Eq. 27
+    Fx = ax
+    Fy = ay + gbeta * (T - T0)                       # Eq. 4
+    fo, ux, uy = _flow(f, s, Fx, Fy, rho0)
     geq = [(1 - varpi) * T] + [varpi * T / 4 + (ex * ux + ey * uy) * T / 2 for (ex, ey) in E5[1:]]  # Eq. 30
     Qt = matmul(N5I, matmul(diag(q), N5))
     d = matvec(Qt, [gi - ge for gi, ge in zip(g, geq)])
     go = [gi - di for gi, di in zip(g, d)]           # Eq. 23
     return fo, go
+
+
+CS2 = Fr(1, 3)   # D2Q9 sound speed squared
+
+
+def geq_d2q9(T, ux, uy, theta):
+    """Eq. 31 written with c_s^2 = 1/3 kept symbolic."""
+    usq = ux * ux + uy * uy
+    out = []
+    for (ex, ey), w in zip(E9, W9):
+        eu = ex * ux + ey * uy
+        out.append(w * T * (1 + eu / CS2 + theta * (eu * eu / (2 * CS2 * CS2) - usq / (2 * CS2))))
+    return out
+
+
+def collide_d2q9t(f, g, s, q, theta, gbeta, T0, ax, ay, rho0=Fr(1)):
+    """Exact post-collision at one node, D2Q9 temperature model: the
+    velocity-space update g* = g - N^-1 Q N (g - g^eq) with N the D2Q9
+    basis matrix of Eq. 12, Q of Eq. 32 and g^eq of Eq. 31."""
+    T = sum(g)
+    Fx = ax
+    Fy = ay + gbeta * (T - T0)
+    fo, ux, uy = _flow(f, s, Fx, Fy, rho0)
+    geq = geq_d2q9(T, ux, uy, theta)
+    Qt = matmul(M9I, matmul(diag(q), M9))
+    d = matvec(Qt, [gi - ge for gi, ge in zip(g, geq)])
+    return fo, [gi - di for gi, di in zip(g, d)]
+
+
+def collide_isothermal(f, s, ax, ay, rho0=Fr(1)):
+    """Exact fbar* without a temperature field: the force is a alone."""
+    return _flow(f, s, ax, ay, rho0)[0]
 
 
 def guo_moments(ux, uy, Fx, Fy, rho0=Fr(1)):

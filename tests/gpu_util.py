@@ -10,30 +10,36 @@ from paper_1510_08224_amd import workloads as W
 W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
 
-def population_scale(pb):
+def population_scale(pb, ng=5):
     """Reference magnitudes for the relative comparison of populations:
-    max(|p_oracle|, p_ref) with p_ref = w_i for fbar and the D2Q5 rest
-    equilibrium at the largest wall/reference temperature for g."""
+    max(|p_oracle|, p_ref) with p_ref = w_i for fbar and the rest
+    equilibrium of the temperature model (D2Q5: (1 - varpi) T, varpi T / 4;
+    D2Q9: w_i T) at the largest wall/reference temperature for g."""
     tmax = max(abs(pb.t_hot), abs(pb.t_cold), *(abs(t) for t in pb.wall_T), 1e-300)
-    gref = np.array([(1 - pb.varpi) * tmax] + [pb.varpi * tmax / 4] * 4)
+    if ng == 9:
+        gref = W9 * tmax
+    else:
+        gref = np.array([(1 - pb.varpi) * tmax] + [pb.varpi * tmax / 4] * 4)[:ng]
     return W9[:, None, None], gref[:, None, None]
 
 
 def max_rel_pop_error(pb, fa, ga, fb, gb):
-    fr, gr = population_scale(pb)
+    ng = ga.shape[0]
+    fr, gr = population_scale(pb, ng)
     ef = np.max(np.abs(fa - fb) / np.maximum(np.abs(fb), fr))
-    eg = np.max(np.abs(ga - gb) / np.maximum(np.abs(gb), gr))
-    return float(ef), float(eg)
+    eg = float(np.max(np.abs(ga - gb) / np.maximum(np.abs(gb), gr))) if ng else 0.0
+    return float(ef), eg
 
 
-def run_pair(pb, steps, storage="f64", T_init=None, pops=None, launch=None, s8_literal=False):
+def run_pair(pb, steps, storage="f64", T_init=None, pops=None, launch=None, s8_literal=False,
+             model="d2q5"):
     """Advance the GPU solver and the oracle from the same initial state.
     Returns (solver, oracle lattice) after `steps` steps."""
-    S = lbm.Solver(pb.nx, pb.ny, storage)
+    S = lbm.Solver(pb.nx, pb.ny, storage, model=model)
     S.set_params(pb)
     if launch:
         S.set_launch(*launch)
-    L = oracle.Lattice(pb, s8_literal=s8_literal, T_init=T_init)
+    L = oracle.Lattice(pb, s8_literal=s8_literal, T_init=T_init, model=model)
     if T_init is not None:
         S.init_temperature(T_init)
     if pops is not None:

@@ -28,20 +28,22 @@ def test_params_struct_layout_matches():
     assert list(p.bc_temp) == [lbm.LBM_T_DIRICHLET, lbm.LBM_T_DIRICHLET, lbm.LBM_T_ADIABATIC,
                                lbm.LBM_T_ADIABATIC]
     assert list(p.wall_T) == [1.0, 0.0, 0.0, 0.0]
+    assert (p.zeta_q, p.zeta_eps, p.theta) == (1.9, 1.9, 1.0)
 
 
 def test_abi_version_and_info():
-    assert lbm.lib().lbm_abi_version() == 1
+    assert lbm.lib().lbm_abi_version() == 2
     assert b"gfx950" in lbm.lib().lbm_build_info()
 
 
+@pytest.mark.parametrize("model,planes", [("d2q5", 14), ("d2q9t", 18), ("isothermal", 9)])
 @pytest.mark.parametrize("storage,b", [(lbm.LBM_F64, 8), (lbm.LBM_F32, 4), (lbm.LBM_F16, 2)])
-def test_required_bytes(storage, b):
-    # two buffers of 14 planes; rows padded to 256 bytes, planes to 4 KiB
+def test_required_bytes(storage, b, model, planes):
+    # two buffers of 9 + NG planes; rows padded to 256 bytes, planes to 4 KiB
     for nx, ny in [(64, 64), (2048, 2048), (37, 23), (1, 1), (4096, 1024)]:
         pitch = -(-nx * b // 256) * 256
         plane = -(-pitch * ny // 4096) * 4096
-        assert lbm.lbm_required_bytes(nx, ny, storage) == 2 * 14 * plane
+        assert lbm.lbm_required_bytes(nx, ny, storage, lbm.MODEL[model]) == 2 * planes * plane
 
 
 def test_required_bytes_rejects_bad_input():
@@ -51,6 +53,8 @@ def test_required_bytes_rejects_bad_input():
     with pytest.raises(lbm.LbmError):
         lbm.lbm_required_bytes(5, 5, 7)
     assert b"lbm_required_bytes" in lbm.lib().lbm_last_error(None)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_required_bytes(5, 5, lbm.LBM_F64, 3)
 
 
 def test_create_rejects_bad_arguments_before_touching_a_device():
@@ -60,8 +64,11 @@ def test_create_rejects_bad_arguments_before_touching_a_device():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_create(4, 4, 9)
     assert e.value.code == lbm.LBM_ERR_ARG
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(4, 4, lbm.LBM_F64, 5)
+    assert e.value.code == lbm.LBM_ERR_ARG
     with pytest.raises(lbm.LbmError):
-        lbm.lbm_create_ext(4, 4, lbm.LBM_F64, 0, 0)
+        lbm.lbm_create_ext(4, 4, lbm.LBM_F64, 0, 0, 0)
 
 
 def test_null_handles_are_rejected():

@@ -1,0 +1,238 @@
+"""GPU parity of the other temperature models against the CPU FP64 oracle:
+the D2Q9 thermal model (Eqs. 31-32, theta 0 and 1) and the flow without a
+temperature field (Secs. 3.1-3.2), through the C ABI.
+
+Bar (FP64 storage) as for the D2Q5 model: every pre-collision population
+within 1e-12 of the oracle relative to max(|p_oracle|, p_ref), p_ref the
+rest weight (w_i for fbar, the rest equilibrium at the largest temperature
+for g); moments within 1e-12 of the field scale; Nusselt numbers within
+1e-11 relative.  Deviation storage (FP32, FP16) is held to the bounds its
+rounding allows over a short run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import field_scale, max_rel_pop_error, run_pair
+from paper_1510_08224_amd import lbm
+from paper_1510_08224_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _check(pb, S, L, model, tol=TOL):
+    fa, ga = S.get_populations()
+    fb, gb = L.get_state()
+    assert ga.shape == gb.shape
+    ef, eg = max_rel_pop_error(pb, fa, ga, fb, gb)
+    assert ef < tol and eg < tol, (ef, eg)
+    us, ts = field_scale(pb)
+    mg, mo = S.moments(), L.moments()
+    us = max(us, float(np.max(np.abs(mo[1]))), float(np.max(np.abs(mo[2]))))   # force-driven flows
+    assert np.max(np.abs(mg[0] - mo[0])) < tol
+    assert np.max(np.abs(mg[1] - mo[1])) < tol * us and np.max(np.abs(mg[2] - mo[2])) < tol * us
+    assert np.max(np.abs(mg[3] - mo[3])) < tol * ts
+    if model == "isothermal":
+        with pytest.raises(lbm.LbmError) as e:
+            S.nusselt(W.LEFT)
+        assert e.value.code == lbm.LBM_ERR_UNSUPPORTED
+        return ef, eg
+    for side in range(4):
+        if pb.bc_temp[side] not in (W.TEMP_DIRICHLET, W.TEMP_NEE_DIRICHLET) or pb.t_hot == pb.t_cold:
+            continue
+        a, b = S.nusselt(side), L.nusselt(side)
+        assert abs(a[0] - b[0]) <= 1e-11 * max(1.0, abs(b[0]))
+        assert abs(a[1] - b[1]) <= 1e-11 * max(1.0, abs(b[1]))
+    return ef, eg
+
+
+def _lid(n, re=100.0, u0=0.1):
+    return W.lid_cavity(n, oracle.rate_for_reynolds(re, n, u0), u0)
+
+
+def _poiseuille_nee(nx=6, ny=60, s_nu=1.754, ax=2e-6):
+    # Sec. 3.1: body-force channel, periodic in x, NEE plates, rates 1 but s_nu
+    return W.with_nee_walls(W.channel(nx, ny, s_nu=s_nu, zeta_alpha=1.0, ax=ax, rates_one=True))
+
+
+# (model, problem, initial temperature, initial populations)
+CASES = {
+    "d2q9t_cavity37x23_randT": ("d2q9t", lambda: W.cavity(37, 1e5, ny=23),
+                                lambda pb: W.random_temperature(37, 23, 0.0, 1.0, seed=11), None),
+    "d2q9t_theta0_cavity30": ("d2q9t", lambda: W.cavity(30, 1e5).replace(theta=0.0), None, None),
+    "d2q9t_rb50x17_noise": ("d2q9t", lambda: W.rayleigh_benard(50, 17, 2e4),
+                            lambda pb: W.rb_initial_temperature(50, 17, amp=1e-2, seed=1510), None),
+    "d2q9t_injection_channel13x20": ("d2q9t", lambda: W.channel(
+        13, 20, s_nu=0.8, zeta_alpha=0.9, u_top=(0.02, 0.01), u_bottom=(0.0, 0.01), t_bottom=0.0, t_top=1.0),
+        None, None),
+    "d2q9t_moving_walls_30": ("d2q9t", lambda: W.cavity(30, 1e5).replace(
+        wall_u=((0.0, 0.003), (0.0, -0.01), (0.01, 0.0), (0.05, 0.0))), None, None),
+    "d2q9t_periodic_box19x11_random": ("d2q9t", lambda: W.periodic_box(
+        19, 11, s_nu=1.1, zeta_alpha=1.3, ax=2e-4, ay=1e-4, u_c=0.05),
+        None, lambda pb: W.random_populations(19, 11, 3, g_scale=0.05, ng=9)),
+    "d2q9t_adiabatic_random16x9": ("d2q9t", lambda: W.cavity(16, 1e4, ny=9).replace(
+        bc_temp=(W.TEMP_ADIABATIC,) * 4), None, lambda pb: W.random_populations(16, 9, 4, g_scale=0.05, ng=9)),
+    "d2q9t_cavity130x70_fastpath": ("d2q9t", lambda: W.cavity(130, 3e5, ny=70),
+                                    lambda pb: W.random_temperature(130, 70, 0.0, 1.0, seed=19), None),
+    "d2q9t_nee_cavity40x30": ("d2q9t", lambda: W.with_nee_walls(W.cavity(40, 1e5, ny=30)),
+                              lambda pb: W.random_temperature(40, 30, 0.0, 1.0, seed=13), None),
+    "d2q9t_nee_injection13x21": ("d2q9t", lambda: W.with_nee_walls(W.channel(
+        13, 21, s_nu=0.8, zeta_alpha=0.9, u_top=(0.02, 0.01), u_bottom=(0.0, 0.01))), None, None),
+    "d2q9t_nee_rb130x17": ("d2q9t", lambda: W.with_nee_walls(W.rayleigh_benard(130, 17, 2e4)),
+                           lambda pb: W.rb_initial_temperature(130, 17, amp=1e-2, seed=7), None),
+    "iso_lid_cavity40": ("isothermal", lambda: _lid(40), None, None),
+    "iso_lid_cavity130x130_fastpath": ("isothermal", lambda: _lid(130, re=400.0), None, None),
+    "iso_poiseuille_nee6x60": ("isothermal", lambda: _poiseuille_nee(), None, None),
+    "iso_periodic_box19x11_random": ("isothermal", lambda: W.periodic_box(
+        19, 11, s_nu=1.1, zeta_alpha=1.3, ax=2e-4, ay=1e-4), None, lambda pb: W.random_populations(19, 11, 3, ng=0)),
+    "iso_y_periodic_21x14_random": ("isothermal", lambda: _lid(21).replace(
+        ny=14, bc_flow=(W.FLOW_WALL, W.FLOW_WALL, W.FLOW_PERIODIC, W.FLOW_PERIODIC),
+        bc_temp=(W.TEMP_ADIABATIC, W.TEMP_ADIABATIC, W.TEMP_PERIODIC, W.TEMP_PERIODIC),
+        wall_u=((0.0, 0.01), (0.0, -0.02), (0.0, 0.0), (0.0, 0.0))),
+        None, lambda pb: W.random_populations(21, 14, 5, ng=0)),
+    "iso_nee_lid_cavity_random24x20": ("isothermal", lambda: W.with_nee_walls(_lid(24).replace(ny=20)), None,
+                                       lambda pb: W.random_populations(24, 20, 17, ng=0)),
+}
+
+
+@pytest.mark.parametrize("steps", [1, 10, 100])
+@pytest.mark.parametrize("case", list(CASES))
+def test_model_parity_short_runs(case, steps):
+    model, mk, mkT, mkP = CASES[case]
+    pb = mk()
+    T = mkT(pb) if mkT else None
+    P = mkP(pb) if mkP else None
+    S, L = run_pair(pb, steps, T_init=T, pops=P, model=model)
+    assert S.model_name == model
+    _check(pb, S, L, model)
+    S.close()
+
+
+@pytest.mark.parametrize("model", ["d2q9t", "isothermal"])
+def test_single_node_periodic_is_pure_collision(model):
+    ng = {"d2q9t": 9, "isothermal": 0}[model]
+    for seed in range(3):
+        rng = np.random.default_rng(seed)
+        pb = W.periodic_box(1, 1, s_nu=float(rng.uniform(0.5, 1.9)), zeta_alpha=float(rng.uniform(0.5, 1.9)),
+                            ax=1e-3, ay=-2e-3, u_c=0.05, s_e=1.4, s_q=0.9, s_eps=1.7, zeta_e=1.3, zeta_nu=0.7,
+                            zeta_q=1.1, zeta_eps=0.6, theta=float(seed % 2))
+        pops = W.random_populations(1, 1, seed=seed, spread=0.5, g_scale=0.05, ng=ng)
+        S, L = run_pair(pb, 1, pops=pops, model=model)
+        fa, ga = S.get_populations()
+        fb, gb = L.get_state()
+        assert np.max(np.abs(fa - fb)) < 1e-15
+        assert ga.shape == gb.shape == (ng, 1, 1)
+        assert ng == 0 or np.max(np.abs(ga - gb)) < 1e-15
+        S.close()
+
+
+def test_d2q9t_cavity64_long_run():
+    """The 64 x 64 cavity, Ra = 1e4, with the D2Q9 thermal model: 5000 steps,
+    every population and both wall Nusselt numbers."""
+    pb = W.workload_cavity64()
+    S, L = run_pair(pb, 5000, model="d2q9t")
+    ef, eg = _check(pb, S, L, "d2q9t")
+    print(f"d2q9t cavity64 5000 steps: max rel population error f {ef:.3e} g {eg:.3e}")
+    S.close()
+
+
+def test_isothermal_lid_cavity_long_run():
+    pb = _lid(64, re=400.0)
+    S, L = run_pair(pb, 5000, model="isothermal")
+    ef, _ = _check(pb, S, L, "isothermal")
+    print(f"isothermal lid cavity 64 5000 steps: max rel population error f {ef:.3e}")
+    S.close()
+
+
+@pytest.mark.parametrize("launch", [(64, 4, 1), (128, 2, 2), (256, 1, 1)])
+@pytest.mark.parametrize("model", ["d2q9t", "isothermal"])
+def test_launch_shape_does_not_change_results(model, launch):
+    pb = W.cavity(150, 1e5, ny=70) if model == "d2q9t" else _lid(150).replace(ny=70)
+    runs = []
+    for shape in (None, launch):
+        S = lbm.Solver(150, 70, "f64", model=model)
+        S.set_params(pb)
+        if shape:
+            S.set_launch(*shape)
+        if model == "d2q9t":
+            S.init_temperature(W.random_temperature(150, 70, 0.0, 1.0, seed=8))
+        S.step(40)
+        runs.append(S.get_populations())
+        S.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("model", ["d2q9t", "isothermal"])
+def test_checkpoint_roundtrip(model):
+    ng = {"d2q9t": 9, "isothermal": 0}[model]
+    pb = W.rayleigh_benard(40, 20, 5e4)
+    f0, g0 = W.random_populations(40, 20, seed=12, g_scale=0.05, ng=ng)
+    S = lbm.Solver(40, 20, "f64", model=model)
+    S.set_params(pb)
+    S.set_populations(f0, g0)
+    f1, g1 = S.get_populations()
+    assert np.max(np.abs(f1 - f0)) < 1e-16 and (ng == 0 or np.max(np.abs(g1 - g0)) < 4e-16)
+    S.step(37)
+    blob = S.save_state()
+    S.step(41)
+    fa, ga = S.get_populations()
+    S.load_state(blob)
+    S.step(41)
+    fb, gb = S.get_populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    S.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-5), ("f16", 2e-2)])
+@pytest.mark.parametrize("model", ["d2q9t", "isothermal"])
+def test_deviation_storage_tracks_oracle(model, storage, tol):
+    # 200 steps of a heated cavity (lid cavity without temperature): the
+    # moments stay within the rounding of the stored deviations.
+    pb = W.cavity(48, 1e5) if model == "d2q9t" else _lid(48)
+    S, L = run_pair(pb, 200, storage=storage, model=model)
+    us, ts = field_scale(pb)
+    mg, mo = S.moments(), L.moments()
+    assert np.max(np.abs(mg[1] - mo[1])) < tol * us and np.max(np.abs(mg[2] - mo[2])) < tol * us
+    assert np.max(np.abs(mg[3] - mo[3])) < tol * ts
+    # rounding of the stored deviations moves the total mass only slightly
+    assert abs(mg[0].sum() - mo[0].sum()) / mo[0].sum() < 1e-5
+    S.close()
+
+
+def test_residual_for_models():
+    for model in ("d2q9t", "isothermal"):
+        pb = W.cavity(48, 1e4) if model == "d2q9t" else _lid(48)
+        S = lbm.Solver(48, 48, "f64", model=model)
+        S.set_params(pb)
+        L = oracle.Lattice(pb, model=model)
+        S.residual()
+        prev = L.moments()[1:]
+        S.step(300); L.step(300)
+        r, bad = S.residual()
+        ro = oracle.residual(prev, L.moments()[1:])
+        assert bad == 0 and abs(r - ro) <= 1e-12 * ro + 1e-17, model
+        S.close()
+
+
+def test_model_errors():
+    S = lbm.Solver(8, 8, "f64", model="d2q9t")
+    with pytest.raises(lbm.LbmError) as e:
+        S.set_params(W.cavity(8, 1e4).replace(theta=0.5))
+    assert e.value.code == lbm.LBM_ERR_ARG
+    with pytest.raises(lbm.LbmError) as e:
+        S.set_params(W.cavity(8, 1e4).replace(zeta_q=2.0))
+    assert e.value.code == lbm.LBM_ERR_ARG
+    S.set_params(W.cavity(8, 1e4))
+    d = S.derived()
+    o = oracle.derive(W.cavity(8, 1e4), "d2q9t")
+    assert np.allclose(d["s"], o["s"], rtol=1e-15) and np.allclose(d["q"], o["q"], rtol=1e-15)
+    assert len(d["q"]) == 9
+    S.close()
+    S = lbm.Solver(8, 8, "f64", model="isothermal")
+    S.set_params(_lid(8))
+    assert len(S.derived()["q"]) == 0 and S.derived()["gbeta"] == 0.0
+    with pytest.raises(lbm.LbmError) as e:
+        S.init_temperature(np.zeros((8, 8)))
+    assert e.value.code == lbm.LBM_ERR_UNSUPPORTED
+    S.close()

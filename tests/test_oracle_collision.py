@@ -45,7 +45,7 @@ def _rand_state(rng, far=False):
 
 def _exact(p, f, g):
     s = [Fr(v) for v in p.s]
-    q = [Fr(v) for v in p.q]
+    q = [Fr(v) for v in p.q[:5]]
     fo, go = X.collide([Fr(v) for v in f], [Fr(v) for v in g], s, q, Fr(p.varpi),
                        Fr(p.gbeta), Fr(p.T0), Fr(p.ax), Fr(p.ay))
     return np.array([float(v) for v in fo]), np.array([float(v) for v in go])

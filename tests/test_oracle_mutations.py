@@ -28,7 +28,7 @@ MUTANTS = {
     "neq3_no_varpi": ("neq[3] = p->varpi * T;", "neq[3] = T;"),
     "neq1_wrong_u": ("neq[1] = ux * T;", "neq[1] = uy * T;"),
     "opposite_table": ("{0, 3, 4, 1, 2, 7, 8, 5, 6}", "{0, 3, 4, 1, 2, 8, 7, 6, 5}"),
-    "antibounce_sign": ("= -L->gp[c * 5 + i] + 0.5 * p->varpi", "= L->gp[c * 5 + i] + 0.5 * p->varpi"),
+    "antibounce_sign": ("= -L->gp[c * ng + i] + 2.0 * even;", "= L->gp[c * ng + i] + 2.0 * even;"),
     "moving_wall_sign": ("L->fp[c * 9 + i] - 6.0 * W9[i]", "L->fp[c * 9 + i] + 6.0 * W9[i]"),
     "buoyancy_sign": ("p->ay + p->gbeta * (t - p->T0)", "p->ay - p->gbeta * (t - p->T0)"),
     "nusselt_first_order": ("(9.0 * t[0] - t[1] - 8.0 * tw) / 3.0", "2.0 * (t[0] - tw)"),
@@ -37,6 +37,14 @@ MUTANTS = {
     "nee_wall_temperature": ("double Tb = tside >= 0 ? p->wall_T[tside] : T;", "double Tb = T;"),
     "nee_wall_velocity": ("double uwx = p->wall_u[vside][0], uwy = p->wall_u[vside][1];",
                           "double uwx = ux, uwy = uy;"),
+    "d2q9t_theta_term_sign": ("p->theta * (4.5 * eu * eu - 1.5 * usq));\n    }\n    if (i == 0)",
+                              "p->theta * (4.5 * eu * eu + 1.5 * usq));\n    }\n    if (i == 0)"),
+    "d2q9t_advection_coefficient": ("(1.0 + 3.0 * eu + p->theta", "(1.0 + 2.0 * eu + p->theta"),
+    "d2q9t_rates_reversed": ("ns9[k] = n9[k] - p->q[k] * (n9[k] - ne9[k]);",
+                             "ns9[k] = n9[k] - p->q[8 - k] * (n9[k] - ne9[k]);"),
+    "d2q9t_antibounce_weight": ("even = W9[i] * p->wall_T[side]", "even = 0.25 * p->wall_T[side]"),
+    "d2q9t_antibounce_no_velocity": ("(1.0 + p->theta * (4.5 * eu * eu - 1.5 * usq));\n                    } else",
+                                     "(1.0 + 0.0 * (4.5 * eu * eu - 1.5 * usq));\n                    } else"),
     "stream_index": ("L->fn[((size_t)ty * nx + tx) * 9 + i]", "L->fn[((size_t)ty * nx + tx) * 9 + OPP9[i]]"),
 }
 
@@ -59,7 +67,7 @@ def _p(lib_s, s, q, **kw):
     p.nx = p.ny = 1
     for k in range(9):
         p.s[k] = s[k]
-    for k in range(5):
+    for k in range(len(q)):
         p.q[k] = q[k]
     p.varpi, p.rho0 = kw.get("varpi", 0.5), 1.0
     p.gbeta, p.T0, p.ax, p.ay = kw.get("gbeta", 0.0), kw.get("T0", 0.5), kw.get("ax", 0.0), kw.get("ay", 0.0)
@@ -80,11 +88,45 @@ def _battery(lib):
         g = np.array([0.5] + [0.125] * 4) * (1 + 0.4 * rng.uniform(-1, 1, 5))
         fo, go = oracle.collide_node(p, f, g, library=lib)
         fe, ge = X.collide([Fr(v) for v in f], [Fr(v) for v in g], [Fr(v) for v in p.s],
-                           [Fr(v) for v in p.q], Fr(p.varpi), Fr(p.gbeta), Fr(p.T0), Fr(p.ax), Fr(p.ay))
+                           [Fr(v) for v in p.q][:5], Fr(p.varpi), Fr(p.gbeta), Fr(p.T0), Fr(p.ax), Fr(p.ay))
         if (np.max(np.abs(fo - np.array([float(v) for v in fe]))) > 1e-14
                 or np.max(np.abs(go - np.array([float(v) for v in ge]))) > 1e-14):
             failed.append("collision_exact")
             break
+    # exact single-node collision of the D2Q9 thermal model (Eqs. 31-32)
+    p = _p(lib, [1, 1, 1, 1.6, 1.3, 1.3, 1.1, 1.1, 1.8], [1, 1.2, 1.2, 1.9, 1.7, 1.7, 1.4, 1.4, 0.8],
+           gbeta=0.03, T0=0.4, ax=2e-3, ay=-1e-3)
+    p.model, p.theta = oracle.MODEL_D2Q9T, 1.0
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    f = w * (1 + 0.4 * rng.uniform(-1, 1, 9))
+    g = w * 0.7 * (1 + 0.4 * rng.uniform(-1, 1, 9))
+    fo, go = oracle.collide_node(p, f, g, library=lib)
+    fe, ge = X.collide_d2q9t([Fr(v) for v in f], [Fr(v) for v in g], [Fr(v) for v in p.s],
+                             [Fr(v) for v in p.q], Fr(1), Fr(p.gbeta), Fr(p.T0), Fr(p.ax), Fr(p.ay))
+    if (np.max(np.abs(fo - np.array([float(v) for v in fe]))) > 1e-14
+            or np.max(np.abs(go - np.array([float(v) for v in ge]))) > 1e-14):
+        failed.append("collision_exact_d2q9t")
+    # Couette exact, D2Q9 thermal model (moving wall, Dirichlet walls)
+    L = oracle.Lattice(W.channel(3, 16, s_nu=1.3, zeta_alpha=1.1, u_top=(0.05, 0.0)), library=lib,
+                       model="d2q9t")
+    L.step(12000)
+    _, ux, uy, T = L.moments()
+    y = (np.arange(16) + 0.5) / 16
+    if not (np.max(np.abs(ux - 0.05 * y[:, None])) < 1e-13 and np.max(np.abs(T - y[:, None])) < 1e-13):
+        failed.append("couette_exact_d2q9t")
+    # uniformly moving equilibrium between moving Dirichlet plates is a fixed point
+    u = np.array([0.05, 0.02])
+    e = np.array(X.E9, dtype=float)
+    eu = e @ u
+    feq = w * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * (u @ u))
+    pb = W.channel(3, 8, s_nu=1.3, zeta_alpha=1.1, u_top=(0.05, 0.02), u_bottom=(0.05, 0.02),
+                   t_bottom=1.0, t_top=1.0).replace(t_hot=1.0, t_cold=0.0)
+    L = oracle.Lattice(pb, library=lib, model="d2q9t")
+    L.set_state(np.broadcast_to(feq[:, None, None], (9, 8, 3)).copy(),
+                np.broadcast_to(feq[:, None, None], (9, 8, 3)).copy())
+    L.step(200)
+    if np.max(np.abs(L.moments()[3] - 1)) > 1e-14:
+        failed.append("moving_equilibrium_d2q9t")
     # Couette exact (moving wall, Dirichlet walls)
     L = oracle.Lattice(W.channel(3, 16, s_nu=1.3, zeta_alpha=1.1, u_top=(0.05, 0.0)), library=lib)
     L.step(12000)
