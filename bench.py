@@ -10,10 +10,13 @@ solve does.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line: MLUPS for FP64 storage (the plain method) with the
 roofline of the step kernel measured with HIP events on the solver's
-stream, the same figures for FP32 and FP16 deviation storage, and the CPU
-oracle timed on a bounded sample of the same workload.
+stream, the same figures for FP32 and FP16 deviation storage and for the
+other temperature models in FP64 (the D2Q9 thermal model on the same
+cavity; the flow alone on a lid-driven cavity of the same size, Re = 1000),
+and the CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--storage f64] [--variants f32,f16]
+                    [--models d2q9t,isothermal]
 """
 from __future__ import annotations
 
@@ -29,8 +32,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0              # MI355X HBM3E, published peak
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
-VALUES_PER_NODE = 28               # 9 + 5 populations read, 9 + 5 written
+NG = {"d2q5": 5, "d2q9t": 9, "isothermal": 0}   # temperature populations per node
 REDUCE_EVERY = 1000
+
+
+def values_per_node(model: str) -> int:
+    """Populations read plus written per node and step: 9 + NG each way."""
+    return 2 * (9 + NG[model])
 
 
 def kernel_source_hash() -> str:
@@ -58,14 +66,16 @@ def measured_traffic(storage: str, nodes: int):
     return ent.get("bytes_per_launch")
 
 
-def time_storage(storage: str, pb, steps: int, warmup: int, launch=None) -> dict:
+def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: str = "d2q5") -> dict:
     import torch
     from paper_1510_08224_amd import lbm
 
-    S = lbm.Solver(pb.nx, pb.ny, storage, torch_memory=True)
+    S = lbm.Solver(pb.nx, pb.ny, storage, torch_memory=True, model=model)
     S.set_params(pb)
     if launch:
         S.set_launch(*launch)
+    shape = S.get_launch()
+    thermal = NG[model] > 0
     st = torch.cuda.ExternalStream(S.stream)
     S.step(warmup)
     S.residual()
@@ -85,21 +95,24 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None) -> dict
         segs.append((e0, e1, k))
         done += k
         if done % REDUCE_EVERY == 0 or done == steps:
-            S.nusselt(0)
-            S.nusselt(1)
+            if thermal:
+                S.nusselt(0)
+                S.nusselt(1)
             r, bad = S.residual(raise_unstable=False)
     S.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sweep_ms = sum(a.elapsed_time(b) for a, b, _ in segs)
-    nu = S.nusselt(1)[0]
+    nu = S.nusselt(1)[0] if thermal else None
     S.close()
     avg_launch_s = sweep_ms / 1e3 / steps
-    alg_bytes = VALUES_PER_NODE * BYTES[storage] * nodes
+    alg_bytes = values_per_node(model) * BYTES[storage] * nodes
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = measured_traffic(storage, nodes)
+    traffic = measured_traffic(storage, nodes) if model == "d2q5" else None
     return {
         "storage": storage,
+        "model": model,
+        "launch": {"block_x": shape[0], "block_y": shape[1], "rows": shape[2], "policy": shape[3]},
         "mlups": nodes * steps / wall / 1e6,
         "ms_per_step": wall * 1e3 / steps,
         "sweep_us_per_launch": avg_launch_s * 1e6,
@@ -133,10 +146,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="f64", choices=list(BYTES))
     ap.add_argument("--variants", default="f32,f16", help="other storages to time ('none' for none)")
+    ap.add_argument("--models", default="d2q9t,isothermal",
+                    help="other temperature models to time in the main storage ('none' for none)")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=2048, help="cavity side")
-    ap.add_argument("--launch", default="", help="block_x,block_y,rows")
+    ap.add_argument("--launch", default="", help="block_x,block_y,rows[,policy]")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one elementwise pass over 1 GiB (reference kernel for counter runs)")
     args = ap.parse_args()
@@ -147,6 +162,7 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_1510_08224_amd import lbm
     from paper_1510_08224_amd import workloads as W
 
     if not torch.cuda.is_available():
@@ -161,6 +177,13 @@ def main():
         for s in args.variants.split(","):
             if s and s != args.storage:
                 variants[s] = time_storage(s, pb, args.steps, args.warmup, launch)
+    models = {}
+    if args.models != "none":
+        for m in args.models.split(","):
+            if m and m != "d2q5":
+                mpb = pb if m != "isothermal" else W.lid_cavity(args.n, lbm.viscous_rate(1000.0, args.n, 0.1), 0.1)
+                models[m] = time_storage(args.storage, mpb, args.steps, args.warmup, launch, model=m)
+                models[m]["workload"] = mpb.name
     if args.calibrate_copy:
         # reference for counter runs: one dispatch reading and writing 1 GiB
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -183,8 +206,8 @@ def main():
         "dtype": args.storage,
         "data": "synthetic",
         "config": {"workload": f"cavity{args.n}_ra1e6_pr0.71_uc0.1", "nx": args.n, "ny": args.n,
-                   "storage": args.storage, "reduce_every": REDUCE_EVERY,
-                   "device": torch.cuda.get_device_name(0)},
+                   "storage": args.storage, "model": "d2q5", "reduce_every": REDUCE_EVERY,
+                   "launch": main_res["launch"], "device": torch.cuda.get_device_name(0)},
         "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
         "sweep_mlups": round(main_res["sweep_mlups"], 1),
@@ -192,8 +215,12 @@ def main():
         "nu_right_mean": main_res["nu_right_mean"],
         "storage_variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
                                  "sweep_mlups": round(v["sweep_mlups"], 1), "roofline": v["roofline"],
-                                 "nu_right_mean": v["nu_right_mean"]}
+                                 "nu_right_mean": v["nu_right_mean"], "launch": v["launch"]}
                              for k, v in variants.items()},
+        "model_variants": {k: {"workload": v["workload"], "storage": args.storage, "mlups": round(v["mlups"], 1),
+                               "sweep_mlups": round(v["sweep_mlups"], 1), "roofline": v["roofline"],
+                               "launch": v["launch"]}
+                           for k, v in models.items()},
         "source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)

@@ -257,12 +257,31 @@ void* lbm_stream(const lbm_solver* h);
 int32_t lbm_storage_of(const lbm_solver* h);
 int32_t lbm_model_of(const lbm_solver* h);
 
+/* Memory policy of the step kernel (bit mask):
+ *   LBM_POLICY_XCD_BANDS    each of the 8 XCDs takes a contiguous band of
+ *                           tiles; otherwise tile b runs on XCD b % 8
+ *                           (column strips when a row holds a multiple of 8
+ *                           tiles);
+ *   LBM_POLICY_KEEP_STORES  stores keep their lines in the last-level
+ *                           cache; otherwise they are non-temporal.
+ * The default follows the footprint F of both population buffers: bands
+ * while F <= 500 MiB, kept stores while F <= 256 MiB. */
+enum {
+    LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
+    LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
+    LBM_POLICY_XCD_BANDS = 1,
+    LBM_POLICY_KEEP_STORES = 2
+};
+
 /* Launch shape of the step kernel: block_x threads along x (64, 128 or
  * 256), block_y rows of threads (block_x * block_y <= 256) and
- * rows_per_thread (1, 2 or 4) consecutive rows handled by each thread.
- * 0 keeps the current value.  Results do not depend on the shape. */
-int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread);
-int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread);
+ * rows_per_thread (1 or 2) consecutive rows handled by each thread; 0
+ * keeps the current value.  policy: a mask of LBM_POLICY_* bits,
+ * LBM_POLICY_KEEP or LBM_POLICY_DEFAULT.  Results do not depend on the
+ * shape or the policy (bitwise).  LBM_ERR_ARG for other values. */
+int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread, int32_t policy);
+int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread,
+                   int32_t* policy);
 
 /* ------------------------------------------------------------------------
  * Batches.  A batch advances many independent solvers (each with its own

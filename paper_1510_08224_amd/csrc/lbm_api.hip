@@ -154,15 +154,30 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
     return LBM_OK;
 }
 
+// Memory policy from the footprint of both population buffers, measured on
+// MI355X (1024^2 to 4096^2 lattices, every storage): when both fit the
+// 256 MB last-level cache, stores keep their lines there (FP16 2048^2:
+// +34%); above it non-temporal stores win.  XCD row bands win up to about
+// half a gigabyte (FP32 2048^2, 470 MB: +16%), column strips above (FP16
+// 3072^2, 528 MB: +11%; FP16 4096^2: +8%).
+static void default_policy(lbm_solver* h) {
+    const double ws = 2.0 * (double)h->buf_bytes;
+    h->L.keep = ws <= 256.0 * 1024 * 1024;
+    h->L.remap = ws <= 500.0 * 1024 * 1024;
+}
+
 static void default_launch(lbm_solver* h) {
-    // Measured on MI355X at 2048^2: 64 x 4 blocks for FP64 storage, full
-    // 256-wide rows for FP32/FP16; one row per thread (more rows per thread
-    // cost occupancy and lose bandwidth).
-    int bx = h->storage == LBM_F64 ? 64 : 256;
+    // Measured on MI355X (1024^2 to 4096^2, every model and storage): 64 x 4
+    // blocks for FP64 storage and for any state of up to about 320 MB, full
+    // 256-wide rows for larger FP32/FP16 states; one row per thread (more
+    // rows per thread cost occupancy and lose bandwidth).
+    const double ws = 2.0 * (double)h->buf_bytes;
+    int bx = (h->storage == LBM_F64 || ws <= 320.0 * 1024 * 1024) ? 64 : 256;
     while (bx > 64 && bx / 2 >= h->nx) bx /= 2;
     h->L.bx = bx;
     h->L.by = 256 / bx;
     h->L.rows = 1;
+    default_policy(h);
     // Small lattices finish a sweep in a few microseconds, less than a
     // kernel launch costs: replay captured graphs of many sweeps instead.
     h->graph_steps = ((long long)h->nx * h->ny <= (1ll << 18)) ? 64 : 0;
@@ -753,26 +768,36 @@ int lbm_load_state(lbm_solver* h, const void* host, uint64_t bytes) {
     return LBM_OK;
 }
 
-int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread) {
+int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread, int32_t policy) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_set_launch: NULL handle");
     Launch L = h->L;
     if (block_x) L.bx = block_x;
     if (block_y) L.by = block_y;
     if (rows_per_thread) L.rows = rows_per_thread;
     if (!(L.bx == 64 || L.bx == 128 || L.bx == 256) || L.by < 1 || L.bx * L.by > 256 ||
-        !(L.rows == 1 || L.rows == 2 || L.rows == 4))
-        return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2,4}");
+        !(L.rows == 1 || L.rows == 2))
+        return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2}");
+    if (policy < LBM_POLICY_DEFAULT || policy > (LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES))
+        return fail(h, LBM_ERR_ARG, "lbm_set_launch: unknown policy");
     h->L = L;
+    if (policy == LBM_POLICY_DEFAULT) {
+        default_policy(h);
+    } else if (policy >= 0) {
+        h->L.remap = (policy & LBM_POLICY_XCD_BANDS) != 0;
+        h->L.keep = (policy & LBM_POLICY_KEEP_STORES) != 0;
+    }
     drop_graphs(h);
     if (h->batch) batch_invalidate(h->batch);
     return LBM_OK;
 }
 
-int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread) {
+int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread,
+                   int32_t* policy) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_get_launch: NULL handle");
     if (block_x) *block_x = h->L.bx;
     if (block_y) *block_y = h->L.by;
     if (rows_per_thread) *rows_per_thread = h->L.rows;
+    if (policy) *policy = (h->L.remap ? LBM_POLICY_XCD_BANDS : 0) | (h->L.keep ? LBM_POLICY_KEEP_STORES : 0);
     return LBM_OK;
 }
 

@@ -85,6 +85,15 @@ struct Coeffs {
     float fscale, finv, gscale, ginv;
 };
 
+// Per-side constants of the NEE rebuild picked by a lane-varying side
+// index, as a chain of selects.
+__device__ __forceinline__ double by_side(const double (&a)[4], int s) {
+    return s == 0 ? a[0] : (s == 1 ? a[1] : (s == 2 ? a[2] : a[3]));
+}
+__device__ __forceinline__ int by_side(const int (&a)[4], int s) {
+    return s == 0 ? a[0] : (s == 1 ? a[1] : (s == 2 ? a[2] : a[3]));
+}
+
 // ---------------------------------------------------------------------------
 // Storage codecs.  FP64 holds full populations; FP32 and FP16 hold
 // deviations from the rest equilibrium.
@@ -238,11 +247,15 @@ __device__ __forceinline__ void pull_interior(const S* __restrict__ src, const G
 // ---------------------------------------------------------------------------
 // Buffer-resource access (one descriptor for a whole population buffer,
 // per-plane offsets in scalar registers, one 32-bit lane offset shared by
-// all planes).  Usable while the buffer is below 4 GiB.  Stores are
-// non-temporal: the written buffer is not read again in the same step.
+// all planes).  Usable while the buffer is below 4 GiB.  Stores carry the
+// cache policy CP: non-temporal (the written buffer is not read again in
+// the same step, so it need not displace what is) or default (when both
+// buffers fit the 256 MB last-level cache, the written buffer is read by
+// the next step and is worth keeping there).
 // ---------------------------------------------------------------------------
 typedef unsigned int lbm_v2u __attribute__((ext_vector_type(2)));
 constexpr int kCachePolicyNT = 2;
+constexpr int kCachePolicyDefault = 0;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
     // dword 3 = 0x00020000: 32-bit data format, the raw-buffer setting of gfx9-class GPUs
@@ -254,18 +267,20 @@ template <> struct Buf<double> {
     __device__ static __forceinline__ double load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float) {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
     }
+    template <int CP>
     __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double v,
                                                  float) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lbm_v2u, v), r, vo, so, kCachePolicyNT);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lbm_v2u, v), r, vo, so, CP);
     }
 };
 template <> struct Buf<float> {
     __device__ static __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
     }
+    template <int CP>
     __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v,
                                                  float) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, kCachePolicyNT);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, CP);
     }
 };
 template <> struct Buf<__half> {
@@ -273,10 +288,11 @@ template <> struct Buf<__half> {
         const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
         return __half2float(__ushort_as_half(u)) * inv;
     }
+    template <int CP>
     __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v,
                                                  float scale) {
         const unsigned short u = __half_as_ushort(__float2half_rn(v * scale));
-        __builtin_amdgcn_raw_buffer_store_b16(u, r, vo, so, kCachePolicyNT);
+        __builtin_amdgcn_raw_buffer_store_b16(u, r, vo, so, CP);
     }
 };
 
@@ -517,15 +533,18 @@ __device__ void nee_node(const S* __restrict__ src, const Geom& G, const Coeffs&
     const int sx = onL ? kLeft : (onR ? kRight : -1);
     const int sy = onB ? kBottom : (onT ? kTop : -1);
     const int vs = sy >= 0 ? sy : sx;
-    const int ts = (sy >= 0 && C.tdir[sy]) ? sy : ((sx >= 0 && C.tdir[sx]) ? sx : -1);
+    const int ts = (sy >= 0 && by_side(C.tdir, sy)) ? sy : ((sx >= 0 && by_side(C.tdir, sx)) ? sx : -1);
     R ff[9], gf[NG > 0 ? NG : 1];
     pull_node<S, NG>(src, G, C, fx, fy, ff, gf);
     const Macro m = macro<R, NG>(ff, gf, C);
-    const double uwx = C.uw[vs][0], uwy = C.uw[vs][1];
+    const double uwx = vs == 0 ? C.uw[0][0] : (vs == 1 ? C.uw[1][0] : (vs == 2 ? C.uw[2][0] : C.uw[3][0]));
+    const double uwy = vs == 0 ? C.uw[0][1] : (vs == 1 ? C.uw[1][1] : (vs == 2 ? C.uw[2][1] : C.uw[3][1]));
+#pragma unroll
     for (int i = 0; i < 9; ++i)
         f[i] = (R)(feq_rep(i, m.rho, uwx, uwy) + ((double)ff[i] - feq_rep(i, m.rho, m.ux, m.uy)));
     if constexpr (NG > 0) {
-        const double Tb = ts >= 0 ? C.wT[ts] : m.T;
+        const double Tb = ts >= 0 ? by_side(C.wT, ts) : m.T;
+#pragma unroll
         for (int i = 0; i < NG; ++i)
             g[i] = (R)(geq_rep<NG>(i, Tb, uwx, uwy, C) + ((double)gf[i] - geq_rep<NG>(i, m.T, m.ux, m.uy, C)));
     }

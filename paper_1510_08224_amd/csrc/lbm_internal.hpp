@@ -12,6 +12,8 @@ enum Storage { kF64 = 0, kF32 = 1, kF16 = 2 };
 struct Launch {
     int bx = 256, by = 1, rows = 1;
     bool buffer = true;  // buffer-resource addressing when the buffer is below 4 GiB
+    bool remap = true;   // XCD row bands (true) or column strips (false)
+    bool keep = false;   // default-policy stores (true) or non-temporal stores (false)
 };
 
 // A lattice of a batch as the batched step kernel sees it.

@@ -24,10 +24,15 @@ namespace lbm {
 
 constexpr int gdim(int NG) { return NG > 0 ? NG : 1; }
 
-// Workgroup b runs on XCD b % 8 of the MI355X.  Remap so that each XCD
-// walks a contiguous range of tiles (neighbouring tiles share cache lines of
-// the x-shifted pulls; keeping them on one XCD keeps those lines in one L2).
-__device__ __forceinline__ int xcd_remap(int b, int n) {
+// Workgroup b runs on XCD b % 8 of the MI355X.  The remap gives each XCD a
+// contiguous range of tiles (a band of rows: the lines that the y-shifted
+// pulls of neighbouring tiles share stay in one L2).  Without it, when a
+// row holds a multiple of 8 tiles, XCD k takes the tile columns k, k + 8,
+// ... of every row: column strips, which share lines vertically too, and
+// all XCDs stream through the same rows together.  Which is faster depends
+// on how much of the state the caches hold; the host picks.
+__device__ __forceinline__ int xcd_remap(int b, int n, int remap) {
+    if (!remap) return b;
     const int xcd = b & 7, idx = b >> 3;
     const int q = n >> 3, r = n & 7;
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
@@ -44,17 +49,26 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, const Geom& G, c
         Codec<S>::store(at_bytes(dst + (long long)(9 + i) * G.plane, boff), g[i], C.gscale);
 }
 
-template <class S, int NG>
+template <class S, int NG, int CP>
 __device__ __forceinline__ void store_node_buf(__amdgpu_buffer_rsrc_t r, const Geom& G, const Coeffs& C,
                                                unsigned boff, const typename Codec<S>::R f[9],
                                                const typename Codec<S>::R g[gdim(NG)]) {
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        Buf<S>::store(r, boff, (unsigned)((long long)i * G.plane * (long long)sizeof(S)), f[i], C.fscale);
+        Buf<S>::template store<CP>(r, boff, (unsigned)((long long)i * G.plane * (long long)sizeof(S)), f[i],
+                                   C.fscale);
 #pragma unroll
     for (int i = 0; i < NG; ++i)
-        Buf<S>::store(r, boff, (unsigned)((long long)(9 + i) * G.plane * (long long)sizeof(S)), g[i], C.gscale);
+        Buf<S>::template store<CP>(r, boff, (unsigned)((long long)(9 + i) * G.plane * (long long)sizeof(S)), g[i],
+                                   C.gscale);
 }
+
+// Addressing and store modes of the step kernels.
+enum Mode {
+    kGlobal = 0,     // 64-bit addresses, non-temporal stores (buffers of 4 GiB or more)
+    kBufferNT = 1,   // buffer descriptors, non-temporal stores
+    kBufferKeep = 2  // buffer descriptors, default-policy stores (state fits the last-level cache)
+};
 
 // One time step of the nodes (x, y0 .. y0 + ROWS - 1) of one lattice.
 // Fast path (wave-uniform): a wave whose 64 columns all lie in the lattice
@@ -62,9 +76,9 @@ __device__ __forceinline__ void store_node_buf(__amdgpu_buffer_rsrc_t r, const G
 // with one shared lane offset, all ROWS x (9 + NG) loads issued before any
 // arithmetic; lanes in the first or last column then correct their
 // x-shifted pulls.  Waves touching the bottom or top row, or the ragged
-// right end, resolve walls and wraps per link.  BUF selects buffer-resource
-// addressing (buffers below 4 GiB) over global addressing.
-template <class S, int NG, int ROWS, bool BUF>
+// right end, resolve walls and wraps per link.  MODE selects the addressing
+// and the store policy of the fast path.
+template <class S, int NG, int ROWS, int MODE>
 __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, const S* __restrict__ src,
                                             S* __restrict__ dst, int x, int y0, unsigned buf_bytes) {
     using R = typename Codec<S>::R;
@@ -76,7 +90,7 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
         unsigned boff[ROWS];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) boff[r] = (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S);
-        if (BUF) {
+        if (MODE != kGlobal) {
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) pull_interior_buf<S, NG>(rs, G, C, boff[r], f[r], g[r]);
@@ -92,8 +106,12 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
         for (int r = 0; r < ROWS; ++r) {
             const Macro m = macro<R, NG>(f[r], g[r], C);
             collide<R, NG>(f[r], g[r], m, C);
-            if (BUF) store_node_buf<S, NG>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
-            else store_node<S, NG>(dst, G, C, boff[r], f[r], g[r]);
+            if (MODE == kBufferNT)
+                store_node_buf<S, NG, kCachePolicyNT>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
+            else if (MODE == kBufferKeep)
+                store_node_buf<S, NG, kCachePolicyDefault>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
+            else
+                store_node<S, NG>(dst, G, C, boff[r], f[r], g[r]);
         }
         return;
     }
@@ -113,32 +131,32 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
 }
 
 // One time step of one lattice: tiles of blockDim.x x (blockDim.y * ROWS)
-// nodes, walked XCD by XCD.
-template <class S, int NG, int ROWS, bool BUF>
+// nodes, in row bands per XCD (remap) or in column strips.
+template <class S, int NG, int ROWS, int MODE>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
-                                               S* __restrict__ dst, int tiles_x, unsigned buf_bytes) {
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+                                               S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int remap) {
+    const int tile = xcd_remap(blockIdx.x, gridDim.x, remap);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x = tx * blockDim.x + threadIdx.x;
     const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
-    sweep_nodes<S, NG, ROWS, BUF>(G, C, src, dst, x, y0, buf_bytes);
+    sweep_nodes<S, NG, ROWS, MODE>(G, C, src, dst, x, y0, buf_bytes);
 }
 
 // One time step of every lattice of a batch.  Each workgroup of 256
 // threads takes one entry of the tile table: a member lattice and a tile
 // of bx x (256 / bx) nodes at (x0, y0).  Member m reads buffer
 // (cur0 + parity) & 1 and writes the other one.
-template <class S, int NG, bool BUF>
+template <class S, int NG, int MODE>
 __global__ __launch_bounds__(256) void k_sweep_batch(const BatchMember* __restrict__ members,
                                                      const BatchTile* __restrict__ tiles, int parity) {
-    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, 1)];
     const BatchMember& M = members[t.member];
     const int sel = (M.cur0 + parity) & 1;
     const S* src = static_cast<const S*>(M.buf[sel]);
     S* dst = static_cast<S*>(M.buf[sel ^ 1]);
     const int x = t.x0 + (int)(threadIdx.x % (unsigned)t.bx);
     const int y = t.y0 + (int)(threadIdx.x / (unsigned)t.bx);
-    sweep_nodes<S, NG, 1, BUF>(M.G, M.C, src, dst, x, y, M.buf_bytes);
+    sweep_nodes<S, NG, 1, MODE>(M.G, M.C, src, dst, x, y, M.buf_bytes);
 }
 
 template <class S, int NG>
@@ -484,31 +502,34 @@ static inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / 
         default: return hipErrorInvalidValue;                                             \
     }
 
-template <class S, int NG, bool BUF>
+template <class S, int NG, int MODE>
 static void sweep_launch(int rows, dim3 grid, dim3 block, hipStream_t st, const Geom& G, const Coeffs& C,
-                         const S* s, S* d, int tiles_x, unsigned bytes) {
-    switch (rows) {
-        case 1: hipLaunchKernelGGL((k_sweep<S, NG, 1, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
-        case 2: hipLaunchKernelGGL((k_sweep<S, NG, 2, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
-        default: hipLaunchKernelGGL((k_sweep<S, NG, 4, BUF>), grid, block, 0, st, G, C, s, d, tiles_x, bytes); break;
-    }
+                         const S* s, S* d, int tiles_x, unsigned bytes, int remap) {
+    if (rows == 1)
+        hipLaunchKernelGGL((k_sweep<S, NG, 1, MODE>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, remap);
+    else
+        hipLaunchKernelGGL((k_sweep<S, NG, 2, MODE>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, remap);
 }
 
 template <class S, int NG>
 static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const void* src, void* dst,
                           hipStream_t st) {
     const int rows = L.rows;
-    if (rows != 1 && rows != 2 && rows != 4) return hipErrorInvalidValue;
+    if (rows != 1 && rows != 2) return hipErrorInvalidValue;
     const int tiles_x = (G.nx + L.bx - 1) / L.bx;
     const int tiles_y = (G.ny + L.by * rows - 1) / (L.by * rows);
     const int nt = tiles_x * tiles_y;
     const S* s = static_cast<const S*>(src);
     S* d = static_cast<S*>(dst);
     const unsigned long long bytes = (unsigned long long)(9 + NG) * (unsigned long long)G.plane * sizeof(S);
-    if (L.buffer && bytes < (1ull << 32))
-        sweep_launch<S, NG, true>(rows, dim3(nt), dim3(L.bx, L.by), st, G, C, s, d, tiles_x, (unsigned)bytes);
+    const dim3 grid(nt), block(L.bx, L.by);
+    const int remap = L.remap ? 1 : 0;
+    if (!L.buffer || bytes >= (1ull << 32))
+        sweep_launch<S, NG, kGlobal>(rows, grid, block, st, G, C, s, d, tiles_x, 0u, remap);
+    else if (L.keep)
+        sweep_launch<S, NG, kBufferKeep>(rows, grid, block, st, G, C, s, d, tiles_x, (unsigned)bytes, remap);
     else
-        sweep_launch<S, NG, false>(rows, dim3(nt), dim3(L.bx, L.by), st, G, C, s, d, tiles_x, 0u);
+        sweep_launch<S, NG, kBufferNT>(rows, grid, block, st, G, C, s, d, tiles_x, (unsigned)bytes, remap);
     return hipGetLastError();
 }
 
@@ -522,8 +543,10 @@ hipError_t launch_sweep_batch(int storage, int ng, bool buffer, const BatchMembe
                               int ntiles, int parity, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     LBM_DISPATCH(storage, ng, {
-        if (buffer) hipLaunchKernelGGL((k_sweep_batch<S, NG, true>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
-        else hipLaunchKernelGGL((k_sweep_batch<S, NG, false>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+        if (buffer)
+            hipLaunchKernelGGL((k_sweep_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+        else
+            hipLaunchKernelGGL((k_sweep_batch<S, NG, kGlobal>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
     });
     return hipGetLastError();
 }

@@ -28,6 +28,7 @@ LBM_BC_PERIODIC, LBM_BC_WALL, LBM_BC_NEE = 0, 1, 2
 LBM_T_PERIODIC, LBM_T_DIRICHLET, LBM_T_ADIABATIC, LBM_T_NEE_DIRICHLET, LBM_T_NEE_ADIABATIC = 0, 1, 2, 3, 4
 
 LBM_MODEL_D2Q5, LBM_MODEL_D2Q9T, LBM_MODEL_ISOTHERMAL = 0, 1, 2
+LBM_POLICY_DEFAULT, LBM_POLICY_KEEP, LBM_POLICY_XCD_BANDS, LBM_POLICY_KEEP_STORES = -2, -1, 1, 2
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16}
 MODEL = {"d2q5": LBM_MODEL_D2Q5, "d2q9t": LBM_MODEL_D2Q9T, "isothermal": LBM_MODEL_ISOTHERMAL}
 MODEL_NG = {LBM_MODEL_D2Q5: 5, LBM_MODEL_D2Q9T: 9, LBM_MODEL_ISOTHERMAL: 0}
@@ -88,9 +89,9 @@ _SIGS = {
     "lbm_stream": (_P, [_P]),
     "lbm_storage_of": (ctypes.c_int32, [_P]),
     "lbm_model_of": (ctypes.c_int32, [_P]),
-    "lbm_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "lbm_get_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                      ctypes.POINTER(ctypes.c_int32)]),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "lbm_set_graph_steps": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lbm_get_graph_steps": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, _P]),
@@ -158,6 +159,12 @@ def lbm_params_default() -> LbmParams:
     p = LbmParams()
     lib().lbm_params_default(ctypes.byref(p))
     return p
+
+
+def viscous_rate(re: float, length: float, u: float) -> float:
+    """s_nu for a Reynolds number Re = L u / nu with nu = (1/s_nu - 1/2) / 3
+    (lattice units; the rate map of the lid-driven cavity, Sec. 3.2)."""
+    return 1.0 / (0.5 + 3.0 * length * u / re)
 
 
 def lbm_params_from_problem(pb) -> LbmParams:
@@ -263,13 +270,15 @@ class Solver:
             T = np.ascontiguousarray(T, dtype=np.float64).reshape(self.ny, self.nx)
         _check(lib().lbm_init_temperature(self.h, _dp(T)), self.h)
 
-    def set_launch(self, block_x=0, block_y=0, rows=0):
-        _check(lib().lbm_set_launch(self.h, block_x, block_y, rows), self.h)
+    def set_launch(self, block_x=0, block_y=0, rows=0, policy=LBM_POLICY_KEEP):
+        _check(lib().lbm_set_launch(self.h, block_x, block_y, rows, policy), self.h)
 
     def get_launch(self):
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().lbm_get_launch(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), self.h)
-        return a.value, b.value, c.value
+        """(block_x, block_y, rows_per_thread, policy mask)."""
+        a, b, c, d = (ctypes.c_int32() for _ in range(4))
+        _check(lib().lbm_get_launch(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
+               self.h)
+        return a.value, b.value, c.value, d.value
 
     def set_graph_steps(self, steps: int):
         _check(lib().lbm_set_graph_steps(self.h, int(steps)), self.h)

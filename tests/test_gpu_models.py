@@ -29,7 +29,9 @@ def _check(pb, S, L, model, tol=TOL):
     assert ef < tol and eg < tol, (ef, eg)
     us, ts = field_scale(pb)
     mg, mo = S.moments(), L.moments()
-    us = max(us, float(np.max(np.abs(mo[1]))), float(np.max(np.abs(mo[2]))))   # force-driven flows
+    # u is a sum of populations of order w_i (|du| <= sum |df_i|): for slow
+    # force-driven flows the bar is not relative to the small flow speed
+    us = max(us, 1e-2)
     assert np.max(np.abs(mg[0] - mo[0])) < tol
     assert np.max(np.abs(mg[1] - mo[1])) < tol * us and np.max(np.abs(mg[2] - mo[2])) < tol * us
     assert np.max(np.abs(mg[3] - mo[3])) < tol * ts
@@ -145,7 +147,7 @@ def test_isothermal_lid_cavity_long_run():
     S.close()
 
 
-@pytest.mark.parametrize("launch", [(64, 4, 1), (128, 2, 2), (256, 1, 1)])
+@pytest.mark.parametrize("launch", [(64, 4, 1, 0), (128, 2, 2, 3), (256, 1, 1, 2)])
 @pytest.mark.parametrize("model", ["d2q9t", "isothermal"])
 def test_launch_shape_does_not_change_results(model, launch):
     pb = W.cavity(150, 1e5, ny=70) if model == "d2q9t" else _lid(150).replace(ny=70)

@@ -120,8 +120,9 @@ def test_parity_cavity64_20000_steps():
     S.close()
 
 
-@pytest.mark.parametrize("launch", [(64, 4, 1), (128, 2, 2), (256, 1, 4), (64, 1, 2), (128, 1, 1)])
-def test_launch_shape_does_not_change_results(launch):
+@pytest.mark.parametrize("launch", [(64, 4, 1, 0), (128, 2, 2, 3), (256, 1, 2, 1), (64, 1, 2, 2),
+                                    (128, 1, 1, lbm.LBM_POLICY_DEFAULT)])
+def test_launch_shape_and_policy_do_not_change_results(launch):
     pb = W.cavity(150, 1e5, ny=70)
     T = W.random_temperature(150, 70, 0.0, 1.0, seed=8)
     ref = lbm.Solver(150, 70, "f64")
@@ -137,6 +138,42 @@ def test_launch_shape_does_not_change_results(launch):
     fb, gb = S.get_populations()
     assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
     ref.close(); S.close()
+
+
+@pytest.mark.parametrize("n,storage,policy", [(64, "f64", 3), (2048, "f64", 0), (2048, "f32", 1), (2048, "f16", 3),
+                                              (3072, "f16", 0), (4096, "f16", 0)])
+def test_default_policy_follows_footprint(n, storage, policy):
+    S = lbm.Solver(n, n, storage)
+    assert S.get_launch()[3] == policy
+    S.set_launch(policy=lbm.LBM_POLICY_XCD_BANDS)
+    assert S.get_launch()[3] == lbm.LBM_POLICY_XCD_BANDS
+    S.set_launch(policy=lbm.LBM_POLICY_DEFAULT)
+    assert S.get_launch()[3] == policy
+    with pytest.raises(lbm.LbmError):
+        S.set_launch(policy=4)
+    with pytest.raises(lbm.LbmError):
+        S.set_launch(rows=4)
+    S.close()
+
+
+def test_autotune_keeps_state_and_results():
+    from paper_1510_08224_amd import tuning
+    pb = W.cavity(150, 1e5, ny=70)
+    T = W.random_temperature(150, 70, 0.0, 1.0, seed=8)
+    runs = []
+    for tune in (False, True):
+        S = lbm.Solver(150, 70, "f64")
+        S.set_params(pb)
+        S.init_temperature(T)
+        S.step(7)
+        if tune:
+            bx, pol, gbs = tuning.autotune(S, steps=4)
+            assert S.get_launch()[0] == bx and S.get_launch()[3] == pol and gbs > 0
+            assert S.time == 7
+        S.step(30)
+        runs.append(S.get_populations())
+        S.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
 
 
 def test_set_get_roundtrip_and_checkpoint():
