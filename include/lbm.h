@@ -79,6 +79,20 @@ enum lbm_side { LBM_LEFT = 0, LBM_RIGHT = 1, LBM_BOTTOM = 2, LBM_TOP = 3 };
  *   is the external acceleration a only. */
 enum lbm_model { LBM_MODEL_D2Q5 = 0, LBM_MODEL_D2Q9T = 1, LBM_MODEL_ISOTHERMAL = 2 };
 
+/* Collision operator (lbm_params.collision).
+ * LBM_COLLISION_MRT: the paper's non-orthogonal MRT (Eqs. 8, 24), the
+ *   default.
+ * LBM_COLLISION_BGK and LBM_COLLISION_ORTHO_MRT: the two operators Sec. 3.2
+ *   compares it with.  BGK relaxes every flow population at s_nu (f^eq of
+ *   Eq. 22, Guo source in velocity space) and every temperature population
+ *   at zeta_alpha (g^eq of Eq. 30 or 31).  ORTHO_MRT is the classical MRT on
+ *   the orthogonal D2Q9 basis (Gram-Schmidt of 1, |e|^2, |e|^4, e_x,
+ *   e_x|e|^2, e_y, e_y|e|^2, e_x^2 - e_y^2, e_x e_y), m^eq = M_o f^eq,
+ *   sources M_o S, with s_e, s_eps, s_q, s_nu on the energy, energy-square,
+ *   heat-flux and stress moments; the temperature keeps the model's MRT.
+ *   Both run one row per thread and cannot join a batch. */
+enum lbm_collision { LBM_COLLISION_MRT = 0, LBM_COLLISION_BGK = 1, LBM_COLLISION_ORTHO_MRT = 2 };
+
 /* Flow boundary per side.  LBM_BC_WALL is halfway bounce-back with the
  * moving-wall term: the wall lies half a spacing outside the last node,
  * and a population leaving node x through it returns to x in the opposite
@@ -119,6 +133,8 @@ typedef struct {
     double ax, ay;                 /* external acceleration a (Eq. 4) */
     int32_t bc_flow[4];            /* enum lbm_bc_flow, indexed by enum lbm_side */
     int32_t bc_temp[4];            /* enum lbm_bc_temp */
+    int32_t collision;             /* enum lbm_collision; LBM_COLLISION_MRT */
+    int32_t reserved1;
     double wall_T[4];              /* Dirichlet wall temperatures */
     double wall_u[4][2];           /* wall velocities (ux, uy) */
 } lbm_params;

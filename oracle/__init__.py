@@ -39,6 +39,7 @@ TEMP_PERIODIC, TEMP_DIRICHLET, TEMP_ADIABATIC, TEMP_NEE_DIRICHLET, TEMP_NEE_ADIA
 MODEL_D2Q5, MODEL_D2Q9T, MODEL_ISOTHERMAL = 0, 1, 2
 MODELS = {"d2q5": MODEL_D2Q5, "d2q9t": MODEL_D2Q9T, "isothermal": MODEL_ISOTHERMAL}
 MODEL_NG = {MODEL_D2Q5: 5, MODEL_D2Q9T: 9, MODEL_ISOTHERMAL: 0}
+COLL_MRT, COLL_BGK, COLL_ORTHO = 0, 1, 2
 
 CS2 = 1.0 / 3.0  # D2Q9 lattice sound speed squared (Sec. 2.1, after Eq. 19)
 
@@ -61,7 +62,7 @@ class OrcParams(ctypes.Structure):
         ("ax", ctypes.c_double), ("ay", ctypes.c_double),
         ("bc_flow", ctypes.c_int32 * 4), ("bc_temp", ctypes.c_int32 * 4),
         ("wall_T", ctypes.c_double * 4), ("wall_u", (ctypes.c_double * 2) * 4),
-        ("s8_literal", ctypes.c_int32),
+        ("s8_literal", ctypes.c_int32), ("collision", ctypes.c_int32),
     ]
 
 
@@ -204,6 +205,7 @@ def make_params(pb, s8_literal: bool = False, overrides: dict | None = None,
         p.wall_u[k][0] = float(pb.wall_u[k][0])
         p.wall_u[k][1] = float(pb.wall_u[k][1])
     p.s8_literal = 1 if s8_literal else 0
+    p.collision = int(getattr(pb, "collision", COLL_MRT))
     return p
 
 

@@ -8,6 +8,19 @@
  *   MODEL_D2Q9T     the D2Q9 thermal model (Eqs. 31-32);
  *   MODEL_ISOTHERMAL no temperature field: the flow alone, driven by the
  *                   acceleration a and the walls (Secs. 3.1, 3.2).
+ * The collision operator is the paper's non-orthogonal MRT, or one of the
+ * two operators Sec. 3.2 compares it with:
+ *   COLL_BGK        single relaxation time: fbar* = fbar - w (fbar - f^eq)
+ *                   + (1 - w/2) S with w = s_nu and the Guo source S in
+ *                   velocity space; g* = g - zeta (g - g^eq), zeta =
+ *                   zeta_alpha;
+ *   COLL_ORTHO      the classical MRT with an orthogonal basis: M_o is built
+ *                   by Gram-Schmidt from the monomials 1, |e|^2, |e|^4, e_x,
+ *                   e_x |e|^2, e_y, e_y |e|^2, e_x^2 - e_y^2, e_x e_y (the
+ *                   paper does not print it), m^eq = M_o f^eq, source moments
+ *                   M_o S, rates s_e, s_eps, s_q, s_nu on the energy, energy
+ *                   square, heat-flux and stress moments; the temperature
+ *                   keeps the model's own MRT.
  *
  * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the tests, the smoke check
  * and the CPU-baseline leg of the benchmark load this library.  It shares
@@ -109,6 +122,7 @@ static const double NI5[5][5] = {
     {0, 0, -0.5, 0.25, -0.25}};
 
 enum { MODEL_D2Q5 = 0, MODEL_D2Q9T = 1, MODEL_ISOTHERMAL = 2 };
+enum { COLL_MRT = 0, COLL_BGK = 1, COLL_ORTHO = 2 };
 enum { SIDE_LEFT = 0, SIDE_RIGHT = 1, SIDE_BOTTOM = 2, SIDE_TOP = 3 };
 enum { FLOW_PERIODIC = 0, FLOW_WALL = 1, FLOW_NEE = 2 };
 enum { TEMP_PERIODIC = 0, TEMP_DIRICHLET = 1, TEMP_ADIABATIC = 2, TEMP_NEE_DIRICHLET = 3,
@@ -130,6 +144,7 @@ typedef struct {
     double wall_T[4];
     double wall_u[4][2];
     int32_t s8_literal;
+    int32_t collision; /* COLL_* */
 } orc_params;
 
 typedef struct {
@@ -188,12 +203,103 @@ static void macroscopic(const orc_params* p, const double f[9], const double* g,
     *Fy = fy;
 }
 
-void orc_collide_node(const orc_params* p, const double f[9], const double* g,
-                      double fo[9], double* go) {
-    double rho, ux, uy, T, Fx, Fy;
-    macroscopic(p, f, g, &rho, &ux, &uy, &T, &Fx, &Fy);
-    const double r0 = p->rho0;
+/* f_i^eq of Eq. 22 under reading R1. */
+static double feq_i(const orc_params* p, int i, double rho, double ux, double uy) {
+    double eu = EX[i] * ux + EY[i] * uy;
+    double usq = ux * ux + uy * uy;
+    return W9[i] * (rho + p->rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+}
 
+/* The Guo forcing term in velocity space, whose moments Eq. 10 calls S~:
+ * S_i = w_i rho0 [3 (e_i - u).F + 9 (e_i.u)(e_i.F)]. */
+static double guo_i(const orc_params* p, int i, double ux, double uy, double Fx, double Fy) {
+    double eu = EX[i] * ux + EY[i] * uy;
+    double eF = EX[i] * Fx + EY[i] * Fy;
+    double uF = ux * Fx + uy * Fy;
+    return W9[i] * p->rho0 * (3.0 * (eF - uF) + 9.0 * eu * eF);
+}
+
+/* Orthogonal D2Q9 basis by Gram-Schmidt (plain dot product over the nine
+ * velocities) of the monomials 1, |e|^2, |e|^4, e_x, e_x|e|^2, e_y,
+ * e_y|e|^2, e_x^2 - e_y^2, e_x e_y; its inverse is M_o^T diag(1/|row|^2). */
+static double MO9[9][9], MOI9[9][9];
+static int mo9_ready = 0;
+
+static void ortho_basis(void) {
+    if (mo9_ready) return;
+    double v[9][9];
+    for (int i = 0; i < 9; ++i) {
+        double x = EX[i], y = EY[i], r = x * x + y * y;
+        v[0][i] = 1.0;
+        v[1][i] = r;
+        v[2][i] = r * r;
+        v[3][i] = x;
+        v[4][i] = x * r;
+        v[5][i] = y;
+        v[6][i] = y * r;
+        v[7][i] = x * x - y * y;
+        v[8][i] = x * y;
+    }
+    for (int k = 0; k < 9; ++k) {
+        for (int j = 0; j < k; ++j) {
+            double num = 0.0, den = 0.0;
+            for (int i = 0; i < 9; ++i) {
+                num += v[k][i] * MO9[j][i];
+                den += MO9[j][i] * MO9[j][i];
+            }
+            for (int i = 0; i < 9; ++i) v[k][i] -= num / den * MO9[j][i];
+        }
+        for (int i = 0; i < 9; ++i) MO9[k][i] = v[k][i];
+    }
+    for (int k = 0; k < 9; ++k) {
+        double n2 = 0.0;
+        for (int i = 0; i < 9; ++i) n2 += MO9[k][i] * MO9[k][i];
+        for (int i = 0; i < 9; ++i) MOI9[i][k] = MO9[k][i] / n2;
+    }
+    mo9_ready = 1;
+}
+
+static void collide_flow_bgk(const orc_params* p, const double f[9], double rho, double ux, double uy,
+                             double Fx, double Fy, double fo[9]) {
+    const double w = p->s[4];
+    for (int i = 0; i < 9; ++i)
+        fo[i] = f[i] - w * (f[i] - feq_i(p, i, rho, ux, uy)) + (1.0 - 0.5 * w) * guo_i(p, i, ux, uy, Fx, Fy);
+}
+
+static void collide_flow_ortho(const orc_params* p, const double f[9], double rho, double ux, double uy,
+                               double Fx, double Fy, double fo[9]) {
+    ortho_basis();
+    /* rates along the basis: conserved moments 1, then e, eps, -, q_x, -,
+     * q_y, p_xx, p_xy */
+    const double s[9] = {1.0, p->s[3], p->s[8], 1.0, p->s[6], 1.0, p->s[6], p->s[4], p->s[4]};
+    double feq[9], S[9], m[9], meq[9], ms[9], sm[9];
+    for (int i = 0; i < 9; ++i) {
+        feq[i] = feq_i(p, i, rho, ux, uy);
+        S[i] = guo_i(p, i, ux, uy, Fx, Fy);
+    }
+    for (int k = 0; k < 9; ++k) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            a += MO9[k][i] * f[i];
+            b += MO9[k][i] * feq[i];
+            c += MO9[k][i] * S[i];
+        }
+        m[k] = a;
+        meq[k] = b;
+        sm[k] = c;
+    }
+    for (int k = 0; k < 9; ++k) ms[k] = m[k] - s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * s[k]) * sm[k];
+    for (int i = 0; i < 9; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < 9; ++k) acc += MOI9[i][k] * ms[k];
+        fo[i] = acc;
+    }
+}
+
+/* The paper's flow collision: Eq. 8 in the moment space of M (Eq. 13). */
+static void collide_flow_mrt(const orc_params* p, const double f[9], double rho, double ux, double uy,
+                             double Fx, double Fy, double fo[9]) {
+    const double r0 = p->rho0;
     /* m_bar = M fbar (Eq. 10, dense product) */
     double m[9];
     for (int k = 0; k < 9; ++k) {
@@ -235,7 +341,12 @@ void orc_collide_node(const orc_params* p, const double f[9], const double* g,
         for (int k = 0; k < 9; ++k) acc += MI9[i][k] * ms[k];
         fo[i] = acc;
     }
+}
 
+/* The temperature collision of the model: Eq. 24 in the moment space of N
+ * (D2Q5) or of M (D2Q9, reading R6). */
+static void collide_thermal_mrt(const orc_params* p, const double* g, double T, double ux, double uy,
+                                double* go) {
     if (p->model == MODEL_ISOTHERMAL) return;
     if (p->model == MODEL_D2Q9T) {
         /* n = M g, n^eq = M g^eq (Eq. 31, reading R6), Q of Eq. 32 */
@@ -283,6 +394,21 @@ void orc_collide_node(const orc_params* p, const double f[9], const double* g,
     }
 }
 
+void orc_collide_node(const orc_params* p, const double f[9], const double* g,
+                      double fo[9], double* go) {
+    double rho, ux, uy, T, Fx, Fy;
+    macroscopic(p, f, g, &rho, &ux, &uy, &T, &Fx, &Fy);
+    if (p->collision == COLL_BGK) {
+        collide_flow_bgk(p, f, rho, ux, uy, Fx, Fy, fo);
+        const double z = p->q[1];
+        for (int i = 0; i < model_ng(p); ++i) go[i] = g[i] - z * (g[i] - geq_i(p, i, T, ux, uy));
+        return;
+    }
+    if (p->collision == COLL_ORTHO) collide_flow_ortho(p, f, rho, ux, uy, Fx, Fy, fo);
+    else collide_flow_mrt(p, f, rho, ux, uy, Fx, Fy, fo);
+    collide_thermal_mrt(p, g, T, ux, uy, go);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Lattice                                                                    */
 /* ------------------------------------------------------------------------- */
@@ -314,6 +440,7 @@ int orc_check_params(const orc_params* p) {
     if (!(p->rho0 > 0.0)) return -4;
     if (p->model < MODEL_D2Q5 || p->model > MODEL_ISOTHERMAL) return -8;
     if (p->model == MODEL_D2Q9T && !(p->theta == 0.0 || p->theta == 1.0)) return -9;
+    if (p->collision < COLL_MRT || p->collision > COLL_ORTHO) return -10;
     return 0;
 }
 
@@ -383,13 +510,6 @@ void orc_get_state(const orc_lattice* L, double* f, double* g) {
 }
 
 int64_t orc_time(const orc_lattice* L) { return L->t; }
-
-/* f_i^eq of Eq. 22 under reading R1. */
-static double feq_i(const orc_params* p, int i, double rho, double ux, double uy) {
-    double eu = EX[i] * ux + EY[i] * uy;
-    double usq = ux * ux + uy * uy;
-    return W9[i] * (rho + p->rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
-}
 
 static int is_nee(const orc_params* p, int side) { return p->bc_flow[side] == FLOW_NEE; }
 

@@ -306,6 +306,10 @@ static bool rate_ok(double s) { return isfinite(s) && s > 0.0 && s < 2.0; }
 static const double kW9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
 static int derive(lbm_solver* h, const lbm_params* p) {
+    if (p->collision < LBM_COLLISION_MRT || p->collision > LBM_COLLISION_ORTHO_MRT)
+        return fail(h, LBM_ERR_ARG, "lbm_set_params: unknown collision operator");
+    if (p->collision != LBM_COLLISION_MRT && h->batch)
+        return fail(h, LBM_ERR_UNSUPPORTED, "lbm_set_params: batch members use the MRT collision");
     int nee = 0, linkwise = 0;
     for (int s = 0; s < 4; ++s) {
         if (p->bc_flow[s] < LBM_BC_PERIODIC || p->bc_flow[s] > LBM_BC_NEE)
@@ -416,6 +420,7 @@ static int derive(lbm_solver* h, const lbm_params* p) {
         C.uw[s][1] = p->wall_u[s][1];
         C.wT[s] = p->wall_T[s];
     }
+    C.collision = p->collision;
     C.fscale = C.finv = C.gscale = C.ginv = 1.0f;
     if (h->storage == LBM_F16) {
         // Powers of two: deviations of O(0.1) for fbar and of O(|T - T0|)
@@ -872,6 +877,8 @@ int lbm_batch_add(lbm_batch* b, lbm_solver* h, int32_t* slot) {
     if (active && h->ng != b->ng) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: thermal model differs from the batch's");
     if (h->stream != b->stream) return bfail(b, LBM_ERR_ARG, "lbm_batch_add: the solver must use the batch's stream");
     if (!h->params_set) return bfail(b, LBM_ERR_STATE, "lbm_batch_add: call lbm_set_params on the solver first");
+    if (h->C.collision != LBM_COLLISION_MRT)
+        return bfail(b, LBM_ERR_UNSUPPORTED, "lbm_batch_add: batch members use the MRT collision");
     // members keep a residual snapshot so that the batch can take every
     // member's residual in one launch
     if (ensure(h, reinterpret_cast<void**>(&h->snap), 3 * (size_t)h->nx * h->ny * sizeof(double),

@@ -83,6 +83,7 @@ struct Coeffs {
     double uw[4][2], wT[4];
     // Deviation storage scales (FP16): stored = value * scale.
     float fscale, finv, gscale, ginv;
+    int collision;      // 0 the paper's MRT, 1 BGK, 2 orthogonal MRT (Sec. 3.2)
 };
 
 // Per-side constants of the NEE rebuild picked by a lane-varying side
@@ -403,15 +404,15 @@ __device__ __forceinline__ void inverse9(R v[9], R k0, R k1, R k2, R k3, R k4, R
 // expressions act on deviations: the rest state is a fixed point and every
 // map here is affine in rho and T with the rest parts cancelling.
 // ---------------------------------------------------------------------------
-template <class R, int NG>
-__device__ __forceinline__ void collide(R f[9], R g[NG > 0 ? NG : 1], const Macro& mc, const Coeffs& C) {
+template <class R, int NG, bool FLOW_MRT = true>
+__device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const Macro& mc, const Coeffs& C) {
     const R rho = (R)mc.rho;
     const R ux = (R)mc.ux, uy = (R)mc.uy;
     const R Fx = (R)mc.Fx, Fy = (R)mc.Fy;
     const R usq = ux * ux + uy * uy;
     const R uF = ux * Fx + uy * Fy;
     const R third = (R)(1.0 / 3.0);
-    {
+    if constexpr (FLOW_MRT) {
         const Moments9<R> m(f);
         // Relaxation toward m^eq (Eq. 16) with the source of Eq. 17.
         const R s3 = (R)C.s3, s4 = (R)C.s4, s6 = (R)C.s6, s8 = (R)C.s8;
@@ -480,6 +481,126 @@ __device__ __forceinline__ void collide(R f[9], R g[NG > 0 ? NG : 1], const Macr
         const R k7 = m.m7 - z6 * (m.m7 - third * ux * T);
         const R k8 = m.m8 - z8 * (m.m8 - ((R)(1.0 / 9.0) * t0 + third * th * usq * T));
         inverse9<R>(g, t0, k1, k2, k3, k4, k5, k6, k7, k8);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The operators the paper compares its collision with (Sec. 3.2).
+//
+// Single relaxation time (BGK): fbar* = fbar - w (fbar - f^eq) + (1 - w/2) S
+// with w = s_nu, f^eq of Eq. 22 and the Guo source in velocity space,
+// S_i = w_i [3 (e_i - u).F + 9 (e_i.u)(e_i.F)]; g* = g - z (g - g^eq) with
+// z = zeta_alpha and g^eq of Eq. 30 or 31.
+//
+// Classical MRT with an orthogonal basis (the Gram-Schmidt basis of the
+// monomials 1, |e|^2, |e|^4, e_x, e_x|e|^2, e_y, e_y|e|^2, e_x^2 - e_y^2,
+// e_x e_y, scaled to integer rows): moments rho, e, eps, j_x, q_x, j_y, q_y,
+// p_xx, p_xy with equilibria rho, -2 rho + 3|u|^2, rho - 3|u|^2, u_x, -u_x,
+// u_y, -u_y, u_x^2 - u_y^2, u_x u_y (the M_o f^eq of Eq. 22) and sources
+// 0, 6 u.F, -6 u.F, F_x, -F_x, F_y, -F_y, 2 (u_x F_x - u_y F_y),
+// u_x F_y + u_y F_x (M_o S); rates s_e, s_eps, s_q, s_nu; the inverse is
+// M_o^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).  The
+// temperature keeps the model's own MRT.
+// ---------------------------------------------------------------------------
+enum Collision { kCollMRT = 0, kCollBGK = 1, kCollOrtho = 2 };
+
+template <class R>
+__device__ __forceinline__ void collide_flow_bgk(R f[9], const Macro& mc, const Coeffs& C) {
+    const R rho = (R)mc.rho, ux = (R)mc.ux, uy = (R)mc.uy, Fx = (R)mc.Fx, Fy = (R)mc.Fy;
+    const R w = (R)C.s4, a = (R)1 - (R)0.5 * w;
+    const R usq15 = (R)1.5 * (ux * ux + uy * uy);
+    const R uF3 = (R)3 * (ux * Fx + uy * Fy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
+        const R eF = (R)ex(i) * Fx + (R)ey(i) * Fy;
+        const R wi = (R)w9(i);
+        const R feq = wi * (rho + ((R)3 * eu + (R)4.5 * eu * eu - usq15));
+        const R S = wi * (((R)3 * eF - uF3) + (R)9 * eu * eF);
+        f[i] = f[i] - w * (f[i] - feq) + a * S;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void collide_flow_ortho(R f[9], const Macro& mc, const Coeffs& C) {
+    const R rho = (R)mc.rho, ux = (R)mc.ux, uy = (R)mc.uy, Fx = (R)mc.Fx, Fy = (R)mc.Fy;
+    const R usq = ux * ux + uy * uy, uF = ux * Fx + uy * Fy;
+    const R ax = f[1] + f[3], ay = f[2] + f[4];
+    const R a = ax + ay, d = (f[5] + f[6]) + (f[7] + f[8]);
+    const R d13 = f[1] - f[3], d24 = f[2] - f[4];
+    const R sx = (f[5] - f[6]) - (f[7] - f[8]);   // diagonal part of j_x
+    const R sy = (f[5] + f[6]) - (f[7] + f[8]);   // diagonal part of j_y
+    const R m_e = ((R)-4 * f[0] - a) + (R)2 * d;
+    const R m_eps = ((R)4 * f[0] - (R)2 * a) + d;
+    const R m_qx = (R)-2 * d13 + sx;
+    const R m_qy = (R)-2 * d24 + sy;
+    const R m_xx = ax - ay;
+    const R m_xy = (f[5] - f[6]) + (f[7] - f[8]);
+    const R s_e = (R)C.s3, s_eps = (R)C.s8, s_q = (R)C.s6, s_nu = (R)C.s4;
+    const R k_e = m_e - s_e * (m_e - ((R)-2 * rho + (R)3 * usq)) + ((R)1 - (R)0.5 * s_e) * ((R)6 * uF);
+    const R k_eps = m_eps - s_eps * (m_eps - (rho - (R)3 * usq)) + ((R)1 - (R)0.5 * s_eps) * ((R)-6 * uF);
+    const R k_qx = m_qx - s_q * (m_qx + ux) - ((R)1 - (R)0.5 * s_q) * Fx;
+    const R k_qy = m_qy - s_q * (m_qy + uy) - ((R)1 - (R)0.5 * s_q) * Fy;
+    const R k_xx = m_xx - s_nu * (m_xx - (ux * ux - uy * uy)) + ((R)1 - (R)0.5 * s_nu) * ((R)2 * (ux * Fx - uy * Fy));
+    const R k_xy = m_xy - s_nu * (m_xy - ux * uy) + ((R)1 - (R)0.5 * s_nu) * (ux * Fy + uy * Fx);
+    // conserved moments after collision: rho, j + F (Eq. 15 puts -F/2 in j)
+    const R jx = (R)(mc.ux + 0.5 * mc.Fx), jy = (R)(mc.uy + 0.5 * mc.Fy);
+    // f = M_o^T D^-1 m*
+    const R c0 = rho * (R)(1.0 / 9.0), c1 = k_e * (R)(1.0 / 36.0), c2 = k_eps * (R)(1.0 / 36.0);
+    const R c3 = jx * (R)(1.0 / 6.0), c4 = k_qx * (R)(1.0 / 12.0);
+    const R c5 = jy * (R)(1.0 / 6.0), c6 = k_qy * (R)(1.0 / 12.0);
+    const R c7 = k_xx * (R)0.25, c8 = k_xy * (R)0.25;
+    const R axis = (c0 - c1) - (R)2 * c2;
+    const R diag = (c0 + (R)2 * c1) + c2;
+    const R px = c3 - (R)2 * c4, py = c5 - (R)2 * c6;
+    const R qx = c3 + c4, qy = c5 + c6;
+    f[0] = (c0 - (R)4 * c1) + (R)4 * c2;
+    f[1] = (axis + px) + c7;
+    f[3] = (axis - px) + c7;
+    f[2] = (axis + py) - c7;
+    f[4] = (axis - py) - c7;
+    f[5] = (diag + qx) + (qy + c8);
+    f[6] = (diag - qx) + (qy - c8);
+    f[7] = (diag - qx) - (qy - c8);
+    f[8] = (diag + qx) - (qy + c8);
+}
+
+template <class R, int NG>
+__device__ __forceinline__ void collide_thermal_bgk(R g[NG > 0 ? NG : 1], const Macro& mc, const Coeffs& C) {
+    if constexpr (NG > 0) {
+        const R ux = (R)mc.ux, uy = (R)mc.uy, T = (R)mc.T, t0 = (R)mc.Tsum;
+        const R z = (R)C.z1;
+        if constexpr (NG == 5) {
+            const R vp = (R)C.varpi;
+            g[0] = g[0] - z * (g[0] - ((R)1 - vp) * t0);
+#pragma unroll
+            for (int i = 1; i < 5; ++i) {
+                const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
+                g[i] = g[i] - z * (g[i] - ((R)0.25 * vp * t0 + (R)0.5 * eu * T));
+            }
+        } else {
+            const R th = (R)C.theta, usq15 = (R)1.5 * (ux * ux + uy * uy);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
+                const R geq = (R)w9(i) * (t0 + T * ((R)3 * eu + th * ((R)4.5 * eu * eu - usq15)));
+                g[i] = g[i] - z * (g[i] - geq);
+            }
+        }
+    }
+}
+
+// Collision of one node with the operator COLL.
+template <class R, int NG, int COLL>
+__device__ __forceinline__ void collide(R f[9], R g[NG > 0 ? NG : 1], const Macro& mc, const Coeffs& C) {
+    if constexpr (COLL == kCollBGK) {
+        collide_flow_bgk<R>(f, mc, C);
+        collide_thermal_bgk<R, NG>(g, mc, C);
+    } else if constexpr (COLL == kCollOrtho) {
+        collide_flow_ortho<R>(f, mc, C);
+        collide_mrt<R, NG, false>(f, g, mc, C);
+    } else {
+        collide_mrt<R, NG>(f, g, mc, C);
     }
 }
 
@@ -575,49 +696,81 @@ __device__ __forceinline__ void fix_x_edges(const S* __restrict__ src, const Geo
     auto ld = [&](int pl, int xx, int yy, float inv) -> R {
         return Codec<S>::load(src + (long long)pl * G.plane + (long long)yy * G.pitch + xx, inv);
     };
-    // populations moving in +x (1, 5, 8) at x = 0 and in -x (3, 6, 7) at x = nx - 1
+    // Populations moving in +x (1, 5, 8) at x = 0 and in -x (3, 6, 7) at
+    // x = nx - 1.  The corrected values go through locals written back with
+    // fixed indices (stores to different elements under different branches
+    // would otherwise be merged into one indexed store, which keeps f and g
+    // in scratch memory).
+    R f1 = f[1], f5 = f[5], f8 = f[8], f3 = f[3], f6 = f[6], f7 = f[7];
+    R g1 = 0, g5 = 0, g8 = 0, g3 = 0, g6 = 0, g7 = 0;
+    if constexpr (NG > 0) {
+        g1 = g[1];
+        g3 = g[3];
+    }
+    if constexpr (NG == 9) {
+        g5 = g[5];
+        g8 = g[8];
+        g6 = g[6];
+        g7 = g[7];
+    }
     if (x == 0) {
         if (G.px) {
             const int xs = G.nx - 1;
-            f[1] = ld(1, xs, y, C.finv);
-            f[5] = ld(5, xs, y - 1, C.finv);
-            f[8] = ld(8, xs, y + 1, C.finv);
-            if constexpr (NG > 0) g[1] = ld(10, xs, y, C.ginv);
+            f1 = ld(1, xs, y, C.finv);
+            f5 = ld(5, xs, y - 1, C.finv);
+            f8 = ld(8, xs, y + 1, C.finv);
+            if constexpr (NG > 0) g1 = ld(10, xs, y, C.ginv);
             if constexpr (NG == 9) {
-                g[5] = ld(14, xs, y - 1, C.ginv);
-                g[8] = ld(17, xs, y + 1, C.ginv);
+                g5 = ld(14, xs, y - 1, C.ginv);
+                g8 = ld(17, xs, y + 1, C.ginv);
             }
         } else {
-            f[1] = ld(3, 0, y, C.finv) + (R)C.bbf[kLeft][1];
-            f[5] = ld(7, 0, y, C.finv) + (R)C.bbf[kLeft][5];
-            f[8] = ld(6, 0, y, C.finv) + (R)C.bbf[kLeft][8];
-            if constexpr (NG > 0) g[1] = (R)C.gsign[kLeft] * ld(12, 0, y, C.ginv) + (R)C.gconst[kLeft][1];
+            f1 = ld(3, 0, y, C.finv) + (R)C.bbf[kLeft][1];
+            f5 = ld(7, 0, y, C.finv) + (R)C.bbf[kLeft][5];
+            f8 = ld(6, 0, y, C.finv) + (R)C.bbf[kLeft][8];
+            if constexpr (NG > 0) g1 = (R)C.gsign[kLeft] * ld(12, 0, y, C.ginv) + (R)C.gconst[kLeft][1];
             if constexpr (NG == 9) {
-                g[5] = (R)C.gsign[kLeft] * ld(16, 0, y, C.ginv) + (R)C.gconst[kLeft][5];
-                g[8] = (R)C.gsign[kLeft] * ld(15, 0, y, C.ginv) + (R)C.gconst[kLeft][8];
+                g5 = (R)C.gsign[kLeft] * ld(16, 0, y, C.ginv) + (R)C.gconst[kLeft][5];
+                g8 = (R)C.gsign[kLeft] * ld(15, 0, y, C.ginv) + (R)C.gconst[kLeft][8];
             }
         }
     }
     if (x == G.nx - 1) {
         if (G.px) {
-            f[3] = ld(3, 0, y, C.finv);
-            f[6] = ld(6, 0, y - 1, C.finv);
-            f[7] = ld(7, 0, y + 1, C.finv);
-            if constexpr (NG > 0) g[3] = ld(12, 0, y, C.ginv);
+            f3 = ld(3, 0, y, C.finv);
+            f6 = ld(6, 0, y - 1, C.finv);
+            f7 = ld(7, 0, y + 1, C.finv);
+            if constexpr (NG > 0) g3 = ld(12, 0, y, C.ginv);
             if constexpr (NG == 9) {
-                g[6] = ld(15, 0, y - 1, C.ginv);
-                g[7] = ld(16, 0, y + 1, C.ginv);
+                g6 = ld(15, 0, y - 1, C.ginv);
+                g7 = ld(16, 0, y + 1, C.ginv);
             }
         } else {
-            f[3] = ld(1, x, y, C.finv) + (R)C.bbf[kRight][3];
-            f[6] = ld(8, x, y, C.finv) + (R)C.bbf[kRight][6];
-            f[7] = ld(5, x, y, C.finv) + (R)C.bbf[kRight][7];
-            if constexpr (NG > 0) g[3] = (R)C.gsign[kRight] * ld(10, x, y, C.ginv) + (R)C.gconst[kRight][3];
+            f3 = ld(1, x, y, C.finv) + (R)C.bbf[kRight][3];
+            f6 = ld(8, x, y, C.finv) + (R)C.bbf[kRight][6];
+            f7 = ld(5, x, y, C.finv) + (R)C.bbf[kRight][7];
+            if constexpr (NG > 0) g3 = (R)C.gsign[kRight] * ld(10, x, y, C.ginv) + (R)C.gconst[kRight][3];
             if constexpr (NG == 9) {
-                g[6] = (R)C.gsign[kRight] * ld(17, x, y, C.ginv) + (R)C.gconst[kRight][6];
-                g[7] = (R)C.gsign[kRight] * ld(14, x, y, C.ginv) + (R)C.gconst[kRight][7];
+                g6 = (R)C.gsign[kRight] * ld(17, x, y, C.ginv) + (R)C.gconst[kRight][6];
+                g7 = (R)C.gsign[kRight] * ld(14, x, y, C.ginv) + (R)C.gconst[kRight][7];
             }
         }
+    }
+    f[1] = f1;
+    f[5] = f5;
+    f[8] = f8;
+    f[3] = f3;
+    f[6] = f6;
+    f[7] = f7;
+    if constexpr (NG > 0) {
+        g[1] = g1;
+        g[3] = g3;
+    }
+    if constexpr (NG == 9) {
+        g[5] = g5;
+        g[8] = g8;
+        g[6] = g6;
+        g[7] = g7;
     }
 }
 

@@ -77,8 +77,8 @@ enum Mode {
 // arithmetic; lanes in the first or last column then correct their
 // x-shifted pulls.  Waves touching the bottom or top row, or the ragged
 // right end, resolve walls and wraps per link.  MODE selects the addressing
-// and the store policy of the fast path.
-template <class S, int NG, int ROWS, int MODE>
+// and the store policy of the fast path, COLL the collision operator.
+template <class S, int NG, int ROWS, int MODE, int COLL>
 __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, const S* __restrict__ src,
                                             S* __restrict__ dst, int x, int y0, unsigned buf_bytes) {
     using R = typename Codec<S>::R;
@@ -105,7 +105,7 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const Macro m = macro<R, NG>(f[r], g[r], C);
-            collide<R, NG>(f[r], g[r], m, C);
+            collide<R, NG, COLL>(f[r], g[r], m, C);
             if (MODE == kBufferNT)
                 store_node_buf<S, NG, kCachePolicyNT>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
             else if (MODE == kBufferKeep)
@@ -124,7 +124,7 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
     for (int r = 0; r < ROWS; ++r) {
         if (y0 + r < G.ny) {
             const Macro m = macro<R, NG>(f[r], g[r], C);
-            collide<R, NG>(f[r], g[r], m, C);
+            collide<R, NG, COLL>(f[r], g[r], m, C);
             store_node<S, NG>(dst, G, C, (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S), f[r], g[r]);
         }
     }
@@ -132,14 +132,14 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
 
 // One time step of one lattice: tiles of blockDim.x x (blockDim.y * ROWS)
 // nodes, in row bands per XCD (remap) or in column strips.
-template <class S, int NG, int ROWS, int MODE>
+template <class S, int NG, int ROWS, int MODE, int COLL>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
                                                S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int remap) {
     const int tile = xcd_remap(blockIdx.x, gridDim.x, remap);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x = tx * blockDim.x + threadIdx.x;
     const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
-    sweep_nodes<S, NG, ROWS, MODE>(G, C, src, dst, x, y0, buf_bytes);
+    sweep_nodes<S, NG, ROWS, MODE, COLL>(G, C, src, dst, x, y0, buf_bytes);
 }
 
 // One time step of every lattice of a batch.  Each workgroup of 256
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const BatchMember* __restri
     S* dst = static_cast<S*>(M.buf[sel ^ 1]);
     const int x = t.x0 + (int)(threadIdx.x % (unsigned)t.bx);
     const int y = t.y0 + (int)(threadIdx.x / (unsigned)t.bx);
-    sweep_nodes<S, NG, 1, MODE>(M.G, M.C, src, dst, x, y, M.buf_bytes);
+    sweep_nodes<S, NG, 1, MODE, kCollMRT>(M.G, M.C, src, dst, x, y, M.buf_bytes);
 }
 
 template <class S, int NG>
@@ -502,20 +502,28 @@ static inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / 
         default: return hipErrorInvalidValue;                                             \
     }
 
+// The comparison operators (BGK, orthogonal MRT) run one row per thread.
 template <class S, int NG, int MODE>
-static void sweep_launch(int rows, dim3 grid, dim3 block, hipStream_t st, const Geom& G, const Coeffs& C,
-                         const S* s, S* d, int tiles_x, unsigned bytes, int remap) {
-    if (rows == 1)
-        hipLaunchKernelGGL((k_sweep<S, NG, 1, MODE>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, remap);
+static void sweep_launch(int rows, int coll, dim3 grid, dim3 block, hipStream_t st, const Geom& G,
+                         const Coeffs& C, const S* s, S* d, int tiles_x, unsigned bytes, int remap) {
+    if (coll == kCollBGK)
+        hipLaunchKernelGGL((k_sweep<S, NG, 1, MODE, kCollBGK>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, remap);
+    else if (coll == kCollOrtho)
+        hipLaunchKernelGGL((k_sweep<S, NG, 1, MODE, kCollOrtho>), grid, block, 0, st, G, C, s, d, tiles_x, bytes,
+                           remap);
+    else if (rows == 1)
+        hipLaunchKernelGGL((k_sweep<S, NG, 1, MODE, kCollMRT>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, remap);
     else
-        hipLaunchKernelGGL((k_sweep<S, NG, 2, MODE>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, remap);
+        hipLaunchKernelGGL((k_sweep<S, NG, 2, MODE, kCollMRT>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, remap);
 }
 
 template <class S, int NG>
 static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const void* src, void* dst,
                           hipStream_t st) {
-    const int rows = L.rows;
+    const int coll = C.collision;
+    const int rows = coll == kCollMRT ? L.rows : 1;
     if (rows != 1 && rows != 2) return hipErrorInvalidValue;
+    if (coll < kCollMRT || coll > kCollOrtho) return hipErrorInvalidValue;
     const int tiles_x = (G.nx + L.bx - 1) / L.bx;
     const int tiles_y = (G.ny + L.by * rows - 1) / (L.by * rows);
     const int nt = tiles_x * tiles_y;
@@ -525,11 +533,11 @@ static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const
     const dim3 grid(nt), block(L.bx, L.by);
     const int remap = L.remap ? 1 : 0;
     if (!L.buffer || bytes >= (1ull << 32))
-        sweep_launch<S, NG, kGlobal>(rows, grid, block, st, G, C, s, d, tiles_x, 0u, remap);
+        sweep_launch<S, NG, kGlobal>(rows, coll, grid, block, st, G, C, s, d, tiles_x, 0u, remap);
     else if (L.keep)
-        sweep_launch<S, NG, kBufferKeep>(rows, grid, block, st, G, C, s, d, tiles_x, (unsigned)bytes, remap);
+        sweep_launch<S, NG, kBufferKeep>(rows, coll, grid, block, st, G, C, s, d, tiles_x, (unsigned)bytes, remap);
     else
-        sweep_launch<S, NG, kBufferNT>(rows, grid, block, st, G, C, s, d, tiles_x, (unsigned)bytes, remap);
+        sweep_launch<S, NG, kBufferNT>(rows, coll, grid, block, st, G, C, s, d, tiles_x, (unsigned)bytes, remap);
     return hipGetLastError();
 }
 

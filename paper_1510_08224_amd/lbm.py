@@ -29,6 +29,7 @@ LBM_T_PERIODIC, LBM_T_DIRICHLET, LBM_T_ADIABATIC, LBM_T_NEE_DIRICHLET, LBM_T_NEE
 
 LBM_MODEL_D2Q5, LBM_MODEL_D2Q9T, LBM_MODEL_ISOTHERMAL = 0, 1, 2
 LBM_POLICY_DEFAULT, LBM_POLICY_KEEP, LBM_POLICY_XCD_BANDS, LBM_POLICY_KEEP_STORES = -2, -1, 1, 2
+LBM_COLLISION_MRT, LBM_COLLISION_BGK, LBM_COLLISION_ORTHO_MRT = 0, 1, 2
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16}
 MODEL = {"d2q5": LBM_MODEL_D2Q5, "d2q9t": LBM_MODEL_D2Q9T, "isothermal": LBM_MODEL_ISOTHERMAL}
 MODEL_NG = {LBM_MODEL_D2Q5: 5, LBM_MODEL_D2Q9T: 9, LBM_MODEL_ISOTHERMAL: 0}
@@ -53,6 +54,7 @@ class LbmParams(ctypes.Structure):
         ("s_nu", ctypes.c_double), ("zeta_alpha", ctypes.c_double),
         ("ax", ctypes.c_double), ("ay", ctypes.c_double),
         ("bc_flow", ctypes.c_int32 * 4), ("bc_temp", ctypes.c_int32 * 4),
+        ("collision", ctypes.c_int32), ("reserved1", ctypes.c_int32),
         ("wall_T", ctypes.c_double * 4), ("wall_u", (ctypes.c_double * 2) * 4),
     ]
 
@@ -179,6 +181,7 @@ def lbm_params_from_problem(pb) -> LbmParams:
         p.wall_T[s] = float(pb.wall_T[s])
         p.wall_u[s][0] = float(pb.wall_u[s][0])
         p.wall_u[s][1] = float(pb.wall_u[s][1])
+    p.collision = int(getattr(pb, "collision", LBM_COLLISION_MRT))
     return p
 
 

@@ -22,6 +22,7 @@ import numpy as np
 LEFT, RIGHT, BOTTOM, TOP = 0, 1, 2, 3
 FLOW_PERIODIC, FLOW_WALL, FLOW_NEE = 0, 1, 2
 TEMP_PERIODIC, TEMP_DIRICHLET, TEMP_ADIABATIC, TEMP_NEE_DIRICHLET, TEMP_NEE_ADIABATIC = 0, 1, 2, 3, 4
+COLL_MRT, COLL_BGK, COLL_ORTHO = 0, 1, 2   # collision operator (the paper's MRT and its comparisons)
 
 
 def with_nee_walls(pb: "Problem") -> "Problem":
@@ -63,6 +64,7 @@ class Problem:
     bc_temp: tuple = (TEMP_DIRICHLET, TEMP_DIRICHLET, TEMP_ADIABATIC, TEMP_ADIABATIC)
     wall_T: tuple = (1.0, 0.0, 0.0, 0.0)
     wall_u: tuple = ((0.0, 0.0), (0.0, 0.0), (0.0, 0.0), (0.0, 0.0))
+    collision: int = COLL_MRT
     name: str = ""
 
     def replace(self, **kw) -> "Problem":

@@ -87,8 +87,36 @@ N5 = basis_n5()
 N5I = inverse(N5)
 
 
-def _flow(f, s, Fx, Fy, rho0):
-    """Exact fbar* of Eq. 7 for given force; returns (fbar*, ux, uy)."""
+def gram_schmidt(rows):
+    """Orthogonalize rows (lists of Fractions) in order, plain dot product."""
+    out = []
+    for v in rows:
+        w = list(v)
+        for u in out:
+            c = sum(a * b for a, b in zip(w, u)) / sum(b * b for b in u)
+            w = [a - c * b for a, b in zip(w, u)]
+        out.append(w)
+    return out
+
+
+def basis_ortho9():
+    """The orthogonal D2Q9 basis: Gram-Schmidt of 1, |e|^2, |e|^4, e_x,
+    e_x|e|^2, e_y, e_y|e|^2, e_x^2 - e_y^2, e_x e_y."""
+    defs = [lambda x, y: 1, lambda x, y: x * x + y * y, lambda x, y: (x * x + y * y) ** 2,
+            lambda x, y: x, lambda x, y: x * (x * x + y * y), lambda x, y: y,
+            lambda x, y: y * (x * x + y * y), lambda x, y: x * x - y * y, lambda x, y: x * y]
+    return gram_schmidt([[Fr(d(ex, ey)) for (ex, ey) in E9] for d in defs])
+
+
+MO9 = basis_ortho9()
+MO9I = inverse(MO9)
+
+
+def _flow(f, s, Fx, Fy, rho0, M=None, MI=None):
+    """Exact fbar* of Eq. 7 for given force, Lambda~ = M^-1 diag(s) M
+    (M of Eq. 12 unless given); returns (fbar*, ux, uy)."""
+    M = M9 if M is None else M
+    MI = M9I if MI is None else MI
     rho = sum(f)                                     # Eq. 18
     ux = (sum(e[0] * fi for e, fi in zip(E9, f)) + rho0 * Fx / 2) / rho0   # Eq. 19
     uy = (sum(e[1] * fi for e, fi in zip(E9, f)) + rho0 * Fy / 2) / rho0
@@ -100,7 +128,7 @@ def _flow(f, s, Fx, Fy, rho0):
         uF = ux * Fx + uy * Fy
         feq.append(w * (rho + rho0 * (3 * eu + Fr(9, 2) * eu * eu - Fr(3, 2) * usq)))  # Eq. 22
         S.append(w * rho0 * (3 * eF - 3 * uF + 9 * eu * eF))       # Guo source
-    Lt = matmul(M9I, matmul(diag(s), M9))            # Lambda~ = M^-1 Lambda M
+    Lt = matmul(MI, matmul(diag(s), M))              # Lambda~ = M^-1 Lambda M
     neq = [fi - fe for fi, fe in zip(f, feq)]
     c1 = matvec(Lt, neq)
     c2 = matvec(Lt, S)
@@ -153,6 +181,17 @@ def collide_d2q9t(f, g, s, q, theta, gbeta, T0, ax, ay, rho0=Fr(1)):
 def collide_isothermal(f, s, ax, ay, rho0=Fr(1)):
     """Exact fbar* without a temperature field: the force is a alone."""
     return _flow(f, s, ax, ay, rho0)[0]
+
+
+def collide_ortho_flow(f, s_ortho, Fx, Fy, rho0=Fr(1)):
+    """Exact fbar* of the classical orthogonal MRT: Eq. 7 with
+    Lambda~ = M_o^-1 diag(s_ortho) M_o."""
+    return _flow(f, s_ortho, Fx, Fy, rho0, MO9, MO9I)[0]
+
+
+def collide_bgk_flow(f, w, Fx, Fy, rho0=Fr(1)):
+    """Exact single-relaxation-time update with the Guo source."""
+    return _flow(f, [w] * 9, Fx, Fy, rho0)[0]
 
 
 def guo_moments(ux, uy, Fx, Fy, rho0=Fr(1)):

@@ -29,6 +29,7 @@ def test_params_struct_layout_matches():
                                lbm.LBM_T_ADIABATIC]
     assert list(p.wall_T) == [1.0, 0.0, 0.0, 0.0]
     assert (p.zeta_q, p.zeta_eps, p.theta) == (1.9, 1.9, 1.0)
+    assert p.collision == lbm.LBM_COLLISION_MRT
 
 
 def test_abi_version_and_info():

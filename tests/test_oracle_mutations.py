@@ -45,6 +45,11 @@ MUTANTS = {
     "d2q9t_antibounce_weight": ("even = W9[i] * p->wall_T[side]", "even = 0.25 * p->wall_T[side]"),
     "d2q9t_antibounce_no_velocity": ("(1.0 + p->theta * (4.5 * eu * eu - 1.5 * usq));\n                    } else",
                                      "(1.0 + 0.0 * (4.5 * eu * eu - 1.5 * usq));\n                    } else"),
+    "bgk_source_factor": ("+ (1.0 - 0.5 * w) * guo_i(", "+ (1.0 - w) * guo_i("),
+    "guo_velocity_sign": ("(3.0 * (eF - uF) + 9.0 * eu * eF)", "(3.0 * (eF + uF) + 9.0 * eu * eF)"),
+    "bgk_thermal_rate": ("const double z = p->q[1];", "const double z = p->q[3];"),
+    "ortho_rates_swapped": ("{1.0, p->s[3], p->s[8], 1.0,", "{1.0, p->s[8], p->s[3], 1.0,"),
+    "gram_schmidt_sign": ("v[k][i] -= num / den * MO9[j][i];", "v[k][i] += num / den * MO9[j][i];"),
     "stream_index": ("L->fn[((size_t)ty * nx + tx) * 9 + i]", "L->fn[((size_t)ty * nx + tx) * 9 + OPP9[i]]"),
 }
 
@@ -114,6 +119,29 @@ def _battery(lib):
     y = (np.arange(16) + 0.5) / 16
     if not (np.max(np.abs(ux - 0.05 * y[:, None])) < 1e-13 and np.max(np.abs(T - y[:, None])) < 1e-13):
         failed.append("couette_exact_d2q9t")
+    # BGK (velocity-space flow update, textbook temperature update) and the
+    # orthogonal MRT, each against its exact reference
+    s = [1, 1, 1, 1.5, 1.2, 1.2, 1.1, 1.1, 1.7]
+    f = w * (1 + 0.4 * rng.uniform(-1, 1, 9))
+    g = np.array([0.5] + [0.125] * 4) * (1 + 0.4 * rng.uniform(-1, 1, 5))
+    Fx, Fy = 2e-3, -1e-3 + 0.03 * (g.sum() - 0.4)
+    for coll in (oracle.COLL_BGK, oracle.COLL_ORTHO):
+        p = _p(lib, s, [1, 1.2, 1.2, 1.9, 1.7], gbeta=0.03, T0=0.4, ax=2e-3, ay=-1e-3)
+        p.collision = coll
+        fo, go = oracle.collide_node(p, f, g, library=lib)
+        if coll == oracle.COLL_BGK:
+            fe = X.collide_bgk_flow([Fr(v) for v in f], Fr(1.2), Fr(Fx), Fr(Fy))
+            e = np.array(X.E9, dtype=float)
+            u = e.T @ f + np.array([Fx, Fy]) / 2
+            T = g.sum()
+            geq = np.concatenate([[0.5 * T], 0.125 * T + 0.5 * (e[1:5] @ u) * T])
+            if np.max(np.abs(go - (g - 1.2 * (g - geq)))) > 1e-14:
+                failed.append("bgk_thermal")
+        else:
+            so = [Fr(1), Fr(1.5), Fr(1.7), Fr(1), Fr(1.1), Fr(1), Fr(1.1), Fr(1.2), Fr(1.2)]
+            fe = X.collide_ortho_flow([Fr(v) for v in f], so, Fr(Fx), Fr(Fy))
+        if np.max(np.abs(fo - np.array([float(v) for v in fe]))) > 1e-14:
+            failed.append(f"collision_exact_{coll}")
     # uniformly moving equilibrium between moving Dirichlet plates is a fixed point
     u = np.array([0.05, 0.02])
     e = np.array(X.E9, dtype=float)
