@@ -13,10 +13,12 @@ roofline of the step kernel measured with HIP events on the solver's
 stream, the same figures for FP32 and FP16 deviation storage and for the
 other temperature models in FP64 (the D2Q9 thermal model on the same
 cavity; the flow alone on a lid-driven cavity of the same size, Re = 1000),
-and the CPU oracle timed on a bounded sample of the same workload.
+the step time of the comparison collision operators of Sec. 3.2 (BGK,
+orthogonal MRT) relative to the paper's, and the CPU oracle timed on a
+bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--storage f64] [--variants f32,f16]
-                    [--models d2q9t,isothermal]
+                    [--models d2q9t,isothermal] [--collisions bgk,ortho_mrt]
 """
 from __future__ import annotations
 
@@ -52,15 +54,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str, nodes: int):
+def measured_traffic(key: str, nodes: int):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter runs, if they were taken on the current kernel sources."""
+    counter runs (key: storage for the D2Q5 model, model_storage for the
+    others), if they were taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    ent = rec.get("kernels", {}).get(storage)
+    ent = rec.get("kernels", {}).get(key)
     if not ent or rec.get("source_hash") != kernel_source_hash() or ent.get("nodes") != nodes:
         return None
     return ent.get("bytes_per_launch")
@@ -108,7 +111,7 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
     avg_launch_s = sweep_ms / 1e3 / steps
     alg_bytes = values_per_node(model) * BYTES[storage] * nodes
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = measured_traffic(storage, nodes) if model == "d2q5" else None
+    traffic = measured_traffic(storage if model == "d2q5" else f"{model}_{storage}", nodes)
     return {
         "storage": storage,
         "model": model,
@@ -148,7 +151,9 @@ def main():
     ap.add_argument("--variants", default="f32,f16", help="other storages to time ('none' for none)")
     ap.add_argument("--models", default="d2q9t,isothermal",
                     help="other temperature models to time in the main storage ('none' for none)")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--collisions", default="bgk,ortho_mrt",
+                    help="comparison collision operators to time in the main storage ('none' for none)")
+    ap.add_argument("--cpu-steps", type=int, default=48, help="oracle steps of the CPU baseline (~20 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=2048, help="cavity side")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows[,policy]")
@@ -184,6 +189,12 @@ def main():
                 mpb = pb if m != "isothermal" else W.lid_cavity(args.n, lbm.viscous_rate(1000.0, args.n, 0.1), 0.1)
                 models[m] = time_storage(args.storage, mpb, args.steps, args.warmup, launch, model=m)
                 models[m]["workload"] = mpb.name
+    colls = {}
+    if args.collisions != "none":
+        codes = {"bgk": W.COLL_BGK, "ortho_mrt": W.COLL_ORTHO}
+        for c in args.collisions.split(","):
+            if c in codes:
+                colls[c] = time_storage(args.storage, pb.replace(collision=codes[c]), args.steps, args.warmup, launch)
     if args.calibrate_copy:
         # reference for counter runs: one dispatch reading and writing 1 GiB
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -221,6 +232,10 @@ def main():
                                "sweep_mlups": round(v["sweep_mlups"], 1), "roofline": v["roofline"],
                                "launch": v["launch"]}
                            for k, v in models.items()},
+        "collision_variants": {k: {"storage": args.storage, "mlups": round(v["mlups"], 1),
+                                   "sweep_us_per_launch": round(v["sweep_us_per_launch"], 3),
+                                   "ratio_to_mrt": round(v["sweep_us_per_launch"] / main_res["sweep_us_per_launch"], 4)}
+                               for k, v in colls.items()},
         "source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)

@@ -275,18 +275,22 @@ int32_t lbm_model_of(const lbm_solver* h);
 
 /* Memory policy of the step kernel (bit mask):
  *   LBM_POLICY_XCD_BANDS    each of the 8 XCDs takes a contiguous band of
- *                           tiles; otherwise tile b runs on XCD b % 8
- *                           (column strips when a row holds a multiple of 8
- *                           tiles);
+ *                           tiles (rows);
+ *   LBM_POLICY_XCD_STRIPS   each XCD takes a contiguous eighth of every
+ *                           row of tiles (when a row holds a multiple of 8
+ *                           tiles; bands otherwise);
+ *                           with neither bit, tile b runs on XCD b % 8;
  *   LBM_POLICY_KEEP_STORES  stores keep their lines in the last-level
  *                           cache; otherwise they are non-temporal.
  * The default follows the footprint F of both population buffers: bands
- * while F <= 500 MiB, kept stores while F <= 256 MiB. */
+ * while F <= 500 MiB (FP64 storage: 1 GiB), kept stores while
+ * F <= 256 MiB. */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
     LBM_POLICY_XCD_BANDS = 1,
-    LBM_POLICY_KEEP_STORES = 2
+    LBM_POLICY_KEEP_STORES = 2,
+    LBM_POLICY_XCD_STRIPS = 4
 };
 
 /* Launch shape of the step kernel: block_x threads along x (64, 128 or

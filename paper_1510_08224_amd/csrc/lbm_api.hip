@@ -155,15 +155,20 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 }
 
 // Memory policy from the footprint of both population buffers, measured on
-// MI355X (1024^2 to 4096^2 lattices, every storage): when both fit the
-// 256 MB last-level cache, stores keep their lines there (FP16 2048^2:
-// +34%); above it non-temporal stores win.  XCD row bands win up to about
-// half a gigabyte (FP32 2048^2, 470 MB: +16%), column strips above (FP16
-// 3072^2, 528 MB: +11%; FP16 4096^2: +8%).
+// MI355X (1024^2 to 4096^2 lattices, every model and storage): when both
+// fit the 256 MB last-level cache, stores keep their lines there (FP16
+// 2048^2: +34%); above it non-temporal stores win.  XCD row bands win up
+// to about half a gigabyte (FP32 2048^2, 470 MB: +16%) and tie with the
+// round-robin order for FP64 states up to a gigabyte, where they fetch each
+// line once (round robin fetches 7% more: the x-shifted pulls of
+// neighbouring 64-wide tiles on different XCDs); the round-robin order wins
+// above (FP16 3072^2, 528 MB: +11%; FP64 4096^2: +2%).  Contiguous strips
+// per XCD (LBM_POLICY_XCD_STRIPS) are within a few percent either way and
+// left to the autotuner.
 static void default_policy(lbm_solver* h) {
-    const double ws = 2.0 * (double)h->buf_bytes;
-    h->L.keep = ws <= 256.0 * 1024 * 1024;
-    h->L.remap = ws <= 500.0 * 1024 * 1024;
+    const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
+    h->L.keep = ws <= 256.0 * mib;
+    h->L.order = (ws <= 500.0 * mib || (h->storage == LBM_F64 && ws <= 1024.0 * mib)) ? 1 : 0;
 }
 
 static void default_launch(lbm_solver* h) {
@@ -782,13 +787,15 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
     if (!(L.bx == 64 || L.bx == 128 || L.bx == 256) || L.by < 1 || L.bx * L.by > 256 ||
         !(L.rows == 1 || L.rows == 2))
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2}");
-    if (policy < LBM_POLICY_DEFAULT || policy > (LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES))
-        return fail(h, LBM_ERR_ARG, "lbm_set_launch: unknown policy");
+    if (policy < LBM_POLICY_DEFAULT ||
+        policy > (LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES | LBM_POLICY_XCD_STRIPS) ||
+        (policy >= 0 && (policy & LBM_POLICY_XCD_BANDS) && (policy & LBM_POLICY_XCD_STRIPS)))
+        return fail(h, LBM_ERR_ARG, "lbm_set_launch: unknown policy (bands and strips exclude each other)");
     h->L = L;
     if (policy == LBM_POLICY_DEFAULT) {
         default_policy(h);
     } else if (policy >= 0) {
-        h->L.remap = (policy & LBM_POLICY_XCD_BANDS) != 0;
+        h->L.order = (policy & LBM_POLICY_XCD_BANDS) ? 1 : ((policy & LBM_POLICY_XCD_STRIPS) ? 2 : 0);
         h->L.keep = (policy & LBM_POLICY_KEEP_STORES) != 0;
     }
     drop_graphs(h);
@@ -802,7 +809,9 @@ int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int3
     if (block_x) *block_x = h->L.bx;
     if (block_y) *block_y = h->L.by;
     if (rows_per_thread) *rows_per_thread = h->L.rows;
-    if (policy) *policy = (h->L.remap ? LBM_POLICY_XCD_BANDS : 0) | (h->L.keep ? LBM_POLICY_KEEP_STORES : 0);
+    if (policy)
+        *policy = (h->L.order == 1 ? LBM_POLICY_XCD_BANDS : 0) | (h->L.order == 2 ? LBM_POLICY_XCD_STRIPS : 0) |
+                  (h->L.keep ? LBM_POLICY_KEEP_STORES : 0);
     return LBM_OK;
 }
 

@@ -12,7 +12,7 @@ enum Storage { kF64 = 0, kF32 = 1, kF16 = 2 };
 struct Launch {
     int bx = 256, by = 1, rows = 1;
     bool buffer = true;  // buffer-resource addressing when the buffer is below 4 GiB
-    bool remap = true;   // XCD row bands (true) or column strips (false)
+    int order = 1;       // XCD tile order: 0 round robin, 1 bands, 2 strips (lbm_kernels.hip)
     bool keep = false;   // default-policy stores (true) or non-temporal stores (false)
 };
 

@@ -24,16 +24,29 @@ namespace lbm {
 
 constexpr int gdim(int NG) { return NG > 0 ? NG : 1; }
 
-// Workgroup b runs on XCD b % 8 of the MI355X.  The remap gives each XCD a
-// contiguous range of tiles (a band of rows: the lines that the y-shifted
-// pulls of neighbouring tiles share stay in one L2).  Without it, when a
-// row holds a multiple of 8 tiles, XCD k takes the tile columns k, k + 8,
-// ... of every row: column strips, which share lines vertically too, and
-// all XCDs stream through the same rows together.  Which is faster depends
-// on how much of the state the caches hold; the host picks.
-__device__ __forceinline__ int xcd_remap(int b, int n, int remap) {
-    if (!remap) return b;
+// Workgroup b runs on XCD b % 8 of the MI355X; each XCD has its own L2.
+// Tile orders (tiles numbered row-major, tiles_x per row):
+//   kXcdRoundRobin  tile b: with a multiple of 8 tiles per row, XCD k takes
+//                   the tile columns k, k + 8, ...; neighbouring tiles of a
+//                   row sit on different XCDs, so the cache lines that their
+//                   x-shifted pulls share are fetched twice;
+//   kXcdBands       each XCD takes a contiguous range of tiles (a band of
+//                   rows): shared lines stay in one L2;
+//   kXcdStrips      each XCD takes a contiguous eighth of every row (needs
+//                   a multiple of 8 tiles per row): shared lines stay in one
+//                   L2 except at the 8 strip edges, and all XCDs stream
+//                   through the same rows together.
+// Which is fastest depends on how much of the state the caches hold; the
+// host picks.
+enum XcdOrder { kXcdRoundRobin = 0, kXcdBands = 1, kXcdStrips = 2 };
+
+__device__ __forceinline__ int xcd_remap(int b, int n, int order, int tiles_x) {
+    if (order == kXcdRoundRobin) return b;
     const int xcd = b & 7, idx = b >> 3;
+    if (order == kXcdStrips) {
+        const int w = tiles_x >> 3;
+        return (idx / w) * tiles_x + xcd * w + idx % w;
+    }
     const int q = n >> 3, r = n & 7;
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
@@ -131,11 +144,11 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
 }
 
 // One time step of one lattice: tiles of blockDim.x x (blockDim.y * ROWS)
-// nodes, in row bands per XCD (remap) or in column strips.
+// nodes, in the XCD order `remap`.
 template <class S, int NG, int ROWS, int MODE, int COLL>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
                                                S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int remap) {
-    const int tile = xcd_remap(blockIdx.x, gridDim.x, remap);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x, remap, tiles_x);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x = tx * blockDim.x + threadIdx.x;
     const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
@@ -149,7 +162,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __rest
 template <class S, int NG, int MODE>
 __global__ __launch_bounds__(256) void k_sweep_batch(const BatchMember* __restrict__ members,
                                                      const BatchTile* __restrict__ tiles, int parity) {
-    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, 1)];
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, kXcdBands, 0)];
     const BatchMember& M = members[t.member];
     const int sel = (M.cur0 + parity) & 1;
     const S* src = static_cast<const S*>(M.buf[sel]);
@@ -531,7 +544,8 @@ static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const
     S* d = static_cast<S*>(dst);
     const unsigned long long bytes = (unsigned long long)(9 + NG) * (unsigned long long)G.plane * sizeof(S);
     const dim3 grid(nt), block(L.bx, L.by);
-    const int remap = L.remap ? 1 : 0;
+    // strips need a whole number of tiles per XCD in every row
+    const int remap = (L.order == kXcdStrips && tiles_x % 8 != 0) ? kXcdBands : L.order;
     if (!L.buffer || bytes >= (1ull << 32))
         sweep_launch<S, NG, kGlobal>(rows, coll, grid, block, st, G, C, s, d, tiles_x, 0u, remap);
     else if (L.keep)

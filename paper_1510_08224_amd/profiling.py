@@ -1,7 +1,10 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
     python -m paper_1510_08224_amd.profiling stats  <rocprof dir> <out.md> "<command>"
-    python -m paper_1510_08224_amd.profiling traffic <fetch dir> <write dir> <out.json> "<commands>"
+    python -m paper_1510_08224_amd.profiling traffic <fetch dir> <write dir> <out.json> "<commands>" <nodes> [out.md]
+
+Step kernels are keyed by storage ("f64") for the D2Q5 model and by
+model and storage ("d2q9t_f64", "isothermal_f64") for the others.
 
 ``stats`` turns the kernel statistics of a ``rocprofv3 --kernel-trace
 --stats -f csv`` run into a short Markdown table.  ``traffic`` reads two
@@ -23,8 +26,10 @@ import re
 import sys
 
 COPY_BYTES = 1 << 30
-SWEEP = re.compile(r"k_sweep<(double|float|__half)")
+# k_sweep<storage type, NG, ROWS, MODE, COLL>: the MRT step of each model
+SWEEP = re.compile(r"k_sweep<(double|float|__half), (\d), 1, \d, 0>")
 STORAGE = {"double": "f64", "float": "f32", "__half": "f16"}
+MODEL = {"5": "d2q5", "9": "d2q9t", "0": "isothermal"}
 
 
 def _find(d: str, suffix: str) -> list[str]:
@@ -114,11 +119,12 @@ def write_traffic(fetch_dir: str, write_dir: str, out_json: str, commands: str, 
         m = SWEEP.search(name)
         if not m:
             continue
-        st = STORAGE[m.group(1)]
+        st, model = STORAGE[m.group(1)], MODEL[m.group(2)]
+        key = st if model == "d2q5" else f"{model}_{st}"
         wv = write.get(name, (float("nan"), 0))[0]
         rb, wb = fv * 1024.0 * sf, wv * 1024.0 * sw
-        alg = 28 * {"f64": 8, "f32": 4, "f16": 2}[st] * nodes
-        rec["kernels"][st] = {"kernel": name, "dispatches": n, "nodes": nodes,
+        alg = 2 * (9 + int(m.group(2))) * {"f64": 8, "f32": 4, "f16": 2}[st] * nodes
+        rec["kernels"][key] = {"kernel": name, "dispatches": n, "nodes": nodes,
                               "read_bytes_per_launch": rb, "write_bytes_per_launch": wb,
                               "bytes_per_launch": rb + wb, "algorithmic_bytes_per_launch": alg,
                               "traffic_over_algorithmic": (rb + wb) / alg}
@@ -127,12 +133,34 @@ def write_traffic(fetch_dir: str, write_dir: str, out_json: str, commands: str, 
     return rec
 
 
+def write_traffic_md(rec: dict, out_md: str):
+    """Markdown table of a traffic record."""
+    cal = rec["calibration"]
+    lines = ["# HBM traffic of the step kernel (rocprofv3 counters)", "",
+             "Commands (two runs, one counter each):", "", "```", rec["commands"], "```", "",
+             f"Kernel sources: hash `{rec['source_hash']}`.  Reference kernel (`--calibrate-copy`): one "
+             "elementwise dispatch reading 1 GiB and writing 1 GiB; its counters read "
+             f"FETCH_SIZE {cal['fetch_counter_bytes'] / 2**30:.4f} GiB and WRITE_SIZE "
+             f"{cal['write_counter_bytes'] / 2**30:.4f} GiB, so the scale factors are "
+             f"{cal['fetch_scale']:.3f} (reads) and {cal['write_scale']:.3f} (writes).", "",
+             "| step kernel (2048 x 2048, bench launch) | read MB | write MB | algorithmic MB | traffic / algorithmic |",
+             "|---|---:|---:|---:|---:|"]
+    for key, k in rec["kernels"].items():
+        lines.append(f"| {key}: `{k['kernel'].split('(')[0]}` | {k['read_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{k['write_bytes_per_launch'] / 1e6:.1f} | {k['algorithmic_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{k['traffic_over_algorithmic']:.4f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     if len(sys.argv) >= 5 and sys.argv[1] == "stats":
         write_stats_md(sys.argv[2], sys.argv[3], sys.argv[4])
     elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         rec = write_traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]), root)
+        if len(sys.argv) >= 8:
+            write_traffic_md(rec, sys.argv[7])
         print(json.dumps(rec["kernels"], indent=1))
     else:
         print(__doc__)

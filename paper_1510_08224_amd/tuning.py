@@ -26,8 +26,8 @@ from . import workloads as W
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
 NG = {"d2q5": 5, "d2q9t": 9, "isothermal": 0}
 SHAPES = (64, 128, 256)
-POLICIES = (0, lbm.LBM_POLICY_XCD_BANDS, lbm.LBM_POLICY_KEEP_STORES,
-            lbm.LBM_POLICY_XCD_BANDS | lbm.LBM_POLICY_KEEP_STORES)
+POLICIES = tuple(order | keep for order in (0, lbm.LBM_POLICY_XCD_BANDS, lbm.LBM_POLICY_XCD_STRIPS)
+                 for keep in (0, lbm.LBM_POLICY_KEEP_STORES))
 
 
 def _time_steps(S, steps: int) -> float:

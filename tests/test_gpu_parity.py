@@ -121,7 +121,7 @@ def test_parity_cavity64_20000_steps():
 
 
 @pytest.mark.parametrize("launch", [(64, 4, 1, 0), (128, 2, 2, 3), (256, 1, 2, 1), (64, 1, 2, 2),
-                                    (128, 1, 1, lbm.LBM_POLICY_DEFAULT)])
+                                    (128, 1, 1, lbm.LBM_POLICY_DEFAULT), (64, 4, 1, 4), (64, 2, 2, 6)])
 def test_launch_shape_and_policy_do_not_change_results(launch):
     pb = W.cavity(150, 1e5, ny=70)
     T = W.random_temperature(150, 70, 0.0, 1.0, seed=8)
@@ -140,8 +140,26 @@ def test_launch_shape_and_policy_do_not_change_results(launch):
     ref.close(); S.close()
 
 
-@pytest.mark.parametrize("n,storage,policy", [(64, "f64", 3), (2048, "f64", 0), (2048, "f32", 1), (2048, "f16", 3),
-                                              (3072, "f16", 0), (4096, "f16", 0)])
+@pytest.mark.parametrize("launch", [(64, 4, 1, 4), (64, 2, 2, 6), (128, 2, 1, 4)])
+def test_xcd_strips_order_does_not_change_results(launch):
+    # 512 columns: 8 tiles of 64 per row (strips active) or 4 of 128 (bands)
+    pb = W.rayleigh_benard(512, 37, 3e4)
+    T = W.rb_initial_temperature(512, 37, amp=1e-2, seed=4)
+    runs = []
+    for shape in (None, launch):
+        S = lbm.Solver(512, 37, "f64")
+        S.set_params(pb)
+        if shape:
+            S.set_launch(*shape)
+        S.init_temperature(T)
+        S.step(25)
+        runs.append(S.get_populations())
+        S.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("n,storage,policy", [(64, "f64", 3), (2048, "f64", 1), (2048, "f32", 1), (2048, "f16", 3),
+                                              (3072, "f16", 0), (4096, "f16", 0), (4096, "f64", 0)])
 def test_default_policy_follows_footprint(n, storage, policy):
     S = lbm.Solver(n, n, storage)
     assert S.get_launch()[3] == policy
@@ -150,7 +168,11 @@ def test_default_policy_follows_footprint(n, storage, policy):
     S.set_launch(policy=lbm.LBM_POLICY_DEFAULT)
     assert S.get_launch()[3] == policy
     with pytest.raises(lbm.LbmError):
-        S.set_launch(policy=4)
+        S.set_launch(policy=lbm.LBM_POLICY_XCD_BANDS | lbm.LBM_POLICY_XCD_STRIPS)
+    with pytest.raises(lbm.LbmError):
+        S.set_launch(policy=8)
+    S.set_launch(policy=lbm.LBM_POLICY_XCD_STRIPS | lbm.LBM_POLICY_KEEP_STORES)
+    assert S.get_launch()[3] == lbm.LBM_POLICY_XCD_STRIPS | lbm.LBM_POLICY_KEEP_STORES
     with pytest.raises(lbm.LbmError):
         S.set_launch(rows=4)
     S.close()
