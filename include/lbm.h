@@ -281,7 +281,15 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           tiles; bands otherwise);
  *                           with neither bit, tile b runs on XCD b % 8;
  *   LBM_POLICY_KEEP_STORES  stores keep their lines in the last-level
- *                           cache; otherwise they are non-temporal.
+ *                           cache; otherwise they are non-temporal;
+ *   LBM_POLICY_FUSE2        lbm_step runs pairs of time steps in one launch:
+ *                           a workgroup steps its tile and a one-node halo
+ *                           from HBM into LDS, then steps the tile again from
+ *                           LDS and stores it, so the state crosses HBM once
+ *                           per two steps.  Bitwise the same results.  Used
+ *                           with the MRT collision on buffers below 4 GiB and,
+ *                           with NEE walls, when no edge tile is one node
+ *                           wide or high; otherwise steps run singly.
  * The default follows the footprint F of both population buffers: bands
  * while F <= 500 MiB (FP64 storage: 1 GiB), kept stores while
  * F <= 256 MiB. */
@@ -290,7 +298,8 @@ enum {
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
     LBM_POLICY_XCD_BANDS = 1,
     LBM_POLICY_KEEP_STORES = 2,
-    LBM_POLICY_XCD_STRIPS = 4
+    LBM_POLICY_XCD_STRIPS = 4,
+    LBM_POLICY_FUSE2 = 8
 };
 
 /* Launch shape of the step kernel: block_x threads along x (64, 128 or

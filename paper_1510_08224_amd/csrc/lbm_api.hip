@@ -19,8 +19,9 @@ struct lbm_solver {
     int model = LBM_MODEL_D2Q5, ng = 5;  // thermal model and its population count
     Geom G{};
     Coeffs C{};
+    Coeffs* d_coeffs = nullptr;  // device copy of C, read by the step kernels
     Launch L{};
-    size_t buf_bytes = 0;        // bytes of one population buffer (14 planes)
+    size_t buf_bytes = 0;        // bytes of one population buffer (9 + ng planes)
     void* base = nullptr;        // both buffers, contiguous
     bool own_base = false;
     void* buf[2] = {nullptr, nullptr};
@@ -43,6 +44,7 @@ struct lbm_solver {
     // Captured graphs of graph_steps sweeps (an even count), one per
     // starting buffer; rebuilt after any change of parameters or launch.
     int graph_steps = 0;
+    int64_t graph_launches = 0;  // launches in one captured graph (fused pairs count once)
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     lbm_batch* batch = nullptr;  // batch this solver belongs to, if any
     std::string err;
@@ -255,6 +257,7 @@ static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t stora
     }
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->host_small), 8 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->small), 8 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->d_coeffs), sizeof(Coeffs));
     if (e != hipSuccess) {
         lbm_destroy(h);
         return fail(nullptr, LBM_ERR_NOMEM, "lbm_create: small buffers");
@@ -292,6 +295,7 @@ void lbm_destroy(lbm_solver* h) {
     if (h->rbad) (void)hipFree(h->rbad);
     if (h->fields) (void)hipFree(h->fields);
     if (h->small) (void)hipFree(h->small);
+    if (h->d_coeffs) (void)hipFree(h->d_coeffs);
     if (h->nu_local) (void)hipFree(h->nu_local);
     if (h->host_small) (void)hipHostFree(h->host_small);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -445,6 +449,9 @@ static int derive(lbm_solver* h, const lbm_params* p) {
     h->G.px = p->bc_flow[LBM_LEFT] == LBM_BC_PERIODIC;
     h->G.py = p->bc_flow[LBM_BOTTOM] == LBM_BC_PERIODIC;
     h->C = C;
+    // device copy read by the step kernels, ordered on the solver's stream
+    LBM_HIP(h, hipMemcpyAsync(h->d_coeffs, &h->C, sizeof(Coeffs), hipMemcpyHostToDevice, h->stream),
+            "copy of the step constants");
     h->s_nu = s_nu;
     h->zeta_alpha = z_a;
     h->gbeta = gbeta;
@@ -522,15 +529,50 @@ int lbm_init_temperature(lbm_solver* h, const double* T) {
 
 // Capture graph_steps sweeps starting from buffer `start` on the solver's
 // stream.
+// Whether lbm_step may fuse pairs of time steps into one launch: asked for
+// by the policy, the paper's collision, buffers below 4 GiB, and, with NEE
+// walls, no last tile one node wide or high (its wall rebuild would need
+// rows beyond the fused tile's halo).
+static bool fuse2_active(const lbm_solver* h) {
+    if (!h->L.fuse2 || !h->L.buffer || h->C.collision != LBM_COLLISION_MRT) return false;
+    if (h->buf_bytes >= (1ull << 32)) return false;
+    if (h->C.any_nee) {
+        const int ty = fuse2_rows(h->storage, h->ng);
+        if (h->nx % 64 == 1 || ty <= 0 || h->ny % ty == 1) return false;
+    }
+    return true;
+}
+
+// Sweeps of `steps` time steps from buffer `cur`; returns the number of
+// launches (each swaps the buffers once) or a negative HIP error.
+static hipError_t launch_steps(lbm_solver* h, int cur, int64_t steps, int64_t* launches) {
+    const bool fuse = fuse2_active(h);
+    int64_t n = 0;
+    while (steps > 0) {
+        hipError_t e;
+        if (fuse && steps >= 2) {
+            e = launch_sweep2(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
+                              h->stream);
+            steps -= 2;
+        } else {
+            e = launch_sweep(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
+                             h->stream);
+            steps -= 1;
+        }
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+        ++n;
+    }
+    *launches = n;
+    return hipSuccess;
+}
+
 static int build_graph(lbm_solver* h, int start) {
     hipGraph_t g = nullptr;
     LBM_HIP(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    int cur = start;
-    hipError_t le = hipSuccess;
-    for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k) {
-        le = launch_sweep(h->storage, h->ng, h->L, h->G, h->C, h->buf[cur], h->buf[cur ^ 1], h->stream);
-        cur ^= 1;
-    }
+    int64_t launches = 0;
+    hipError_t le = launch_steps(h, start, h->graph_steps, &launches);
+    h->graph_launches = launches;
     hipError_t ee = hipStreamEndCapture(h->stream, &g);
     if (le != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -558,15 +600,17 @@ int lbm_step(lbm_solver* h, int64_t nsteps) {
                 if (rc != LBM_OK) return rc;
             }
             LBM_HIP(h, hipGraphLaunch(h->graph_exec[h->cur], h->stream), "hipGraphLaunch");
-            h->t += h->graph_steps;   // an even count: the state ends in the same buffer
+            h->t += h->graph_steps;
+            h->cur ^= (int)(h->graph_launches & 1);
             nsteps -= h->graph_steps;
         }
     }
-    for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e = launch_sweep(h->storage, h->ng, h->L, h->G, h->C, h->buf[h->cur], h->buf[h->cur ^ 1], h->stream);
+    if (nsteps > 0) {
+        int64_t launches = 0;
+        hipError_t e = launch_steps(h, h->cur, nsteps, &launches);
         if (e != hipSuccess) return hip_fail(h, e, "sweep launch");
-        h->cur ^= 1;
-        h->t += 1;
+        h->cur ^= (int)(launches & 1);
+        h->t += nsteps;
     }
     return LBM_OK;
 }
@@ -788,7 +832,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
         !(L.rows == 1 || L.rows == 2))
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2}");
     if (policy < LBM_POLICY_DEFAULT ||
-        policy > (LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES | LBM_POLICY_XCD_STRIPS) ||
+        policy > (LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES | LBM_POLICY_XCD_STRIPS | LBM_POLICY_FUSE2) ||
         (policy >= 0 && (policy & LBM_POLICY_XCD_BANDS) && (policy & LBM_POLICY_XCD_STRIPS)))
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: unknown policy (bands and strips exclude each other)");
     h->L = L;
@@ -797,6 +841,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
     } else if (policy >= 0) {
         h->L.order = (policy & LBM_POLICY_XCD_BANDS) ? 1 : ((policy & LBM_POLICY_XCD_STRIPS) ? 2 : 0);
         h->L.keep = (policy & LBM_POLICY_KEEP_STORES) != 0;
+        h->L.fuse2 = (policy & LBM_POLICY_FUSE2) != 0;
     }
     drop_graphs(h);
     if (h->batch) batch_invalidate(h->batch);
@@ -811,7 +856,7 @@ int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int3
     if (rows_per_thread) *rows_per_thread = h->L.rows;
     if (policy)
         *policy = (h->L.order == 1 ? LBM_POLICY_XCD_BANDS : 0) | (h->L.order == 2 ? LBM_POLICY_XCD_STRIPS : 0) |
-                  (h->L.keep ? LBM_POLICY_KEEP_STORES : 0);
+                  (h->L.keep ? LBM_POLICY_KEEP_STORES : 0) | (h->L.fuse2 ? LBM_POLICY_FUSE2 : 0);
     return LBM_OK;
 }
 

@@ -24,6 +24,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 enum Side { kLeft = 0, kRight = 1, kBottom = 2, kTop = 3 };
@@ -303,12 +305,30 @@ template <class S, int NG>
 __device__ __forceinline__ void pull_interior_buf(__amdgpu_buffer_rsrc_t r, const Geom& G, const Coeffs& C,
                                                   unsigned boff, typename Codec<S>::R f[9],
                                                   typename Codec<S>::R g[NG > 0 ? NG : 1]) {
+    if constexpr (std::is_same<S, __half>::value) {
+        // Issue every 16-bit load before the first conversion: under
+        // register pressure the scheduler otherwise waits for each load
+        // before issuing the next.
+        unsigned short u[9 + NG];
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-        f[i] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(i, i) * (long long)sizeof(S)), C.finv);
+        for (int i = 0; i < 9; ++i)
+            u[i] = __builtin_amdgcn_raw_buffer_load_b16(r, boff, (unsigned)(LBM_SHIFT(i, i) * 2ll), 0);
 #pragma unroll
-    for (int i = 0; i < NG; ++i)
-        g[i] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(i, 9 + i) * (long long)sizeof(S)), C.ginv);
+        for (int i = 0; i < NG; ++i)
+            u[9 + i] = __builtin_amdgcn_raw_buffer_load_b16(r, boff, (unsigned)(LBM_SHIFT(i, 9 + i) * 2ll), 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = __half2float(__ushort_as_half(u[i])) * C.finv;
+#pragma unroll
+        for (int i = 0; i < NG; ++i) g[i] = __half2float(__ushort_as_half(u[9 + i])) * C.ginv;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            f[i] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(i, i) * (long long)sizeof(S)), C.finv);
+#pragma unroll
+        for (int i = 0; i < NG; ++i)
+            g[i] = Buf<S>::load(r, boff, (unsigned)(LBM_SHIFT(i, 9 + i) * (long long)sizeof(S)), C.ginv);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -643,32 +663,54 @@ __device__ __forceinline__ bool nee_node_at(const Geom& G, const Coeffs& C, int 
            (C.nee[kTop] && y == G.ny - 1);
 }
 
-template <class S, int NG>
-__device__ void nee_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
-                         typename Codec<S>::R f[9], typename Codec<S>::R g[NG > 0 ? NG : 1]) {
-    using R = typename Codec<S>::R;
+// The inward neighbour of NEE wall node (x, y) and the sides it touches.
+struct NeeWall {
+    int fx, fy;   // inward neighbour
+    int vs;       // side whose wall velocity applies
+    int ts;       // side whose Dirichlet temperature applies, or -1
+};
+
+__device__ __forceinline__ NeeWall nee_wall(const Geom& G, const Coeffs& C, int x, int y) {
     const bool onL = C.nee[kLeft] && x == 0, onR = C.nee[kRight] && x == G.nx - 1;
     const bool onB = C.nee[kBottom] && y == 0, onT = C.nee[kTop] && y == G.ny - 1;
-    const int fx = x + (onL ? 1 : (onR ? -1 : 0));
-    const int fy = y + (onB ? 1 : (onT ? -1 : 0));
     const int sx = onL ? kLeft : (onR ? kRight : -1);
     const int sy = onB ? kBottom : (onT ? kTop : -1);
-    const int vs = sy >= 0 ? sy : sx;
-    const int ts = (sy >= 0 && by_side(C.tdir, sy)) ? sy : ((sx >= 0 && by_side(C.tdir, sx)) ? sx : -1);
-    R ff[9], gf[NG > 0 ? NG : 1];
-    pull_node<S, NG>(src, G, C, fx, fy, ff, gf);
+    NeeWall w;
+    w.fx = x + (onL ? 1 : (onR ? -1 : 0));
+    w.fy = y + (onB ? 1 : (onT ? -1 : 0));
+    w.vs = sy >= 0 ? sy : sx;
+    w.ts = (sy >= 0 && by_side(C.tdir, sy)) ? sy : ((sx >= 0 && by_side(C.tdir, sx)) ? sx : -1);
+    return w;
+}
+
+// Rebuild of a wall node from the pre-collision populations ff, gf of its
+// inward neighbour.
+template <class R, int NG>
+__device__ __forceinline__ void nee_rebuild(const NeeWall& w, const Coeffs& C, const R ff[9],
+                                            const R gf[NG > 0 ? NG : 1], R f[9], R g[NG > 0 ? NG : 1]) {
     const Macro m = macro<R, NG>(ff, gf, C);
+    const int vs = w.vs;
     const double uwx = vs == 0 ? C.uw[0][0] : (vs == 1 ? C.uw[1][0] : (vs == 2 ? C.uw[2][0] : C.uw[3][0]));
     const double uwy = vs == 0 ? C.uw[0][1] : (vs == 1 ? C.uw[1][1] : (vs == 2 ? C.uw[2][1] : C.uw[3][1]));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         f[i] = (R)(feq_rep(i, m.rho, uwx, uwy) + ((double)ff[i] - feq_rep(i, m.rho, m.ux, m.uy)));
     if constexpr (NG > 0) {
-        const double Tb = ts >= 0 ? by_side(C.wT, ts) : m.T;
+        const double Tb = w.ts >= 0 ? by_side(C.wT, w.ts) : m.T;
 #pragma unroll
         for (int i = 0; i < NG; ++i)
             g[i] = (R)(geq_rep<NG>(i, Tb, uwx, uwy, C) + ((double)gf[i] - geq_rep<NG>(i, m.T, m.ux, m.uy, C)));
     }
+}
+
+template <class S, int NG>
+__device__ void nee_node(const S* __restrict__ src, const Geom& G, const Coeffs& C, int x, int y,
+                         typename Codec<S>::R f[9], typename Codec<S>::R g[NG > 0 ? NG : 1]) {
+    using R = typename Codec<S>::R;
+    const NeeWall w = nee_wall(G, C, x, y);
+    R ff[9], gf[NG > 0 ? NG : 1];
+    pull_node<S, NG>(src, G, C, w.fx, w.fy, ff, gf);
+    nee_rebuild<R, NG>(w, C, ff, gf, f, g);
 }
 
 // Pre-collision populations of any node: extrapolated on NEE walls,

@@ -14,6 +14,7 @@ struct Launch {
     bool buffer = true;  // buffer-resource addressing when the buffer is below 4 GiB
     int order = 1;       // XCD tile order: 0 round robin, 1 bands, 2 strips (lbm_kernels.hip)
     bool keep = false;   // default-policy stores (true) or non-temporal stores (false)
+    bool fuse2 = false;  // two time steps per launch where the lattice allows it
 };
 
 // A lattice of a batch as the batched step kernel sees it.
@@ -35,8 +36,15 @@ struct BatchTile {
 
 inline int storage_bytes(int storage) { return storage == kF64 ? 8 : (storage == kF32 ? 4 : 2); }
 
-hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
-                        void* dst, hipStream_t st);
+// Two time steps per launch (MRT collision, buffers below 4 GiB); rows of
+// one fused tile.
+hipError_t launch_sweep2(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
+                         const void* src, void* dst, hipStream_t st);
+int fuse2_rows(int storage, int ng);
+// C: the host copy (launch decisions); dC: the same constants in device
+// memory (read by the kernels).
+hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
+                        const void* src, void* dst, hipStream_t st);
 hipError_t launch_sweep_batch(int storage, int ng, bool buffer, const BatchMember* members, const BatchTile* tiles,
                               int ntiles, int parity, hipStream_t st);
 hipError_t launch_residual_batch(int storage, int ng, const BatchMember* members, int nmembers, const BatchTile* tiles,

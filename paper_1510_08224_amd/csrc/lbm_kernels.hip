@@ -18,6 +18,8 @@
 #include "lbm_internal.hpp"
 
 #include <float.h>
+#include <type_traits>
+#include <utility>
 #include <math.h>
 
 namespace lbm {
@@ -145,14 +147,186 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
 
 // One time step of one lattice: tiles of blockDim.x x (blockDim.y * ROWS)
 // nodes, in the XCD order `remap`.
+// The step constants come by pointer to device memory: a lane-varying
+// index into them (the wall tables) is then a plain load, where an index
+// into a by-value kernel argument would make the compiler copy the whole
+// argument to scratch memory in every lane.
 template <class S, int NG, int ROWS, int MODE, int COLL>
-__global__ __launch_bounds__(256) void k_sweep(Geom G, Coeffs C, const S* __restrict__ src,
+__global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
                                                S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int remap) {
+    const Coeffs& C = *Cp;
     const int tile = xcd_remap(blockIdx.x, gridDim.x, remap, tiles_x);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x = tx * blockDim.x + threadIdx.x;
     const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
     sweep_nodes<S, NG, ROWS, MODE, COLL>(G, C, src, dst, x, y0, buf_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per launch.  A workgroup owns a tile of 64 x TY nodes.
+// First it runs the step t -> t + 1 on the tile and a one-node halo around
+// it, reading the state from HBM as the single-step kernel does, and keeps
+// the post-collision populations in LDS (rounded exactly as a store to the
+// storage type would round them).  Then it runs the step t + 1 -> t + 2 on
+// the tile, pulling from LDS, and stores to HBM.  Every population crosses
+// HBM once per two steps instead of once per step; the halo costs
+// (66 (TY + 2)) / (64 TY) - 1 extra collisions.  The result is bitwise the
+// result of two single steps.  TY is a multiple of 4 (the 256 threads take
+// whole rows in the second step) chosen so that the LDS of one workgroup
+// stays within 80 KB: two workgroups per 160 KB CU.
+// ---------------------------------------------------------------------------
+// The value a store to storage type S followed by a load would give.
+template <class S>
+__device__ __forceinline__ typename Codec<S>::R as_stored(typename Codec<S>::R v, float scale, float inv) {
+    if constexpr (std::is_same<S, __half>::value) return __half2float(__float2half_rn(v * scale)) * inv;
+    else return v;
+}
+
+template <class S, int NG>
+struct Fuse2 {
+    using R = typename Codec<S>::R;
+    static constexpr int NP = 9 + NG;
+    static constexpr int TX = 64;
+    static constexpr int EW = TX + 2;
+    static constexpr int ROW_BYTES = EW * NP * (int)sizeof(R);
+    static constexpr int TY_FIT = 81920 / ROW_BYTES - 2;
+    static constexpr int TY = TY_FIT >= 32 ? 32 : (TY_FIT < 4 ? 4 : TY_FIT / 4 * 4);
+    static constexpr int EH = TY + 2;
+    static constexpr int PLANE = EW * EH;
+    static_assert(NP * PLANE * (int)sizeof(R) <= 81920, "fused tile exceeds its LDS budget");
+};
+
+// The first fused step on extended slot e of a tile at (x0, y0): pull (or
+// extrapolate) the pre-collision populations.  Returns false for a slot
+// outside a non-periodic axis.
+template <class S, int NG>
+__device__ __forceinline__ bool fuse2_load(const S* __restrict__ src, __amdgpu_buffer_rsrc_t rs, const Geom& G,
+                                           const Coeffs& C, int x0, int y0, int e, typename Codec<S>::R f[9],
+                                           typename Codec<S>::R g[gdim(NG)]) {
+    using F = Fuse2<S, NG>;
+    int x = x0 - 1 + e % F::EW, y = y0 - 1 + e / F::EW;
+    if (x < 0 || x >= G.nx) {
+        if (!G.px) return false;
+        x = ((x % G.nx) + G.nx) % G.nx;
+    }
+    if (y < 0 || y >= G.ny) {
+        if (!G.py) return false;
+        y = ((y % G.ny) + G.ny) % G.ny;
+    }
+    if (x >= 1 && x <= G.nx - 2 && y >= 1 && y <= G.ny - 2)
+        pull_interior_buf<S, NG>(rs, G, C, (unsigned)(y * G.pitch + x) * (unsigned)sizeof(S), f, g);
+    else
+        load_node<S, NG>(src, G, C, x, y, f, g);
+    return true;
+}
+
+// Collide the pulled populations of slot e and keep them in LDS as a store
+// to S would round them.
+template <class S, int NG, int COLL>
+__device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Coeffs& C, int e,
+                                           typename Codec<S>::R f[9], typename Codec<S>::R g[gdim(NG)]) {
+    using F = Fuse2<S, NG>;
+    using R = typename Codec<S>::R;
+    const Macro m = macro<R, NG>(f, g, C);
+    collide<R, NG, COLL>(f, g, m, C);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lds[i * F::PLANE + e] = as_stored<S>(f[i], C.fscale, C.finv);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) lds[(9 + i) * F::PLANE + e] = as_stored<S>(g[i], C.gscale, C.ginv);
+}
+
+// Pull of population I of node (x, y) whose LDS coordinates are (lx, ly),
+// with the wall rules of `source`.  A periodic wrap needs no case: the
+// halo slot holds the wrapped node.
+template <class S, int NG, int I, int P0>
+__device__ __forceinline__ typename Codec<S>::R lds_pull1(const typename Codec<S>::R* __restrict__ lds,
+                                                          const Geom& G, const Coeffs& C, int x, int y, int lx,
+                                                          int ly) {
+    using F = Fuse2<S, NG>;
+    using R = typename Codec<S>::R;
+    constexpr int dx = ex(I), dy = ey(I);
+    const int sx = x - dx, sy = y - dy;
+    int side = -1;
+    if (dy != 0 && (sy < 0 || sy >= G.ny) && !G.py) side = sy < 0 ? kBottom : kTop;
+    if (dx != 0 && (sx < 0 || sx >= G.nx) && !G.px && side < 0) side = sx < 0 ? kLeft : kRight;
+    if (side < 0) return lds[(P0 + I) * F::PLANE + (ly - dy) * F::EW + (lx - dx)];
+    const R own = lds[(P0 + opp(I)) * F::PLANE + ly * F::EW + lx];
+    if constexpr (P0 == 0) return own + (R)C.bbf[side][I];
+    else return (R)C.gsign[side] * own + (R)C.gconst[side][I];
+}
+
+template <class S, int NG, int... I>
+__device__ __forceinline__ void lds_pull_f(const typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x,
+                                           int y, int lx, int ly, typename Codec<S>::R f[9],
+                                           std::integer_sequence<int, I...>) {
+    ((f[I] = lds_pull1<S, NG, I, 0>(lds, G, C, x, y, lx, ly)), ...);
+}
+template <class S, int NG, int... I>
+__device__ __forceinline__ void lds_pull_g(const typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x,
+                                           int y, int lx, int ly, typename Codec<S>::R g[gdim(NG)],
+                                           std::integer_sequence<int, I...>) {
+    ((g[I] = lds_pull1<S, NG, I, 9>(lds, G, C, x, y, lx, ly)), ...);
+}
+
+template <class S, int NG>
+__device__ __forceinline__ void lds_pull_node(const typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x,
+                                              int y, int lx, int ly, typename Codec<S>::R f[9],
+                                              typename Codec<S>::R g[gdim(NG)]) {
+    lds_pull_f<S, NG>(lds, G, C, x, y, lx, ly, f, std::make_integer_sequence<int, 9>{});
+    if constexpr (NG > 0) lds_pull_g<S, NG>(lds, G, C, x, y, lx, ly, g, std::make_integer_sequence<int, NG>{});
+}
+
+template <class S, int NG, int MODE, int COLL>
+__global__ __launch_bounds__(256) void k_sweep2(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
+                                                S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int order) {
+    const Coeffs& C = *Cp;
+    using F = Fuse2<S, NG>;
+    using R = typename Codec<S>::R;
+    __shared__ R lds[F::NP * F::PLANE];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x, order, tiles_x);
+    const int x0 = (tile % tiles_x) * F::TX, y0 = (tile / tiles_x) * F::TY;
+
+    // Step t -> t + 1 on the tile and its halo, two slots per thread at a
+    // time so that both slots' loads are in flight together.
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
+    for (int e = threadIdx.x; e < F::PLANE; e += 512) {
+        R fa[9], ga[gdim(NG)], fb[9], gb[gdim(NG)];
+        const int e2 = e + 256;
+        const bool va = fuse2_load<S, NG>(src, rs, G, C, x0, y0, e, fa, ga);
+        const bool vb = e2 < F::PLANE && fuse2_load<S, NG>(src, rs, G, C, x0, y0, e2, fb, gb);
+        if (va) fuse2_keep<S, NG, COLL>(lds, C, e, fa, ga);
+        if (vb) fuse2_keep<S, NG, COLL>(lds, C, e2, fb, gb);
+    }
+    __syncthreads();
+
+    // Step t + 1 -> t + 2 on the tile, pulling from LDS.
+    const bool simple = (G.px || (x0 > 0 && x0 + F::TX < G.nx)) && (G.py || (y0 > 0 && y0 + F::TY < G.ny));
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, buf_bytes);
+    for (int n = threadIdx.x; n < F::TX * F::TY; n += 256) {
+        const int ix = n % F::TX, iy = n / F::TX;
+        const int x = x0 + ix, y = y0 + iy;
+        if (x >= G.nx || y >= G.ny) continue;
+        const int lx = ix + 1, ly = iy + 1;
+        R f[9], g[gdim(NG)];
+        if (simple) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = lds[i * F::PLANE + (ly - ey(i)) * F::EW + (lx - ex(i))];
+#pragma unroll
+            for (int i = 0; i < NG; ++i) g[i] = lds[(9 + i) * F::PLANE + (ly - ey(i)) * F::EW + (lx - ex(i))];
+        } else if (C.any_nee && nee_node_at(G, C, x, y)) {
+            const NeeWall w = nee_wall(G, C, x, y);
+            R ff[9], gf[gdim(NG)];
+            lds_pull_node<S, NG>(lds, G, C, w.fx, w.fy, lx + (w.fx - x), ly + (w.fy - y), ff, gf);
+            nee_rebuild<R, NG>(w, C, ff, gf, f, g);
+        } else {
+            lds_pull_node<S, NG>(lds, G, C, x, y, lx, ly, f, g);
+        }
+        const Macro m = macro<R, NG>(f, g, C);
+        collide<R, NG, COLL>(f, g, m, C);
+        const unsigned boff = (unsigned)(y * G.pitch + x) * (unsigned)sizeof(S);
+        if (MODE == kBufferKeep) store_node_buf<S, NG, kCachePolicyDefault>(rd, G, C, boff, f, g);
+        else store_node_buf<S, NG, kCachePolicyNT>(rd, G, C, boff, f, g);
+    }
 }
 
 // One time step of every lattice of a batch.  Each workgroup of 256
@@ -518,7 +692,7 @@ static inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / 
 // The comparison operators (BGK, orthogonal MRT) run one row per thread.
 template <class S, int NG, int MODE>
 static void sweep_launch(int rows, int coll, dim3 grid, dim3 block, hipStream_t st, const Geom& G,
-                         const Coeffs& C, const S* s, S* d, int tiles_x, unsigned bytes, int remap) {
+                         const Coeffs* C, const S* s, S* d, int tiles_x, unsigned bytes, int remap) {
     if (coll == kCollBGK)
         hipLaunchKernelGGL((k_sweep<S, NG, 1, MODE, kCollBGK>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, remap);
     else if (coll == kCollOrtho)
@@ -531,9 +705,9 @@ static void sweep_launch(int rows, int coll, dim3 grid, dim3 block, hipStream_t 
 }
 
 template <class S, int NG>
-static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const void* src, void* dst,
-                          hipStream_t st) {
-    const int coll = C.collision;
+static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& Ch, const Coeffs* C, const void* src,
+                          void* dst, hipStream_t st) {
+    const int coll = Ch.collision;
     const int rows = coll == kCollMRT ? L.rows : 1;
     if (rows != 1 && rows != 2) return hipErrorInvalidValue;
     if (coll < kCollMRT || coll > kCollOrtho) return hipErrorInvalidValue;
@@ -555,9 +729,40 @@ static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& C, const
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const void* src,
-                        void* dst, hipStream_t st) {
-    LBM_DISPATCH(storage, ng, { hipError_t e = sweep_t<S, NG>(L, G, C, src, dst, st); if (e != hipSuccess) return e; });
+int fuse2_rows(int storage, int ng) {
+    LBM_DISPATCH(storage, ng, return Fuse2<S, NG>::TY);
+    return 0;
+}
+
+template <class S, int NG>
+static hipError_t sweep2_t(const Launch& L, const Geom& G, const Coeffs& Ch, const Coeffs* C, const void* src,
+                           void* dst, hipStream_t st) {
+    using F = Fuse2<S, NG>;
+    const unsigned long long bytes = (unsigned long long)(9 + NG) * (unsigned long long)G.plane * sizeof(S);
+    if (!L.buffer || bytes >= (1ull << 32) || Ch.collision != kCollMRT) return hipErrorInvalidValue;
+    const int tiles_x = (G.nx + F::TX - 1) / F::TX;
+    const int tiles_y = (G.ny + F::TY - 1) / F::TY;
+    const int order = (L.order == kXcdStrips && tiles_x % 8 != 0) ? kXcdBands : L.order;
+    const S* s = static_cast<const S*>(src);
+    S* d = static_cast<S*>(dst);
+    if (L.keep)
+        hipLaunchKernelGGL((k_sweep2<S, NG, kBufferKeep, kCollMRT>), dim3(tiles_x * tiles_y), dim3(256), 0, st, G, C, s,
+                           d, tiles_x, (unsigned)bytes, order);
+    else
+        hipLaunchKernelGGL((k_sweep2<S, NG, kBufferNT, kCollMRT>), dim3(tiles_x * tiles_y), dim3(256), 0, st, G, C, s,
+                           d, tiles_x, (unsigned)bytes, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep2(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
+                         const void* src, void* dst, hipStream_t st) {
+    LBM_DISPATCH(storage, ng, { hipError_t e = sweep2_t<S, NG>(L, G, C, dC, src, dst, st); if (e != hipSuccess) return e; });
+    return hipSuccess;
+}
+
+hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
+                        const void* src, void* dst, hipStream_t st) {
+    LBM_DISPATCH(storage, ng, { hipError_t e = sweep_t<S, NG>(L, G, C, dC, src, dst, st); if (e != hipSuccess) return e; });
     return hipSuccess;
 }
 

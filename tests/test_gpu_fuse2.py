@@ -1,0 +1,101 @@
+"""Two time steps per launch (LBM_POLICY_FUSE2): the fused kernel steps a
+tile and its halo from HBM into LDS and the tile again from LDS, and must
+give bitwise the populations of two single steps, for every storage,
+temperature model and wall family, on ragged and periodic lattices, with
+and without graph replay, including the cases where lbm_step falls back to
+single steps (NEE walls with a one-row edge tile, comparison collisions)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import max_rel_pop_error, run_pair
+from paper_1510_08224_amd import lbm
+from paper_1510_08224_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FUSE = lbm.LBM_POLICY_FUSE2
+
+
+def _lid(n, re=100.0, u0=0.1):
+    return W.lid_cavity(n, oracle.rate_for_reynolds(re, n, u0), u0)
+
+
+CASES = {
+    "cavity150x70": ("d2q5", lambda: W.cavity(150, 1e5, ny=70), 8),
+    "rb130x37": ("d2q5", lambda: W.rayleigh_benard(130, 37, 2e4), 8),
+    "periodic70x45": ("d2q5", lambda: W.periodic_box(70, 45, s_nu=1.1, zeta_alpha=1.3, ax=2e-4, ay=1e-4,
+                                                     u_c=0.05), 8),
+    "small20x9": ("d2q5", lambda: W.cavity(20, 1e4, ny=9), 8),
+    "injection13x20": ("d2q5", lambda: W.channel(13, 20, s_nu=0.8, zeta_alpha=0.9, u_top=(0.02, 0.01),
+                                                 u_bottom=(0.0, 0.01)), 8),
+    "moving_walls130x40": ("d2q5", lambda: W.cavity(130, 1e5, ny=40).replace(
+        wall_u=((0.0, 0.003), (0.0, -0.01), (0.01, 0.0), (0.05, 0.0))), 8),
+    "nee_cavity130x70": ("d2q5", lambda: W.with_nee_walls(W.cavity(130, 3e5, ny=70)), 8),
+    "nee_rb140x33": ("d2q5", lambda: W.with_nee_walls(W.rayleigh_benard(140, 33, 2e4)), 8),
+    "nee_last_column_one_wide": ("d2q5", lambda: W.with_nee_walls(W.cavity(129, 1e4, ny=40)), 8),
+    "d2q9t_cavity130x50": ("d2q9t", lambda: W.cavity(130, 1e5, ny=50), 8),
+    "d2q9t_nee_cavity70x41": ("d2q9t", lambda: W.with_nee_walls(W.cavity(70, 1e5, ny=41)), 8),
+    "iso_lid130x61": ("isothermal", lambda: _lid(130).replace(ny=61), 8),
+    "iso_nee_lid66x35": ("isothermal", lambda: W.with_nee_walls(_lid(66).replace(ny=35)), 8),
+    "bgk_falls_back": ("d2q5", lambda: W.cavity(90, 1e5, ny=30).replace(collision=W.COLL_BGK), 8),
+}
+
+
+def _run(model, pb, storage, steps, policy, graph, T=None):
+    S = lbm.Solver(pb.nx, pb.ny, storage, model=model)
+    S.set_params(pb)
+    S.set_graph_steps(graph)
+    if policy is not None:
+        S.set_launch(policy=policy)
+    if T is not None and model != "isothermal":
+        S.init_temperature(T)
+    for k in steps:
+        S.step(k)
+    out = S.get_populations(), S.time
+    S.close()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_fused_pairs_equal_single_steps(case, storage):
+    model, mk, _ = CASES[case]
+    pb = mk()
+    T = W.random_temperature(pb.nx, pb.ny, 0.0, 1.0, seed=21)
+    steps = [1, 2, 3, 7, 11]
+    (fa, ga), ta = _run(model, pb, storage, steps, None, 0, T)
+    for pol in (FUSE, FUSE | lbm.LBM_POLICY_XCD_BANDS | lbm.LBM_POLICY_KEEP_STORES,
+                FUSE | lbm.LBM_POLICY_XCD_STRIPS):
+        (fb, gb), tb = _run(model, pb, storage, steps, pol, 0, T)
+        assert ta == tb == sum(steps)
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), pol
+
+
+def test_fused_graph_replay():
+    pb = W.cavity(130, 1e5, ny=70)
+    T = W.random_temperature(130, 70, 0.0, 1.0, seed=5)
+    ref = _run("d2q5", pb, "f64", [8, 8, 5, 16], None, 0, T)
+    for graph in (8, 6):   # 4 and 3 fused launches per graph: odd launch counts swap the buffers
+        got = _run("d2q5", pb, "f64", [8, 8, 5, 16], FUSE, graph, T)
+        assert got[1] == ref[1]
+        assert np.array_equal(got[0][0], ref[0][0]) and np.array_equal(got[0][1], ref[0][1])
+
+
+@pytest.mark.parametrize("model", ["d2q5", "d2q9t", "isothermal"])
+def test_fused_matches_oracle(model):
+    pb = W.with_nee_walls(W.cavity(100, 1e5, ny=44)) if model != "isothermal" else _lid(100).replace(ny=44)
+    S, L = run_pair(pb, 40, launch=(0, 0, 0, FUSE | lbm.LBM_POLICY_XCD_BANDS), model=model)
+    assert S.get_launch()[3] & FUSE
+    fa, ga = S.get_populations()
+    fb, gb = L.get_state()
+    ef, eg = max_rel_pop_error(pb, fa, ga, fb, gb)
+    assert ef < 1e-12 and eg < 1e-12, (ef, eg)
+    S.close()
+
+
+def test_fused_full_size_cavity2048():
+    pb = W.workload_cavity2048()
+    T = W.random_temperature(2048, 2048, 0.0, 1.0, seed=3)
+    ref = _run("d2q5", pb, "f64", [4], None, 0, T)
+    got = _run("d2q5", pb, "f64", [4], FUSE, 0, T)
+    assert np.array_equal(got[0][0], ref[0][0]) and np.array_equal(got[0][1], ref[0][1])

@@ -170,7 +170,7 @@ def test_default_policy_follows_footprint(n, storage, policy):
     with pytest.raises(lbm.LbmError):
         S.set_launch(policy=lbm.LBM_POLICY_XCD_BANDS | lbm.LBM_POLICY_XCD_STRIPS)
     with pytest.raises(lbm.LbmError):
-        S.set_launch(policy=8)
+        S.set_launch(policy=16)
     S.set_launch(policy=lbm.LBM_POLICY_XCD_STRIPS | lbm.LBM_POLICY_KEEP_STORES)
     assert S.get_launch()[3] == lbm.LBM_POLICY_XCD_STRIPS | lbm.LBM_POLICY_KEEP_STORES
     with pytest.raises(lbm.LbmError):
