@@ -54,22 +54,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key: str, nodes: int):
+def measured_traffic(key: str, nodes: int, steps_per_launch: int):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter runs (key: storage for the D2Q5 model, model_storage for the
-    others), if they were taken on the current kernel sources."""
+    others), if they were taken on the current kernel sources with the same
+    number of time steps per launch."""
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    ent = rec.get("kernels", {}).get(key)
-    if not ent or rec.get("source_hash") != kernel_source_hash() or ent.get("nodes") != nodes:
+    ent = rec.get("kernels", {}).get(f"{key}/{steps_per_launch}")
+    if (not ent or rec.get("source_hash") != kernel_source_hash() or ent.get("nodes") != nodes
+            or ent.get("steps_per_launch", 1) != steps_per_launch):
         return None
     return ent.get("bytes_per_launch")
 
 
-def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: str = "d2q5") -> dict:
+def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: str = "d2q5",
+                 single_steps: bool = False) -> dict:
     import torch
     from paper_1510_08224_amd import lbm
 
@@ -77,7 +80,10 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
     S.set_params(pb)
     if launch:
         S.set_launch(*launch)
+    if single_steps:
+        S.set_launch(policy=S.get_launch()[3] & ~lbm.LBM_POLICY_FUSE2)
     shape = S.get_launch()
+    spl = S.steps_per_launch
     thermal = NG[model] > 0
     st = torch.cuda.ExternalStream(S.stream)
     S.step(warmup)
@@ -108,24 +114,29 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
     sweep_ms = sum(a.elapsed_time(b) for a, b, _ in segs)
     nu = S.nusselt(1)[0] if thermal else None
     S.close()
-    avg_launch_s = sweep_ms / 1e3 / steps
-    alg_bytes = values_per_node(model) * BYTES[storage] * nodes
+    avg_step_s = sweep_ms / 1e3 / steps
+    # one launch of the step kernel advances `spl` steps (2 with fused pairs)
+    alg_bytes = spl * values_per_node(model) * BYTES[storage] * nodes
+    avg_launch_s = spl * avg_step_s
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = measured_traffic(storage if model == "d2q5" else f"{model}_{storage}", nodes)
+    traffic = measured_traffic(storage if model == "d2q5" else f"{model}_{storage}", nodes, spl)
     return {
         "storage": storage,
         "model": model,
-        "launch": {"block_x": shape[0], "block_y": shape[1], "rows": shape[2], "policy": shape[3]},
+        "launch": {"block_x": shape[0], "block_y": shape[1], "rows": shape[2], "policy": shape[3],
+                   "steps_per_launch": spl},
         "mlups": nodes * steps / wall / 1e6,
         "ms_per_step": wall * 1e3 / steps,
         "sweep_us_per_launch": avg_launch_s * 1e6,
-        "sweep_mlups": nodes / avg_launch_s / 1e6,
+        "sweep_us_per_step": avg_step_s * 1e6,
+        "sweep_mlups": nodes / avg_step_s / 1e6,
         "residual_last": r,
         "nonfinite": bad,
         "nu_right_mean": nu,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+                     "steps_per_launch": spl},
     }
 
 
@@ -191,6 +202,9 @@ def main():
                 models[m]["workload"] = mpb.name
     colls = {}
     if args.collisions != "none":
+        # the comparison operators run one step per launch: compare them with
+        # the paper's operator run the same way
+        colls["mrt"] = time_storage(args.storage, pb, args.steps, args.warmup, launch, single_steps=True)
         codes = {"bgk": W.COLL_BGK, "ortho_mrt": W.COLL_ORTHO}
         for c in args.collisions.split(","):
             if c in codes:
@@ -223,6 +237,7 @@ def main():
         "cpu_baseline": cpu,
         "sweep_mlups": round(main_res["sweep_mlups"], 1),
         "sweep_us_per_launch": round(main_res["sweep_us_per_launch"], 3),
+        "sweep_us_per_step": round(main_res["sweep_us_per_step"], 3),
         "nu_right_mean": main_res["nu_right_mean"],
         "storage_variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
                                  "sweep_mlups": round(v["sweep_mlups"], 1), "roofline": v["roofline"],
@@ -233,8 +248,9 @@ def main():
                                "launch": v["launch"]}
                            for k, v in models.items()},
         "collision_variants": {k: {"storage": args.storage, "mlups": round(v["mlups"], 1),
-                                   "sweep_us_per_launch": round(v["sweep_us_per_launch"], 3),
-                                   "ratio_to_mrt": round(v["sweep_us_per_launch"] / main_res["sweep_us_per_launch"], 4)}
+                                   "sweep_us_per_step": round(v["sweep_us_per_step"], 3),
+                                   "ratio_to_mrt_single_step": round(v["sweep_us_per_step"] /
+                                                                     colls["mrt"]["sweep_us_per_step"], 4)}
                                for k, v in colls.items()},
         "source_hash": kernel_source_hash(),
     }

@@ -290,9 +290,10 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           with the MRT collision on buffers below 4 GiB and,
  *                           with NEE walls, when no edge tile is one node
  *                           wide or high; otherwise steps run singly.
- * The default follows the footprint F of both population buffers: bands
- * while F <= 500 MiB (FP64 storage: 1 GiB), kept stores while
- * F <= 256 MiB. */
+ * The default follows the storage and the footprint F of both population
+ * buffers: kept stores while F <= 256 MiB; fused pairs for FP64 storage
+ * and for FP32 storage above 256 MiB, with bands; otherwise bands while
+ * F <= 500 MiB (FP64: 1 GiB). */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
@@ -309,6 +310,10 @@ enum {
  * LBM_POLICY_KEEP or LBM_POLICY_DEFAULT.  Results do not depend on the
  * shape or the policy (bitwise).  LBM_ERR_ARG for other values. */
 int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread, int32_t policy);
+
+/* Time steps one step-kernel launch advances with the current parameters
+ * and launch settings: 2 when fused pairs are in use, else 1. */
+int lbm_steps_per_launch(const lbm_solver* h, int32_t* steps);
 int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread,
                    int32_t* policy);
 

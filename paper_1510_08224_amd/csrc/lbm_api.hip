@@ -166,11 +166,17 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // neighbouring 64-wide tiles on different XCDs); the round-robin order wins
 // above (FP16 3072^2, 528 MB: +11%; FP64 4096^2: +2%).  Contiguous strips
 // per XCD (LBM_POLICY_XCD_STRIPS) are within a few percent either way and
-// left to the autotuner.
+// left to the autotuner.  Fused pairs of steps (LBM_POLICY_FUSE2) win for
+// FP64 at every size measured (512^2 to 4096^2: 1.2x to 1.7x) and for FP32
+// once the state outgrows the last-level cache (2048^2: 1.47x; 1024^2:
+// 0.92x); never for FP16, whose fused kernel is latency-bound.  Fused
+// pairs run best with XCD bands.
 static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
     h->L.order = (ws <= 500.0 * mib || (h->storage == LBM_F64 && ws <= 1024.0 * mib)) ? 1 : 0;
+    h->L.fuse2 = h->storage == LBM_F64 || (h->storage == LBM_F32 && ws > 256.0 * mib);
+    if (h->L.fuse2) h->L.order = 1;
 }
 
 static void default_launch(lbm_solver* h) {
@@ -845,6 +851,12 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
     }
     drop_graphs(h);
     if (h->batch) batch_invalidate(h->batch);
+    return LBM_OK;
+}
+
+int lbm_steps_per_launch(const lbm_solver* h, int32_t* steps) {
+    if (!h || !steps) return fail(nullptr, LBM_ERR_ARG, "lbm_steps_per_launch: NULL argument");
+    *steps = fuse2_active(h) ? 2 : 1;
     return LBM_OK;
 }
 

@@ -172,8 +172,11 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 // HBM once per two steps instead of once per step; the halo costs
 // (66 (TY + 2)) / (64 TY) - 1 extra collisions.  The result is bitwise the
 // result of two single steps.  TY is a multiple of 4 (the 256 threads take
-// whole rows in the second step) chosen so that the LDS of one workgroup
-// stays within 80 KB: two workgroups per 160 KB CU.
+// whole rows in the second step), the largest whose LDS fits 40 KB, at
+// least 4: the kernel is bound by latency, not arithmetic, so three to
+// five workgroups per 160 KB CU beat taller tiles with less halo work
+// (measured on MI355X: FP32 2048^2 8.3 TB/s algorithmic at 40 KB against
+// 6.9 TB/s at 80 KB).
 // ---------------------------------------------------------------------------
 // The value a store to storage type S followed by a load would give.
 template <class S>
@@ -189,11 +192,11 @@ struct Fuse2 {
     static constexpr int TX = 64;
     static constexpr int EW = TX + 2;
     static constexpr int ROW_BYTES = EW * NP * (int)sizeof(R);
-    static constexpr int TY_FIT = 81920 / ROW_BYTES - 2;
+    static constexpr int TY_FIT = 40960 / ROW_BYTES - 2;
     static constexpr int TY = TY_FIT >= 32 ? 32 : (TY_FIT < 4 ? 4 : TY_FIT / 4 * 4);
     static constexpr int EH = TY + 2;
     static constexpr int PLANE = EW * EH;
-    static_assert(NP * PLANE * (int)sizeof(R) <= 81920, "fused tile exceeds its LDS budget");
+    static_assert(NP * PLANE * (int)sizeof(R) <= 81920, "fused tile needs more than half the LDS of a CU");
 };
 
 // The first fused step on extended slot e of a tile at (x0, y0): pull (or

@@ -97,6 +97,7 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "lbm_set_graph_steps": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lbm_get_graph_steps": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_steps_per_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, _P]),
     "lbm_batch_add": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -283,6 +284,13 @@ class Solver:
         _check(lib().lbm_get_launch(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
                self.h)
         return a.value, b.value, c.value, d.value
+
+    @property
+    def steps_per_launch(self) -> int:
+        """Time steps per step-kernel launch (2 with fused pairs)."""
+        v = ctypes.c_int32()
+        _check(lib().lbm_steps_per_launch(self.h, ctypes.byref(v)), self.h)
+        return v.value
 
     def set_graph_steps(self, steps: int):
         _check(lib().lbm_set_graph_steps(self.h, int(steps)), self.h)

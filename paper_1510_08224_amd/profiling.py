@@ -4,7 +4,9 @@
     python -m paper_1510_08224_amd.profiling traffic <fetch dir> <write dir> <out.json> "<commands>" <nodes> [out.md]
 
 Step kernels are keyed by storage ("f64") for the D2Q5 model and by
-model and storage ("d2q9t_f64", "isothermal_f64") for the others.
+model and storage ("d2q9t_f64", "isothermal_f64") for the others, with
+the time steps per launch appended ("f64/2": fused pairs, "f64/1": single
+steps).
 
 ``stats`` turns the kernel statistics of a ``rocprofv3 --kernel-trace
 --stats -f csv`` run into a short Markdown table.  ``traffic`` reads two
@@ -26,8 +28,9 @@ import re
 import sys
 
 COPY_BYTES = 1 << 30
-# k_sweep<storage type, NG, ROWS, MODE, COLL>: the MRT step of each model
-SWEEP = re.compile(r"k_sweep<(double|float|__half), (\d), 1, \d, 0>")
+# k_sweep<storage type, NG, ROWS, MODE, COLL> (one step per launch) and
+# k_sweep2<storage type, NG, MODE, COLL> (two): the MRT step of each model
+SWEEP = re.compile(r"k_sweep(2?)<(double|float|__half), (\d), (?:1, )?\d, 0>")
 STORAGE = {"double": "f64", "float": "f32", "__half": "f16"}
 MODEL = {"5": "d2q5", "9": "d2q9t", "0": "isothermal"}
 
@@ -119,12 +122,13 @@ def write_traffic(fetch_dir: str, write_dir: str, out_json: str, commands: str, 
         m = SWEEP.search(name)
         if not m:
             continue
-        st, model = STORAGE[m.group(1)], MODEL[m.group(2)]
-        key = st if model == "d2q5" else f"{model}_{st}"
+        steps = 2 if m.group(1) else 1
+        st, model = STORAGE[m.group(2)], MODEL[m.group(3)]
+        key = (st if model == "d2q5" else f"{model}_{st}") + f"/{steps}"
         wv = write.get(name, (float("nan"), 0))[0]
         rb, wb = fv * 1024.0 * sf, wv * 1024.0 * sw
-        alg = 2 * (9 + int(m.group(2))) * {"f64": 8, "f32": 4, "f16": 2}[st] * nodes
-        rec["kernels"][key] = {"kernel": name, "dispatches": n, "nodes": nodes,
+        alg = steps * 2 * (9 + int(m.group(3))) * {"f64": 8, "f32": 4, "f16": 2}[st] * nodes
+        rec["kernels"][key] = {"kernel": name, "dispatches": n, "nodes": nodes, "steps_per_launch": steps,
                               "read_bytes_per_launch": rb, "write_bytes_per_launch": wb,
                               "bytes_per_launch": rb + wb, "algorithmic_bytes_per_launch": alg,
                               "traffic_over_algorithmic": (rb + wb) / alg}
