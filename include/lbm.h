@@ -352,9 +352,28 @@ lbm_solver* lbm_batch_member(const lbm_batch* b, int32_t slot);
 /* Advance every member nsteps steps (asynchronous). */
 int lbm_batch_step(lbm_batch* b, int64_t nsteps);
 
-/* Replay captured graphs of `steps` batched launches (even, <= 4096;
- * 0 = one launch per step, the default). */
+/* Replay captured graphs of `steps` batched time steps (even, <= 4096;
+ * 0 = launches issued one by one, the default). */
 int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
+
+/* Fused pairs of time steps for the whole batch (the two-step kernel of
+ * lbm_set_launch's LBM_POLICY_FUSE2, one launch per pair for all members,
+ * 64 x TY tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
+ * or LBM_POLICY_FUSE2.  The default fuses pairs when the node-weighted
+ * mean of the members' shorter side is at least 128 (FP64 storage), or at
+ * least 384 with both buffers of all members above 256 MiB (FP32); tiles
+ * on a wall cost more than interior ones, so small members step faster
+ * one step per launch.  Fused pairs apply only
+ * when every member qualifies (buffers below 4 GiB; with walls by
+ * non-equilibrium extrapolation, nx % 64 != 1 and ny % TY != 1); else the
+ * batch steps one launch per step.  Results are bitwise the same either
+ * way.  Takes effect at the next lbm_batch_step.  LBM_ERR_ARG for any
+ * other value. */
+int lbm_batch_set_policy(lbm_batch* b, int32_t policy);
+
+/* Time steps one batched launch advances with the current members and
+ * policy (1 or 2); rebuilds the tile table if members changed. */
+int lbm_batch_steps_per_launch(lbm_batch* b, int32_t* steps);
 
 /* Wait for the batch's stream. */
 int lbm_batch_synchronize(lbm_batch* b);

@@ -41,6 +41,9 @@ inline int storage_bytes(int storage) { return storage == kF64 ? 8 : (storage ==
 hipError_t launch_sweep2(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st);
 int fuse2_rows(int storage, int ng);
+// Fused pairs of steps for a batch (buffer addressing; keep: default-policy stores).
+hipError_t launch_sweep2_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
+                               int ntiles, int parity, hipStream_t st);
 // C: the host copy (launch decisions); dC: the same constants in device
 // memory (read by the kernels).
 hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,

@@ -279,16 +279,13 @@ __device__ __forceinline__ void lds_pull_node(const typename Codec<S>::R* lds, c
     if constexpr (NG > 0) lds_pull_g<S, NG>(lds, G, C, x, y, lx, ly, g, std::make_integer_sequence<int, NG>{});
 }
 
+// One fused pair of steps on the tile at (x0, y0) of one lattice.
 template <class S, int NG, int MODE, int COLL>
-__global__ __launch_bounds__(256) void k_sweep2(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
-                                                S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int order) {
-    const Coeffs& C = *Cp;
+__device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const S* __restrict__ src,
+                                           S* __restrict__ dst, unsigned buf_bytes, int x0, int y0,
+                                           typename Codec<S>::R* lds) {
     using F = Fuse2<S, NG>;
     using R = typename Codec<S>::R;
-    __shared__ R lds[F::NP * F::PLANE];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x, order, tiles_x);
-    const int x0 = (tile % tiles_x) * F::TX, y0 = (tile / tiles_x) * F::TY;
-
     // Step t -> t + 1 on the tile and its halo, two slots per thread at a
     // time so that both slots' loads are in flight together.
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
@@ -330,6 +327,30 @@ __global__ __launch_bounds__(256) void k_sweep2(Geom G, const Coeffs* __restrict
         if (MODE == kBufferKeep) store_node_buf<S, NG, kCachePolicyDefault>(rd, G, C, boff, f, g);
         else store_node_buf<S, NG, kCachePolicyNT>(rd, G, C, boff, f, g);
     }
+}
+
+template <class S, int NG, int MODE, int COLL>
+__global__ __launch_bounds__(256) void k_sweep2(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
+                                                S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int order) {
+    using F = Fuse2<S, NG>;
+    __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x, order, tiles_x);
+    fused_tile<S, NG, MODE, COLL>(G, *Cp, src, dst, buf_bytes, (tile % tiles_x) * F::TX, (tile / tiles_x) * F::TY,
+                                  lds);
+}
+
+// Fused pairs of steps for every lattice of a batch: each workgroup takes
+// one entry of the fused tile table (a member and its 64 x TY tile).
+template <class S, int NG, int MODE>
+__global__ __launch_bounds__(256) void k_sweep2_batch(const BatchMember* __restrict__ members,
+                                                      const BatchTile* __restrict__ tiles, int parity) {
+    using F = Fuse2<S, NG>;
+    __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, kXcdBands, 0)];
+    const BatchMember& M = members[t.member];
+    const int sel = (M.cur0 + parity) & 1;
+    fused_tile<S, NG, MODE, kCollMRT>(M.G, M.C, static_cast<const S*>(M.buf[sel]), static_cast<S*>(M.buf[sel ^ 1]),
+                                      M.buf_bytes, t.x0, t.y0, lds);
 }
 
 // One time step of every lattice of a batch.  Each workgroup of 256
@@ -777,6 +798,20 @@ hipError_t launch_sweep_batch(int storage, int ng, bool buffer, const BatchMembe
             hipLaunchKernelGGL((k_sweep_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
         else
             hipLaunchKernelGGL((k_sweep_batch<S, NG, kGlobal>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep2_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
+                               int ntiles, int parity, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    LBM_DISPATCH(storage, ng, {
+        if (keep)
+            hipLaunchKernelGGL((k_sweep2_batch<S, NG, kBufferKeep>), dim3(ntiles), dim3(256), 0, st, members, tiles,
+                               parity);
+        else
+            hipLaunchKernelGGL((k_sweep2_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(256), 0, st, members, tiles,
+                               parity);
     });
     return hipGetLastError();
 }

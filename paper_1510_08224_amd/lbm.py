@@ -105,6 +105,8 @@ _SIGS = {
     "lbm_batch_member": (_P, [_P, ctypes.c_int32]),
     "lbm_batch_step": (ctypes.c_int, [_P, ctypes.c_int64]),
     "lbm_batch_set_graph_steps": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbm_batch_set_policy": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbm_batch_steps_per_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_synchronize": (ctypes.c_int, [_P]),
     "lbm_batch_residual": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
     "lbm_batch_stream": (_P, [_P]),
@@ -418,6 +420,16 @@ class Batch:
 
     def set_graph_steps(self, steps: int):
         _bcheck(lib().lbm_batch_set_graph_steps(self.h, int(steps)), self.h)
+
+    def set_policy(self, policy: int):
+        """LBM_POLICY_DEFAULT, 0 (one launch per step) or LBM_POLICY_FUSE2."""
+        _bcheck(lib().lbm_batch_set_policy(self.h, int(policy)), self.h)
+
+    @property
+    def steps_per_launch(self) -> int:
+        v = ctypes.c_int32()
+        _bcheck(lib().lbm_batch_steps_per_launch(self.h, ctypes.byref(v)), self.h)
+        return v.value
 
     def synchronize(self):
         _bcheck(lib().lbm_batch_synchronize(self.h), self.h)

@@ -138,3 +138,136 @@ def test_nonfinite_member_is_isolated():
         fa, _ = _alone(pb, mkT() if mkT else None, "f32", 60)
         assert np.array_equal(fa, sols[k].get_populations()[0])
     B.close()
+
+
+# ---------------------------------------------------------------------------
+# Fused pairs of steps for a whole batch (lbm_batch_set_policy).
+# ---------------------------------------------------------------------------
+FUSE = lbm.LBM_POLICY_FUSE2
+
+
+def _fused_mix():
+    return _mix() + [
+        (W.with_nee_walls(W.cavity(96, 2e5, ny=70)), None),
+        (W.periodic_box(70, 45, s_nu=1.1, zeta_alpha=1.3, ax=2e-4, ay=1e-4, u_c=0.05), None),
+    ]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_fused_batch_matches_alone_bitwise(storage):
+    mix = _fused_mix()
+    B, sols = _batch(storage, mix)
+    B.set_policy(FUSE)
+    assert B.steps_per_launch == 2
+    B.step(37)            # 18 fused launches and one single step
+    B.step(25)
+    B.residual()          # first call: snapshot only
+    B.step(1)
+    r, bad = B.residual()
+    for k, ((pb, mkT), S) in enumerate(zip(mix, sols)):
+        A = lbm.Solver(pb.nx, pb.ny, storage)
+        A.set_params(pb)
+        A.set_launch(policy=0)
+        if mkT:
+            A.init_temperature(mkT())
+        A.step(62)
+        A.residual()
+        A.step(1)
+        ra, _ = A.residual()
+        fa, ga = A.get_populations()
+        A.close()
+        fb, gb = S.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), pb.name
+        assert S.time == 63 and bad[k] == 0
+        assert r[k] == ra, pb.name
+    B.close()
+
+
+@pytest.mark.parametrize("model", ["d2q9t", "isothermal"])
+def test_fused_batch_other_models(model):
+    lid = W.lid_cavity(72, oracle.rate_for_reynolds(100.0, 72, 0.1), 0.1)
+    mix = ([(W.cavity(70, 1e5, ny=41), None), (W.with_nee_walls(W.cavity(96, 1e4, ny=66)), None)]
+           if model == "d2q9t" else [(lid, None), (W.with_nee_walls(lid.replace(nx=130, ny=62)), None)])
+    B = lbm.Batch("f64")
+    B.set_policy(FUSE)
+    sols = []
+    for pb, _ in mix:
+        S = B.new_solver(pb.nx, pb.ny, model=model)
+        S.set_params(pb)
+        B.add(S)
+        sols.append(S)
+    assert B.steps_per_launch == 2
+    B.step(21)
+    for (pb, _), S in zip(mix, sols):
+        A = lbm.Solver(pb.nx, pb.ny, "f64", model=model)
+        A.set_params(pb)
+        A.set_launch(policy=0)
+        A.step(21)
+        fa, ga = A.get_populations()
+        A.close()
+        fb, gb = S.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), pb.name
+    B.close()
+
+
+def test_fused_batch_graphs_odd_launch_count_and_membership():
+    # graphs of 6 steps hold 3 fused launches: each replay swaps the buffers
+    mix = _fused_mix()
+    B, sols = _batch("f32", mix, graph=6)
+    B.set_policy(FUSE)
+    B.step(13)            # two replays and one single step
+    B.remove(3)
+    B.step(12)
+    sols[0].step(1)       # a member stepped on its own
+    B.step(7)
+    expect = {0: 33, 3: 13}
+    for k, S in enumerate(sols):
+        pb, mkT = mix[k]
+        fa, ga = _alone(pb, mkT() if mkT else None, "f32", expect.get(k, 32), launch=(64, 4, 1, 0))
+        fb, gb = S.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), k
+        assert S.time == expect.get(k, 32)
+    B.close()
+
+
+def test_fused_batch_policy_rules():
+    B = lbm.Batch("f64")
+    S = B.new_solver(128, 128)
+    S.set_params(W.cavity(128, 1e4))
+    B.add(S)
+    assert B.steps_per_launch == 2            # FP64, members of side >= 128
+    B.set_policy(0)
+    assert B.steps_per_launch == 1
+    B.set_policy(lbm.LBM_POLICY_DEFAULT)
+    S3 = B.new_solver(64, 64)
+    S3.set_params(W.cavity(64, 1e4))
+    slot3 = B.add(S3)
+    for _ in range(3):
+        S4 = B.new_solver(64, 64)
+        S4.set_params(W.cavity(64, 1e4))
+        B.add(S4)
+    assert B.steps_per_launch == 1            # mean side below 128
+    B.set_policy(FUSE)
+    assert B.steps_per_launch == 2
+    # a wall rebuilt by extrapolation on a one-column edge tile: single steps
+    S2 = B.new_solver(129, 40)
+    pb2 = W.with_nee_walls(W.cavity(129, 1e4, ny=40))
+    S2.set_params(pb2)
+    B.add(S2)
+    assert B.steps_per_launch == 1
+    B.step(9)
+    fa, ga = _alone(pb2, None, "f64", 9)
+    assert np.array_equal(fa, S2.get_populations()[0])
+    assert slot3 == 1
+    for bad in (1, 4, 8 | 1, -3):
+        with pytest.raises(lbm.LbmError):
+            B.set_policy(bad)
+    B.close()
+    B = lbm.Batch("f32")
+    S = B.new_solver(64, 64)
+    S.set_params(W.cavity(64, 1e4))
+    B.add(S)
+    assert B.steps_per_launch == 1            # small FP32 batch: single steps
+    B.set_policy(FUSE)
+    assert B.steps_per_launch == 2
+    B.close()
