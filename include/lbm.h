@@ -360,8 +360,8 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
  * lbm_set_launch's LBM_POLICY_FUSE2, one launch per pair for all members,
  * 64 x TY tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
  * or LBM_POLICY_FUSE2.  The default fuses pairs when the node-weighted
- * mean of the members' shorter side is at least 128 (FP64 storage), or at
- * least 384 with both buffers of all members above 256 MiB (FP32); tiles
+ * mean of the members' shorter side is at least 96 (FP64 storage), or at
+ * least 160 with both buffers of all members above 256 MiB (FP32); tiles
  * on a wall cost more than interior ones, so small members step faster
  * one step per launch.  Fused pairs apply only
  * when every member qualifies (buffers below 4 GiB; with walls by

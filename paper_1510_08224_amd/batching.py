@@ -1,6 +1,7 @@
 """Batched solves and the tile autotuner.
 
     python -m paper_1510_08224_amd.batching [--count 256 --seed 3 --steps 2000]
+    python -m paper_1510_08224_amd.batching --size-sweep
 
 Builds the batch workload (independent differentially heated cavities,
 side uniform over {64, 96, 128, 192, 256}, Ra log-uniform in [1e3, 1e6],
@@ -183,6 +184,35 @@ def report(count: int = 256, seed: int = 3, steps: int = 2000, base_steps: int =
     return out
 
 
+def size_sweep(storages=("f32", "f64"), sides=(64, 96, 128, 192, 256, 384, 512, 1024), total: float = 6.7e6,
+               steps: int = 400):
+    """Fused pairs against one step per launch for batches of equal square
+    cavities of each side (about `total` nodes per batch); one JSON line
+    per (storage, side)."""
+    import torch
+    torch.cuda.set_device(0)
+    for storage in storages:
+        for side in sides:
+            count = max(1, int(round(total / side ** 2)))
+            B, sols = build([W.cavity(side, 1e5)] * count, storage)
+            t = {}
+            for pol in (0, lbm.LBM_POLICY_FUSE2):
+                B.set_policy(pol)
+                t[pol] = time_batch(B, steps)
+            B.set_policy(lbm.LBM_POLICY_DEFAULT)
+            nodes = count * side * side
+            print(json.dumps({"storage": storage, "side": side, "members": count,
+                              "single_us": round(t[0] * 1e6, 2),
+                              "fused_us": round(t[lbm.LBM_POLICY_FUSE2] * 1e6, 2),
+                              "single_over_fused": round(t[0] / t[lbm.LBM_POLICY_FUSE2], 3),
+                              "single_mlups": round(nodes / t[0] / 1e6),
+                              "fused_mlups": round(nodes / t[lbm.LBM_POLICY_FUSE2] / 1e6),
+                              "default_steps_per_launch": B.steps_per_launch}), flush=True)
+            B.close()
+            for S in sols:
+                S.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=256)
@@ -192,7 +222,12 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cache", default=None)
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="fused pairs vs one step per launch by member size, then exit")
     args = ap.parse_args()
+    if args.size_sweep:
+        size_sweep()
+        return
     print(json.dumps(report(args.count, args.seed, args.steps, args.base_steps, args.storage,
                             not args.no_tune, args.cache)), flush=True)
 

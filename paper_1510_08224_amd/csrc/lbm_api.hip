@@ -1048,17 +1048,18 @@ static int batch_build(lbm_batch* b) {
         mem.push_back(M);
         b->member_slot.push_back((int)k);
     }
-    // Fused tiles on a wall take the general pull, so fused pairs pay off
-    // only for members large enough to be mostly interior tiles.  Measured
-    // on MI355X with batches of equal square cavities (6.7e6 nodes in all):
-    // FP64 gains from side 128 (1.2x) up, FP32 from side 384 (1.25x) up and
-    // loses up to 26% below; FP16 gains nowhere.  The default uses the
-    // node-weighted mean of the members' shorter side.
+    // Fused tiles on a wall pull through the general load in the first
+    // step, so fused pairs pay off only for members large enough to be
+    // mostly interior tiles.  Measured on MI355X with batches of equal
+    // square cavities (6.7e6 nodes in all): FP64 gains 1.06x at side 96 and
+    // 1.3-1.7x from 128 up; FP32 breaks even at 96-128 and gains 1.06-1.5x
+    // from 192 up, losing 14% at 64; FP16 gains nowhere.  The default uses
+    // the node-weighted mean of the members' shorter side.
     const double mib = 1024.0 * 1024.0;
     const double side = nodes > 0.0 ? side_nodes / nodes : 0.0;
     const bool want = b->policy == LBM_POLICY_DEFAULT
-                          ? ((b->storage == LBM_F64 && side >= 128.0) ||
-                             (b->storage == LBM_F32 && ws > 256.0 * mib && side >= 384.0))
+                          ? ((b->storage == LBM_F64 && side >= 96.0) ||
+                             (b->storage == LBM_F32 && ws > 256.0 * mib && side >= 160.0))
                           : (b->policy & LBM_POLICY_FUSE2) != 0;
     b->fuse = want && can_fuse && b->buffer && !mem.empty();
     b->keep = ws <= 256.0 * mib;

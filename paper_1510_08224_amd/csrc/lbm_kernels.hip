@@ -166,18 +166,37 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 // Two time steps per launch.  A workgroup owns a tile of 64 x TY nodes.
 // First it runs the step t -> t + 1 on the tile and a one-node halo around
 // it, reading the state from HBM as the single-step kernel does, and keeps
-// the post-collision populations in LDS (rounded exactly as a store to the
-// storage type would round them).  Then it runs the step t + 1 -> t + 2 on
-// the tile, pulling from LDS, and stores to HBM.  Every population crosses
-// HBM once per two steps instead of once per step; the halo costs
-// (66 (TY + 2)) / (64 TY) - 1 extra collisions.  The result is bitwise the
-// result of two single steps.  TY is a multiple of 4 (the 256 threads take
-// whole rows in the second step), the largest whose LDS fits 40 KB, at
-// least 4: the kernel is bound by latency, not arithmetic, so three to
-// five workgroups per 160 KB CU beat taller tiles with less halo work
-// (measured on MI355X: FP32 2048^2 8.3 TB/s algorithmic at 40 KB against
-// 6.9 TB/s at 80 KB).
+// in LDS the post-collision populations that the tile pulls next (rounded
+// exactly as a store to the storage type would round them).  Then it runs
+// the step t + 1 -> t + 2 on the tile, pulling from LDS, and stores to HBM.
+// Every population crosses HBM once per two steps instead of once per
+// step; the halo costs (66 (TY + 2)) / (64 TY) - 1 extra collisions.  The
+// result is bitwise the result of two single steps.
+//
+// LDS layout: population i of the second step's pull at tile node n comes
+// from node n - e_i, so plane i holds exactly a 64 x TY window (the tile
+// shifted by -e_i), indexed by the pulling node.  A node of the first step
+// writes population i to window slot n + e_i when that lies in the tile.
+// Where the link into tile node n crosses a non-periodic side, no node
+// exists at n - e_i; the first step at n writes there the wall rule of the
+// pull instead (the kept opposite population plus bbf, or gsign times it
+// plus gconst, the y side first at a corner), so the second step reads
+// every node's populations with plain LDS loads.
+//
+// TY is a multiple of 4 (the 256 threads take whole rows in the second
+// step), the largest whose LDS fits kFuse2Lds bytes, at least 4.  The
+// kernel is bound by latency, not arithmetic or bandwidth, so short tiles
+// win: with one pass per phase the compiler keeps the step constants in
+// scalar registers, and more workgroups fit a CU.  Measured on MI355X
+// (2048^2, algorithmic GB/s): FP32 D2Q5 8.4 TB/s at TY = 4 against 7.4 at
+// 8 and 6.5 at 16; FP64 D2Q5 9.5 at 4 against 8.6 at 8.  The isothermal
+// kernels also ask for five waves per SIMD (FP32: 7.7 against 6.9 TB/s).
 // ---------------------------------------------------------------------------
+#ifndef LBM_FUSE2_LDS
+#define LBM_FUSE2_LDS 20480
+#endif
+constexpr int kFuse2Lds = LBM_FUSE2_LDS;
+
 // The value a store to storage type S followed by a load would give.
 template <class S>
 __device__ __forceinline__ typename Codec<S>::R as_stored(typename Codec<S>::R v, float scale, float inv) {
@@ -191,17 +210,19 @@ struct Fuse2 {
     static constexpr int NP = 9 + NG;
     static constexpr int TX = 64;
     static constexpr int EW = TX + 2;
-    static constexpr int ROW_BYTES = EW * NP * (int)sizeof(R);
-    static constexpr int TY_FIT = 40960 / ROW_BYTES - 2;
+    static constexpr int ROW_BYTES = TX * NP * (int)sizeof(R);
+    static constexpr int TY_FIT = kFuse2Lds / ROW_BYTES;
     static constexpr int TY = TY_FIT >= 32 ? 32 : (TY_FIT < 4 ? 4 : TY_FIT / 4 * 4);
     static constexpr int EH = TY + 2;
-    static constexpr int PLANE = EW * EH;
+    static constexpr int SLOTS = EW * EH;   // nodes of the first step
+    static constexpr int PLANE = TX * TY;   // LDS values per population
     static_assert(NP * PLANE * (int)sizeof(R) <= 81920, "fused tile needs more than half the LDS of a CU");
 };
 
-// The first fused step on extended slot e of a tile at (x0, y0): pull (or
-// extrapolate) the pre-collision populations.  Returns false for a slot
-// outside a non-periodic axis.
+// The first fused step on slot e of a tile at (x0, y0) (slots: the tile and
+// its halo, row-major, 66 per row): pull (or extrapolate) the
+// pre-collision populations.  Returns false for a slot outside a
+// non-periodic side.
 template <class S, int NG>
 __device__ __forceinline__ bool fuse2_load(const S* __restrict__ src, __amdgpu_buffer_rsrc_t rs, const Geom& G,
                                            const Coeffs& C, int x0, int y0, int e, typename Codec<S>::R f[9],
@@ -223,28 +244,20 @@ __device__ __forceinline__ bool fuse2_load(const S* __restrict__ src, __amdgpu_b
     return true;
 }
 
-// Collide the pulled populations of slot e and keep them in LDS as a store
-// to S would round them.
-template <class S, int NG, int COLL>
-__device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Coeffs& C, int e,
-                                           typename Codec<S>::R f[9], typename Codec<S>::R g[gdim(NG)]) {
+// Population I of slot (sx, sy) (tile coordinates) into its window slot.
+template <class S, int NG, int P0, int I>
+__device__ __forceinline__ void fuse2_put(typename Codec<S>::R* lds, int sx, int sy, typename Codec<S>::R v) {
     using F = Fuse2<S, NG>;
-    using R = typename Codec<S>::R;
-    const Macro m = macro<R, NG>(f, g, C);
-    collide<R, NG, COLL>(f, g, m, C);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) lds[i * F::PLANE + e] = as_stored<S>(f[i], C.fscale, C.finv);
-#pragma unroll
-    for (int i = 0; i < NG; ++i) lds[(9 + i) * F::PLANE + e] = as_stored<S>(g[i], C.gscale, C.ginv);
+    const int tx = sx + ex(I), ty = sy + ey(I);
+    if (tx >= 0 && tx < F::TX && ty >= 0 && ty < F::TY) lds[(P0 + I) * F::PLANE + ty * F::TX + tx] = v;
 }
 
-// Pull of population I of node (x, y) whose LDS coordinates are (lx, ly),
-// with the wall rules of `source`.  A periodic wrap needs no case: the
-// halo slot holds the wrapped node.
-template <class S, int NG, int I, int P0>
-__device__ __forceinline__ typename Codec<S>::R lds_pull1(const typename Codec<S>::R* __restrict__ lds,
-                                                          const Geom& G, const Coeffs& C, int x, int y, int lx,
-                                                          int ly) {
+// The wall rule of link I into tile node (x, y) = (x0 + sx, y0 + sy), if
+// the link crosses a non-periodic side; the same arithmetic as the pull.
+template <class S, int NG, int I>
+__device__ __forceinline__ void fuse2_wall(typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x, int y,
+                                           int idx, const typename Codec<S>::R f[9],
+                                           const typename Codec<S>::R g[gdim(NG)]) {
     using F = Fuse2<S, NG>;
     using R = typename Codec<S>::R;
     constexpr int dx = ex(I), dy = ey(I);
@@ -252,31 +265,45 @@ __device__ __forceinline__ typename Codec<S>::R lds_pull1(const typename Codec<S
     int side = -1;
     if (dy != 0 && (sy < 0 || sy >= G.ny) && !G.py) side = sy < 0 ? kBottom : kTop;
     if (dx != 0 && (sx < 0 || sx >= G.nx) && !G.px && side < 0) side = sx < 0 ? kLeft : kRight;
-    if (side < 0) return lds[(P0 + I) * F::PLANE + (ly - dy) * F::EW + (lx - dx)];
-    const R own = lds[(P0 + opp(I)) * F::PLANE + ly * F::EW + lx];
-    if constexpr (P0 == 0) return own + (R)C.bbf[side][I];
-    else return (R)C.gsign[side] * own + (R)C.gconst[side][I];
+    if (side < 0) return;
+    lds[I * F::PLANE + idx] = f[opp(I)] + (R)C.bbf[side][I];
+    if constexpr (I < NG) lds[(9 + I) * F::PLANE + idx] = (R)C.gsign[side] * g[opp(I)] + (R)C.gconst[side][I];
+}
+
+template <class S, int NG, int P0, int... I>
+__device__ __forceinline__ void fuse2_put_set(typename Codec<S>::R* lds, int sx, int sy,
+                                              const typename Codec<S>::R* v, std::integer_sequence<int, I...>) {
+    (fuse2_put<S, NG, P0, I>(lds, sx, sy, v[I]), ...);
 }
 
 template <class S, int NG, int... I>
-__device__ __forceinline__ void lds_pull_f(const typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x,
-                                           int y, int lx, int ly, typename Codec<S>::R f[9],
-                                           std::integer_sequence<int, I...>) {
-    ((f[I] = lds_pull1<S, NG, I, 0>(lds, G, C, x, y, lx, ly)), ...);
-}
-template <class S, int NG, int... I>
-__device__ __forceinline__ void lds_pull_g(const typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x,
-                                           int y, int lx, int ly, typename Codec<S>::R g[gdim(NG)],
-                                           std::integer_sequence<int, I...>) {
-    ((g[I] = lds_pull1<S, NG, I, 9>(lds, G, C, x, y, lx, ly)), ...);
+__device__ __forceinline__ void fuse2_walls(typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x, int y,
+                                            int idx, const typename Codec<S>::R f[9],
+                                            const typename Codec<S>::R g[gdim(NG)],
+                                            std::integer_sequence<int, I...>) {
+    (fuse2_wall<S, NG, I + 1>(lds, G, C, x, y, idx, f, g), ...);
 }
 
-template <class S, int NG>
-__device__ __forceinline__ void lds_pull_node(const typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x,
-                                              int y, int lx, int ly, typename Codec<S>::R f[9],
-                                              typename Codec<S>::R g[gdim(NG)]) {
-    lds_pull_f<S, NG>(lds, G, C, x, y, lx, ly, f, std::make_integer_sequence<int, 9>{});
-    if constexpr (NG > 0) lds_pull_g<S, NG>(lds, G, C, x, y, lx, ly, g, std::make_integer_sequence<int, NG>{});
+// Collide the pulled populations of slot e, round them as a store to S
+// would, and keep what the second step pulls.
+template <class S, int NG, int COLL>
+__device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x0, int y0,
+                                           int e, typename Codec<S>::R f[9], typename Codec<S>::R g[gdim(NG)]) {
+    using F = Fuse2<S, NG>;
+    using R = typename Codec<S>::R;
+    const Macro m = macro<R, NG>(f, g, C);
+    collide<R, NG, COLL>(f, g, m, C);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = as_stored<S>(f[i], C.fscale, C.finv);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) g[i] = as_stored<S>(g[i], C.gscale, C.ginv);
+    const int sx = e % F::EW - 1, sy = e / F::EW - 1;
+    fuse2_put_set<S, NG, 0>(lds, sx, sy, f, std::make_integer_sequence<int, 9>{});
+    if constexpr (NG > 0) fuse2_put_set<S, NG, 9>(lds, sx, sy, g, std::make_integer_sequence<int, NG>{});
+    const int x = x0 + sx, y = y0 + sy;
+    const bool in_tile = sx >= 0 && sx < F::TX && sy >= 0 && sy < F::TY;
+    const bool wall = (!G.px && (x == 0 || x == G.nx - 1)) || (!G.py && (y == 0 || y == G.ny - 1));
+    if (in_tile && wall) fuse2_walls<S, NG>(lds, G, C, x, y, sy * F::TX + sx, f, g, std::make_integer_sequence<int, 8>{});
 }
 
 // One fused pair of steps on the tile at (x0, y0) of one lattice.
@@ -289,37 +316,41 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
     // Step t -> t + 1 on the tile and its halo, two slots per thread at a
     // time so that both slots' loads are in flight together.
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
-    for (int e = threadIdx.x; e < F::PLANE; e += 512) {
+    for (int e = threadIdx.x; e < F::SLOTS; e += 512) {
         R fa[9], ga[gdim(NG)], fb[9], gb[gdim(NG)];
         const int e2 = e + 256;
         const bool va = fuse2_load<S, NG>(src, rs, G, C, x0, y0, e, fa, ga);
-        const bool vb = e2 < F::PLANE && fuse2_load<S, NG>(src, rs, G, C, x0, y0, e2, fb, gb);
-        if (va) fuse2_keep<S, NG, COLL>(lds, C, e, fa, ga);
-        if (vb) fuse2_keep<S, NG, COLL>(lds, C, e2, fb, gb);
+        const bool vb = e2 < F::SLOTS && fuse2_load<S, NG>(src, rs, G, C, x0, y0, e2, fb, gb);
+        if (va) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, e, fa, ga);
+        if (vb) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, e2, fb, gb);
     }
     __syncthreads();
 
-    // Step t + 1 -> t + 2 on the tile, pulling from LDS.
-    const bool simple = (G.px || (x0 > 0 && x0 + F::TX < G.nx)) && (G.py || (y0 > 0 && y0 + F::TY < G.ny));
+    // Step t + 1 -> t + 2 on the tile, pulling from LDS.  Only wall nodes
+    // rebuilt by extrapolation read elsewhere: their fluid neighbour's
+    // pulls, which lie in the tile (the launch rules out one-node edge
+    // tiles on such sides).
+    const bool nee = C.any_nee && !((G.px || (x0 > 0 && x0 + F::TX < G.nx)) && (G.py || (y0 > 0 && y0 + F::TY < G.ny)));
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, buf_bytes);
     for (int n = threadIdx.x; n < F::TX * F::TY; n += 256) {
         const int ix = n % F::TX, iy = n / F::TX;
         const int x = x0 + ix, y = y0 + iy;
         if (x >= G.nx || y >= G.ny) continue;
-        const int lx = ix + 1, ly = iy + 1;
         R f[9], g[gdim(NG)];
-        if (simple) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) f[i] = lds[i * F::PLANE + (ly - ey(i)) * F::EW + (lx - ex(i))];
-#pragma unroll
-            for (int i = 0; i < NG; ++i) g[i] = lds[(9 + i) * F::PLANE + (ly - ey(i)) * F::EW + (lx - ex(i))];
-        } else if (C.any_nee && nee_node_at(G, C, x, y)) {
+        if (nee && nee_node_at(G, C, x, y)) {
             const NeeWall w = nee_wall(G, C, x, y);
+            const int fn = (w.fy - y0) * F::TX + (w.fx - x0);
             R ff[9], gf[gdim(NG)];
-            lds_pull_node<S, NG>(lds, G, C, w.fx, w.fy, lx + (w.fx - x), ly + (w.fy - y), ff, gf);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) ff[i] = lds[i * F::PLANE + fn];
+#pragma unroll
+            for (int i = 0; i < NG; ++i) gf[i] = lds[(9 + i) * F::PLANE + fn];
             nee_rebuild<R, NG>(w, C, ff, gf, f, g);
         } else {
-            lds_pull_node<S, NG>(lds, G, C, x, y, lx, ly, f, g);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = lds[i * F::PLANE + n];
+#pragma unroll
+            for (int i = 0; i < NG; ++i) g[i] = lds[(9 + i) * F::PLANE + n];
         }
         const Macro m = macro<R, NG>(f, g, C);
         collide<R, NG, COLL>(f, g, m, C);
@@ -330,7 +361,7 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
 }
 
 template <class S, int NG, int MODE, int COLL>
-__global__ __launch_bounds__(256) void k_sweep2(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5 : 1, 8))) void k_sweep2(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
                                                 S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int order) {
     using F = Fuse2<S, NG>;
     __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];
@@ -342,7 +373,7 @@ __global__ __launch_bounds__(256) void k_sweep2(Geom G, const Coeffs* __restrict
 // Fused pairs of steps for every lattice of a batch: each workgroup takes
 // one entry of the fused tile table (a member and its 64 x TY tile).
 template <class S, int NG, int MODE>
-__global__ __launch_bounds__(256) void k_sweep2_batch(const BatchMember* __restrict__ members,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5 : 1, 8))) void k_sweep2_batch(const BatchMember* __restrict__ members,
                                                       const BatchTile* __restrict__ tiles, int parity) {
     using F = Fuse2<S, NG>;
     __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];

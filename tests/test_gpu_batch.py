@@ -235,18 +235,18 @@ def test_fused_batch_policy_rules():
     S = B.new_solver(128, 128)
     S.set_params(W.cavity(128, 1e4))
     B.add(S)
-    assert B.steps_per_launch == 2            # FP64, members of side >= 128
+    assert B.steps_per_launch == 2            # FP64, members of side >= 96
     B.set_policy(0)
     assert B.steps_per_launch == 1
     B.set_policy(lbm.LBM_POLICY_DEFAULT)
     S3 = B.new_solver(64, 64)
     S3.set_params(W.cavity(64, 1e4))
     slot3 = B.add(S3)
-    for _ in range(3):
+    for _ in range(5):
         S4 = B.new_solver(64, 64)
         S4.set_params(W.cavity(64, 1e4))
         B.add(S4)
-    assert B.steps_per_launch == 1            # mean side below 128
+    assert B.steps_per_launch == 1            # node-weighted mean side 90
     B.set_policy(FUSE)
     assert B.steps_per_launch == 2
     # a wall rebuilt by extrapolation on a one-column edge tile: single steps
