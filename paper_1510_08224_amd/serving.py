@@ -249,7 +249,8 @@ def benchmark(count: int = 32, rates=(0.5, 1.0, 2.0, 4.0), seed: int = 4, cap: i
         lup_serial += req.problem.nx * req.problem.ny * res.steps
         serial_results[req.rid] = res
     mu = count / sum(service.values())     # serial solves per second
-    out = {"workload": f"serve{count}_seed{seed}_cap{cap}", "count": count, "cap_steps": cap, "tol": tol,
+    out = {"workload": f"serve{count}_seed{seed}_cap{cap}", "count": count, "sides": list(n_range),
+           "cap_steps": cap, "tol": tol,
            "check_every": check_every, "hbm_budget_bytes": int(budget_gib * 2 ** 30), "max_slots": max_slots,
            "serial_service_rate_per_s": round(mu, 4),
            "serial_mlups": round(lup_serial / sum(service.values()) / 1e6, 1),
@@ -284,6 +285,36 @@ def benchmark(count: int = 32, rates=(0.5, 1.0, 2.0, 4.0), seed: int = 4, cap: i
     return out
 
 
+def markdown(res: dict, command: str) -> str:
+    """The benchmark's result as a Markdown summary (the table of every
+    rate factor and the live check of the FIFO model)."""
+    out = ["# Continuous-batching solve server vs the plain method (MI355X)", "", "Command:", "", "```", command,
+           "```", "",
+           f"Workload `{res['workload']}`: {res['count']} requests (cavity and Rayleigh-Benard solves, 50/50, "
+           f"sides {res.get('sides', ['?', '?'])[0]}-{res.get('sides', ['?', '?'])[1]}, FP32 storage), Poisson arrivals at a rate factor times the measured serial service rate "
+           f"({res['serial_service_rate_per_s']} solves/s). A request stops when its residual over "
+           f"{res['check_every']} steps falls below {res['tol']:g} or at {res['cap_steps']} steps (serial status "
+           f"{res['serial_status']}). HBM budget {res['hbm_budget_bytes'] / 2 ** 30:g} GiB, at most "
+           f"{res['max_slots']} slots. The plain method: FIFO, one solve at a time, each with the library's "
+           f"default launch; its latencies follow a FIFO queue over the measured per-request service times.",
+           "",
+           "| rate factor | arrivals/s | batched p50 s | batched p99 s | batched solves/s | batched MLUPS "
+           "| plain p50 s | plain p99 s | plain MLUPS | same steps as alone |",
+           "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---|"]
+    for e in res["rates"]:
+        b, s = e["batched"], e["serial"]
+        out.append(f"| {e['rate_factor']} | {e['arrival_rate_per_s']} | {b['p50_latency_s']} | {b['p99_latency_s']} "
+                   f"| {b['solves_per_s']} | {b['mlups']} | {s['p50_latency_s']} | {s['p99_latency_s']} "
+                   f"| {s['mlups']} | {e['same_steps_as_alone']} |")
+    for e in res["rates"]:
+        if "serial_live" in e:
+            lv, s = e["serial_live"], e["serial"]
+            out += ["", f"Plain method run live at rate factor {e['rate_factor']}: p50 {lv['p50_latency_s']} s, "
+                        f"p99 {lv['p99_latency_s']} s, {lv['solves_per_s']} solves/s, {lv['mlups']} MLUPS "
+                        f"(FIFO model: p50 {s['p50_latency_s']} s, p99 {s['p99_latency_s']} s)."]
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=32)
@@ -293,11 +324,15 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=2.0)
     ap.add_argument("--max-slots", type=int, default=64)
     ap.add_argument("--nmax", type=int, default=1024)
+    ap.add_argument("--md", default=None, help="also write a Markdown summary to this file")
     args = ap.parse_args()
     rates = tuple(float(v) for v in args.rates.split(","))
     res = benchmark(args.count, rates, args.seed, args.cap, budget_gib=args.budget_gib,
                     max_slots=args.max_slots, n_range=(64, args.nmax))
     print(json.dumps(res), flush=True)
+    if args.md:
+        with open(args.md, "w") as fh:
+            fh.write(markdown(res, "python -m paper_1510_08224_amd.serving"))
 
 
 if __name__ == "__main__":
