@@ -172,7 +172,7 @@ def main():
                     help="also run one elementwise pass over 1 GiB (reference kernel for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(a single lattice would shard as y-slabs with a halo exchange, not implemented)",
               file=sys.stderr)
         sys.exit(2)

@@ -56,7 +56,7 @@ enum lbm_status {
     LBM_ERR_DEVICE = -3,      /* a HIP runtime call or kernel launch failed */
     LBM_ERR_STATE = -4,       /* call out of order (e.g. step before set_params) */
     LBM_ERR_UNSTABLE = -5,    /* non-finite values found by a reduction */
-    LBM_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+    LBM_ERR_UNSUPPORTED = -6  /* valid request the library does not implement */
 };
 
 /* Population storage in device memory.  LBM_F64 stores the populations
