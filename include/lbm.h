@@ -291,9 +291,8 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           with NEE walls, when no edge tile is one node
  *                           wide or high; otherwise steps run singly.
  * The default follows the storage and the footprint F of both population
- * buffers: kept stores while F <= 256 MiB; fused pairs for FP64 storage
- * and for FP32 storage above 256 MiB, with bands; otherwise bands while
- * F <= 500 MiB (FP64: 1 GiB). */
+ * buffers: kept stores while F <= 256 MiB; fused pairs with bands for FP64
+ * and FP32 storage; for FP16, single steps with bands while F <= 500 MiB. */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
@@ -360,10 +359,9 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
  * lbm_set_launch's LBM_POLICY_FUSE2, one launch per pair for all members,
  * 64 x TY tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
  * or LBM_POLICY_FUSE2.  The default fuses pairs when the node-weighted
- * mean of the members' shorter side is at least 96 (FP64 storage), or at
- * least 160 with both buffers of all members above 256 MiB (FP32); tiles
- * on a wall cost more than interior ones, so small members step faster
- * one step per launch.  Fused pairs apply only
+ * mean of the members' shorter side is at least 96 (FP64 storage) or 160
+ * (FP32); tiles on a wall cost more than interior ones, so small members
+ * step faster one step per launch.  Fused pairs apply only
  * when every member qualifies (buffers below 4 GiB; with walls by
  * non-equilibrium extrapolation, nx % 64 != 1 and ny % TY != 1); else the
  * batch steps one launch per step.  Results are bitwise the same either

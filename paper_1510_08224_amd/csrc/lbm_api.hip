@@ -177,15 +177,15 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // above (FP16 3072^2, 528 MB: +11%; FP64 4096^2: +2%).  Contiguous strips
 // per XCD (LBM_POLICY_XCD_STRIPS) are within a few percent either way and
 // left to the autotuner.  Fused pairs of steps (LBM_POLICY_FUSE2) win for
-// FP64 at every size measured (512^2 to 4096^2: 1.2x to 1.7x) and for FP32
-// once the state outgrows the last-level cache (2048^2: 1.47x; 1024^2:
-// 0.92x); never for FP16, whose fused kernel is latency-bound.  Fused
-// pairs run best with XCD bands.
+// FP64 and FP32 at every size measured (FP64 512^2 to 4096^2: 1.2x to
+// 1.7x; FP32 512^2: 1.35x, 1024^2: 1.27x, 2048^2 and up: 1.3x to 1.5x);
+// never for FP16, whose fused kernel is latency-bound.  Fused pairs run
+// best with XCD bands.
 static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
     h->L.order = (ws <= 500.0 * mib || (h->storage == LBM_F64 && ws <= 1024.0 * mib)) ? 1 : 0;
-    h->L.fuse2 = h->storage == LBM_F64 || (h->storage == LBM_F32 && ws > 256.0 * mib);
+    h->L.fuse2 = h->storage == LBM_F64 || h->storage == LBM_F32;
     if (h->L.fuse2) h->L.order = 1;
 }
 
@@ -1058,8 +1058,7 @@ static int batch_build(lbm_batch* b) {
     const double mib = 1024.0 * 1024.0;
     const double side = nodes > 0.0 ? side_nodes / nodes : 0.0;
     const bool want = b->policy == LBM_POLICY_DEFAULT
-                          ? ((b->storage == LBM_F64 && side >= 96.0) ||
-                             (b->storage == LBM_F32 && ws > 256.0 * mib && side >= 160.0))
+                          ? ((b->storage == LBM_F64 && side >= 96.0) || (b->storage == LBM_F32 && side >= 160.0))
                           : (b->policy & LBM_POLICY_FUSE2) != 0;
     b->fuse = want && can_fuse && b->buffer && !mem.empty();
     b->keep = ws <= 256.0 * mib;

@@ -158,7 +158,7 @@ def test_xcd_strips_order_does_not_change_results(launch):
     assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
 
 
-@pytest.mark.parametrize("n,storage,policy", [(64, "f64", 11), (2048, "f64", 9), (2048, "f32", 9), (1024, "f32", 3),
+@pytest.mark.parametrize("n,storage,policy", [(64, "f64", 11), (2048, "f64", 9), (2048, "f32", 9), (1024, "f32", 11),
                                               (2048, "f16", 3), (3072, "f16", 0), (4096, "f16", 0), (4096, "f64", 9)])
 def test_default_policy_follows_footprint(n, storage, policy):
     S = lbm.Solver(n, n, storage)
