@@ -358,10 +358,8 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
 /* Fused pairs of time steps for the whole batch (the two-step kernel of
  * lbm_set_launch's LBM_POLICY_FUSE2, one launch per pair for all members,
  * 64 x TY tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
- * or LBM_POLICY_FUSE2.  The default fuses pairs when the node-weighted
- * mean of the members' shorter side is at least 96 (FP64 storage) or 160
- * (FP32); tiles on a wall cost more than interior ones, so small members
- * step faster one step per launch.  Fused pairs apply only
+ * or LBM_POLICY_FUSE2.  The default fuses pairs for FP64 and FP32
+ * storage and steps FP16 once per launch, as for a single lattice.  Fused pairs apply only
  * when every member qualifies (buffers below 4 GiB; with walls by
  * non-equilibrium extrapolation, nx % 64 != 1 and ny % TY != 1); else the
  * batch steps one launch per step.  Results are bitwise the same either

@@ -8,7 +8,6 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -1018,7 +1017,7 @@ static int batch_build(lbm_batch* b) {
     b->buffer = true;
     const int fty = fuse2_rows(b->storage, b->ng < 0 ? 5 : b->ng);
     bool can_fuse = fty > 0;
-    double ws = 0.0, side_nodes = 0.0, nodes = 0.0;
+    double ws = 0.0;
     for (size_t k = 0; k < b->slots.size(); ++k) {
         lbm_solver* h = b->slots[k];
         if (!h) continue;
@@ -1043,22 +1042,16 @@ static int batch_build(lbm_batch* b) {
         // neighbour inside the same fused tile
         if (h->C.any_nee && (h->nx % 64 == 1 || h->ny % fty == 1)) can_fuse = false;
         ws += 2.0 * (double)h->buf_bytes;
-        nodes += (double)h->nx * h->ny;
-        side_nodes += (double)h->nx * h->ny * std::min(h->nx, h->ny);
         mem.push_back(M);
         b->member_slot.push_back((int)k);
     }
-    // Fused tiles on a wall pull through the general load in the first
-    // step, so fused pairs pay off only for members large enough to be
-    // mostly interior tiles.  Measured on MI355X with batches of equal
-    // square cavities (6.7e6 nodes in all): FP64 gains 1.06x at side 96 and
-    // 1.3-1.7x from 128 up; FP32 breaks even at 96-128 and gains 1.06-1.5x
-    // from 192 up, losing 14% at 64; FP16 gains nowhere.  The default uses
-    // the node-weighted mean of the members' shorter side.
+    // Fused pairs win for FP64 and FP32 batches at every member size
+    // measured on MI355X (batches of equal square cavities, 6.7e6 nodes in
+    // all, sides 64 to 1024: FP32 1.07x to 1.6x, FP64 1.25x to 1.8x over one
+    // step per launch); FP16's fused kernel is slower than its single step.
     const double mib = 1024.0 * 1024.0;
-    const double side = nodes > 0.0 ? side_nodes / nodes : 0.0;
     const bool want = b->policy == LBM_POLICY_DEFAULT
-                          ? ((b->storage == LBM_F64 && side >= 96.0) || (b->storage == LBM_F32 && side >= 160.0))
+                          ? (b->storage == LBM_F64 || b->storage == LBM_F32)
                           : (b->policy & LBM_POLICY_FUSE2) != 0;
     b->fuse = want && can_fuse && b->buffer && !mem.empty();
     b->keep = ws <= 256.0 * mib;

@@ -219,16 +219,102 @@ struct Fuse2 {
     static_assert(NP * PLANE * (int)sizeof(R) <= 81920, "fused tile needs more than half the LDS of a CU");
 };
 
-// The first fused step on slot e of a tile at (x0, y0) (slots: the tile and
-// its halo, row-major, 66 per row): pull (or extrapolate) the
-// pre-collision populations.  Returns false for a slot outside a
-// non-periodic side.
+// Slots of the first fused step: the tile and its halo, (sx, sy) in
+// [-1, 64] x [-1, TY] relative to the tile origin.  SlotOrder numbers the
+// slots that lie in the lattice (or wrap on a periodic axis) so that the
+// interior nodes, which pull with the fast path, come first and the nodes
+// on the lattice's edge rows and columns, which take the general pull,
+// come last: a wave then runs one of the two paths, not both.  The order
+// is a permutation of the same slots; results do not depend on it.
+struct SlotOrder {
+    int cv0, wv, rv0;             // the rectangle of slots in the lattice
+    int ci0, ci1, ri0, ri1;       // its interior rectangle
+    int n_int, nb, nt, nl;        // interior, bottom, top, left counts
+    int wi, wl, wr;               // interior, left and right strip widths
+    float inv_wi, inv_wv, inv_wl, inv_wr;
+    int count;
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// w / d for 0 <= w < 2^12 and 1 <= d <= 68, with inv = 1 / d: the margin
+// of (w + 1/2) / d from an integer (at least 1 / 136) dwarfs the rounding
+// of the product.
+__device__ __forceinline__ int small_div(int w, float inv) { return (int)(((float)w + 0.5f) * inv); }
+
+template <class F>
+__device__ __forceinline__ SlotOrder slot_order(const Geom& G, int x0, int y0) {
+    SlotOrder o;
+    // slot column l holds x = x0 - 1 + l; rows likewise
+    const int cv0 = G.px ? 0 : clampi(1 - x0, 0, F::EW), cv1 = G.px ? F::EW : clampi(G.nx - x0 + 1, cv0, F::EW);
+    const int rv0 = G.py ? 0 : clampi(1 - y0, 0, F::EH), rv1 = G.py ? F::EH : clampi(G.ny - y0 + 1, rv0, F::EH);
+    o.ci0 = clampi(2 - x0, cv0, cv1);
+    o.ci1 = clampi(G.nx - x0, o.ci0, cv1);
+    o.ri0 = clampi(2 - y0, rv0, rv1);
+    o.ri1 = clampi(G.ny - y0, o.ri0, rv1);
+    o.cv0 = cv0;
+    o.rv0 = rv0;
+    o.wv = cv1 - cv0;
+    o.wi = o.ci1 - o.ci0;
+    o.wl = o.ci0 - cv0;
+    o.wr = cv1 - o.ci1;
+    const int hi = o.ri1 - o.ri0;
+    o.n_int = o.wi * hi;
+    o.nb = (o.ri0 - rv0) * o.wv;
+    o.nt = (rv1 - o.ri1) * o.wv;
+    o.nl = o.wl * hi;
+    o.count = o.wv * (rv1 - rv0);
+    o.inv_wi = 1.0f / (float)(o.wi > 0 ? o.wi : 1);
+    o.inv_wv = 1.0f / (float)(o.wv > 0 ? o.wv : 1);
+    o.inv_wl = 1.0f / (float)(o.wl > 0 ? o.wl : 1);
+    o.inv_wr = 1.0f / (float)(o.wr > 0 ? o.wr : 1);
+    return o;
+}
+
+// Slot coordinates (column l, row m of the slot grid) of work item w < count.
+__device__ __forceinline__ void slot_of(const SlotOrder& o, int w, int& l, int& m) {
+    int q;
+    if (w < o.n_int) {
+        q = small_div(w, o.inv_wi);
+        l = o.ci0 + w - q * o.wi;
+        m = o.ri0 + q;
+        return;
+    }
+    int r = w - o.n_int;
+    if (r < o.nb) {
+        q = small_div(r, o.inv_wv);
+        l = o.cv0 + r - q * o.wv;
+        m = o.rv0 + q;
+        return;
+    }
+    r -= o.nb;
+    if (r < o.nt) {
+        q = small_div(r, o.inv_wv);
+        l = o.cv0 + r - q * o.wv;
+        m = o.ri1 + q;
+        return;
+    }
+    r -= o.nt;
+    if (r < o.nl) {
+        q = small_div(r, o.inv_wl);
+        l = o.cv0 + r - q * o.wl;
+        m = o.ri0 + q;
+        return;
+    }
+    r -= o.nl;
+    q = small_div(r, o.inv_wr);
+    l = o.ci1 + r - q * o.wr;
+    m = o.ri0 + q;
+}
+
+// The first fused step on slot (l, m) of the slot grid of a tile at
+// (x0, y0): pull (or extrapolate) the pre-collision populations.  Returns
+// false for a slot outside a non-periodic side.
 template <class S, int NG>
 __device__ __forceinline__ bool fuse2_load(const S* __restrict__ src, __amdgpu_buffer_rsrc_t rs, const Geom& G,
-                                           const Coeffs& C, int x0, int y0, int e, typename Codec<S>::R f[9],
+                                           const Coeffs& C, int x0, int y0, int l, int m, typename Codec<S>::R f[9],
                                            typename Codec<S>::R g[gdim(NG)]) {
-    using F = Fuse2<S, NG>;
-    int x = x0 - 1 + e % F::EW, y = y0 - 1 + e / F::EW;
+    int x = x0 - 1 + l, y = y0 - 1 + m;
     if (x < 0 || x >= G.nx) {
         if (!G.px) return false;
         x = ((x % G.nx) + G.nx) % G.nx;
@@ -284,11 +370,12 @@ __device__ __forceinline__ void fuse2_walls(typename Codec<S>::R* lds, const Geo
     (fuse2_wall<S, NG, I + 1>(lds, G, C, x, y, idx, f, g), ...);
 }
 
-// Collide the pulled populations of slot e, round them as a store to S
-// would, and keep what the second step pulls.
+// Collide the pulled populations of slot (sl, sm), round them as a store
+// to S would, and keep what the second step pulls.
 template <class S, int NG, int COLL>
 __device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x0, int y0,
-                                           int e, typename Codec<S>::R f[9], typename Codec<S>::R g[gdim(NG)]) {
+                                           int sl, int sm, typename Codec<S>::R f[9],
+                                           typename Codec<S>::R g[gdim(NG)]) {
     using F = Fuse2<S, NG>;
     using R = typename Codec<S>::R;
     const Macro m = macro<R, NG>(f, g, C);
@@ -297,7 +384,7 @@ __device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom
     for (int i = 0; i < 9; ++i) f[i] = as_stored<S>(f[i], C.fscale, C.finv);
 #pragma unroll
     for (int i = 0; i < NG; ++i) g[i] = as_stored<S>(g[i], C.gscale, C.ginv);
-    const int sx = e % F::EW - 1, sy = e / F::EW - 1;
+    const int sx = sl - 1, sy = sm - 1;
     fuse2_put_set<S, NG, 0>(lds, sx, sy, f, std::make_integer_sequence<int, 9>{});
     if constexpr (NG > 0) fuse2_put_set<S, NG, 9>(lds, sx, sy, g, std::make_integer_sequence<int, NG>{});
     const int x = x0 + sx, y = y0 + sy;
@@ -316,13 +403,20 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
     // Step t -> t + 1 on the tile and its halo, two slots per thread at a
     // time so that both slots' loads are in flight together.
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
-    for (int e = threadIdx.x; e < F::SLOTS; e += 512) {
+    const SlotOrder o = slot_order<F>(G, x0, y0);
+    // o.count <= SLOTS: the bound known at compile time fixes the trip count
+#pragma unroll
+    for (int w = threadIdx.x; w < F::SLOTS; w += 512) {
+        if (w >= o.count) break;
         R fa[9], ga[gdim(NG)], fb[9], gb[gdim(NG)];
-        const int e2 = e + 256;
-        const bool va = fuse2_load<S, NG>(src, rs, G, C, x0, y0, e, fa, ga);
-        const bool vb = e2 < F::SLOTS && fuse2_load<S, NG>(src, rs, G, C, x0, y0, e2, fb, gb);
-        if (va) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, e, fa, ga);
-        if (vb) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, e2, fb, gb);
+        int la, ma, lb = 0, mb = 0;
+        slot_of(o, w, la, ma);
+        const bool hb = w + 256 < o.count;
+        if (hb) slot_of(o, w + 256, lb, mb);
+        const bool va = fuse2_load<S, NG>(src, rs, G, C, x0, y0, la, ma, fa, ga);
+        const bool vb = hb && fuse2_load<S, NG>(src, rs, G, C, x0, y0, lb, mb, fb, gb);
+        if (va) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, la, ma, fa, ga);
+        if (vb) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, lb, mb, fb, gb);
     }
     __syncthreads();
 
@@ -361,7 +455,7 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
 }
 
 template <class S, int NG, int MODE, int COLL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5 : 1, 8))) void k_sweep2(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5 : (NG == 9 ? 3 : 1), 8))) void k_sweep2(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
                                                 S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int order) {
     using F = Fuse2<S, NG>;
     __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];
@@ -373,7 +467,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5
 // Fused pairs of steps for every lattice of a batch: each workgroup takes
 // one entry of the fused tile table (a member and its 64 x TY tile).
 template <class S, int NG, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5 : 1, 8))) void k_sweep2_batch(const BatchMember* __restrict__ members,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5 : (NG == 9 ? 3 : 1), 8))) void k_sweep2_batch(const BatchMember* __restrict__ members,
                                                       const BatchTile* __restrict__ tiles, int parity) {
     using F = Fuse2<S, NG>;
     __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];

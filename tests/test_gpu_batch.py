@@ -232,42 +232,37 @@ def test_fused_batch_graphs_odd_launch_count_and_membership():
 
 def test_fused_batch_policy_rules():
     B = lbm.Batch("f64")
-    S = B.new_solver(128, 128)
-    S.set_params(W.cavity(128, 1e4))
+    S = B.new_solver(64, 64)
+    S.set_params(W.cavity(64, 1e4))
     B.add(S)
-    assert B.steps_per_launch == 2            # FP64, members of side >= 96
+    assert B.steps_per_launch == 2            # FP64: fused pairs by default
     B.set_policy(0)
     assert B.steps_per_launch == 1
     B.set_policy(lbm.LBM_POLICY_DEFAULT)
-    S3 = B.new_solver(64, 64)
-    S3.set_params(W.cavity(64, 1e4))
-    slot3 = B.add(S3)
-    for _ in range(5):
-        S4 = B.new_solver(64, 64)
-        S4.set_params(W.cavity(64, 1e4))
-        B.add(S4)
-    assert B.steps_per_launch == 1            # node-weighted mean side 90
-    B.set_policy(FUSE)
     assert B.steps_per_launch == 2
     # a wall rebuilt by extrapolation on a one-column edge tile: single steps
     S2 = B.new_solver(129, 40)
     pb2 = W.with_nee_walls(W.cavity(129, 1e4, ny=40))
     S2.set_params(pb2)
-    B.add(S2)
+    slot2 = B.add(S2)
     assert B.steps_per_launch == 1
     B.step(9)
     fa, ga = _alone(pb2, None, "f64", 9)
     assert np.array_equal(fa, S2.get_populations()[0])
-    assert slot3 == 1
+    B.remove(slot2)
+    assert B.steps_per_launch == 2
     for bad in (1, 4, 8 | 1, -3):
         with pytest.raises(lbm.LbmError):
             B.set_policy(bad)
     B.close()
-    B = lbm.Batch("f32")
-    S = B.new_solver(64, 64)
-    S.set_params(W.cavity(64, 1e4))
-    B.add(S)
-    assert B.steps_per_launch == 1            # small FP32 batch: single steps
-    B.set_policy(FUSE)
-    assert B.steps_per_launch == 2
-    B.close()
+    for storage, spl in (("f32", 2), ("f16", 1)):
+        B = lbm.Batch(storage)
+        S = B.new_solver(64, 64)
+        S.set_params(W.cavity(64, 1e4))
+        B.add(S)
+        assert B.steps_per_launch == spl
+        B.set_policy(FUSE)
+        assert B.steps_per_launch == 2
+        B.set_policy(0)
+        assert B.steps_per_launch == 1
+        B.close()
