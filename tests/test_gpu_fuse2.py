@@ -108,3 +108,45 @@ def test_fused_full_size_cavity2048():
     ref = _run("d2q5", pb, "f64", [4], 0, 0, T, spl=1)
     got = _run("d2q5", pb, "f64", [4], FUSE, 0, T, spl=2)
     assert np.array_equal(got[0][0], ref[0][0]) and np.array_equal(got[0][1], ref[0][1])
+
+
+def _sides(pb, px, py):
+    """The cavity's walls with the x and/or y sides made periodic."""
+    flow = ((W.FLOW_PERIODIC,) * 2 if px else (W.FLOW_WALL,) * 2) + \
+           ((W.FLOW_PERIODIC,) * 2 if py else (W.FLOW_WALL,) * 2)
+    temp = ((W.TEMP_PERIODIC,) * 2 if px else (W.TEMP_DIRICHLET,) * 2) + \
+           ((W.TEMP_PERIODIC,) * 2 if py else (W.TEMP_ADIABATIC,) * 2)
+    return pb.replace(bc_flow=flow, bc_temp=temp)
+
+
+# lattices narrower or shorter than a tile, one node wide, and sizes one
+# past a tile edge: the first fused step's slot order must still visit each
+# node of the tile and halo once
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 6), (7, 1), (2, 2), (3, 7), (65, 3), (64, 4), (66, 5), (129, 9)])
+def test_fused_degenerate_sizes(storage, nx, ny):
+    T = W.random_temperature(nx, ny, 0.0, 1.0, seed=nx * 100 + ny)
+    for px in (False, True):
+        for py in (False, True):
+            pb = _sides(W.cavity(max(nx, ny), 1e4).replace(nx=nx, ny=ny), px, py)
+            (fa, ga), _ = _run("d2q5", pb, storage, [1, 2, 3], 0, 0, T, spl=1)
+            (fb, gb), _ = _run("d2q5", pb, storage, [1, 2, 3], FUSE, 0, T, spl=2)
+            assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (px, py)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 6), (7, 1), (2, 2), (3, 7), (65, 3)])
+def test_degenerate_sizes_match_oracle(nx, ny):
+    # a node that is a wall on both sides of an axis, in both step kernels
+    T = W.random_temperature(nx, ny, 0.0, 1.0, seed=nx * 10 + ny)
+    for px in (False, True):
+        for py in (False, True):
+            pb = _sides(W.cavity(max(nx, ny), 1e4).replace(nx=nx, ny=ny, wall_u=((0.0, 0.01), (0.0, -0.02),
+                                                                                   (0.03, 0.0), (0.05, 0.0))),
+                        px, py)
+            for pol in (0, FUSE):
+                S, L = run_pair(pb, 9, T_init=T, launch=(0, 0, 0, pol))
+                fa, ga = S.get_populations()
+                fb, gb = L.get_state()
+                ef, eg = max_rel_pop_error(pb, fa, ga, fb, gb)
+                assert ef < 1e-12 and eg < 1e-12, (px, py, pol, ef, eg)
+                S.close()
