@@ -14,8 +14,8 @@ stream, the same figures for FP32 and FP16 deviation storage and for the
 other temperature models in FP64 (the D2Q9 thermal model on the same
 cavity; the flow alone on a lid-driven cavity of the same size, Re = 1000),
 the step time of the comparison collision operators of Sec. 3.2 (BGK,
-orthogonal MRT) relative to the paper's, and the CPU oracle timed on a
-bounded sample of the same workload.
+orthogonal MRT) relative to the paper's, fused and one step per launch,
+and the CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--storage f64] [--variants f32,f16]
                     [--models d2q9t,isothermal] [--collisions bgk,ortho_mrt]
@@ -200,15 +200,19 @@ def main():
                 mpb = pb if m != "isothermal" else W.lid_cavity(args.n, lbm.viscous_rate(1000.0, args.n, 0.1), 0.1)
                 models[m] = time_storage(args.storage, mpb, args.steps, args.warmup, launch, model=m)
                 models[m]["workload"] = mpb.name
-    colls = {}
+    colls, colls1 = {}, {}
     if args.collisions != "none":
-        # the comparison operators run one step per launch: compare them with
-        # the paper's operator run the same way
-        colls["mrt"] = time_storage(args.storage, pb, args.steps, args.warmup, launch, single_steps=True)
+        # every operator in the default launch (fused pairs: the step is bound
+        # by latency and arithmetic, so operator costs can show) and one step
+        # per launch (bound by bandwidth)
+        colls["mrt"] = main_res
+        colls1["mrt"] = time_storage(args.storage, pb, args.steps, args.warmup, launch, single_steps=True)
         codes = {"bgk": W.COLL_BGK, "ortho_mrt": W.COLL_ORTHO}
         for c in args.collisions.split(","):
             if c in codes:
-                colls[c] = time_storage(args.storage, pb.replace(collision=codes[c]), args.steps, args.warmup, launch)
+                cpb = pb.replace(collision=codes[c])
+                colls[c] = time_storage(args.storage, cpb, args.steps, args.warmup, launch)
+                colls1[c] = time_storage(args.storage, cpb, args.steps, args.warmup, launch, single_steps=True)
     if args.calibrate_copy:
         # reference for counter runs: one dispatch reading and writing 1 GiB
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -248,9 +252,12 @@ def main():
                                "launch": v["launch"]}
                            for k, v in models.items()},
         "collision_variants": {k: {"storage": args.storage, "mlups": round(v["mlups"], 1),
+                                   "steps_per_launch": v["launch"]["steps_per_launch"],
                                    "sweep_us_per_step": round(v["sweep_us_per_step"], 3),
-                                   "ratio_to_mrt_single_step": round(v["sweep_us_per_step"] /
-                                                                     colls["mrt"]["sweep_us_per_step"], 4)}
+                                   "ratio_to_mrt": round(v["sweep_us_per_step"] / colls["mrt"]["sweep_us_per_step"], 4),
+                                   "single_step_us": round(colls1[k]["sweep_us_per_step"], 3),
+                                   "single_step_ratio_to_mrt": round(colls1[k]["sweep_us_per_step"] /
+                                                                     colls1["mrt"]["sweep_us_per_step"], 4)}
                                for k, v in colls.items()},
         "source_hash": kernel_source_hash(),
     }

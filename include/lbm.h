@@ -287,9 +287,11 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           from HBM into LDS, then steps the tile again from
  *                           LDS and stores it, so the state crosses HBM once
  *                           per two steps.  Bitwise the same results.  Used
- *                           with the MRT collision on buffers below 4 GiB and,
- *                           with NEE walls, when no edge tile is one node
- *                           wide or high; otherwise steps run singly.
+ *                           with every collision operator on buffers below
+ *                           4 GiB and, with NEE walls, when no edge tile is
+ *                           one node wide or high (tiles are 64 nodes wide
+ *                           and 4, or 8 for FP32 storage without
+ *                           temperature, high); otherwise steps run singly.
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; fused pairs with bands for FP64
  * and FP32 storage; for FP16, single steps with bands while F <= 500 MiB. */

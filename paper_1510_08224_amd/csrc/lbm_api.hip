@@ -545,11 +545,11 @@ int lbm_init_temperature(lbm_solver* h, const double* T) {
 // Capture graph_steps sweeps starting from buffer `start` on the solver's
 // stream.
 // Whether lbm_step may fuse pairs of time steps into one launch: asked for
-// by the policy, the paper's collision, buffers below 4 GiB, and, with NEE
-// walls, no last tile one node wide or high (its wall rebuild would need
-// rows beyond the fused tile's halo).
+// by the policy, buffers below 4 GiB, and, with NEE walls, no last tile one
+// node wide or high (its wall rebuild would need rows beyond the fused
+// tile's halo).
 static bool fuse2_active(const lbm_solver* h) {
-    if (!h->L.fuse2 || !h->L.buffer || h->C.collision != LBM_COLLISION_MRT) return false;
+    if (!h->L.fuse2 || !h->L.buffer) return false;
     if (h->buf_bytes >= (1ull << 32)) return false;
     if (h->C.any_nee) {
         const int ty = fuse2_rows(h->storage, h->ng);

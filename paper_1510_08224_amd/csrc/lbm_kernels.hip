@@ -883,23 +883,33 @@ int fuse2_rows(int storage, int ng) {
     return 0;
 }
 
+template <class S, int NG, int MODE>
+static void sweep2_launch(int coll, dim3 grid, hipStream_t st, const Geom& G, const Coeffs* C, const S* s, S* d,
+                          int tiles_x, unsigned bytes, int order) {
+    if (coll == kCollBGK)
+        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollBGK>), grid, dim3(256), 0, st, G, C, s, d, tiles_x, bytes, order);
+    else if (coll == kCollOrtho)
+        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollOrtho>), grid, dim3(256), 0, st, G, C, s, d, tiles_x, bytes,
+                           order);
+    else
+        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollMRT>), grid, dim3(256), 0, st, G, C, s, d, tiles_x, bytes, order);
+}
+
 template <class S, int NG>
 static hipError_t sweep2_t(const Launch& L, const Geom& G, const Coeffs& Ch, const Coeffs* C, const void* src,
                            void* dst, hipStream_t st) {
     using F = Fuse2<S, NG>;
     const unsigned long long bytes = (unsigned long long)(9 + NG) * (unsigned long long)G.plane * sizeof(S);
-    if (!L.buffer || bytes >= (1ull << 32) || Ch.collision != kCollMRT) return hipErrorInvalidValue;
+    const int coll = Ch.collision;
+    if (!L.buffer || bytes >= (1ull << 32) || coll < kCollMRT || coll > kCollOrtho) return hipErrorInvalidValue;
     const int tiles_x = (G.nx + F::TX - 1) / F::TX;
     const int tiles_y = (G.ny + F::TY - 1) / F::TY;
     const int order = (L.order == kXcdStrips && tiles_x % 8 != 0) ? kXcdBands : L.order;
     const S* s = static_cast<const S*>(src);
     S* d = static_cast<S*>(dst);
-    if (L.keep)
-        hipLaunchKernelGGL((k_sweep2<S, NG, kBufferKeep, kCollMRT>), dim3(tiles_x * tiles_y), dim3(256), 0, st, G, C, s,
-                           d, tiles_x, (unsigned)bytes, order);
-    else
-        hipLaunchKernelGGL((k_sweep2<S, NG, kBufferNT, kCollMRT>), dim3(tiles_x * tiles_y), dim3(256), 0, st, G, C, s,
-                           d, tiles_x, (unsigned)bytes, order);
+    const dim3 grid(tiles_x * tiles_y);
+    if (L.keep) sweep2_launch<S, NG, kBufferKeep>(coll, grid, st, G, C, s, d, tiles_x, (unsigned)bytes, order);
+    else sweep2_launch<S, NG, kBufferNT>(coll, grid, st, G, C, s, d, tiles_x, (unsigned)bytes, order);
     return hipGetLastError();
 }
 

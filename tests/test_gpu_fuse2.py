@@ -3,7 +3,8 @@ tile and its halo from HBM into LDS and the tile again from LDS, and must
 give bitwise the populations of two single steps, for every storage,
 temperature model and wall family, on ragged and periodic lattices, with
 and without graph replay, including the cases where lbm_step falls back to
-single steps (NEE walls with a one-row edge tile, comparison collisions)."""
+single steps (NEE walls with a one-node edge tile).  The comparison
+collision operators (BGK, orthogonal MRT) fuse too."""
 import numpy as np
 import pytest
 
@@ -38,14 +39,17 @@ CASES = {
     "d2q9t_nee_cavity70x42": ("d2q9t", lambda: W.with_nee_walls(W.cavity(70, 1e5, ny=42)), 8),
     "iso_lid130x61": ("isothermal", lambda: _lid(130).replace(ny=61), 8),
     "iso_nee_lid66x35": ("isothermal", lambda: W.with_nee_walls(_lid(66).replace(ny=35)), 8),
-    "bgk_falls_back": ("d2q5", lambda: W.cavity(90, 1e5, ny=30).replace(collision=W.COLL_BGK), 8),
+    "bgk_cavity90x30": ("d2q5", lambda: W.cavity(90, 1e5, ny=30).replace(collision=W.COLL_BGK), 8),
+    "ortho_nee_cavity130x70": ("d2q5", lambda: W.with_nee_walls(W.cavity(130, 1e5, ny=70)).replace(
+        collision=W.COLL_ORTHO), 8),
+    "bgk_iso_lid130x61": ("isothermal", lambda: _lid(130).replace(ny=61, collision=W.COLL_BGK), 8),
+    "ortho_d2q9t_rb130x42": ("d2q9t", lambda: W.rayleigh_benard(130, 42, 2e4).replace(collision=W.COLL_ORTHO), 8),
 }
 
 
 # cases where lbm_step must fall back to single steps: walls rebuilt by
-# extrapolation with a one-node edge tile (64-wide tiles; 4, 8 or 16 rows),
-# and the comparison collisions
-FALLBACK = {"nee_last_column_one_wide", "nee_top_row_one_high", "bgk_falls_back"}
+# extrapolation with a one-node edge tile (64-wide tiles, 4 or 8 rows)
+FALLBACK = {"nee_last_column_one_wide", "nee_top_row_one_high"}
 
 
 def _run(model, pb, storage, steps, policy, graph, T=None, spl=None):
