@@ -18,7 +18,12 @@ orthogonal MRT) relative to the paper's, fused and one step per launch,
 and the CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--storage f64] [--variants f32,f16]
-                    [--models d2q9t,isothermal] [--collisions bgk,ortho_mrt]
+                    [--models d2q9t,isothermal] [--collisions bgk,ortho_mrt] [--slabs 2,4,8]
+
+`slab_variants` times one GPU's share of the same lattice cut into 2, 4 or 8
+y-slabs (2048 x 1024 / 512 / 256), with periodic rows standing in for the
+halo rows a neighbour would send: the kernel at the shape each GPU of a
+sharded run would sweep.  No figure at several GPUs is measured.
 """
 from __future__ import annotations
 
@@ -164,6 +169,8 @@ def main():
                     help="other temperature models to time in the main storage ('none' for none)")
     ap.add_argument("--collisions", default="bgk,ortho_mrt",
                     help="comparison collision operators to time in the main storage ('none' for none)")
+    ap.add_argument("--slabs", default="2,4,8",
+                    help="GPU counts whose y-slab share of the lattice to time on this GPU ('none' for none)")
     ap.add_argument("--cpu-steps", type=int, default=48, help="oracle steps of the CPU baseline (~20 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=2048, help="cavity side")
@@ -213,6 +220,17 @@ def main():
                 cpb = pb.replace(collision=codes[c])
                 colls[c] = time_storage(args.storage, cpb, args.steps, args.warmup, launch)
                 colls1[c] = time_storage(args.storage, cpb, args.steps, args.warmup, launch, single_steps=True)
+    slabs = {}
+    if args.slabs != "none":
+        # one GPU's share of the lattice cut into k y-slabs: the same rates
+        # (length of the whole cavity), walls left and right, and periodic
+        # rows standing in for the halo rows a neighbour would send
+        for k in (int(v) for v in args.slabs.split(",")):
+            spb = pb.replace(ny=args.n // k, length=float(args.n), name=f"slab{args.n}x{args.n // k}",
+                             bc_flow=(W.FLOW_WALL, W.FLOW_WALL, W.FLOW_PERIODIC, W.FLOW_PERIODIC),
+                             bc_temp=(W.TEMP_DIRICHLET, W.TEMP_DIRICHLET, W.TEMP_PERIODIC, W.TEMP_PERIODIC))
+            slabs[k] = time_storage(args.storage, spb, args.steps, args.warmup, launch)
+            slabs[k]["shape"] = f"{args.n}x{args.n // k}"
     if args.calibrate_copy:
         # reference for counter runs: one dispatch reading and writing 1 GiB
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -259,6 +277,11 @@ def main():
                                    "single_step_ratio_to_mrt": round(colls1[k]["sweep_us_per_step"] /
                                                                      colls1["mrt"]["sweep_us_per_step"], 4)}
                                for k, v in colls.items()},
+        "slab_variants": {f"{k}_gpus": {"shape": v["shape"], "storage": args.storage,
+                                        "sweep_mlups": round(v["sweep_mlups"], 1),
+                                        "sweep_us_per_step": round(v["sweep_us_per_step"], 3),
+                                        "roofline": v["roofline"]}
+                          for k, v in slabs.items()},
         "source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)
