@@ -1,0 +1,55 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU refusal, the bytes per
+node behind the roofline, and the lookup of counter-measured traffic."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_is_refused(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
+
+
+def test_values_per_node():
+    # 9 + NG populations read and written per node and step
+    assert bench.values_per_node("d2q5") == 28
+    assert bench.values_per_node("d2q9t") == 36
+    assert bench.values_per_node("isothermal") == 18
+    assert bench.BYTES == {"f64": 8, "f32": 4, "f16": 2}
+
+
+def _write(tmp_path, rec):
+    d = tmp_path / "profiles"
+    d.mkdir()
+    (d / "sweep_traffic.json").write_text(json.dumps(rec))
+
+
+def test_traffic_lookup_checks_sources_size_and_steps(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("f64", 100, 2) is None          # no file
+    h = "0123456789abcdef"
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    ent = {"nodes": 100, "steps_per_launch": 2, "bytes_per_launch": 12345.0}
+    _write(tmp_path, {"source_hash": h, "kernels": {"f64/2": ent}})
+    assert bench.measured_traffic("f64", 100, 2) == 12345.0
+    assert bench.measured_traffic("f64", 101, 2) is None          # other lattice
+    assert bench.measured_traffic("f64", 100, 1) is None          # other kernel
+    assert bench.measured_traffic("f32", 100, 2) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "fedcba9876543210")
+    assert bench.measured_traffic("f64", 100, 2) is None          # counters taken on other sources
+
+
+def test_source_hash_covers_the_library_sources():
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
+    assert h == bench.kernel_source_hash()
