@@ -185,12 +185,14 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 //
 // TY is a multiple of 4 (the 256 threads take whole rows in the second
 // step), the largest whose LDS fits kFuse2Lds bytes, at least 4.  The
-// kernel is bound by latency, not arithmetic or bandwidth, so short tiles
-// win: with one pass per phase the compiler keeps the step constants in
-// scalar registers, and more workgroups fit a CU.  Measured on MI355X
-// (2048^2, algorithmic GB/s): FP32 D2Q5 8.4 TB/s at TY = 4 against 7.4 at
-// 8 and 6.5 at 16; FP64 D2Q5 9.5 at 4 against 8.6 at 8.  The isothermal
-// kernels also ask for five waves per SIMD (FP32: 7.7 against 6.9 TB/s).
+// kernel is bound by latency more than by arithmetic or bandwidth, so
+// short tiles win: with one pass per phase the compiler keeps the step
+// constants in scalar registers, and more workgroups fit a CU.  Measured
+// on MI355X (2048^2, algorithmic GB/s): FP32 D2Q5 8.4 TB/s at TY = 4
+// against 7.4 at 8 and 6.5 at 16; FP64 D2Q5 9.5 at 4 against 8.6 at 8.
+// The kernels without temperature ask for five waves per SIMD (FP32: 7.7
+// against 6.9 TB/s), the D2Q9 thermal ones for three (their register count
+// sits just above that limit; FP64 spills 12 bytes per lane for it).
 // ---------------------------------------------------------------------------
 #ifndef LBM_FUSE2_LDS
 #define LBM_FUSE2_LDS 20480
@@ -424,7 +426,8 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
     // rebuilt by extrapolation read elsewhere: their fluid neighbour's
     // pulls, which lie in the tile (the launch rules out one-node edge
     // tiles on such sides).
-    const bool nee = C.any_nee && !((G.px || (x0 > 0 && x0 + F::TX < G.nx)) && (G.py || (y0 > 0 && y0 + F::TY < G.ny)));
+    const bool inner = (G.px || (x0 > 0 && x0 + F::TX < G.nx)) && (G.py || (y0 > 0 && y0 + F::TY < G.ny));
+    const bool nee = C.any_nee && !inner;
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, buf_bytes);
     for (int n = threadIdx.x; n < F::TX * F::TY; n += 256) {
         const int ix = n % F::TX, iy = n / F::TX;
@@ -454,9 +457,13 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
     }
 }
 
+// Waves per SIMD the fused kernels ask the compiler for (1: no request).
+constexpr int fuse2_waves(int NG) { return NG == 0 ? 5 : (NG == 9 ? 3 : 1); }
+
 template <class S, int NG, int MODE, int COLL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5 : (NG == 9 ? 3 : 1), 8))) void k_sweep2(Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src,
-                                                S* __restrict__ dst, int tiles_x, unsigned buf_bytes, int order) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fuse2_waves(NG), 8))) void k_sweep2(
+    Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src, S* __restrict__ dst, int tiles_x,
+    unsigned buf_bytes, int order) {
     using F = Fuse2<S, NG>;
     __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];
     const int tile = xcd_remap(blockIdx.x, gridDim.x, order, tiles_x);
@@ -467,8 +474,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5
 // Fused pairs of steps for every lattice of a batch: each workgroup takes
 // one entry of the fused tile table (a member and its 64 x TY tile).
 template <class S, int NG, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NG == 0 ? 5 : (NG == 9 ? 3 : 1), 8))) void k_sweep2_batch(const BatchMember* __restrict__ members,
-                                                      const BatchTile* __restrict__ tiles, int parity) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fuse2_waves(NG), 8))) void k_sweep2_batch(
+    const BatchMember* __restrict__ members, const BatchTile* __restrict__ tiles, int parity) {
     using F = Fuse2<S, NG>;
     __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, kXcdBands, 0)];
