@@ -290,8 +290,9 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           with every collision operator on buffers below
  *                           4 GiB and, with NEE walls, when no edge tile is
  *                           one node wide or high (tiles are 64 nodes wide
- *                           and 4, or 8 for FP32 storage without
- *                           temperature, high); otherwise steps run singly.
+ *                           and 8 high for FP64 D2Q5 and without
+ *                           temperature, 4 high otherwise); otherwise steps
+ *                           run singly (lbm_steps_per_launch tells which).
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; fused pairs with bands for FP64
  * and FP32 storage; for FP16, single steps with bands while F <= 500 MiB. */

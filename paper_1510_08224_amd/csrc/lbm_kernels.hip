@@ -183,13 +183,17 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 // plus gconst, the y side first at a corner), so the second step reads
 // every node's populations with plain LDS loads.
 //
-// TY is a multiple of 4 (the 256 threads take whole rows in the second
-// step), the largest whose LDS fits kFuse2Lds bytes, at least 4.  The
-// kernel is bound by latency more than by arithmetic or bandwidth, so
-// short tiles win: with one pass per phase the compiler keeps the step
-// constants in scalar registers, and more workgroups fit a CU.  Measured
-// on MI355X (2048^2, algorithmic GB/s): FP32 D2Q5 8.4 TB/s at TY = 4
-// against 7.4 at 8 and 6.5 at 16; FP64 D2Q5 9.5 at 4 against 8.6 at 8.
+// A workgroup has one thread per tile node (64 TY threads), so each phase
+// is one pass and the compiler keeps the step constants in scalar
+// registers (a loop over rows made it hold them in vector registers, at
+// the cost of occupancy).  The kernel is bound by latency more than by
+// arithmetic or bandwidth; TY trades halo work against workgroups per CU.
+// Measured on MI355X (algorithmic GB/s): FP64 D2Q5 and FP64 without
+// temperature take TY = 8 (two 512-thread workgroups per CU; D2Q5 2048^2
+// 9.8 TB/s against 9.6 at TY = 4, 4096^2 10.4 against 9.8); FP64 D2Q9
+// thermal and the FP32/FP16 D2Q5 and D2Q9 kernels take TY = 4 (8 rows cost
+// them 8-15%); FP32/FP16 without temperature take 8.  Otherwise TY is a
+// multiple of 4, the largest whose LDS fits kFuse2Lds bytes, from 4 to 16.
 // The kernels without temperature ask for five waves per SIMD (FP32: 7.7
 // against 6.9 TB/s), the D2Q9 thermal ones for three (their register count
 // sits just above that limit; FP64 spills 12 bytes per lane for it).
@@ -213,8 +217,16 @@ struct Fuse2 {
     static constexpr int TX = 64;
     static constexpr int EW = TX + 2;
     static constexpr int ROW_BYTES = TX * NP * (int)sizeof(R);
+#ifdef LBM_FUSE2_ROWS
+    static constexpr int TY = LBM_FUSE2_ROWS;
+#else
     static constexpr int TY_FIT = kFuse2Lds / ROW_BYTES;
-    static constexpr int TY = TY_FIT >= 32 ? 32 : (TY_FIT < 4 ? 4 : TY_FIT / 4 * 4);
+    static constexpr int TY = (std::is_same<S, double>::value && NG != 9)
+                                  ? 8
+                                  : (TY_FIT >= 16 ? 16 : (TY_FIT < 4 ? 4 : TY_FIT / 4 * 4));
+#endif
+    static constexpr int NT = TX * TY;      // threads: one per tile node
+    static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
     static constexpr int EH = TY + 2;
     static constexpr int SLOTS = EW * EH;   // nodes of the first step
     static constexpr int PLANE = TX * TY;   // LDS values per population
@@ -408,13 +420,13 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
     const SlotOrder o = slot_order<F>(G, x0, y0);
     // o.count <= SLOTS: the bound known at compile time fixes the trip count
 #pragma unroll
-    for (int w = threadIdx.x; w < F::SLOTS; w += 512) {
+    for (int w = threadIdx.x; w < F::SLOTS; w += 2 * F::NT) {
         if (w >= o.count) break;
         R fa[9], ga[gdim(NG)], fb[9], gb[gdim(NG)];
         int la, ma, lb = 0, mb = 0;
         slot_of(o, w, la, ma);
-        const bool hb = w + 256 < o.count;
-        if (hb) slot_of(o, w + 256, lb, mb);
+        const bool hb = w + F::NT < o.count;
+        if (hb) slot_of(o, w + F::NT, lb, mb);
         const bool va = fuse2_load<S, NG>(src, rs, G, C, x0, y0, la, ma, fa, ga);
         const bool vb = hb && fuse2_load<S, NG>(src, rs, G, C, x0, y0, lb, mb, fb, gb);
         if (va) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, la, ma, fa, ga);
@@ -429,7 +441,7 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
     const bool inner = (G.px || (x0 > 0 && x0 + F::TX < G.nx)) && (G.py || (y0 > 0 && y0 + F::TY < G.ny));
     const bool nee = C.any_nee && !inner;
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, buf_bytes);
-    for (int n = threadIdx.x; n < F::TX * F::TY; n += 256) {
+    for (int n = threadIdx.x; n < F::TX * F::TY; n += F::NT) {
         const int ix = n % F::TX, iy = n / F::TX;
         const int x = x0 + ix, y = y0 + iy;
         if (x >= G.nx || y >= G.ny) continue;
@@ -461,7 +473,7 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
 constexpr int fuse2_waves(int NG) { return NG == 0 ? 5 : (NG == 9 ? 3 : 1); }
 
 template <class S, int NG, int MODE, int COLL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fuse2_waves(NG), 8))) void k_sweep2(
+__global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per_eu(fuse2_waves(NG), 8))) void k_sweep2(
     Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src, S* __restrict__ dst, int tiles_x,
     unsigned buf_bytes, int order) {
     using F = Fuse2<S, NG>;
@@ -474,7 +486,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fuse2_waves
 // Fused pairs of steps for every lattice of a batch: each workgroup takes
 // one entry of the fused tile table (a member and its 64 x TY tile).
 template <class S, int NG, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fuse2_waves(NG), 8))) void k_sweep2_batch(
+__global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per_eu(fuse2_waves(NG), 8)))
+void k_sweep2_batch(
     const BatchMember* __restrict__ members, const BatchTile* __restrict__ tiles, int parity) {
     using F = Fuse2<S, NG>;
     __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];
@@ -893,13 +906,14 @@ int fuse2_rows(int storage, int ng) {
 template <class S, int NG, int MODE>
 static void sweep2_launch(int coll, dim3 grid, hipStream_t st, const Geom& G, const Coeffs* C, const S* s, S* d,
                           int tiles_x, unsigned bytes, int order) {
+    const dim3 block(Fuse2<S, NG>::NT);
     if (coll == kCollBGK)
-        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollBGK>), grid, dim3(256), 0, st, G, C, s, d, tiles_x, bytes, order);
+        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollBGK>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, order);
     else if (coll == kCollOrtho)
-        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollOrtho>), grid, dim3(256), 0, st, G, C, s, d, tiles_x, bytes,
+        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollOrtho>), grid, block, 0, st, G, C, s, d, tiles_x, bytes,
                            order);
     else
-        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollMRT>), grid, dim3(256), 0, st, G, C, s, d, tiles_x, bytes, order);
+        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollMRT>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, order);
 }
 
 template <class S, int NG>
@@ -949,11 +963,11 @@ hipError_t launch_sweep2_batch(int storage, int ng, bool keep, const BatchMember
     if (ntiles <= 0) return hipSuccess;
     LBM_DISPATCH(storage, ng, {
         if (keep)
-            hipLaunchKernelGGL((k_sweep2_batch<S, NG, kBufferKeep>), dim3(ntiles), dim3(256), 0, st, members, tiles,
-                               parity);
+            hipLaunchKernelGGL((k_sweep2_batch<S, NG, kBufferKeep>), dim3(ntiles), dim3(Fuse2<S, NG>::NT), 0, st,
+                               members, tiles, parity);
         else
-            hipLaunchKernelGGL((k_sweep2_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(256), 0, st, members, tiles,
-                               parity);
+            hipLaunchKernelGGL((k_sweep2_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(Fuse2<S, NG>::NT), 0, st,
+                               members, tiles, parity);
     });
     return hipGetLastError();
 }
