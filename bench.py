@@ -141,7 +141,9 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
-                     "steps_per_launch": spl},
+                     "steps_per_launch": spl,
+                     # HBM bytes the counters measured per launch, over the same launch time
+                     "traffic_GBs": None if traffic is None else round(traffic / avg_launch_s / 1e9, 1)},
     }
 
 

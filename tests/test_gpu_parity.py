@@ -340,3 +340,29 @@ def test_graph_replays_match_eager_launches():
     with pytest.raises(lbm.LbmError):
         graph.set_graph_steps(7)
     eager.close(); graph.close()
+
+
+def test_buffers_above_4gib_match_the_buffer_path():
+    """A population buffer of 4 GiB or more is addressed with 64-bit
+    pointers and steps singly; a buffer below 4 GiB uses buffer descriptors
+    and, for FP64, fused pairs.  An x-periodic Rayleigh-Benard cell 6208
+    wide (4.3 GB per buffer) whose initial temperature repeats every 64
+    columns must equal, column for column and bitwise, the 64-wide cell."""
+    ny, nx_big, reps = 6208, 6208, 97
+    assert lbm.lbm_required_bytes(nx_big, ny, lbm.LBM_F64, lbm.LBM_MODEL_D2Q5) // 2 >= 1 << 32
+    rng = np.random.default_rng(1510)
+    T = 0.5 + 0.1 * rng.uniform(-1, 1, (ny, 64))
+    out = []
+    for nx in (64, nx_big):
+        pb = W.rayleigh_benard(nx, ny, 1e5)
+        S = lbm.Solver(nx, ny, "f64")
+        S.set_params(pb)
+        S.init_temperature(np.tile(T, (1, nx // 64)))
+        assert S.steps_per_launch == (2 if nx == 64 else 1)
+        S.step(5)
+        out.append(S.get_populations())
+        S.close()
+    (fs, gs), (fb, gb) = out
+    for k in range(reps):
+        sl = slice(64 * k, 64 * (k + 1))
+        assert np.array_equal(fb[:, :, sl], fs) and np.array_equal(gb[:, :, sl], gs), k
