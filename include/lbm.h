@@ -294,8 +294,10 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           temperature, 4 high otherwise); otherwise steps
  *                           run singly (lbm_steps_per_launch tells which).
  * The default follows the storage and the footprint F of both population
- * buffers: kept stores while F <= 256 MiB; fused pairs with bands for FP64
- * and FP32 storage; for FP16, single steps with bands while F <= 500 MiB. */
+ * buffers: kept stores while F <= 256 MiB; fused pairs for FP64 and FP32
+ * storage, with bands, or strips once one row of fused tiles (tiles and
+ * halos, every plane) exceeds 3 MiB; for FP16, single steps with bands
+ * while F <= 500 MiB. */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */

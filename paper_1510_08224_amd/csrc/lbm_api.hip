@@ -185,7 +185,17 @@ static void default_policy(lbm_solver* h) {
     h->L.keep = ws <= 256.0 * mib;
     h->L.order = (ws <= 500.0 * mib || (h->storage == LBM_F64 && ws <= 1024.0 * mib)) ? 1 : 0;
     h->L.fuse2 = h->storage == LBM_F64 || h->storage == LBM_F32;
-    if (h->L.fuse2) h->L.order = 1;
+    if (h->L.fuse2) {
+        // Bands keep the halo rows a fused tile shares with the tile row
+        // below in the XCD's 4 MB L2 while one row of tiles (tile and halo,
+        // every plane) fits there; past that, strips of 8 tiles per XCD do
+        // (4096^2 FP64 D2Q5, 4.7 MB per tile row: +4%; FP64 D2Q9 thermal,
+        // 3.7 MB: +2%; rows of 1.5-3 MB: bands by up to 18%).
+        const int ty = fuse2_rows(h->storage, h->ng);
+        const int tiles_x = (h->nx + 63) / 64;
+        const double row = (double)tiles_x * 66.0 * (ty + 2) * (9 + h->ng) * storage_bytes(h->storage);
+        h->L.order = (tiles_x % 8 == 0 && row > 3.0 * mib) ? 2 : 1;
+    }
 }
 
 static void default_launch(lbm_solver* h) {

@@ -159,7 +159,7 @@ def test_xcd_strips_order_does_not_change_results(launch):
 
 
 @pytest.mark.parametrize("n,storage,policy", [(64, "f64", 11), (2048, "f64", 9), (2048, "f32", 9), (1024, "f32", 11),
-                                              (2048, "f16", 3), (3072, "f16", 0), (4096, "f16", 0), (4096, "f64", 9)])
+                                              (2048, "f16", 3), (3072, "f16", 0), (4096, "f16", 0), (4096, "f64", 12)])
 def test_default_policy_follows_footprint(n, storage, policy):
     S = lbm.Solver(n, n, storage)
     assert S.get_launch()[3] == policy
