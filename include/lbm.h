@@ -398,7 +398,14 @@ void lbm_batch_destroy(lbm_batch* b);
  * create when h is NULL).  Library-owned; valid until the next call. */
 const char* lbm_last_error(const lbm_solver* h);
 
-/* Free the solver and everything it allocated.  NULL-safe. */
+/* Free the solver and everything it allocated.  NULL-safe.
+ * Tracing: if the environment variable LBM_PROFILE is set (and not "0")
+ * when the solver is created, lbm_step brackets each call with HIP events
+ * on the solver's stream (not while the stream is being captured), and
+ * lbm_destroy writes one line to stderr:
+ *   {"lbm_profile": {"nx": .., "ny": .., "storage": "f64", "model": ..,
+ *    "calls": .., "steps": .., "launches": .., "gpu_ms": .., "mlups": ..}}
+ * gpu_ms is the summed GPU time between the events of each call. */
 void lbm_destroy(lbm_solver* h);
 
 #ifdef __cplusplus

@@ -6,6 +6,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -47,6 +48,14 @@ struct lbm_solver {
     int64_t graph_launches = 0;  // launches in one captured graph (fused pairs count once)
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     lbm_batch* batch = nullptr;  // batch this solver belongs to, if any
+    // Tracing (environment variable LBM_PROFILE set and not "0" at create):
+    // HIP events bracket each lbm_step call on the solver's stream; pairs
+    // are folded into the totals once complete, and lbm_destroy prints a
+    // one-line JSON summary to stderr.
+    bool prof = false;
+    std::vector<hipEvent_t> prof_ev;   // pending start, stop, start, stop, ...
+    double prof_ms = 0.0;
+    int64_t prof_calls = 0, prof_steps = 0, prof_launches = 0;
     std::string err;
 };
 
@@ -288,6 +297,8 @@ static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t stora
         return fail(nullptr, LBM_ERR_NOMEM, "lbm_create: small buffers");
     }
     default_launch(h);
+    const char* pe = getenv("LBM_PROFILE");
+    h->prof = pe && *pe && strcmp(pe, "0") != 0;
     *out = h;
     return LBM_OK;
 }
@@ -304,6 +315,33 @@ int lbm_create_ext(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, in
 
 int32_t lbm_model_of(const lbm_solver* h) { return h ? h->model : -1; }
 
+// Fold completed event pairs into the totals (all of them: wait for each).
+static void prof_drain(lbm_solver* h, bool all) {
+    size_t k = 0;
+    for (; k + 1 < h->prof_ev.size(); k += 2) {
+        hipEvent_t a = h->prof_ev[k], b = h->prof_ev[k + 1];
+        if (all) (void)hipEventSynchronize(b);
+        else if (hipEventQuery(b) != hipSuccess) break;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, a, b) == hipSuccess) h->prof_ms += ms;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    h->prof_ev.erase(h->prof_ev.begin(), h->prof_ev.begin() + (long)k);
+}
+
+static void prof_report(lbm_solver* h) {
+    prof_drain(h, true);
+    if (!h->prof_calls) return;
+    static const char* names[] = {"f64", "f32", "f16"};
+    const double mlups = h->prof_ms > 0.0 ? (double)h->nx * h->ny * h->prof_steps / (h->prof_ms * 1e3) : 0.0;
+    fprintf(stderr,
+            "{\"lbm_profile\": {\"nx\": %d, \"ny\": %d, \"storage\": \"%s\", \"model\": %d, \"calls\": %lld, "
+            "\"steps\": %lld, \"launches\": %lld, \"gpu_ms\": %.3f, \"mlups\": %.1f}}\n",
+            h->nx, h->ny, names[h->storage], h->model, (long long)h->prof_calls, (long long)h->prof_steps,
+            (long long)h->prof_launches, h->prof_ms, mlups);
+}
+
 void lbm_destroy(lbm_solver* h) {
     if (!h) return;
     if (h->batch) {
@@ -313,6 +351,7 @@ void lbm_destroy(lbm_solver* h) {
         h->batch = nullptr;
     }
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->prof) prof_report(h);
     drop_graphs(h);
     if (h->own_base && h->base) (void)hipFree(h->base);
     if (h->snap) (void)hipFree(h->snap);
@@ -613,11 +652,9 @@ static int build_graph(lbm_solver* h, int start) {
     return LBM_OK;
 }
 
-int lbm_step(lbm_solver* h, int64_t nsteps) {
-    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_step: NULL handle");
-    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_step: call lbm_set_params first");
-    if (nsteps < 0) return fail(h, LBM_ERR_ARG, "lbm_step: nsteps < 0");
-    if (h->batch && nsteps > 0) batch_invalidate(h->batch);
+// The launches of lbm_step: captured graphs of graph_steps steps while
+// enough remain, then single launches; *launched counts kernel launches.
+static int step_body(lbm_solver* h, int64_t nsteps, int64_t* launched) {
     if (h->graph_steps > 0) {
         while (nsteps >= h->graph_steps) {
             if (!h->graph_exec[h->cur]) {
@@ -628,6 +665,7 @@ int lbm_step(lbm_solver* h, int64_t nsteps) {
             h->t += h->graph_steps;
             h->cur ^= (int)(h->graph_launches & 1);
             nsteps -= h->graph_steps;
+            *launched += h->graph_launches;
         }
     }
     if (nsteps > 0) {
@@ -636,7 +674,41 @@ int lbm_step(lbm_solver* h, int64_t nsteps) {
         if (e != hipSuccess) return hip_fail(h, e, "sweep launch");
         h->cur ^= (int)(launches & 1);
         h->t += nsteps;
+        *launched += launches;
     }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_solver* h, int64_t nsteps) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_step: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_step: call lbm_set_params first");
+    if (nsteps < 0) return fail(h, LBM_ERR_ARG, "lbm_step: nsteps < 0");
+    if (h->batch && nsteps > 0) batch_invalidate(h->batch);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool prof = h->prof && nsteps > 0 && hipStreamIsCapturing(h->stream, &cap) == hipSuccess &&
+                      cap == hipStreamCaptureStatusNone;
+    int64_t launched = 0;
+    if (!prof) return step_body(h, nsteps, &launched);
+    if (h->prof_ev.size() >= 256) prof_drain(h, false);
+    if (h->prof_ev.size() >= 256) prof_drain(h, true);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int rc = LBM_OK;
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess ||
+        hipEventRecord(ev[0], h->stream) != hipSuccess)
+        rc = fail(h, LBM_ERR_DEVICE, "lbm_step: profiling events");
+    if (rc == LBM_OK) rc = step_body(h, nsteps, &launched);
+    if (rc == LBM_OK && hipEventRecord(ev[1], h->stream) != hipSuccess)
+        rc = fail(h, LBM_ERR_DEVICE, "lbm_step: profiling events");
+    if (rc != LBM_OK) {
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+        return rc;
+    }
+    h->prof_ev.push_back(ev[0]);
+    h->prof_ev.push_back(ev[1]);
+    h->prof_calls += 1;
+    h->prof_steps += nsteps;
+    h->prof_launches += launched;
     return LBM_OK;
 }
 

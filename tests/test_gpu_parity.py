@@ -366,3 +366,28 @@ def test_buffers_above_4gib_match_the_buffer_path():
     for k in range(reps):
         sl = slice(64 * k, 64 * (k + 1))
         assert np.array_equal(fb[:, :, sl], fs) and np.array_equal(gb[:, :, sl], gs), k
+
+
+def test_profile_trace(capfd, monkeypatch):
+    """LBM_PROFILE set at create: lbm_destroy reports the traced calls."""
+    import json
+    pb = W.cavity(64, 1e4)
+    monkeypatch.setenv("LBM_PROFILE", "1")
+    S = lbm.Solver(64, 64, "f64")
+    monkeypatch.delenv("LBM_PROFILE")
+    S.set_params(pb)
+    S.step(100)          # a captured graph of 64 steps and a tail of 36
+    S.step(7)
+    S.step(0)
+    S.close()
+    lines = [l for l in capfd.readouterr().err.splitlines() if l.startswith('{"lbm_profile"')]
+    assert len(lines) == 1
+    rec = json.loads(lines[0])["lbm_profile"]
+    assert rec["nx"] == 64 and rec["ny"] == 64 and rec["storage"] == "f64"
+    assert rec["calls"] == 2 and rec["steps"] == 107
+    assert rec["launches"] == 32 + 18 + 4 and rec["gpu_ms"] > 0 and rec["mlups"] > 0
+    S2 = lbm.Solver(64, 64, "f64")     # not traced
+    S2.set_params(pb)
+    S2.step(10)
+    S2.close()
+    assert '"lbm_profile"' not in capfd.readouterr().err
