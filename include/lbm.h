@@ -90,7 +90,8 @@ enum lbm_model { LBM_MODEL_D2Q5 = 0, LBM_MODEL_D2Q9T = 1, LBM_MODEL_ISOTHERMAL =
  *   e_x|e|^2, e_y, e_y|e|^2, e_x^2 - e_y^2, e_x e_y), m^eq = M_o f^eq,
  *   sources M_o S, with s_e, s_eps, s_q, s_nu on the energy, energy-square,
  *   heat-flux and stress moments; the temperature keeps the model's MRT.
- *   Both run one row per thread and cannot join a batch. */
+ *   Both run in the same step kernels (fused pairs included) and cannot
+ *   join a batch. */
 enum lbm_collision { LBM_COLLISION_MRT = 0, LBM_COLLISION_BGK = 1, LBM_COLLISION_ORTHO_MRT = 2 };
 
 /* Flow boundary per side.  LBM_BC_WALL is halfway bounce-back with the
