@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #include <vector>
 
@@ -163,10 +164,13 @@ int main() {
                     for (int nee = 0; nee < 2; ++nee)
                         for (int px = 0; px < 2; ++px) one_solver(s[0], s[1], storage, model, coll, nee, px);
     for (int storage = LBM_F64; storage <= LBM_F16; ++storage) batches(storage);
-    if (g_fail) {
-        fprintf(stderr, "host check: %d failures\n", g_fail);
-        return 1;
-    }
-    printf("host check ok\n");
-    return 0;
+    if (g_fail) fprintf(stderr, "host check: %d failures\n", g_fail);
+    else printf("host check ok\n");
+    // Every object of ours is destroyed above.  End without running the
+    // HIP runtime's global finalizers: under AddressSanitizer its teardown
+    // frees runtime objects after the sanitizer's device allocator has
+    // been told the device runtime is gone, which fails a sanitizer check.
+    fflush(stdout);
+    fflush(stderr);
+    _exit(g_fail ? 1 : 0);
 }
