@@ -3,9 +3,11 @@
 residual of 1e-11.  The paper used non-equilibrium extrapolation walls; the
 link-wise walls are a different discretisation of the same boundary, so
 the bars are those of a grid-level comparison: 0.5% on the mean Nusselt
-number, 1.5% on the velocity maxima, 2% on the local Nusselt maximum (where
-the wall gradient is steepest and the wall scheme matters most), and the
-positions within 1.5 node spacings."""
+number, 1.5% on the velocity maxima, 2% on the local Nusselt maximum of
+the cold wall (where the wall gradient is steepest and the wall scheme
+matters most), the positions of the velocity maxima within 1.5 node
+spacings and that of the Nusselt maximum, which sits on a flat peak, within
+2.5."""
 import pytest
 
 from golden_io import paper_tables
@@ -31,3 +33,4 @@ def test_steady_cavity_matches_table3(ra, nee):
     assert abs(r["nu_max"] / t[5] - 1) < 2e-2, r
     h = 1.5 / n
     assert abs(r["y_ux_max"] - t[2]) < h and abs(r["x_uy_max"] - t[4]) < h, r
+    assert abs(r["y_nu_max"] - t[6]) < 2.5 / n, r
