@@ -151,7 +151,9 @@ int32_t lbm_abi_version(void);
 const char* lbm_build_info(void);
 
 /* Device bytes a solver of this size, storage and thermal model needs
- * (both population buffers with row and plane padding). */
+ * (both population buffers with row and plane padding).  LBM_ERR_ARG for
+ * the sizes lbm_create rejects (more than 2^31 nodes, or one population
+ * plane of 4 GiB or more), a bad storage or model, or a NULL output. */
 int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, uint64_t* bytes);
 
 /* Create a solver for an nx x ny lattice (nx, ny >= 1, one population

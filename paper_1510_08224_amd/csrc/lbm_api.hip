@@ -56,7 +56,7 @@ struct lbm_solver {
     std::vector<hipEvent_t> prof_ev;   // pending start, stop, start, stop, ...
     double prof_ms = 0.0;
     int64_t prof_calls = 0, prof_steps = 0, prof_launches = 0;
-    std::string err;
+    mutable std::string err;  // last error; const readouts report theirs too
 };
 
 struct lbm_batch {
@@ -96,7 +96,7 @@ static void batch_invalidate(lbm_batch* b);
 
 static thread_local std::string g_create_error;
 
-static int fail(lbm_solver* h, int code, const std::string& msg) {
+static int fail(const lbm_solver* h, int code, const std::string& msg) {
     if (h) h->err = msg;
     else g_create_error = msg;
     return code;
@@ -166,10 +166,14 @@ const char* lbm_build_info(void) {
 int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, uint64_t* bytes) {
     if (!bytes || nx < 1 || ny < 1 || storage < LBM_F64 || storage > LBM_F16 || !model_ok(model))
         return fail(nullptr, LBM_ERR_ARG, "lbm_required_bytes: bad size, storage, model or NULL output");
+    if ((long long)nx * ny > (1ll << 31))
+        return fail(nullptr, LBM_ERR_ARG, "lbm_required_bytes: more than 2^31 nodes");
     int pitch;
     long long plane;
     size_t bb;
     layout(nx, ny, storage, model_ng(model), &pitch, &plane, &bb);
+    if ((unsigned long long)plane * storage_bytes(storage) >= (1ull << 32))
+        return fail(nullptr, LBM_ERR_ARG, "lbm_required_bytes: one population plane would exceed 4 GiB");
     *bytes = 2 * (uint64_t)bb;
     return LBM_OK;
 }
@@ -564,7 +568,7 @@ int lbm_set_params(lbm_solver* h, const lbm_params* p) {
 int lbm_get_derived(const lbm_solver* h, double* s9, double* q9, double* gbeta, double* T0,
                     double* length, double* dT) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_get_derived: NULL handle");
-    if (!h->params_set) return LBM_ERR_STATE;
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_get_derived: call lbm_set_params first");
     if (s9) {
         const double s[9] = {1, 1, 1, h->C.s3, h->C.s4, h->C.s4, h->C.s6, h->C.s6, h->C.s8};
         memcpy(s9, s, sizeof(s));

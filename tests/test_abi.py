@@ -58,6 +58,19 @@ def test_required_bytes_rejects_bad_input():
         lbm.lbm_required_bytes(5, 5, lbm.LBM_F64, 3)
 
 
+def test_required_bytes_rejects_what_create_rejects():
+    """Sizes lbm_create refuses get no byte count either: more than 2^31
+    nodes, or one population plane of 4 GiB or more (FP64: 2^29 nodes)."""
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_required_bytes(65536, 32769, lbm.LBM_F64)
+    assert e.value.code == lbm.LBM_ERR_ARG
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_required_bytes(32768, 16384, lbm.LBM_F64)
+    assert b"4 GiB" in lbm.lib().lbm_last_error(None)
+    # the same plane in FP32 storage is 2 GiB: accepted
+    assert lbm.lbm_required_bytes(32768, 16384, lbm.LBM_F32) == 2 * 14 * 32768 * 16384 * 4
+
+
 def test_create_rejects_bad_arguments_before_touching_a_device():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_create(0, 4, lbm.LBM_F64)
