@@ -160,7 +160,8 @@ void lbm_params_default(lbm_params* p) {
 int32_t lbm_abi_version(void) { return LBM_ABI_VERSION; }
 
 const char* lbm_build_info(void) {
-    return "lbm non-orthogonal MRT D2Q9+D2Q5, HIP gfx950, storage f64/f32/f16";
+    return "lbm non-orthogonal MRT: D2Q9 flow with D2Q5, D2Q9 or no temperature lattice; HIP gfx950; "
+           "storage f64/f32/f16";
 }
 
 int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, uint64_t* bytes) {

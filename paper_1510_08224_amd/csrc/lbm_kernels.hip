@@ -6,12 +6,15 @@
 //                    temperature collision + store (one time step; Eqs. 4, 8,
 //                    9, 24, 25)
 //   k_sweep_batch    the same step for every lattice of a batch
+//   k_sweep2(_batch) two time steps per launch: the first on a tile and its
+//                    halo into LDS, the second from LDS to memory
 //   k_moments        rho, u, T at time t (Eqs. 18, 19, 27)
 //   k_gather         pre-collision populations at time t, FP64
 //   k_unstream       write a buffer whose pull yields given pre-collision
 //                    populations (state restore and initial equilibrium)
 //   k_nusselt        wall Nusselt number (Eq. 39), one block, fixed-order FP64
-//   k_residual(_batch) steady-state residual and non-finite count, FP64
+//   k_residual(_batch) steady-state residual and non-finite count, FP64,
+//                    reduced in a fixed order by k_reduce_final / k_reduce_members
 //
 // All kernels read the state through load_node / pull_node / source
 // (lbm_device.hpp), so the wall rules exist in one place.
