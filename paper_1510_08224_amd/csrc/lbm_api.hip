@@ -383,6 +383,29 @@ static bool rate_ok(double s) { return isfinite(s) && s > 0.0 && s < 2.0; }
 // D2Q9 weights (after Eq. 22) for the moving-wall term.
 static const double kW9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
+// The relaxation constants in the arithmetic type T, each rounded as a
+// kernel colliding in T would round it: the double converted to T, then one
+// operation in T.
+extern "C++" template <class T>
+static void fill_rates(Rates<T>& K, const Coeffs& C) {
+    K.s3 = (T)C.s3;
+    K.s4 = (T)C.s4;
+    K.s6 = (T)C.s6;
+    K.s8 = (T)C.s8;
+    K.h3 = (T)1 - (T)0.5 * K.s3;
+    K.h4 = (T)1 - (T)0.5 * K.s4;
+    K.h6 = (T)1 - (T)0.5 * K.s6;
+    K.h8 = (T)1 - (T)0.5 * K.s8;
+    K.z1 = (T)C.z1;
+    K.z3 = (T)C.z3;
+    K.z4 = (T)C.z4;
+    K.z6 = (T)C.z6;
+    K.z8 = (T)C.z8;
+    K.varpi = (T)C.varpi;
+    K.one_m_varpi = (T)1 - K.varpi;
+    K.theta = (T)C.theta;
+}
+
 static int derive(lbm_solver* h, const lbm_params* p) {
     if (p->collision < LBM_COLLISION_MRT || p->collision > LBM_COLLISION_ORTHO_MRT)
         return fail(h, LBM_ERR_ARG, "lbm_set_params: unknown collision operator");
@@ -499,6 +522,8 @@ static int derive(lbm_solver* h, const lbm_params* p) {
         C.wT[s] = p->wall_T[s];
     }
     C.collision = p->collision;
+    fill_rates(C.rd, C);
+    fill_rates(C.rf, C);
     C.fscale = C.finv = C.gscale = C.ginv = 1.0f;
     if (h->storage == LBM_F16) {
         // Powers of two: deviations of O(0.1) for fbar and of O(|T - T0|)

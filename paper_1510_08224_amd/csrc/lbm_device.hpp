@@ -54,6 +54,21 @@ struct Geom {
     long long plane;    // elements per plane
 };
 
+// Relaxation constants in one arithmetic type, rounded once on the host:
+// the rates, the source factors h = 1 - s/2 of Eq. 8 (and of Eq. 24's
+// operators), varpi and 1 - varpi.  The host applies the rounding a kernel
+// would (double to float to nearest even, then one float operation), so the
+// collisions give the results they would with the doubles converted per
+// wave, without the conversions and with half the scalar registers.
+template <class T>
+struct Rates {
+    T s3, s4, s6, s8;        // flow rates (Eq. 20)
+    T h3, h4, h6, h8;        // 1 - s/2 for each of them
+    T z1, z3, z4, z6, z8;    // thermal rates (Eq. 29, or Eq. 32 for D2Q9)
+    T varpi, one_m_varpi;    // Eq. 28 (D2Q5) and 1 - varpi
+    T theta;                 // Eq. 31 (D2Q9), 0 or 1
+};
+
 // Per-problem constants of the step (all derived on the host).
 struct Coeffs {
     // D2Q9 flow rates (Eq. 20): s3 = s_e, s4 = s5 = s_nu, s6 = s7 = s_q, s8 = s_eps.
@@ -86,7 +101,15 @@ struct Coeffs {
     // Deviation storage scales (FP16): stored = value * scale.
     float fscale, finv, gscale, ginv;
     int collision;      // 0 the paper's MRT, 1 BGK, 2 orthogonal MRT (Sec. 3.2)
+    // The rates above in each collision arithmetic: FP64 storage collides
+    // in double, FP32 and FP16 storage in float.
+    Rates<double> rd;
+    Rates<float> rf;
 };
+
+template <class R> __host__ __device__ __forceinline__ const Rates<R>& rates_of(const Coeffs& C);
+template <> __host__ __device__ __forceinline__ const Rates<double>& rates_of<double>(const Coeffs& C) { return C.rd; }
+template <> __host__ __device__ __forceinline__ const Rates<float>& rates_of<float>(const Coeffs& C) { return C.rf; }
 
 // Per-side constants of the NEE rebuild picked by a lane-varying side
 // index, as a chain of selects.
@@ -435,7 +458,8 @@ __device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const 
     if constexpr (FLOW_MRT) {
         const Moments9<R> m(f);
         // Relaxation toward m^eq (Eq. 16) with the source of Eq. 17.
-        const R s3 = (R)C.s3, s4 = (R)C.s4, s6 = (R)C.s6, s8 = (R)C.s8;
+        const Rates<R>& K = rates_of<R>(C);
+        const R s3 = K.s3, s4 = K.s4, s6 = K.s6, s8 = K.s8;
         const R e3 = (R)(2.0 / 3.0) * rho + usq;
         const R e4 = ux * ux - uy * uy;
         const R e5 = ux * uy;
@@ -448,12 +472,12 @@ __device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const 
         const R S6 = third * Fy;
         const R S7 = third * Fx;
         const R S8 = (R)(2.0 / 3.0) * uF;
-        const R n3 = m.m3 - s3 * (m.m3 - e3) + ((R)1 - (R)0.5 * s3) * S3;
-        const R n4 = m.m4 - s4 * (m.m4 - e4) + ((R)1 - (R)0.5 * s4) * S4;
-        const R n5 = m.m5 - s4 * (m.m5 - e5) + ((R)1 - (R)0.5 * s4) * S5;
-        const R n6 = m.m6 - s6 * (m.m6 - e6) + ((R)1 - (R)0.5 * s6) * S6;
-        const R n7 = m.m7 - s6 * (m.m7 - e7) + ((R)1 - (R)0.5 * s6) * S7;
-        const R n8 = m.m8 - s8 * (m.m8 - e8) + ((R)1 - (R)0.5 * s8) * S8;
+        const R n3 = m.m3 - s3 * (m.m3 - e3) + K.h3 * S3;
+        const R n4 = m.m4 - s4 * (m.m4 - e4) + K.h4 * S4;
+        const R n5 = m.m5 - s4 * (m.m5 - e5) + K.h4 * S5;
+        const R n6 = m.m6 - s6 * (m.m6 - e6) + K.h6 * S6;
+        const R n7 = m.m7 - s6 * (m.m7 - e7) + K.h6 * S7;
+        const R n8 = m.m8 - s8 * (m.m8 - e8) + K.h8 * S8;
         // Conserved moments after collision: m0* = rho, m1* = jx + Fx,
         // m2* = jy + Fy (rates 1 in Eq. 20; Eq. 15 puts -F/2 in m_bar).
         const R n1 = (R)(mc.ux + 0.5 * mc.Fx);
@@ -468,10 +492,11 @@ __device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const 
         const R t2 = g[2] - g[4];
         const R t3 = (g[1] + g[3]) + (g[2] + g[4]);
         const R t4 = (g[1] + g[3]) - (g[2] + g[4]);
-        const R z1 = (R)C.z1, z3 = (R)C.z3, z4 = (R)C.z4;
+        const Rates<R>& K = rates_of<R>(C);
+        const R z1 = K.z1, z3 = K.z3, z4 = K.z4;
         const R k1 = t1 - z1 * (t1 - ux * T);
         const R k2 = t2 - z1 * (t2 - uy * T);
-        const R k3 = t3 - z3 * (t3 - (R)C.varpi * t0);
+        const R k3 = t3 - z3 * (t3 - K.varpi * t0);
         const R k4 = t4 - z4 * t4;
         const R w3 = (R)0.25 * k3, w4 = (R)0.25 * k4;
         g[0] = t0 - k3;
@@ -488,10 +513,11 @@ __device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const 
         const Moments9<R> m(g);
         const R T = (R)mc.T;
         const R t0 = (R)mc.Tsum;
-        const R th = (R)C.theta;
+        const Rates<R>& K = rates_of<R>(C);
+        const R th = K.theta;
         const R n1 = m.d13 + m.m7;
         const R n2 = m.d24 + m.m6;
-        const R z1 = (R)C.z1, z3 = (R)C.z3, z4 = (R)C.z4, z6 = (R)C.z6, z8 = (R)C.z8;
+        const R z1 = K.z1, z3 = K.z3, z4 = K.z4, z6 = K.z6, z8 = K.z8;
         const R k1 = n1 - z1 * (n1 - ux * T);
         const R k2 = n2 - z1 * (n2 - uy * T);
         const R k3 = m.m3 - z3 * (m.m3 - ((R)(2.0 / 3.0) * t0 + th * usq * T));
@@ -527,7 +553,7 @@ enum Collision { kCollMRT = 0, kCollBGK = 1, kCollOrtho = 2 };
 template <class R>
 __device__ __forceinline__ void collide_flow_bgk(R f[9], const Macro& mc, const Coeffs& C) {
     const R rho = (R)mc.rho, ux = (R)mc.ux, uy = (R)mc.uy, Fx = (R)mc.Fx, Fy = (R)mc.Fy;
-    const R w = (R)C.s4, a = (R)1 - (R)0.5 * w;
+    const R w = rates_of<R>(C).s4, a = rates_of<R>(C).h4;
     const R usq15 = (R)1.5 * (ux * ux + uy * uy);
     const R uF3 = (R)3 * (ux * Fx + uy * Fy);
 #pragma unroll
@@ -556,13 +582,14 @@ __device__ __forceinline__ void collide_flow_ortho(R f[9], const Macro& mc, cons
     const R m_qy = (R)-2 * d24 + sy;
     const R m_xx = ax - ay;
     const R m_xy = (f[5] - f[6]) + (f[7] - f[8]);
-    const R s_e = (R)C.s3, s_eps = (R)C.s8, s_q = (R)C.s6, s_nu = (R)C.s4;
-    const R k_e = m_e - s_e * (m_e - ((R)-2 * rho + (R)3 * usq)) + ((R)1 - (R)0.5 * s_e) * ((R)6 * uF);
-    const R k_eps = m_eps - s_eps * (m_eps - (rho - (R)3 * usq)) + ((R)1 - (R)0.5 * s_eps) * ((R)-6 * uF);
-    const R k_qx = m_qx - s_q * (m_qx + ux) - ((R)1 - (R)0.5 * s_q) * Fx;
-    const R k_qy = m_qy - s_q * (m_qy + uy) - ((R)1 - (R)0.5 * s_q) * Fy;
-    const R k_xx = m_xx - s_nu * (m_xx - (ux * ux - uy * uy)) + ((R)1 - (R)0.5 * s_nu) * ((R)2 * (ux * Fx - uy * Fy));
-    const R k_xy = m_xy - s_nu * (m_xy - ux * uy) + ((R)1 - (R)0.5 * s_nu) * (ux * Fy + uy * Fx);
+    const Rates<R>& K = rates_of<R>(C);
+    const R s_e = K.s3, s_eps = K.s8, s_q = K.s6, s_nu = K.s4;
+    const R k_e = m_e - s_e * (m_e - ((R)-2 * rho + (R)3 * usq)) + K.h3 * ((R)6 * uF);
+    const R k_eps = m_eps - s_eps * (m_eps - (rho - (R)3 * usq)) + K.h8 * ((R)-6 * uF);
+    const R k_qx = m_qx - s_q * (m_qx + ux) - K.h6 * Fx;
+    const R k_qy = m_qy - s_q * (m_qy + uy) - K.h6 * Fy;
+    const R k_xx = m_xx - s_nu * (m_xx - (ux * ux - uy * uy)) + K.h4 * ((R)2 * (ux * Fx - uy * Fy));
+    const R k_xy = m_xy - s_nu * (m_xy - ux * uy) + K.h4 * (ux * Fy + uy * Fx);
     // conserved moments after collision: rho, j + F (Eq. 15 puts -F/2 in j)
     const R jx = (R)(mc.ux + 0.5 * mc.Fx), jy = (R)(mc.uy + 0.5 * mc.Fy);
     // f = M_o^T D^-1 m*
@@ -589,17 +616,18 @@ template <class R, int NG>
 __device__ __forceinline__ void collide_thermal_bgk(R g[NG > 0 ? NG : 1], const Macro& mc, const Coeffs& C) {
     if constexpr (NG > 0) {
         const R ux = (R)mc.ux, uy = (R)mc.uy, T = (R)mc.T, t0 = (R)mc.Tsum;
-        const R z = (R)C.z1;
+        const Rates<R>& K = rates_of<R>(C);
+        const R z = K.z1;
         if constexpr (NG == 5) {
-            const R vp = (R)C.varpi;
-            g[0] = g[0] - z * (g[0] - ((R)1 - vp) * t0);
+            const R vp = K.varpi;
+            g[0] = g[0] - z * (g[0] - K.one_m_varpi * t0);
 #pragma unroll
             for (int i = 1; i < 5; ++i) {
                 const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
                 g[i] = g[i] - z * (g[i] - ((R)0.25 * vp * t0 + (R)0.5 * eu * T));
             }
         } else {
-            const R th = (R)C.theta, usq15 = (R)1.5 * (ux * ux + uy * uy);
+            const R th = K.theta, usq15 = (R)1.5 * (ux * ux + uy * uy);
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
