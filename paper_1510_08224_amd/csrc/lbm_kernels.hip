@@ -177,14 +177,22 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 // result is bitwise the result of two single steps.
 //
 // LDS layout: population i of the second step's pull at tile node n comes
-// from node n - e_i, so plane i holds exactly a 64 x TY window (the tile
-// shifted by -e_i), indexed by the pulling node.  A node of the first step
-// writes population i to window slot n + e_i when that lies in the tile.
-// Where the link into tile node n crosses a non-periodic side, no node
-// exists at n - e_i; the first step at n writes there the wall rule of the
-// pull instead (the kept opposite population plus bbf, or gsign times it
-// plus gconst, the y side first at a corner), so the second step reads
-// every node's populations with plain LDS loads.
+// from node n - e_i.  In the halo layout plane i covers the whole slot grid
+// of the first step (66 x (TY + 2)): every slot stores all its populations
+// at its own index, without a test and from one address with constant
+// offsets, and the second step reads slot n - e_i, again one address with
+// constant offsets.  In the window layout (FP64 D2Q9 thermal, whose halo
+// planes would cost a workgroup per CU) plane i holds exactly the 64 x TY
+// window the tile pulls (the tile shifted by -e_i), indexed by the pulling
+// node, and a first-step node writes population i to n + e_i when that
+// lies in the tile.  Where the link into tile node n crosses a
+// non-periodic side, no node exists at n - e_i; the first step at n writes
+// the wall rule of the pull where the second step will read it (the kept
+// opposite population plus bbf, or gsign times it plus gconst, the y side
+// first at a corner), so the second step reads every node's populations
+// with plain LDS loads.  (In the halo layout that place is a slot outside
+// the lattice, which no first-step node occupies.)  Halo planes raised the
+// 2048^2 step rates by 1.3-5.4% over windows (FP32 D2Q9 thermal the most).
 //
 // A workgroup has one thread per tile node (64 TY threads), so each phase
 // is one pass and the compiler keeps the step constants in scalar
@@ -232,9 +240,24 @@ struct Fuse2 {
     static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
     static constexpr int EH = TY + 2;
     static constexpr int SLOTS = EW * EH;   // nodes of the first step
-    static constexpr int PLANE = TX * TY;   // LDS values per population
+    // LDS layout.  HALO: plane i holds population i of every slot of the
+    // first step (EW x EH, indexed by the slot), so each slot stores all its
+    // populations without a test, and tile node n pulls population i from
+    // slot n - e_i.  Otherwise plane i holds only the 64 x TY window the
+    // tile pulls, indexed by the pulling node; FP64 D2Q9 thermal keeps it,
+    // since its larger planes would cost a workgroup per CU.
+    static constexpr bool HALO = !(std::is_same<S, double>::value && NG == 9);
+    static constexpr int PLANE = HALO ? SLOTS : TX * TY;   // LDS values per population
     static_assert(NP * PLANE * (int)sizeof(R) <= 81920, "fused tile needs more than half the LDS of a CU");
 };
+
+// LDS index of the value in plane p that tile node (ix, iy) pulls along
+// direction i (p = i for the flow, 9 + i for the temperature).
+template <class F>
+__device__ __forceinline__ int pulled_at(int p, int i, int ix, int iy) {
+    if constexpr (F::HALO) return p * F::PLANE + (iy + 1 - ey(i)) * F::EW + (ix + 1 - ex(i));
+    else return p * F::PLANE + iy * F::TX + ix;
+}
 
 // Slots of the first fused step: the tile and its halo, (sx, sy) in
 // [-1, 64] x [-1, TY] relative to the tile origin.  SlotOrder numbers the
@@ -347,7 +370,8 @@ __device__ __forceinline__ bool fuse2_load(const S* __restrict__ src, __amdgpu_b
     return true;
 }
 
-// Population I of slot (sx, sy) (tile coordinates) into its window slot.
+// Population I of slot (sx, sy) (tile coordinates) into its window slot
+// (window layout only).
 template <class S, int NG, int P0, int I>
 __device__ __forceinline__ void fuse2_put(typename Codec<S>::R* lds, int sx, int sy, typename Codec<S>::R v) {
     using F = Fuse2<S, NG>;
@@ -355,11 +379,13 @@ __device__ __forceinline__ void fuse2_put(typename Codec<S>::R* lds, int sx, int
     if (tx >= 0 && tx < F::TX && ty >= 0 && ty < F::TY) lds[(P0 + I) * F::PLANE + ty * F::TX + tx] = v;
 }
 
-// The wall rule of link I into tile node (x, y) = (x0 + sx, y0 + sy), if
+// The wall rule of link I into tile node (x, y) = (x0 + ix, y0 + iy), if
 // the link crosses a non-periodic side; the same arithmetic as the pull.
+// It goes where the node pulls that link from: in the halo layout a slot
+// outside the lattice, which no first-step node writes.
 template <class S, int NG, int I>
 __device__ __forceinline__ void fuse2_wall(typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x, int y,
-                                           int idx, const typename Codec<S>::R f[9],
+                                           int ix, int iy, const typename Codec<S>::R f[9],
                                            const typename Codec<S>::R g[gdim(NG)]) {
     using F = Fuse2<S, NG>;
     using R = typename Codec<S>::R;
@@ -369,8 +395,8 @@ __device__ __forceinline__ void fuse2_wall(typename Codec<S>::R* lds, const Geom
     if (dy != 0 && (sy < 0 || sy >= G.ny) && !G.py) side = sy < 0 ? kBottom : kTop;
     if (dx != 0 && (sx < 0 || sx >= G.nx) && !G.px && side < 0) side = sx < 0 ? kLeft : kRight;
     if (side < 0) return;
-    lds[I * F::PLANE + idx] = f[opp(I)] + (R)C.bbf[side][I];
-    if constexpr (I < NG) lds[(9 + I) * F::PLANE + idx] = (R)C.gsign[side] * g[opp(I)] + (R)C.gconst[side][I];
+    lds[pulled_at<F>(I, I, ix, iy)] = f[opp(I)] + (R)C.bbf[side][I];
+    if constexpr (I < NG) lds[pulled_at<F>(9 + I, I, ix, iy)] = (R)C.gsign[side] * g[opp(I)] + (R)C.gconst[side][I];
 }
 
 template <class S, int NG, int P0, int... I>
@@ -381,10 +407,10 @@ __device__ __forceinline__ void fuse2_put_set(typename Codec<S>::R* lds, int sx,
 
 template <class S, int NG, int... I>
 __device__ __forceinline__ void fuse2_walls(typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x, int y,
-                                            int idx, const typename Codec<S>::R f[9],
+                                            int ix, int iy, const typename Codec<S>::R f[9],
                                             const typename Codec<S>::R g[gdim(NG)],
                                             std::integer_sequence<int, I...>) {
-    (fuse2_wall<S, NG, I + 1>(lds, G, C, x, y, idx, f, g), ...);
+    (fuse2_wall<S, NG, I + 1>(lds, G, C, x, y, ix, iy, f, g), ...);
 }
 
 // Collide the pulled populations of slot (sl, sm), round them as a store
@@ -402,12 +428,20 @@ __device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom
 #pragma unroll
     for (int i = 0; i < NG; ++i) g[i] = as_stored<S>(g[i], C.gscale, C.ginv);
     const int sx = sl - 1, sy = sm - 1;
-    fuse2_put_set<S, NG, 0>(lds, sx, sy, f, std::make_integer_sequence<int, 9>{});
-    if constexpr (NG > 0) fuse2_put_set<S, NG, 9>(lds, sx, sy, g, std::make_integer_sequence<int, NG>{});
+    if constexpr (F::HALO) {
+        const int at = sm * F::EW + sl;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lds[i * F::PLANE + at] = f[i];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) lds[(9 + i) * F::PLANE + at] = g[i];
+    } else {
+        fuse2_put_set<S, NG, 0>(lds, sx, sy, f, std::make_integer_sequence<int, 9>{});
+        if constexpr (NG > 0) fuse2_put_set<S, NG, 9>(lds, sx, sy, g, std::make_integer_sequence<int, NG>{});
+    }
     const int x = x0 + sx, y = y0 + sy;
     const bool in_tile = sx >= 0 && sx < F::TX && sy >= 0 && sy < F::TY;
     const bool wall = (!G.px && (x == 0 || x == G.nx - 1)) || (!G.py && (y == 0 || y == G.ny - 1));
-    if (in_tile && wall) fuse2_walls<S, NG>(lds, G, C, x, y, sy * F::TX + sx, f, g, std::make_integer_sequence<int, 8>{});
+    if (in_tile && wall) fuse2_walls<S, NG>(lds, G, C, x, y, sx, sy, f, g, std::make_integer_sequence<int, 8>{});
 }
 
 // One fused pair of steps on the tile at (x0, y0) of one lattice.
@@ -451,18 +485,18 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
         R f[9], g[gdim(NG)];
         if (nee && nee_node_at(G, C, x, y)) {
             const NeeWall w = nee_wall(G, C, x, y);
-            const int fn = (w.fy - y0) * F::TX + (w.fx - x0);
+            const int fx = w.fx - x0, fy = w.fy - y0;
             R ff[9], gf[gdim(NG)];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) ff[i] = lds[i * F::PLANE + fn];
+            for (int i = 0; i < 9; ++i) ff[i] = lds[pulled_at<F>(i, i, fx, fy)];
 #pragma unroll
-            for (int i = 0; i < NG; ++i) gf[i] = lds[(9 + i) * F::PLANE + fn];
+            for (int i = 0; i < NG; ++i) gf[i] = lds[pulled_at<F>(9 + i, i, fx, fy)];
             nee_rebuild<R, NG>(w, C, ff, gf, f, g);
         } else {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) f[i] = lds[i * F::PLANE + n];
+            for (int i = 0; i < 9; ++i) f[i] = lds[pulled_at<F>(i, i, ix, iy)];
 #pragma unroll
-            for (int i = 0; i < NG; ++i) g[i] = lds[(9 + i) * F::PLANE + n];
+            for (int i = 0; i < NG; ++i) g[i] = lds[pulled_at<F>(9 + i, i, ix, iy)];
         }
         const Macro m = macro<R, NG>(f, g, C);
         collide<R, NG, COLL>(f, g, m, C);
