@@ -205,9 +205,11 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 // thermal and the FP32/FP16 D2Q5 and D2Q9 kernels take TY = 4 (8 rows cost
 // them 8-15%); FP32/FP16 without temperature take 8.  Otherwise TY is a
 // multiple of 4, the largest whose LDS fits kFuse2Lds bytes, from 4 to 16.
-// The kernels without temperature ask for five waves per SIMD (FP32: 7.7
-// against 6.9 TB/s), the D2Q9 thermal ones for three (their register count
-// sits just above that limit; FP64 spills 12 bytes per lane for it).
+// Each thread steps one first-step slot at a time; the kernels ask the
+// compiler for as many waves per SIMD as their LDS allows (fuse2_waves).
+// Two slots per thread in flight together held twice the populations in
+// registers and cost that occupancy: one slot at a time raised the 2048^2
+// and 4096^2 step rates by 1-11% (D2Q9 thermal and the flow alone the most).
 // ---------------------------------------------------------------------------
 #ifndef LBM_FUSE2_LDS
 #define LBM_FUSE2_LDS 20480
@@ -451,23 +453,17 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
                                            typename Codec<S>::R* lds) {
     using F = Fuse2<S, NG>;
     using R = typename Codec<S>::R;
-    // Step t -> t + 1 on the tile and its halo, two slots per thread at a
-    // time so that both slots' loads are in flight together.
+    // Step t -> t + 1 on the tile and its halo, one slot per thread at a time.
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
     const SlotOrder o = slot_order<F>(G, x0, y0);
     // o.count <= SLOTS: the bound known at compile time fixes the trip count
 #pragma unroll
-    for (int w = threadIdx.x; w < F::SLOTS; w += 2 * F::NT) {
+    for (int w = threadIdx.x; w < F::SLOTS; w += F::NT) {
         if (w >= o.count) break;
-        R fa[9], ga[gdim(NG)], fb[9], gb[gdim(NG)];
-        int la, ma, lb = 0, mb = 0;
-        slot_of(o, w, la, ma);
-        const bool hb = w + F::NT < o.count;
-        if (hb) slot_of(o, w + F::NT, lb, mb);
-        const bool va = fuse2_load<S, NG>(src, rs, G, C, x0, y0, la, ma, fa, ga);
-        const bool vb = hb && fuse2_load<S, NG>(src, rs, G, C, x0, y0, lb, mb, fb, gb);
-        if (va) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, la, ma, fa, ga);
-        if (vb) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, lb, mb, fb, gb);
+        R f[9], g[gdim(NG)];
+        int l, m;
+        slot_of(o, w, l, m);
+        if (fuse2_load<S, NG>(src, rs, G, C, x0, y0, l, m, f, g)) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, l, m, f, g);
     }
     __syncthreads();
 
@@ -506,11 +502,17 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
     }
 }
 
-// Waves per SIMD the fused kernels ask the compiler for (1: no request).
-constexpr int fuse2_waves(int NG) { return NG == 0 ? 5 : (NG == 9 ? 3 : 1); }
+// Waves per SIMD the fused kernels ask the compiler for: what their LDS
+// allows per CU (FP64 D2Q5 is bound by its LDS at four and asks nothing).
+// FP64: 6 without temperature, 4 for D2Q9 thermal (a 28-byte spill);
+// FP32/FP16: 8, 6 and 4.
+template <class S>
+constexpr int fuse2_waves(int NG) {
+    return std::is_same<S, double>::value ? (NG == 0 ? 6 : (NG == 9 ? 4 : 1)) : (NG == 0 ? 8 : (NG == 5 ? 6 : 4));
+}
 
 template <class S, int NG, int MODE, int COLL>
-__global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per_eu(fuse2_waves(NG), 8))) void k_sweep2(
+__global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per_eu(fuse2_waves<S>(NG), 8))) void k_sweep2(
     Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src, S* __restrict__ dst, int tiles_x,
     unsigned buf_bytes, int order) {
     using F = Fuse2<S, NG>;
@@ -523,7 +525,7 @@ __global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per
 // Fused pairs of steps for every lattice of a batch: each workgroup takes
 // one entry of the fused tile table (a member and its 64 x TY tile).
 template <class S, int NG, int MODE>
-__global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per_eu(fuse2_waves(NG), 8)))
+__global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per_eu(fuse2_waves<S>(NG), 8)))
 void k_sweep2_batch(
     const BatchMember* __restrict__ members, const BatchTile* __restrict__ tiles, int parity) {
     using F = Fuse2<S, NG>;
