@@ -292,9 +292,8 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           per two steps.  Bitwise the same results.  Used
  *                           with every collision operator on buffers below
  *                           4 GiB and, with NEE walls, when no edge tile is
- *                           one node wide or high (tiles are 64 nodes wide
- *                           and 8 high for FP64 D2Q5 and without
- *                           temperature, 4 high otherwise); otherwise steps
+ *                           one node wide or high (tiles are 64 x 8 nodes:
+ *                           nx % 64 == 1 or ny % 8 == 1); otherwise steps
  *                           run singly (lbm_steps_per_launch tells which).
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; fused pairs for FP64 and FP32

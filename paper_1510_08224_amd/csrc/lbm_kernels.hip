@@ -199,23 +199,17 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 // registers (a loop over rows made it hold them in vector registers, at
 // the cost of occupancy).  The kernel is bound by latency more than by
 // arithmetic or bandwidth; TY trades halo work against workgroups per CU.
-// Measured on MI355X (algorithmic GB/s): FP64 D2Q5 and FP64 without
-// temperature take TY = 8 (two 512-thread workgroups per CU; D2Q5 2048^2
-// 9.8 TB/s against 9.6 at TY = 4, 4096^2 10.4 against 9.8); FP64 D2Q9
-// thermal and the FP32/FP16 D2Q5 and D2Q9 kernels take TY = 4 (8 rows cost
-// them 8-15%); FP32/FP16 without temperature take 8.  Otherwise TY is a
-// multiple of 4, the largest whose LDS fits kFuse2Lds bytes, from 4 to 16.
+// Every fused kernel takes TY = 8 (measured on MI355X: FP64 D2Q5 2048^2
+// 9.8 TB/s against 9.6 at TY = 4, 4096^2 10.4 against 9.8; with one slot
+// per thread, FP32 D2Q5 and both D2Q9 thermal kernels 2-13% faster than
+// at TY = 4, which they had taken while two slots per thread limited their
+// occupancy).
 // Each thread steps one first-step slot at a time; the kernels ask the
 // compiler for as many waves per SIMD as their LDS allows (fuse2_waves).
 // Two slots per thread in flight together held twice the populations in
 // registers and cost that occupancy: one slot at a time raised the 2048^2
 // and 4096^2 step rates by 1-11% (D2Q9 thermal and the flow alone the most).
 // ---------------------------------------------------------------------------
-#ifndef LBM_FUSE2_LDS
-#define LBM_FUSE2_LDS 20480
-#endif
-constexpr int kFuse2Lds = LBM_FUSE2_LDS;
-
 // The value a store to storage type S followed by a load would give.
 template <class S>
 __device__ __forceinline__ typename Codec<S>::R as_stored(typename Codec<S>::R v, float scale, float inv) {
@@ -229,14 +223,10 @@ struct Fuse2 {
     static constexpr int NP = 9 + NG;
     static constexpr int TX = 64;
     static constexpr int EW = TX + 2;
-    static constexpr int ROW_BYTES = TX * NP * (int)sizeof(R);
 #ifdef LBM_FUSE2_ROWS
-    static constexpr int TY = LBM_FUSE2_ROWS;
+    static constexpr int TY = LBM_FUSE2_ROWS;   // build-time override of the tile height
 #else
-    static constexpr int TY_FIT = kFuse2Lds / ROW_BYTES;
-    static constexpr int TY = (std::is_same<S, double>::value && NG != 9)
-                                  ? 8
-                                  : (TY_FIT >= 16 ? 16 : (TY_FIT < 4 ? 4 : TY_FIT / 4 * 4));
+    static constexpr int TY = 8;
 #endif
     static constexpr int NT = TX * TY;      // threads: one per tile node
     static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
