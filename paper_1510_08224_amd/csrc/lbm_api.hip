@@ -190,10 +190,11 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // above (FP16 3072^2, 528 MB: +11%; FP64 4096^2: +2%).  Contiguous strips
 // per XCD (LBM_POLICY_XCD_STRIPS) are within a few percent either way and
 // left to the autotuner.  Fused pairs of steps (LBM_POLICY_FUSE2) win for
-// FP64 and FP32 at every size measured (FP64 512^2 to 4096^2: 1.2x to
-// 1.7x; FP32 512^2: 1.35x, 1024^2: 1.27x, 2048^2 and up: 1.3x to 1.5x);
-// never for FP16, whose fused kernel is latency-bound.  Fused pairs run
-// best with XCD bands.
+// FP64 and FP32 at every size measured (1024^2 to 4096^2: FP64 1.6x to
+// 1.9x, FP32 1.3x to 1.7x over the best single step); FP16 keeps single
+// steps, which win from 2048^2 up for every model but D2Q5 at 4096^2 (its
+// fused kernel is bound by the latency of decoding and re-rounding).
+// Fused pairs run best with XCD bands.
 static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
@@ -1159,8 +1160,8 @@ static int batch_build(lbm_batch* b) {
     }
     // Fused pairs win for FP64 and FP32 batches at every member size
     // measured on MI355X (batches of equal square cavities, 6.7e6 nodes in
-    // all, sides 64 to 1024: FP32 1.07x to 1.6x, FP64 1.25x to 1.8x over one
-    // step per launch); FP16's fused kernel is slower than its single step.
+    // all, sides 64 to 1024: FP32 1.1x to 1.6x, FP64 1.3x to 1.9x over one
+    // step per launch); FP16 batches keep single steps, like FP16 lattices.
     const double mib = 1024.0 * 1024.0;
     const bool want = b->policy == LBM_POLICY_DEFAULT
                           ? (b->storage == LBM_F64 || b->storage == LBM_F32)

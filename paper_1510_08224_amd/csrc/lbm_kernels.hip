@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 // at its own index, without a test and from one address with constant
 // offsets, and the second step reads slot n - e_i, again one address with
 // constant offsets.  In the window layout (FP64 D2Q9 thermal, whose halo
-// planes would cost a workgroup per CU) plane i holds exactly the 64 x TY
+// planes would take more than half a CU's LDS) plane i holds exactly the 64 x TY
 // window the tile pulls (the tile shifted by -e_i), indexed by the pulling
 // node, and a first-step node writes population i to n + e_i when that
 // lies in the tile.  Where the link into tile node n crosses a
@@ -237,7 +237,7 @@ struct Fuse2 {
     // populations without a test, and tile node n pulls population i from
     // slot n - e_i.  Otherwise plane i holds only the 64 x TY window the
     // tile pulls, indexed by the pulling node; FP64 D2Q9 thermal keeps it,
-    // since its larger planes would cost a workgroup per CU.
+    // since its halo planes would take more than half the LDS of a CU.
     static constexpr bool HALO = !(std::is_same<S, double>::value && NG == 9);
     static constexpr int PLANE = HALO ? SLOTS : TX * TY;   // LDS values per population
     static_assert(NP * PLANE * (int)sizeof(R) <= 81920, "fused tile needs more than half the LDS of a CU");
