@@ -191,10 +191,11 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // per XCD (LBM_POLICY_XCD_STRIPS) are within a few percent either way and
 // left to the autotuner.  Fused pairs of steps (LBM_POLICY_FUSE2) win for
 // FP64 and FP32 at every size measured (1024^2 to 4096^2: FP64 1.6x to
-// 1.9x, FP32 1.3x to 1.7x over the best single step); FP16 keeps single
-// steps, which win from 2048^2 up for every model but D2Q5 at 4096^2 (its
-// fused kernel is bound by the latency of decoding and re-rounding).
-// Fused pairs run best with XCD bands.
+// 1.9x, FP32 1.4x to 1.7x over the best single step).  FP16 keeps single
+// steps: they win where the state stays in the last-level cache (2048^2
+// D2Q5, 235 MB: 16%) and for the flow alone; fused pairs win for the
+// thermal models at other sizes and are one lbm_set_launch away.  Fused
+// pairs run best with XCD bands.
 static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
