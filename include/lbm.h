@@ -297,9 +297,10 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           run singly (lbm_steps_per_launch tells which).
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; fused pairs for FP64 and FP32
- * storage, with bands, or strips once one row of fused tiles (tiles and
- * halos, every plane) exceeds 3 MiB; for FP16, single steps with bands
- * while F <= 500 MiB. */
+ * storage, and for FP16 storage with a temperature field unless
+ * 128 MiB < F <= 256 MiB, with bands, or strips once one row of fused
+ * tiles (tiles and halos, every plane) exceeds 3 MiB; otherwise (FP16)
+ * single steps with bands while F <= 500 MiB. */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
@@ -364,11 +365,11 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
 
 /* Fused pairs of time steps for the whole batch (the two-step kernel of
  * lbm_set_launch's LBM_POLICY_FUSE2, one launch per pair for all members,
- * 64 x TY tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
+ * 64 x 8 tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
  * or LBM_POLICY_FUSE2.  The default fuses pairs for FP64 and FP32
- * storage and steps FP16 once per launch, as for a single lattice.  Fused pairs apply only
+ * storage and steps FP16 once per launch.  Fused pairs apply only
  * when every member qualifies (buffers below 4 GiB; with walls by
- * non-equilibrium extrapolation, nx % 64 != 1 and ny % TY != 1); else the
+ * non-equilibrium extrapolation, nx % 64 != 1 and ny % 8 != 1); else the
  * batch steps one launch per step.  Results are bitwise the same either
  * way.  Takes effect at the next lbm_batch_step.  LBM_ERR_ARG for any
  * other value. */

@@ -191,16 +191,18 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // per XCD (LBM_POLICY_XCD_STRIPS) are within a few percent either way and
 // left to the autotuner.  Fused pairs of steps (LBM_POLICY_FUSE2) win for
 // FP64 and FP32 at every size measured (1024^2 to 4096^2: FP64 1.6x to
-// 1.9x, FP32 1.4x to 1.7x over the best single step).  FP16 keeps single
-// steps: they win where the state stays in the last-level cache (2048^2
-// D2Q5, 235 MB: 16%) and for the flow alone; fused pairs win for the
-// thermal models at other sizes and are one lbm_set_launch away.  Fused
+// 1.9x, FP32 1.4x to 1.7x over the best single step).  FP16 fuses with a
+// temperature field (512^2 to 4096^2: 8-49% over single steps) except for
+// states of 128-256 MiB, which stay in the last-level cache under kept
+// single stores (2048^2 D2Q5, 235 MB: 16% faster than fused pairs); without
+// temperature FP16 keeps single steps, which win from 1024^2 up.  Fused
 // pairs run best with XCD bands.
 static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
     h->L.order = (ws <= 500.0 * mib || (h->storage == LBM_F64 && ws <= 1024.0 * mib)) ? 1 : 0;
-    h->L.fuse2 = h->storage == LBM_F64 || h->storage == LBM_F32;
+    h->L.fuse2 = h->storage == LBM_F64 || h->storage == LBM_F32 ||
+                 (h->storage == LBM_F16 && h->ng > 0 && !(ws > 128.0 * mib && ws <= 256.0 * mib));
     if (h->L.fuse2) {
         // Bands keep the halo rows a fused tile shares with the tile row
         // below in the XCD's 4 MB L2 while one row of tiles (tile and halo,

@@ -158,10 +158,16 @@ def test_xcd_strips_order_does_not_change_results(launch):
     assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
 
 
-@pytest.mark.parametrize("n,storage,policy", [(64, "f64", 11), (2048, "f64", 9), (2048, "f32", 9), (1024, "f32", 11),
-                                              (2048, "f16", 3), (3072, "f16", 0), (4096, "f16", 0), (4096, "f64", 12)])
-def test_default_policy_follows_footprint(n, storage, policy):
-    S = lbm.Solver(n, n, storage)
+@pytest.mark.parametrize("n,storage,model,policy", [
+    (64, "f64", "d2q5", 11), (2048, "f64", "d2q5", 9), (2048, "f32", "d2q5", 9), (1024, "f32", "d2q5", 11),
+    (4096, "f64", "d2q5", 12),
+    # FP16: fused pairs with a temperature field unless the state is 128-256 MiB (2048^2 D2Q5: 235 MB)
+    (1024, "f16", "d2q5", 11), (2048, "f16", "d2q5", 3), (2048, "f16", "d2q9t", 9), (3072, "f16", "d2q5", 9),
+    (4096, "f16", "d2q5", 9),
+    # FP16 without temperature: single steps (bands while the state is <= 500 MiB)
+    (1024, "f16", "isothermal", 3), (4096, "f16", "isothermal", 0)])
+def test_default_policy_follows_footprint(n, storage, model, policy):
+    S = lbm.Solver(n, n, storage, model=model)
     assert S.get_launch()[3] == policy
     S.set_launch(policy=lbm.LBM_POLICY_XCD_BANDS)
     assert S.get_launch()[3] == lbm.LBM_POLICY_XCD_BANDS
