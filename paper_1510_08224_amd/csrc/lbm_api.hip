@@ -73,8 +73,9 @@ struct lbm_batch {
     size_t cap_members = 0, cap_tiles = 0;
     int ntiles = 0;
     // Fused pairs of steps: the policy asked for (LBM_POLICY_DEFAULT, 0 or
-    // LBM_POLICY_FUSE2), whether the current members use them, whether
-    // their stores keep the default cache policy, and the 64 x TY tile table.
+    // LBM_POLICY_FUSE2), whether the current members use them, whether the
+    // stores of either kernel keep the default cache policy (all members'
+    // buffers within the 256 MB last-level cache), and the 64 x 8 tile table.
     int policy = LBM_POLICY_DEFAULT;
     bool fuse = false, keep = false;
     BatchTile* d_ftiles = nullptr;
@@ -1205,7 +1206,8 @@ static hipError_t batch_launch_steps(lbm_batch* b, int parity, int64_t steps, in
             e = launch_sweep2_batch(b->storage, b->ng, b->keep, b->d_members, b->d_ftiles, b->nftiles, parity, b->stream);
             steps -= 2;
         } else {
-            e = launch_sweep_batch(b->storage, b->ng, b->buffer, b->d_members, b->d_tiles, b->ntiles, parity, b->stream);
+            e = launch_sweep_batch(b->storage, b->ng, b->buffer, b->keep, b->d_members, b->d_tiles, b->ntiles, parity,
+                                   b->stream);
             steps -= 1;
         }
         if (e != hipSuccess) return e;

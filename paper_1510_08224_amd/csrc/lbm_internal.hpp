@@ -48,8 +48,9 @@ hipError_t launch_sweep2_batch(int storage, int ng, bool keep, const BatchMember
 // memory (read by the kernels).
 hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                         const void* src, void* dst, hipStream_t st);
-hipError_t launch_sweep_batch(int storage, int ng, bool buffer, const BatchMember* members, const BatchTile* tiles,
-                              int ntiles, int parity, hipStream_t st);
+// keep: default-policy stores (the batch's state fits the last-level cache).
+hipError_t launch_sweep_batch(int storage, int ng, bool buffer, bool keep, const BatchMember* members,
+                              const BatchTile* tiles, int ntiles, int parity, hipStream_t st);
 hipError_t launch_residual_batch(int storage, int ng, const BatchMember* members, int nmembers, const BatchTile* tiles,
                                  int ntiles, int parity, double* tile_max, unsigned long long* tile_bad,
                                  double* out2, hipStream_t st);

@@ -975,11 +975,13 @@ hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, con
     return hipSuccess;
 }
 
-hipError_t launch_sweep_batch(int storage, int ng, bool buffer, const BatchMember* members, const BatchTile* tiles,
-                              int ntiles, int parity, hipStream_t st) {
+hipError_t launch_sweep_batch(int storage, int ng, bool buffer, bool keep, const BatchMember* members,
+                              const BatchTile* tiles, int ntiles, int parity, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     LBM_DISPATCH(storage, ng, {
-        if (buffer)
+        if (buffer && keep)
+            hipLaunchKernelGGL((k_sweep_batch<S, NG, kBufferKeep>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+        else if (buffer)
             hipLaunchKernelGGL((k_sweep_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
         else
             hipLaunchKernelGGL((k_sweep_batch<S, NG, kGlobal>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
