@@ -298,9 +298,10 @@ int32_t lbm_model_of(const lbm_solver* h);
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; fused pairs for FP64 and FP32
  * storage, and for FP16 storage with a temperature field unless
- * 128 MiB < F <= 256 MiB, with bands, or strips once one row of fused
- * tiles (tiles and halos, every plane) exceeds 3 MiB; otherwise (FP16)
- * single steps with bands while F <= 500 MiB. */
+ * 128 MiB < F <= 256 MiB, with bands, or strips (with a multiple of 8
+ * tiles per row) once one row of fused tiles (tiles and halos, every
+ * plane) exceeds 3 MiB or an FP64 lattice is 48 or more tiles wide;
+ * otherwise (FP16) single steps with bands while F <= 500 MiB. */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */

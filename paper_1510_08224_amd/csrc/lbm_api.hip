@@ -207,13 +207,16 @@ static void default_policy(lbm_solver* h) {
     if (h->L.fuse2) {
         // Bands keep the halo rows a fused tile shares with the tile row
         // below in the XCD's 4 MB L2 while one row of tiles (tile and halo,
-        // every plane) fits there; past that, strips of 8 tiles per XCD do
-        // (4096^2 FP64 D2Q5, 4.7 MB per tile row: +4%; FP64 D2Q9 thermal,
-        // 3.7 MB: +2%; rows of 1.5-3 MB: bands by up to 18%).
+        // every plane) fits there; past that, strips of 8 tiles per XCD do.
+        // FP64 lattices 48 or more tiles wide take strips at any row size
+        // (3072^2 and 4096^2, every model: +2.3 to +5.4%; at 2048^2 bands
+        // win by up to 7%); FP32 keeps bands below 3 MiB per row (the one
+        // exception measured: D2Q5 at 4096^2, where strips are 4-5% faster).
         const int ty = fuse2_rows(h->storage, h->ng);
         const int tiles_x = (h->nx + 63) / 64;
         const double row = (double)tiles_x * 66.0 * (ty + 2) * (9 + h->ng) * storage_bytes(h->storage);
-        h->L.order = (tiles_x % 8 == 0 && row > 3.0 * mib) ? 2 : 1;
+        const bool strips = row > 3.0 * mib || (h->storage == LBM_F64 && tiles_x >= 48);
+        h->L.order = (tiles_x % 8 == 0 && strips) ? 2 : 1;
     }
 }
 

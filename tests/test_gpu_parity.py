@@ -161,6 +161,8 @@ def test_xcd_strips_order_does_not_change_results(launch):
 @pytest.mark.parametrize("n,storage,model,policy", [
     (64, "f64", "d2q5", 11), (2048, "f64", "d2q5", 9), (2048, "f32", "d2q5", 9), (1024, "f32", "d2q5", 11),
     (4096, "f64", "d2q5", 12),
+    # FP64 48 or more tiles wide: XCD strips at any tile-row size (isothermal 3072^2: 2.2 MB per row)
+    (3072, "f64", "isothermal", 12), (2048, "f64", "isothermal", 9), (3072, "f32", "d2q5", 9),
     # FP16: fused pairs with a temperature field unless the state is 128-256 MiB (2048^2 D2Q5: 235 MB)
     (1024, "f16", "d2q5", 11), (2048, "f16", "d2q5", 3), (2048, "f16", "d2q9t", 9), (3072, "f16", "d2q5", 9),
     (4096, "f16", "d2q5", 9),
