@@ -51,14 +51,22 @@ MUTANTS = {
     "ortho_rates_swapped": ("{1.0, p->s[3], p->s[8], 1.0,", "{1.0, p->s[8], p->s[3], 1.0,"),
     "gram_schmidt_sign": ("v[k][i] -= num / den * MO9[j][i];", "v[k][i] += num / den * MO9[j][i];"),
     "stream_index": ("L->fn[((size_t)ty * nx + tx) * 9 + i]", "L->fn[((size_t)ty * nx + tx) * 9 + OPP9[i]]"),
+    "nee_nusselt_first_order": ("(-3.0 * t[0] + 4.0 * t[1] - t[2]) / 2.0", "(t[1] - t[0])"),
+    "nee_nusselt_midpoint_mean": [("(nee && (k == 0 || k == count - 1)) ? 0.5 * nu : nu", "nu"),
+                                  ("nee ? sum / (count - 1) : sum / count", "sum / count")],
+    "nee_nusselt_full_end_weights": ("(nee && (k == 0 || k == count - 1)) ? 0.5 * nu : nu",
+                                     "(nee && (k == 0 || k == count - 1)) ? 1.0 * nu : nu"),
+    "nee_nusselt_one_end_weight": ("(nee && (k == 0 || k == count - 1)) ? 0.5 * nu : nu",
+                                   "(nee && k == 0) ? 0.5 * nu : nu"),
+    "nee_nusselt_divisor": ("nee ? sum / (count - 1) : sum / count", "sum / count"),
 }
 
 
 def _build(tmp, name, mut):
     src = open(oracle._SRC).read()
-    if mut is not None:
-        assert src.count(mut[0]) >= 1, name
-        src = src.replace(mut[0], mut[1], 1)
+    for old, new in ([] if mut is None else ([mut] if isinstance(mut, tuple) else mut)):
+        assert src.count(old) >= 1, name
+        src = src.replace(old, new, 1)
     c = os.path.join(tmp, f"{name}.c")
     so = os.path.join(tmp, f"lib{name}.so")
     open(c, "w").write(src)
@@ -190,6 +198,17 @@ def _battery(lib):
     yy = np.arange(12) / 11.0
     if not (np.max(np.abs(ux - 0.04 * yy[:, None])) < 1e-12 and np.max(np.abs(T - yy[:, None])) < 1e-12):
         failed.append("nee_couette_exact")
+    # NEE Nusselt number: quadratic in the wall distance, slope quadratic
+    # along the wall (local values and the trapezoidal mean in closed form)
+    pb = W.cavity(7, 1e4, ny=9).replace(bc_flow=(2, 2, 0, 0), bc_temp=(3, 3, 0, 0), length=6.0)
+    yy, xx = np.mgrid[0:9, 0:7].astype(float)
+    a = 0.013 - 0.0011 * yy + 0.00031 * yy ** 2
+    L = oracle.Lattice(pb, T_init=1.0 + a * xx - 0.0021 * xx ** 2, library=lib)
+    mean, _, _, loc = L.nusselt(W.LEFT, local=True)
+    k = np.arange(9.0)
+    if (np.max(np.abs(loc + 6.0 * (0.013 - 0.0011 * k + 0.00031 * k * k))) > 1e-12
+            or abs(mean + 6.0 * (0.013 - 0.0011 * 4 + 0.00031 * (64 / 3 + 1 / 6))) > 1e-12):
+        failed.append("nee_nusselt_quadratic")
     # mirror symmetry of a Rayleigh-Benard cell with a symmetric start
     T = W.rb_initial_temperature(12, 6, amp=1e-2, seed=9)
     T = 0.5 * (T + T[:, ::-1])

@@ -6,6 +6,9 @@ node rows/columns.
 * Linear profiles are exact: plane Couette flow with a moving NEE wall and
   pure conduction between NEE Dirichlet walls (then Nu = 1 with the
   one-sided NEE stencil and trapezoidal mean of Eq. 39).
+* The NEE Nusselt number is exact, node by node and in its trapezoidal
+  mean, for temperatures quadratic in the wall distance whose slope varies
+  quadratically along the wall, on each of the four walls.
 * Wall nodes carry exactly the wall temperature and velocity.
 * The body-force channel (Eq. 34) and the wall-injection channel
   (Eqs. 36-37) converge at second order, as the paper states (slopes
@@ -62,6 +65,47 @@ def test_nee_conduction_exact_and_nusselt_one():
     for side in (W.LEFT, W.RIGHT):
         mean, mx, _ = L.nusselt(side)
         assert abs(mean - 1) < 1e-12 and abs(mx - 1) < 1e-12
+
+
+@pytest.mark.parametrize("side", [W.LEFT, W.RIGHT, W.BOTTOM, W.TOP])
+def test_nee_nusselt_exact_for_quadratic_profile(side):
+    """Walls through the nodes (Eq. 39 and the local Nusselt number before
+    it): T = T_w + a(s) d + b d^2, with d the distance of a node from the
+    wall and s its position along the wall, a(s) = a0 + a1 s + a2 s^2.
+    Every second-order one-sided stencil from the wall node recovers
+    dT/dn = a(s) exactly (b != 0 exposes a first-order one), so local Nu is
+    -L (+-a(s)) / dT at every wall node.  The mean over the wall, of length
+    n - 1 between its end nodes, by the trapezoidal rule: for a quadratic
+    in s that is the exact mean plus a2 / 6 (Euler-Maclaurin: the rule's
+    error is h^2/12 (f'(n-1) - f'(0)) and ends there), i.e.
+    a0 + a1 (n-1)/2 + a2 ((n-1)^2/3 + 1/6), which neither the midpoint
+    mean nor other end weights give.  The axis along the wall is periodic,
+    so the rebuild of the walls' nodes touches only the two walls across
+    it; the far wall lies beyond the stencil."""
+    nx, ny = 9, 11
+    vertical = side in (W.LEFT, W.RIGHT)
+    walls = (0, 0, 2, 2) if not vertical else (2, 2, 0, 0)
+    temps = (0, 0, 3, 3) if not vertical else (3, 3, 0, 0)
+    wall_T = (0.9, 0.1, 0.7, 0.2)
+    pb = W.cavity(nx, 1e4, ny=ny).replace(bc_flow=walls, bc_temp=temps, wall_T=wall_T,
+                                         t_hot=0.9, t_cold=0.1, length=(nx if vertical else ny) - 1)
+    tw, a0, a1, a2, b = wall_T[side], 0.013, -0.0011, 0.00031, -0.0021
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(float)
+    d = {W.LEFT: xx, W.RIGHT: nx - 1 - xx, W.BOTTOM: yy, W.TOP: ny - 1 - yy}[side]
+    s = yy if vertical else xx
+    T = tw + (a0 + a1 * s + a2 * s * s) * d + b * d * d
+    L = oracle.Lattice(pb, T_init=T)
+    assert np.max(np.abs(L.moments()[3] - T)[d < 3]) < 1e-14
+    mean, mx, imax, loc = L.nusselt(side, local=True)
+    length, dT = L.derived["length"], L.derived["dT"]
+    sign = 1.0 if side in (W.LEFT, W.BOTTOM) else -1.0
+    n = ny if vertical else nx
+    k = np.arange(n, dtype=float)
+    expect_local = -length * sign * (a0 + a1 * k + a2 * k * k) / dT
+    assert np.allclose(loc, expect_local, rtol=1e-12, atol=1e-13)
+    expect_mean = -length * sign * (a0 + a1 * (n - 1) / 2 + a2 * ((n - 1) ** 2 / 3 + 1 / 6)) / dT
+    assert abs(mean - expect_mean) < 1e-12 * abs(expect_mean)
+    assert imax == int(np.argmax(expect_local)) and abs(mx - expect_local.max()) < 1e-12
 
 
 def test_nee_wall_nodes_carry_wall_values():
