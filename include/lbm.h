@@ -151,14 +151,13 @@ int32_t lbm_abi_version(void);
 const char* lbm_build_info(void);
 
 /* Device bytes a solver of this size, storage and thermal model needs
- * (both population buffers with row and plane padding).  LBM_ERR_ARG for
- * the sizes lbm_create rejects (more than 2^31 nodes, or one population
- * plane of 4 GiB or more), a bad storage or model, or a NULL output. */
+ * (both population buffers with row padding).  LBM_ERR_ARG for the sizes
+ * lbm_create rejects (more than 2^31 nodes, or a row of nodes of 2^31
+ * elements or more), a bad storage or model, or a NULL output. */
 int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, uint64_t* bytes);
 
-/* Create a solver for an nx x ny lattice (nx, ny >= 1, one population
- * plane below 4 GiB: up to about 5.3e8 nodes in FP64) on the current HIP
- * device.  hip_stream: a hipStream_t to launch on, or NULL for a stream the
+/* Create a solver for an nx x ny lattice (nx, ny >= 1, at most 2^31 nodes,
+ * (9 + NG) * nx below 2^31) on the current HIP device.  hip_stream: a hipStream_t to launch on, or NULL for a stream the
  * library creates and owns.  Allocates lbm_required_bytes() of device
  * memory.  *out is set to NULL on failure. */
 int lbm_create(lbm_solver** out, int32_t nx, int32_t ny, int32_t storage, int32_t model, void* hip_stream);

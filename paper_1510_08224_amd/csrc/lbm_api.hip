@@ -120,15 +120,20 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 static int model_ng(int model) { return model == LBM_MODEL_D2Q5 ? 5 : (model == LBM_MODEL_D2Q9T ? 9 : 0); }
 static bool model_ok(int model) { return model >= LBM_MODEL_D2Q5 && model <= LBM_MODEL_ISOTHERMAL; }
 
-// Row pitch: whole 256-byte segments; planes start on 4 KiB boundaries;
-// 9 + NG planes per buffer.
-static void layout(int nx, int ny, int storage, int ng, int* pitch, long long* plane, size_t* buf_bytes) {
+// Rows interleaved by population: row y of the buffer holds row y of each of
+// the 9 + NG populations in turn, each padded to whole 256-byte segments
+// (`plane` elements); a row of nodes takes pitch = (9 + NG) * plane
+// elements, and the buffer ny rows, rounded up to 4 KiB.
+// False if a row of nodes would take 2^31 elements or more (the kernels
+// hold the row pitch in 32 bits).
+static bool layout(int nx, int ny, int storage, int ng, int* pitch, long long* plane, size_t* buf_bytes) {
     const size_t b = storage_bytes(storage);
     const size_t p = align_up((size_t)nx, 256 / b);
-    const size_t pl = align_up(p * (size_t)ny, 4096 / b);
-    *pitch = (int)p;
-    *plane = (long long)pl;
-    *buf_bytes = (size_t)(9 + ng) * pl * b;
+    const size_t row = (size_t)(9 + ng) * p;
+    *pitch = row < (1ull << 31) ? (int)row : 0;
+    *plane = (long long)p;
+    *buf_bytes = align_up(row * (size_t)ny * b, 4096);
+    return row < (1ull << 31);
 }
 
 extern "C" {
@@ -173,9 +178,8 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
     int pitch;
     long long plane;
     size_t bb;
-    layout(nx, ny, storage, model_ng(model), &pitch, &plane, &bb);
-    if ((unsigned long long)plane * storage_bytes(storage) >= (1ull << 32))
-        return fail(nullptr, LBM_ERR_ARG, "lbm_required_bytes: one population plane would exceed 4 GiB");
+    if (!layout(nx, ny, storage, model_ng(model), &pitch, &plane, &bb))
+        return fail(nullptr, LBM_ERR_ARG, "lbm_required_bytes: a row of nodes would take 2^31 elements or more");
     *bytes = 2 * (uint64_t)bb;
     return LBM_OK;
 }
@@ -261,14 +265,12 @@ static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t stora
     h->storage = storage;
     h->model = model;
     h->ng = model_ng(model);
-    layout(nx, ny, storage, h->ng, &h->G.pitch, &h->G.plane, &h->buf_bytes);
+    if (!layout(nx, ny, storage, h->ng, &h->G.pitch, &h->G.plane, &h->buf_bytes)) {
+        delete h;
+        return fail(nullptr, LBM_ERR_ARG, "lbm_create: a row of nodes would take 2^31 elements or more");
+    }
     h->G.nx = nx;
     h->G.ny = ny;
-    // Kernels address a plane with 32-bit byte offsets.
-    if ((unsigned long long)h->G.plane * storage_bytes(storage) >= (1ull << 32)) {
-        delete h;
-        return fail(nullptr, LBM_ERR_ARG, "lbm_create: one population plane would exceed 4 GiB");
-    }
     const uint64_t need = 2 * (uint64_t)h->buf_bytes;
     if (dev_buf) {
         if (bytes < need) {

@@ -56,6 +56,12 @@ __device__ __forceinline__ int xcd_remap(int b, int n, int order, int tiles_x) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Bytes of one population buffer: ny rows of pitch elements.
+template <class S>
+static unsigned long long buffer_bytes(const Geom& G) {
+    return (unsigned long long)G.ny * (unsigned long long)G.pitch * sizeof(S);
+}
+
 template <class S, int NG>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, const Geom& G, const Coeffs& C, unsigned boff,
                                            const typename Codec<S>::R f[9],
@@ -105,16 +111,22 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
     const bool fast = xw + 63 <= G.nx - 1 && yw >= 1 && yw + ROWS - 1 <= G.ny - 2;
     if (fast) {
         R f[ROWS][9], g[ROWS][gdim(NG)];
+        // buffer modes: byte offset of the node in its buffer (below 4 GiB);
+        // 64-bit addresses: the row's offset goes into the pointer, the
+        // lane offset is the node's byte offset within the row
         unsigned boff[ROWS];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) boff[r] = (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S);
+        for (int r = 0; r < ROWS; ++r)
+            boff[r] = MODE != kGlobal ? (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S)
+                                      : (unsigned)x * (unsigned)sizeof(S);
         if (MODE != kGlobal) {
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) pull_interior_buf<S, NG>(rs, G, C, boff[r], f[r], g[r]);
         } else {
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) pull_interior<S, NG>(src, G, C, boff[r], f[r], g[r]);
+            for (int r = 0; r < ROWS; ++r)
+                pull_interior<S, NG>(src + (long long)(y0 + r) * G.pitch, G, C, boff[r], f[r], g[r]);
         }
         if (xw == 0 || xw + 63 == G.nx - 1) {
 #pragma unroll
@@ -129,7 +141,7 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
             else if (MODE == kBufferKeep)
                 store_node_buf<S, NG, kCachePolicyDefault>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
             else
-                store_node<S, NG>(dst, G, C, boff[r], f[r], g[r]);
+                store_node<S, NG>(dst + (long long)(y0 + r) * G.pitch, G, C, boff[r], f[r], g[r]);
         }
         return;
     }
@@ -143,7 +155,8 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
         if (y0 + r < G.ny) {
             const Macro m = macro<R, NG>(f[r], g[r], C);
             collide<R, NG, COLL>(f[r], g[r], m, C);
-            store_node<S, NG>(dst, G, C, (unsigned)((y0 + r) * G.pitch + x) * (unsigned)sizeof(S), f[r], g[r]);
+            store_node<S, NG>(dst + (long long)(y0 + r) * G.pitch, G, C, (unsigned)x * (unsigned)sizeof(S), f[r],
+                              g[r]);
         }
     }
 }
@@ -914,7 +927,7 @@ static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& Ch, cons
     const int nt = tiles_x * tiles_y;
     const S* s = static_cast<const S*>(src);
     S* d = static_cast<S*>(dst);
-    const unsigned long long bytes = (unsigned long long)(9 + NG) * (unsigned long long)G.plane * sizeof(S);
+    const unsigned long long bytes = buffer_bytes<S>(G);
     const dim3 grid(nt), block(L.bx, L.by);
     // strips need a whole number of tiles per XCD in every row
     const int remap = (L.order == kXcdStrips && tiles_x % 8 != 0) ? kXcdBands : L.order;
@@ -949,7 +962,7 @@ template <class S, int NG>
 static hipError_t sweep2_t(const Launch& L, const Geom& G, const Coeffs& Ch, const Coeffs* C, const void* src,
                            void* dst, hipStream_t st) {
     using F = Fuse2<S, NG>;
-    const unsigned long long bytes = (unsigned long long)(9 + NG) * (unsigned long long)G.plane * sizeof(S);
+    const unsigned long long bytes = buffer_bytes<S>(G);
     const int coll = Ch.collision;
     if (!L.buffer || bytes >= (1ull << 32) || coll < kCollMRT || coll > kCollOrtho) return hipErrorInvalidValue;
     const int tiles_x = (G.nx + F::TX - 1) / F::TX;

@@ -40,11 +40,12 @@ def test_abi_version_and_info():
 @pytest.mark.parametrize("model,planes", [("d2q5", 14), ("d2q9t", 18), ("isothermal", 9)])
 @pytest.mark.parametrize("storage,b", [(lbm.LBM_F64, 8), (lbm.LBM_F32, 4), (lbm.LBM_F16, 2)])
 def test_required_bytes(storage, b, model, planes):
-    # two buffers of 9 + NG planes; rows padded to 256 bytes, planes to 4 KiB
+    # two buffers of ny rows; a row holds 9 + NG population rows, each
+    # padded to 256 bytes; a buffer rounded up to 4 KiB
     for nx, ny in [(64, 64), (2048, 2048), (37, 23), (1, 1), (4096, 1024)]:
-        pitch = -(-nx * b // 256) * 256
-        plane = -(-pitch * ny // 4096) * 4096
-        assert lbm.lbm_required_bytes(nx, ny, storage, lbm.MODEL[model]) == 2 * planes * plane
+        seg = -(-nx * b // 256) * 256
+        buf = -(-planes * seg * ny // 4096) * 4096
+        assert lbm.lbm_required_bytes(nx, ny, storage, lbm.MODEL[model]) == 2 * buf
 
 
 def test_required_bytes_rejects_bad_input():
@@ -60,15 +61,19 @@ def test_required_bytes_rejects_bad_input():
 
 def test_required_bytes_rejects_what_create_rejects():
     """Sizes lbm_create refuses get no byte count either: more than 2^31
-    nodes, or one population plane of 4 GiB or more (FP64: 2^29 nodes)."""
+    nodes, or a row of nodes of 2^31 elements or more (the kernels hold the
+    row pitch in 32 bits)."""
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_required_bytes(65536, 32769, lbm.LBM_F64)
     assert e.value.code == lbm.LBM_ERR_ARG
+    # D2Q5: 14 population rows of align(nx, 32) FP64 values
     with pytest.raises(lbm.LbmError) as e:
-        lbm.lbm_required_bytes(32768, 16384, lbm.LBM_F64)
-    assert b"4 GiB" in lbm.lib().lbm_last_error(None)
-    # the same plane in FP32 storage is 2 GiB: accepted
-    assert lbm.lbm_required_bytes(32768, 16384, lbm.LBM_F32) == 2 * 14 * 32768 * 16384 * 4
+        lbm.lbm_required_bytes(153391690, 1, lbm.LBM_F64)
+    assert e.value.code == lbm.LBM_ERR_ARG
+    assert b"2^31 elements" in lbm.lib().lbm_last_error(None)
+    assert lbm.lbm_required_bytes(153391680, 1, lbm.LBM_F64) == 2 * (-(-14 * 153391680 * 8 // 4096) * 4096)
+    # large lattices are limited by device memory only
+    assert lbm.lbm_required_bytes(32768, 16384, lbm.LBM_F64) == 2 * 14 * 32768 * 16384 * 8
 
 
 def test_create_rejects_bad_arguments_before_touching_a_device():
