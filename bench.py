@@ -38,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0              # MI355X HBM3E, published peak
+LLC_BYTES = 256 * 2 ** 20          # MI355X last-level (Infinity) cache
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
 NG = {"d2q5": 5, "d2q9t": 9, "isothermal": 0}   # temperature populations per node
 REDUCE_EVERY = 1000
@@ -120,10 +121,7 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
     nu = S.nusselt(1)[0] if thermal else None
     S.close()
     avg_step_s = sweep_ms / 1e3 / steps
-    # one launch of the step kernel advances `spl` steps (2 with fused pairs)
-    alg_bytes = spl * values_per_node(model) * BYTES[storage] * nodes
     avg_launch_s = spl * avg_step_s
-    achieved = alg_bytes / avg_launch_s / 1e9
     traffic = measured_traffic(storage if model == "d2q5" else f"{model}_{storage}", nodes, spl)
     return {
         "storage": storage,
@@ -138,26 +136,68 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
         "residual_last": r,
         "nonfinite": bad,
         "nu_right_mean": nu,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
-                     "steps_per_launch": spl,
-                     # HBM bytes the counters measured per launch, over the same launch time
-                     "traffic_GBs": None if traffic is None else round(traffic / avg_launch_s / 1e9, 1)},
+        "roofline": roofline(storage, model, nodes, spl, avg_launch_s, traffic),
     }
 
 
-def cpu_baseline(pb, steps: int) -> dict:
+def roofline(storage: str, model: str, nodes: int, spl: int, launch_s: float, traffic) -> dict:
+    """Roofline of one launch of the step kernel.  A launch advances `spl`
+    steps (2 with fused pairs) and must read and write the whole state once:
+    its algorithmic HBM bytes are 2 (9 + NG) values per node whatever `spl`
+    is, and `achieved` is those bytes over the launch time.  The
+    single-step equivalent (spl times that: the bytes one-step launches
+    would move for the same steps) is reported beside it as `effective`.
+    `traffic` is the counter-measured HBM bytes of a launch, or None."""
+    alg_bytes = values_per_node(model) * BYTES[storage] * nodes
+    achieved = alg_bytes / launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+            "steps_per_launch": spl,
+            # HBM bytes the counters measured per launch, over the same launch time
+            "traffic_GBs": None if traffic is None else round(traffic / launch_s / 1e9, 1),
+            # the bytes one-step launches would move for the same steps, over the same time
+            "effective_GBs": round(spl * achieved, 1),
+            "effective_frac": round(spl * achieved / HBM_PEAK_GBS, 4),
+            # both buffers (one read and one written: alg_bytes) within the
+            # 256 MB last-level cache: the bytes are then not all HBM traffic
+            "state_in_last_level_cache": alg_bytes <= LLC_BYTES}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pb, steps: int, steps_all: int) -> dict:
+    """The oracle timed on the host: its serial build on one core, and its
+    OpenMP build (the same source, loops over nodes and rows split across
+    threads, results bitwise equal) on all the cores OpenMP is given."""
     import oracle
 
-    L = oracle.Lattice(pb)
-    t0 = time.perf_counter()
-    L.step(steps)
-    dt = time.perf_counter() - t0
-    return {"value": round(pb.nx * pb.ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{pb.nx}x{pb.ny} cavity Ra={pb.ra:g}, {steps} steps from rest, FP64, "
-                      f"single thread, {dt:.1f} s"}
+    def run(library, n):
+        L = oracle.Lattice(pb, library=library)
+        t0 = time.perf_counter()
+        L.step(n)
+        return time.perf_counter() - t0
+
+    dt1 = run(oracle.lib(), steps)
+    omp = oracle.lib_openmp()
+    threads = int(omp.orc_threads())
+    dtn = run(omp, steps_all)
+    mlups1 = pb.nx * pb.ny * steps / dt1 / 1e6
+    mlupsn = pb.nx * pb.ny * steps_all / dtn / 1e6
+    return {"value": round(mlupsn, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{pb.nx}x{pb.ny} cavity Ra={pb.ra:g}, FP64, from rest: {steps_all} steps on {threads} "
+                      f"OpenMP threads in {dtn:.1f} s; {steps} steps on one thread in {dt1:.1f} s",
+            "single_core": {"value": round(mlups1, 3), "unit": "MLUPS", "cores": 1},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def main():
@@ -173,7 +213,9 @@ def main():
                     help="comparison collision operators to time in the main storage ('none' for none)")
     ap.add_argument("--slabs", default="2,4,8",
                     help="GPU counts whose y-slab share of the lattice to time on this GPU ('none' for none)")
-    ap.add_argument("--cpu-steps", type=int, default=48, help="oracle steps of the CPU baseline (~20 s)")
+    ap.add_argument("--cpu-steps", type=int, default=32, help="oracle steps on one core (~12 s)")
+    ap.add_argument("--cpu-steps-all", type=int, default=160,
+                    help="oracle steps on all cores (OpenMP build; ~5 s on 16 cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=2048, help="cavity side")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows[,policy]")
@@ -206,7 +248,7 @@ def main():
     if args.models != "none":
         for m in args.models.split(","):
             if m and m != "d2q5":
-                mpb = pb if m != "isothermal" else W.lid_cavity(args.n, lbm.viscous_rate(1000.0, args.n, 0.1), 0.1)
+                mpb = pb if m != "isothermal" else W.lid_cavity(args.n, lbm.lbm_rate_for_reynolds(1000.0, args.n, 0.1), 0.1)
                 models[m] = time_storage(args.storage, mpb, args.steps, args.warmup, launch, model=m)
                 models[m]["workload"] = mpb.name
     colls, colls1 = {}, {}
@@ -240,7 +282,7 @@ def main():
         torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
-    cpu = None if args.no_cpu else cpu_baseline(pb, args.cpu_steps)
+    cpu = None if args.no_cpu else cpu_baseline(pb, args.cpu_steps, args.cpu_steps_all)
     out = {
         "metric": "MLUPS & %HBM roofline, FP64 vs FP32/FP16 store; served p50/p99 latency",
         "value": round(main_res["mlups"], 1),

@@ -146,6 +146,14 @@ typedef struct {
  * NULL is ignored. */
 void lbm_params_default(lbm_params* p);
 
+/* Shear relaxation rate for a Reynolds number (Sec. 3.2, the lid-driven
+ * cavity; the viscosity stated after Eq. 20): Re = L u / nu with
+ * nu = c_s^2 (1/s_nu - 1/2), c_s^2 = 1/3, so s_nu = 1 / (1/2 + 3 L u / Re).
+ * re > 0, length > 0, u > 0 (lattice units: L in node spacings, u a wall
+ * speed).  Writes s_nu (in (0, 2)) to *s_nu; LBM_ERR_ARG for other
+ * arguments or a NULL output.  Pure host arithmetic, no device. */
+int lbm_rate_for_reynolds(double re, double length, double u, double* s_nu);
+
 /* Library ABI version (LBM_ABI_VERSION) and a build description string. */
 int32_t lbm_abi_version(void);
 const char* lbm_build_info(void);

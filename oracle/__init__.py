@@ -31,6 +31,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orc_lbm.c")
 _LIB = os.path.join(_HERE, "liborc_lbm.so")
+_LIB_OMP = os.path.join(_HERE, "liborc_lbm_omp.so")
 
 # Interface constants (the same values the C library header uses).
 LEFT, RIGHT, BOTTOM, TOP = 0, 1, 2, 3
@@ -44,13 +45,27 @@ COLL_MRT, COLL_BGK, COLL_ORTHO = 0, 1, 2
 CS2 = 1.0 / 3.0  # D2Q9 lattice sound speed squared (Sec. 2.1, after Eq. 19)
 
 
+_CFLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc: -O2, no FMA contraction."""
+    """Compile the oracle with gcc: -O2, no FMA contraction; also its
+    OpenMP build (the same source and flags plus -fopenmp), which only the
+    CPU timing uses."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-               "-Wall", "-o", _LIB, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
+        subprocess.run(["gcc", *_CFLAGS, "-Wno-unknown-pragmas", "-o", _LIB, _SRC, "-lm"], check=True)
+    if force or not os.path.exists(_LIB_OMP):
+        subprocess.run(["gcc", *_CFLAGS, "-fopenmp", "-o", _LIB_OMP, _SRC, "-lm"], check=True)
     return _LIB
+
+
+def lib_openmp():
+    """The OpenMP build of the oracle (built if missing or stale): loops
+    over nodes and rows split across the OpenMP team; results bitwise those
+    of the serial build."""
+    if not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+        build()
+    return load(_LIB_OMP)
 
 
 class OrcParams(ctypes.Structure):
@@ -92,6 +107,8 @@ def load(path: str):
     L.orc_init_equilibrium.argtypes = [ctypes.c_void_p, dp]
     L.orc_set_state.argtypes = [ctypes.c_void_p, dp, dp]
     L.orc_get_state.argtypes = [ctypes.c_void_p, dp, dp]
+    L.orc_threads.argtypes = []
+    L.orc_threads.restype = ctypes.c_int
     L.orc_time.argtypes = [ctypes.c_void_p]
     L.orc_time.restype = ctypes.c_int64
     L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]

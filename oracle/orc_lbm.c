@@ -553,6 +553,8 @@ static void stream_push(orc_lattice* L) {
     const orc_params* p = &L->p;
     const int nx = p->nx, ny = p->ny, ng = L->ng;
     const int px = axis_periodic_x(p), py = axis_periodic_y(p);
+    /* rows are independent: every target slot has exactly one writer */
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             size_t c = (size_t)y * nx + x;
@@ -609,6 +611,7 @@ static void stream_push(orc_lattice* L) {
 static void collide_all(orc_lattice* L) {
     size_t n = (size_t)L->p.nx * (size_t)L->p.ny;
     const int ng = L->ng;
+#pragma omp parallel for schedule(static)
     for (size_t c = 0; c < n; ++c)
         orc_collide_node(&L->p, L->f + c * 9, L->g + c * ng, L->fp + c * 9, L->gp + c * ng);
 }
@@ -718,3 +721,13 @@ void orc_tables(double* m9, double* mi9, double* n5, double* ni5, double* w9,
 }
 
 size_t orc_params_size(void) { return sizeof(orc_params); }
+
+/* Threads a step uses: 1, or the OpenMP team size in the build with
+ * -fopenmp (the same arithmetic; the loops over nodes and rows split
+ * across threads, each node's values computed as in the serial build). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

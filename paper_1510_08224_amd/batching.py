@@ -174,7 +174,10 @@ def report(count: int = 256, seed: int = 3, steps: int = 2000, base_steps: int =
         "one_launch_per_instance": {"us_per_step": round(t_inst * 1e6, 2), "mlups": round(nodes / t_inst / 1e6, 1),
                                     "steps": base_steps},
         "speedup": round(t_inst / t_batch, 2),
-        "hbm_GBs_batched": round(28 * {"f64": 8, "f32": 4, "f16": 2}[storage] * nodes / t_batch / 1e9, 1),
+        # the state read and written once per launch (of steps_per_launch steps)
+        "hbm_GBs_batched": round(28 * {"f64": 8, "f32": 4, "f16": 2}[storage] * nodes / (spl * t_batch) / 1e9, 1),
+        # what one-step launches would move for the same steps
+        "effective_GBs_batched": round(28 * {"f64": 8, "f32": 4, "f16": 2}[storage] * nodes / t_batch / 1e9, 1),
         "nonfinite_members": int((bad > 0).sum()),
         "autotune": tuned,
     }

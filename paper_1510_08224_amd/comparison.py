@@ -72,7 +72,7 @@ def roughness(ux: np.ndarray, uy: np.ndarray) -> float:
 def lid_cavity_run(coll: int, n: int = 80, re: float = 1200.0, u0: float = 0.1, steps: int = 400000,
                    check_every: int = 10000) -> dict:
     # walls through the edge nodes: the cavity side is n - 1 spacings
-    pb = W.with_nee_walls(W.lid_cavity(n, lbm.viscous_rate(re, n - 1, u0), u0)).replace(collision=coll)
+    pb = W.with_nee_walls(W.lid_cavity(n, lbm.lbm_rate_for_reynolds(re, n - 1, u0), u0)).replace(collision=coll)
     S = lbm.Solver(n, n, "f64", model="isothermal")
     S.set_params(pb)
     S.residual()

@@ -163,6 +163,14 @@ void lbm_params_default(lbm_params* p) {
     p->wall_T[LBM_RIGHT] = 0.0;
 }
 
+// Sec. 3.2: Re = L u / nu, nu = (1/s_nu - 1/2) / 3.
+int lbm_rate_for_reynolds(double re, double length, double u, double* s_nu) {
+    if (!s_nu || !(re > 0.0) || !(length > 0.0) || !(u > 0.0) || !isfinite(re) || !isfinite(length) || !isfinite(u))
+        return fail(nullptr, LBM_ERR_ARG, "lbm_rate_for_reynolds: Re, length and u must be finite and positive");
+    *s_nu = 1.0 / (0.5 + 3.0 * length * u / re);
+    return LBM_OK;
+}
+
 int32_t lbm_abi_version(void) { return LBM_ABI_VERSION; }
 
 const char* lbm_build_info(void) {

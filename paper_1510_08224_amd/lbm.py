@@ -66,6 +66,7 @@ _D = ctypes.POINTER(ctypes.c_double)
 _SIGS = {
     "lbm_params_default": (None, [ctypes.POINTER(LbmParams)]),
     "lbm_abi_version": (ctypes.c_int32, []),
+    "lbm_rate_for_reynolds": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]),
     "lbm_build_info": (ctypes.c_char_p, []),
     "lbm_required_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_uint64)]),
@@ -167,10 +168,11 @@ def lbm_params_default() -> LbmParams:
     return p
 
 
-def viscous_rate(re: float, length: float, u: float) -> float:
-    """s_nu for a Reynolds number Re = L u / nu with nu = (1/s_nu - 1/2) / 3
-    (lattice units; the rate map of the lid-driven cavity, Sec. 3.2)."""
-    return 1.0 / (0.5 + 3.0 * length * u / re)
+def lbm_rate_for_reynolds(re: float, length: float, u: float) -> float:
+    """s_nu for a Reynolds number (the library's rate map of Sec. 3.2)."""
+    s = ctypes.c_double()
+    _check(lib().lbm_rate_for_reynolds(float(re), float(length), float(u), ctypes.byref(s)))
+    return s.value
 
 
 def lbm_params_from_problem(pb) -> LbmParams:

@@ -32,13 +32,14 @@ import numpy as np
 from . import lbm
 from . import workloads as W
 
-F32_POP_BYTES = 2 * 14 * 4        # two buffers of 14 populations (FP32 storage)
 SNAPSHOT_BYTES = 3 * 8            # residual snapshot per node
+STORAGE = {"f64": lbm.LBM_F64, "f32": lbm.LBM_F32, "f16": lbm.LBM_F16}
 
 
-def request_bytes(pb, storage: int = lbm.LBM_F32) -> int:
-    """HBM a resident solve needs: population buffers and residual state."""
-    return lbm.lbm_required_bytes(pb.nx, pb.ny, storage) + SNAPSHOT_BYTES * pb.nx * pb.ny + 64 * 1024
+def request_bytes(pb, storage: str) -> int:
+    """HBM a resident solve needs in the given storage ("f64", "f32",
+    "f16"): population buffers and residual state."""
+    return lbm.lbm_required_bytes(pb.nx, pb.ny, STORAGE[storage]) + SNAPSHOT_BYTES * pb.nx * pb.ny + 64 * 1024
 
 
 def initial_temperature(req: W.Request):
@@ -142,6 +143,7 @@ class Server:
                  check_every: int = 1000, cap: int = 30000, graph_steps: int = 50, keep_fields: bool = False):
         self.budget = hbm_budget
         self.max_slots = max_slots
+        self.storage = storage
         self.tol, self.check_every, self.cap = tol, check_every, cap
         self.keep_fields = keep_fields
         self.B = lbm.Batch(storage)
@@ -151,7 +153,7 @@ class Server:
         self.refused = 0
 
     def fits(self, req) -> bool:
-        return len(self.active) < self.max_slots and self.used + request_bytes(req.problem) <= self.budget
+        return len(self.active) < self.max_slots and self.used + request_bytes(req.problem, self.storage) <= self.budget
 
     def admit(self, req, now: float) -> int:
         pb = req.problem
@@ -162,7 +164,7 @@ class Server:
             S.init_temperature(T)
         S.residual()
         slot = self.B.add(S)
-        nbytes = request_bytes(pb)
+        nbytes = request_bytes(pb, self.storage)
         self.used += nbytes
         res = Result(req.rid, req.kind, pb.nx, pb.ny, req.arrival, start=now)
         self.active[slot] = (S, req, res, nbytes)
@@ -183,8 +185,8 @@ class Server:
 
     def run(self, requests) -> dict:
         pending = sorted(requests, key=lambda r: r.arrival)
-        never = [r for r in pending if request_bytes(r.problem) > self.budget]
-        pending = [r for r in pending if request_bytes(r.problem) <= self.budget]
+        never = [r for r in pending if request_bytes(r.problem, self.storage) > self.budget]
+        pending = [r for r in pending if request_bytes(r.problem, self.storage) <= self.budget]
         self.refused = len(never)
         done: list[Result] = []
         t0 = time.perf_counter()

@@ -92,7 +92,7 @@ def sweep(sizes, models, storages, md: str | None = None):
     for n in sizes:
         for model in models:
             pb = (W.cavity(n, 1e6) if model != "isothermal"
-                  else W.lid_cavity(n, lbm.viscous_rate(1000.0, n, 0.1), 0.1))
+                  else W.lid_cavity(n, lbm.lbm_rate_for_reynolds(1000.0, n, 0.1), 0.1))
             for st in storages:
                 S = lbm.Solver(n, n, st, model=model)
                 S.set_params(pb)

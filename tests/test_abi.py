@@ -104,3 +104,18 @@ def test_problem_marshalling():
     p = lbm.lbm_params_from_problem(pb)
     assert p.ra == 1e5 and p.u_c == 0.1 and list(p.bc_flow) == [0, 0, 1, 1]
     assert list(p.bc_temp) == [0, 0, 1, 1] and list(p.wall_T) == [0.0, 0.0, 1.0, 0.0]
+
+
+def test_rate_for_reynolds_matches_the_oracle():
+    """The library's Reynolds-number rate map (Sec. 3.2) against the
+    oracle's, which its own pin ties to Re = L u / nu."""
+    import oracle
+    for re, length, u in [(1000.0, 2048, 0.1), (1200.0, 79, 0.1), (100.0, 72, 0.1), (3.5, 10, 0.05)]:
+        s = lbm.lbm_rate_for_reynolds(re, length, u)
+        assert 0 < s < 2
+        assert abs(s - oracle.rate_for_reynolds(re, length, u)) <= 1e-15 * s
+    for bad in [(0.0, 10, 0.1), (100.0, 0, 0.1), (100.0, 10, 0.0), (float("nan"), 10, 0.1),
+                (float("inf"), 10, 0.1), (-1.0, 10, 0.1)]:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_rate_for_reynolds(*bad)
+        assert e.value.code == lbm.LBM_ERR_ARG

@@ -53,3 +53,26 @@ def test_source_hash_covers_the_library_sources():
     h = bench.kernel_source_hash()
     assert len(h) == 16 and int(h, 16) >= 0
     assert h == bench.kernel_source_hash()
+
+
+def test_roofline_counts_the_state_once_per_launch():
+    # a fused FP64 pair on 2048^2 in 172 us: the state (14 values read and
+    # written per node) crosses HBM once per launch of two steps
+    n = 2048 * 2048
+    r = bench.roofline("f64", "d2q5", n, 2, 172e-6, 943e6)
+    assert r["algorithmic_bytes_per_launch"] == 28 * 8 * n
+    assert abs(r["achieved"] - 28 * 8 * n / 172e-6 / 1e9) < 0.1
+    assert r["frac"] == round(r["achieved"] / 8000.0, 4) and r["frac"] < 1
+    assert abs(r["effective_GBs"] - 2 * r["achieved"]) < 0.2 and r["effective_frac"] > 1
+    assert abs(r["traffic_GBs"] - 943e6 / 172e-6 / 1e9) < 0.1
+    assert r["state_in_last_level_cache"] is False
+    # one step per launch: effective equals achieved
+    r1 = bench.roofline("f64", "d2q5", n, 1, 160e-6, None)
+    assert r1["effective_GBs"] == r1["achieved"] and r1["traffic_GBs"] is None
+    # the FP16 2048^2 state (235 MB for both buffers) fits the 256 MB last-level cache
+    assert bench.roofline("f16", "d2q5", n, 1, 40e-6, None)["state_in_last_level_cache"] is True
+    assert bench.roofline("f32", "d2q5", n, 2, 96e-6, None)["state_in_last_level_cache"] is False
+
+
+def test_cpu_model_string():
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()

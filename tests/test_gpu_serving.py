@@ -35,7 +35,7 @@ def test_each_result_equals_the_solve_alone():
 
 def test_budget_and_slots_bound_residency():
     reqs = _requests()
-    need = sorted(serving.request_bytes(r.problem) for r in reqs)
+    need = sorted(serving.request_bytes(r.problem, "f32") for r in reqs)
     budget = need[-1] + need[-2] // 2        # never two of the largest at once
     srv = serving.Server(hbm_budget=budget, max_slots=2, tol=1e-6, check_every=500, cap=1500)
     peak_slots, peak_bytes = 0, 0
@@ -57,9 +57,9 @@ def test_budget_and_slots_bound_residency():
 
 def test_request_larger_than_budget_is_refused():
     reqs = _requests()
-    smallest = min(serving.request_bytes(r.problem) for r in reqs)
+    smallest = min(serving.request_bytes(r.problem, "f32") for r in reqs)
     srv = serving.Server(hbm_budget=smallest, max_slots=4, tol=1e-6, check_every=500, cap=500)
     run = srv.run(reqs)
     srv.close()
-    assert run["refused"] == sum(serving.request_bytes(r.problem) > smallest for r in reqs)
+    assert run["refused"] == sum(serving.request_bytes(r.problem, "f32") > smallest for r in reqs)
     assert len(run["results"]) == len(reqs) - run["refused"]
