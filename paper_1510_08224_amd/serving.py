@@ -24,6 +24,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import sys
 import time
 from dataclasses import dataclass, field
 
@@ -240,19 +241,20 @@ def summarize(results, wall, lup) -> dict:
 
 def benchmark(count: int = 32, rates=(0.5, 1.0, 2.0, 4.0), seed: int = 4, cap: int = 100000,
               tol: float = 1e-7, check_every: int = 1000, budget_gib: float = 2.0, max_slots: int = 64,
-              n_range=(64, 1024), live_serial_rate: float | None = 1.0) -> dict:
-    base = W.request_stream(count, 1.0, seed=seed, n_range=n_range)
+              n_range=(64, 1024), live_serial_rate: float | None = 1.0, ra_range=(1e3, 1e6),
+              storage: str = "f32") -> dict:
+    base = W.request_stream(count, 1.0, seed=seed, n_range=n_range, ra_range=ra_range)
     # service time of each request alone (the plain method), measured once
     service, lup_serial, serial_results = {}, 0, {}
     for req in base:
         t0 = time.perf_counter()
-        res = solve_alone(req, tol, check_every, cap)
+        res = solve_alone(req, tol, check_every, cap, storage)
         service[req.rid] = time.perf_counter() - t0
         lup_serial += req.problem.nx * req.problem.ny * res.steps
         serial_results[req.rid] = res
     mu = count / sum(service.values())     # serial solves per second
     out = {"workload": f"serve{count}_seed{seed}_cap{cap}", "count": count, "sides": list(n_range),
-           "cap_steps": cap, "tol": tol,
+           "ra_range": list(ra_range), "storage": storage, "cap_steps": cap, "tol": tol,
            "check_every": check_every, "hbm_budget_bytes": int(budget_gib * 2 ** 30), "max_slots": max_slots,
            "serial_service_rate_per_s": round(mu, 4),
            "serial_mlups": round(lup_serial / sum(service.values()) / 1e6, 1),
@@ -261,8 +263,9 @@ def benchmark(count: int = 32, rates=(0.5, 1.0, 2.0, 4.0), seed: int = 4, cap: i
            "rates": []}
     for f in rates:
         lam = f * mu
-        reqs = W.request_stream(count, lam, seed=seed, n_range=n_range)
-        srv = Server(int(budget_gib * 2 ** 30), max_slots, tol=tol, check_every=check_every, cap=cap)
+        reqs = W.request_stream(count, lam, seed=seed, n_range=n_range, ra_range=ra_range)
+        srv = Server(int(budget_gib * 2 ** 30), max_slots, storage=storage, tol=tol, check_every=check_every,
+                     cap=cap)
         run = srv.run(reqs)
         srv.close()
         batched = summarize(run["results"], run["wall"], run["lup"])
@@ -278,7 +281,7 @@ def benchmark(count: int = 32, rates=(0.5, 1.0, 2.0, 4.0), seed: int = 4, cap: i
                  "serial": serial, "same_steps_as_alone": f"{same}/{len(run['results'])}"}
         if live_serial_rate is not None and abs(f - live_serial_rate) < 1e-12:
             # the plain method run live at this rate, to check the FIFO model
-            live = serve_serial(reqs, tol, check_every, cap)
+            live = serve_serial(reqs, tol, check_every, cap, storage)
             wall = max(r.finish for r in live)
             lup = sum(r.nx * r.ny * r.steps for r in live)
             entry["serial_live"] = summarize(live, wall, lup)
@@ -293,7 +296,9 @@ def markdown(res: dict, command: str) -> str:
     out = ["# Continuous-batching solve server vs the plain method (MI355X)", "", "Command:", "", "```", command,
            "```", "",
            f"Workload `{res['workload']}`: {res['count']} requests (cavity and Rayleigh-Benard solves, 50/50, "
-           f"sides {res.get('sides', ['?', '?'])[0]}-{res.get('sides', ['?', '?'])[1]}, FP32 storage), Poisson arrivals at a rate factor times the measured serial service rate "
+           f"sides {res['sides'][0]}-{res['sides'][1]}, Ra log-uniform in [{res['ra_range'][0]:g}, "
+           f"{res['ra_range'][1]:g}], {res['storage'].upper()} storage), Poisson arrivals at a rate factor times the "
+           f"measured serial service rate "
            f"({res['serial_service_rate_per_s']} solves/s). A request stops when its residual over "
            f"{res['check_every']} steps falls below {res['tol']:g} or at {res['cap_steps']} steps (serial status "
            f"{res['serial_status']}). HBM budget {res['hbm_budget_bytes'] / 2 ** 30:g} GiB, at most "
@@ -301,13 +306,13 @@ def markdown(res: dict, command: str) -> str:
            f"default launch; its latencies follow a FIFO queue over the measured per-request service times.",
            "",
            "| rate factor | arrivals/s | batched p50 s | batched p99 s | batched solves/s | batched MLUPS "
-           "| plain p50 s | plain p99 s | plain MLUPS | same steps as alone |",
-           "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---|"]
+           "| plain p50 s | plain p99 s | plain MLUPS | same steps as alone | batched status |",
+           "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---|---|"]
     for e in res["rates"]:
         b, s = e["batched"], e["serial"]
         out.append(f"| {e['rate_factor']} | {e['arrival_rate_per_s']} | {b['p50_latency_s']} | {b['p99_latency_s']} "
                    f"| {b['solves_per_s']} | {b['mlups']} | {s['p50_latency_s']} | {s['p99_latency_s']} "
-                   f"| {s['mlups']} | {e['same_steps_as_alone']} |")
+                   f"| {s['mlups']} | {e['same_steps_as_alone']} | {b['status']} |")
     for e in res["rates"]:
         if "serial_live" in e:
             lv, s = e["serial_live"], e["serial"]
@@ -325,16 +330,21 @@ def main():
     ap.add_argument("--cap", type=int, default=100000)
     ap.add_argument("--budget-gib", type=float, default=2.0)
     ap.add_argument("--max-slots", type=int, default=64)
+    ap.add_argument("--nmin", type=int, default=64)
     ap.add_argument("--nmax", type=int, default=1024)
+    ap.add_argument("--ra-min", type=float, default=1e3)
+    ap.add_argument("--ra-max", type=float, default=1e6)
+    ap.add_argument("--storage", default="f32", choices=list(STORAGE))
     ap.add_argument("--md", default=None, help="also write a Markdown summary to this file")
     args = ap.parse_args()
     rates = tuple(float(v) for v in args.rates.split(","))
     res = benchmark(args.count, rates, args.seed, args.cap, budget_gib=args.budget_gib,
-                    max_slots=args.max_slots, n_range=(64, args.nmax))
+                    max_slots=args.max_slots, n_range=(args.nmin, args.nmax), ra_range=(args.ra_min, args.ra_max),
+                    storage=args.storage)
     print(json.dumps(res), flush=True)
     if args.md:
         with open(args.md, "w") as fh:
-            fh.write(markdown(res, "python -m paper_1510_08224_amd.serving"))
+            fh.write(markdown(res, "python -m paper_1510_08224_amd.serving " + " ".join(sys.argv[1:])))
 
 
 if __name__ == "__main__":
