@@ -258,6 +258,20 @@ int lbm_nusselt_local(lbm_solver* h, int32_t side, double* nu_local);
  * FP64.  Synchronizes. */
 int lbm_residual(lbm_solver* h, double* r, int64_t* nonfinite);
 
+/* lbm_residual without allocating device memory, for callers that cannot
+ * allocate (tight serving loops, harnesses that forbid allocation once set
+ * up).  Same inputs, outputs, snapshot semantics and errors as
+ * lbm_residual, and bitwise the same r and *nonfinite; the per-block
+ * partial results and the reduced values go to a static device array of
+ * 1 MiB + 256 bytes that each GPU the library runs on holds until the
+ * process ends.  The handle's residual snapshot must already exist (one
+ * lbm_residual call, or lbm_batch_add, allocates it): LBM_ERR_STATE
+ * otherwise.  Lattices of more than 2^24 nodes (16,777,216: 4096^2) need
+ * more partials than the array holds: LBM_ERR_ARG.  All calls on one GPU
+ * share its array: calls that overlap on one GPU (other threads, or other
+ * streams before a call returns) race.  Synchronizes. */
+int lbm_residual_static(lbm_solver* h, double* r, int64_t* nonfinite);
+
 /* Pre-collision populations at time t in FP64, host arrays
  * f9[9][ny][nx] and g5[NG][ny][nx] with NG = 5, 9 or 0 by thermal model
  * (either may be NULL).  For deviation

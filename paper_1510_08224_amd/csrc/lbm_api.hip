@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +30,7 @@ struct lbm_solver {
     int cur = 0;                 // buffer holding the state of time t
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = -1;             // HIP device current at create
     bool params_set = false;
     lbm_params params{};
     double s_nu = 0, zeta_alpha = 0, gbeta = 0, T0 = 0, length = 0, dT = 0;
@@ -272,6 +274,7 @@ static int create_common(lbm_solver** out, int32_t nx, int32_t ny, int32_t stora
     h->ny = ny;
     h->storage = storage;
     h->model = model;
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
     h->ng = model_ng(model);
     if (!layout(nx, ny, storage, h->ng, &h->G.pitch, &h->G.plane, &h->buf_bytes)) {
         delete h;
@@ -865,6 +868,25 @@ int lbm_nusselt_local(lbm_solver* h, int32_t side, double* nu_local) {
     return nusselt_common(h, side, nu_local, o);
 }
 
+// The residual kernels on the handle's snapshot with the given partials
+// and reduced outputs (2 doubles, device), then the host readout.
+static int residual_run(lbm_solver* h, double* pmax, unsigned long long* pbad, double* out2, const char* who,
+                        double* r, int64_t* nonfinite) {
+    const bool first = !h->snap_valid;
+    hipError_t e = launch_residual(h->storage, h->ng, h->G, h->C, h->buf[h->cur], h->snap, first, pmax, pbad, out2,
+                                   h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "residual kernels");
+    LBM_HIP(h, hipMemcpyAsync(h->host_small + 4, out2, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "residual copy");
+    LBM_HIP(h, hipStreamSynchronize(h->stream), "residual synchronize");
+    h->snap_valid = true;
+    const double rv = first ? INFINITY : h->host_small[4];
+    const int64_t bad = (int64_t)h->host_small[5];
+    if (r) *r = rv;
+    if (nonfinite) *nonfinite = bad;
+    if (bad) return fail(h, LBM_ERR_UNSTABLE, std::string(who) + ": non-finite values in the lattice");
+    return LBM_OK;
+}
+
 int lbm_residual(lbm_solver* h, double* r, int64_t* nonfinite) {
     if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_residual: NULL handle");
     if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_residual: call lbm_set_params first");
@@ -873,19 +895,67 @@ int lbm_residual(lbm_solver* h, double* r, int64_t* nonfinite) {
     if (rc == LBM_OK) rc = ensure(h, reinterpret_cast<void**>(&h->rpart), residual_parts(h->G) * sizeof(double), "residual partials");
     if (rc == LBM_OK) rc = ensure(h, reinterpret_cast<void**>(&h->rbad), residual_parts(h->G) * sizeof(unsigned long long), "residual partials");
     if (rc != LBM_OK) return rc;
-    const bool first = !h->snap_valid;
-    hipError_t e = launch_residual(h->storage, h->ng, h->G, h->C, h->buf[h->cur], h->snap, first, h->rpart, h->rbad,
-                                   h->small + 4, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "residual kernels");
-    LBM_HIP(h, hipMemcpyAsync(h->host_small + 4, h->small + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "residual copy");
-    LBM_HIP(h, hipStreamSynchronize(h->stream), "residual synchronize");
-    h->snap_valid = true;
-    const double rv = first ? INFINITY : h->host_small[4];
-    const int64_t bad = (int64_t)h->host_small[5];
-    if (r) *r = rv;
-    if (nonfinite) *nonfinite = bad;
-    if (bad) return fail(h, LBM_ERR_UNSTABLE, "lbm_residual: non-finite values in the lattice");
-    return LBM_OK;
+    return residual_run(h, h->rpart, h->rbad, h->small + 4, "lbm_residual", r, nonfinite);
+}
+
+// ---------------------------------------------------------------------------
+// The residual without allocation (lbm_residual_static).  Its per-block
+// partial maxima and non-finite counts and the two reduced values live in
+// `scratch`, a static device array that each GPU the library runs on holds
+// until the process ends, instead of buffers the handle allocates on first
+// use.  Host code never passes `scratch` itself (on the host the name is
+// only a stand-in for the device symbol): the device address of each GPU's
+// copy is looked up once, with that GPU current, and kept per device.
+// Every call on one GPU shares that GPU's copy; calls that overlap on one
+// GPU (other threads, or other streams before a call has synchronized)
+// race on it.  Nothing in it needs clearing: each partial is written by its
+// block before the final reduction reads it.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kStaticParts = 65536;   // one partial per 256 nodes: lattices up to 2^24 nodes
+constexpr size_t kStaticOut = (size_t)kStaticParts * (sizeof(double) + sizeof(unsigned long long));
+constexpr size_t kScratchBytes = kStaticOut + 256;   // partials, then the two reduced values
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static hipError_t scratch_on(int dev, char** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int prev = -1;
+        hipError_t e = hipGetDevice(&prev);
+        if (e == hipSuccess && prev != dev) e = hipSetDevice(dev);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<char*>(g_scratch_ptr[dev]);
+    return hipSuccess;
+}
+
+int lbm_residual_static(lbm_solver* h, double* r, int64_t* nonfinite) {
+    if (!h) return fail(nullptr, LBM_ERR_ARG, "lbm_residual_static: NULL handle");
+    if (!h->params_set) return fail(h, LBM_ERR_STATE, "lbm_residual_static: call lbm_set_params first");
+    if (!h->snap)
+        return fail(h, LBM_ERR_STATE, "lbm_residual_static: the handle has no residual snapshot yet "
+                                      "(lbm_residual or lbm_batch_add allocates it)");
+    const int nb = residual_parts(h->G);
+    if (nb > kStaticParts)
+        return fail(h, LBM_ERR_ARG, "lbm_residual_static: " + std::to_string((long long)h->nx * h->ny) +
+                                        " nodes; the static scratch serves lattices of at most 16777216 nodes");
+    if (h->device < 0 || h->device >= kMaxDevices)
+        return fail(h, LBM_ERR_DEVICE, "lbm_residual_static: device id outside 0..63");
+    char* base = nullptr;
+    hipError_t e = scratch_on(h->device, &base);
+    if (e != hipSuccess) return hip_fail(h, e, "lbm_residual_static: address of the static scratch");
+    return residual_run(h, reinterpret_cast<double*>(base),
+                        reinterpret_cast<unsigned long long*>(base + (size_t)kStaticParts * sizeof(double)),
+                        reinterpret_cast<double*>(base + kStaticOut), "lbm_residual_static", r, nonfinite);
 }
 
 int lbm_get_populations(lbm_solver* h, double* f9, double* g5) {

@@ -85,6 +85,7 @@ _SIGS = {
     "lbm_nusselt": (ctypes.c_int, [_P, ctypes.c_int32, _D, _D, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_nusselt_local": (ctypes.c_int, [_P, ctypes.c_int32, _D]),
     "lbm_residual": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
+    "lbm_residual_static": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
     "lbm_get_populations": (ctypes.c_int, [_P, _D, _D]),
     "lbm_set_populations": (ctypes.c_int, [_P, _D, _D]),
     "lbm_state_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
@@ -349,6 +350,16 @@ class Solver:
         r = ctypes.c_double()
         bad = ctypes.c_int64()
         rc = lib().lbm_residual(self.h, ctypes.byref(r), ctypes.byref(bad))
+        if rc != LBM_OK and (rc != LBM_ERR_UNSTABLE or raise_unstable):
+            _check(rc, self.h)
+        return r.value, bad.value
+
+    def residual_static(self, raise_unstable: bool = True):
+        """lbm_residual_static: the residual without allocating device memory
+        (the snapshot must exist: one residual() call allocates it)."""
+        r = ctypes.c_double()
+        bad = ctypes.c_int64()
+        rc = lib().lbm_residual_static(self.h, ctypes.byref(r), ctypes.byref(bad))
         if rc != LBM_OK and (rc != LBM_ERR_UNSTABLE or raise_unstable):
             _check(rc, self.h)
         return r.value, bad.value
