@@ -245,6 +245,7 @@ struct Fuse2 {
     static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
     static constexpr int EH = TY + 2;
     static constexpr int SLOTS = EW * EH;   // nodes of the first step
+    static_assert(SLOTS >= NT, "every thread has a first-step slot");
     // LDS layout.  HALO: plane i holds population i of every slot of the
     // first step (EW x EH, indexed by the slot), so each slot stores all its
     // populations without a test, and tile node n pulls population i from
@@ -419,11 +420,10 @@ __device__ __forceinline__ void fuse2_walls(typename Codec<S>::R* lds, const Geo
 }
 
 // Collide the pulled populations of slot (sl, sm), round them as a store
-// to S would, and keep what the second step pulls.
+// to S would, and keep what the second step pulls (no wall rule).
 template <class S, int NG, int COLL>
-__device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x0, int y0,
-                                           int sl, int sm, typename Codec<S>::R f[9],
-                                           typename Codec<S>::R g[gdim(NG)]) {
+__device__ __forceinline__ void fuse2_keep_open(typename Codec<S>::R* lds, const Coeffs& C, int sl, int sm,
+                                                typename Codec<S>::R f[9], typename Codec<S>::R g[gdim(NG)]) {
     using F = Fuse2<S, NG>;
     using R = typename Codec<S>::R;
     const Macro m = macro<R, NG>(f, g, C);
@@ -432,7 +432,6 @@ __device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom
     for (int i = 0; i < 9; ++i) f[i] = as_stored<S>(f[i], C.fscale, C.finv);
 #pragma unroll
     for (int i = 0; i < NG; ++i) g[i] = as_stored<S>(g[i], C.gscale, C.ginv);
-    const int sx = sl - 1, sy = sm - 1;
     if constexpr (F::HALO) {
         const int at = sm * F::EW + sl;
 #pragma unroll
@@ -440,24 +439,69 @@ __device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom
 #pragma unroll
         for (int i = 0; i < NG; ++i) lds[(9 + i) * F::PLANE + at] = g[i];
     } else {
-        fuse2_put_set<S, NG, 0>(lds, sx, sy, f, std::make_integer_sequence<int, 9>{});
-        if constexpr (NG > 0) fuse2_put_set<S, NG, 9>(lds, sx, sy, g, std::make_integer_sequence<int, NG>{});
+        fuse2_put_set<S, NG, 0>(lds, sl - 1, sm - 1, f, std::make_integer_sequence<int, 9>{});
+        if constexpr (NG > 0) fuse2_put_set<S, NG, 9>(lds, sl - 1, sm - 1, g, std::make_integer_sequence<int, NG>{});
     }
+}
+
+// fuse2_keep_open, then the wall rules of the links into a tile node on a
+// non-periodic side.
+template <class S, int NG, int COLL>
+__device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom& G, const Coeffs& C, int x0, int y0,
+                                           int sl, int sm, typename Codec<S>::R f[9],
+                                           typename Codec<S>::R g[gdim(NG)]) {
+    using F = Fuse2<S, NG>;
+    fuse2_keep_open<S, NG, COLL>(lds, C, sl, sm, f, g);
+    const int sx = sl - 1, sy = sm - 1;
     const int x = x0 + sx, y = y0 + sy;
     const bool in_tile = sx >= 0 && sx < F::TX && sy >= 0 && sy < F::TY;
     const bool wall = (!G.px && (x == 0 || x == G.nx - 1)) || (!G.py && (y == 0 || y == G.ny - 1));
     if (in_tile && wall) fuse2_walls<S, NG>(lds, G, C, x, y, sx, sy, f, g, std::make_integer_sequence<int, 8>{});
 }
 
-// One fused pair of steps on the tile at (x0, y0) of one lattice.
-template <class S, int NG, int MODE, int COLL>
-__device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const S* __restrict__ src,
-                                           S* __restrict__ dst, unsigned buf_bytes, int x0, int y0,
-                                           typename Codec<S>::R* lds) {
+// A tile whose every first-step slot (the tile and its halo, x0 - 1 ..
+// x0 + TX and y0 - 1 .. y0 + TY) has all its neighbours inside the lattice:
+// every slot pulls with the fast path, none is a wall node or wraps, and
+// slot w of the row-major slot grid is w itself.  Such "open" tiles run
+// the same arithmetic as the general path below without its per-slot
+// tests.
+template <class F>
+__device__ __forceinline__ bool open_tile(const Geom& G, int x0, int y0) {
+    return x0 >= 2 && x0 + F::TX <= G.nx - 2 && y0 >= 2 && y0 + F::TY <= G.ny - 2;
+}
+
+// The pre-collision populations of slot w of an open tile.
+template <class S, int NG>
+__device__ __forceinline__ void open_slot_load(__amdgpu_buffer_rsrc_t rs, const Geom& G, const Coeffs& C, int x0,
+                                               int y0, int w, typename Codec<S>::R f[9],
+                                               typename Codec<S>::R g[gdim(NG)]) {
+    using F = Fuse2<S, NG>;
+    const int m = w / F::EW, l = w - m * F::EW;
+    pull_interior_buf<S, NG>(rs, G, C, (unsigned)((y0 - 1 + m) * G.pitch + (x0 - 1 + l)) * (unsigned)sizeof(S), f, g);
+}
+
+// First step of an open tile, the slots of this thread from `first` on
+// (earlier ones done by the caller), into LDS.
+template <class S, int NG, int COLL>
+__device__ __forceinline__ void open_phase1(__amdgpu_buffer_rsrc_t rs, const Geom& G, const Coeffs& C, int x0, int y0,
+                                            int first, typename Codec<S>::R* lds) {
     using F = Fuse2<S, NG>;
     using R = typename Codec<S>::R;
-    // Step t -> t + 1 on the tile and its halo, one slot per thread at a time.
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
+#pragma unroll
+    for (int w = first; w < F::SLOTS; w += F::NT) {
+        R f[9], g[gdim(NG)];
+        open_slot_load<S, NG>(rs, G, C, x0, y0, w, f, g);
+        const int m = w / F::EW;
+        fuse2_keep_open<S, NG, COLL>(lds, C, w - m * F::EW, m, f, g);
+    }
+}
+
+// First step of a general tile (walls, wraps, lattice edges) into LDS.
+template <class S, int NG, int COLL>
+__device__ __forceinline__ void general_phase1(__amdgpu_buffer_rsrc_t rs, const S* __restrict__ src, const Geom& G,
+                                               const Coeffs& C, int x0, int y0, typename Codec<S>::R* lds) {
+    using F = Fuse2<S, NG>;
+    using R = typename Codec<S>::R;
     const SlotOrder o = slot_order<F>(G, x0, y0);
     // o.count <= SLOTS: the bound known at compile time fixes the trip count
 #pragma unroll
@@ -468,19 +512,25 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
         slot_of(o, w, l, m);
         if (fuse2_load<S, NG>(src, rs, G, C, x0, y0, l, m, f, g)) fuse2_keep<S, NG, COLL>(lds, G, C, x0, y0, l, m, f, g);
     }
-    __syncthreads();
+}
 
-    // Step t + 1 -> t + 2 on the tile, pulling from LDS.  Only wall nodes
-    // rebuilt by extrapolation read elsewhere: their fluid neighbour's
-    // pulls, which lie in the tile (the launch rules out one-node edge
-    // tiles on such sides).
+// Second step of a tile, pulling from LDS, and the store.  Only wall
+// nodes rebuilt by extrapolation read elsewhere: their fluid neighbour's
+// pulls, which lie in the tile (the launch rules out one-node edge tiles
+// on such sides).  OPEN: the tile is open, no node is a wall node or off
+// the lattice.
+template <class S, int NG, int MODE, int COLL, bool OPEN>
+__device__ __forceinline__ void fused_phase2(__amdgpu_buffer_rsrc_t rd, const Geom& G, const Coeffs& C, int x0, int y0,
+                                             const typename Codec<S>::R* lds) {
+    using F = Fuse2<S, NG>;
+    using R = typename Codec<S>::R;
     const bool inner = (G.px || (x0 > 0 && x0 + F::TX < G.nx)) && (G.py || (y0 > 0 && y0 + F::TY < G.ny));
-    const bool nee = C.any_nee && !inner;
-    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, buf_bytes);
+    const bool nee = !OPEN && C.any_nee && !inner;
+#pragma unroll
     for (int n = threadIdx.x; n < F::TX * F::TY; n += F::NT) {
         const int ix = n % F::TX, iy = n / F::TX;
         const int x = x0 + ix, y = y0 + iy;
-        if (x >= G.nx || y >= G.ny) continue;
+        if (!OPEN && (x >= G.nx || y >= G.ny)) continue;
         R f[9], g[gdim(NG)];
         if (nee && nee_node_at(G, C, x, y)) {
             const NeeWall w = nee_wall(G, C, x, y);
@@ -502,6 +552,26 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
         const unsigned boff = (unsigned)(y * G.pitch + x) * (unsigned)sizeof(S);
         if (MODE == kBufferKeep) store_node_buf<S, NG, kCachePolicyDefault>(rd, G, C, boff, f, g);
         else store_node_buf<S, NG, kCachePolicyNT>(rd, G, C, boff, f, g);
+    }
+}
+
+// One fused pair of steps on the tile at (x0, y0) of one lattice (the
+// batch kernel's body).
+template <class S, int NG, int MODE, int COLL>
+__device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const S* __restrict__ src,
+                                           S* __restrict__ dst, unsigned buf_bytes, int x0, int y0,
+                                           typename Codec<S>::R* lds) {
+    using F = Fuse2<S, NG>;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, buf_bytes);
+    if (open_tile<F>(G, x0, y0)) {
+        open_phase1<S, NG, COLL>(rs, G, C, x0, y0, threadIdx.x, lds);
+        __syncthreads();
+        fused_phase2<S, NG, MODE, COLL, true>(rd, G, C, x0, y0, lds);
+    } else {
+        general_phase1<S, NG, COLL>(rs, src, G, C, x0, y0, lds);
+        __syncthreads();
+        fused_phase2<S, NG, MODE, COLL, false>(rd, G, C, x0, y0, lds);
     }
 }
 
@@ -940,22 +1010,25 @@ static hipError_t sweep_t(const Launch& L, const Geom& G, const Coeffs& Ch, cons
     return hipGetLastError();
 }
 
+
 int fuse2_rows(int storage, int ng) {
     LBM_DISPATCH(storage, ng, return Fuse2<S, NG>::TY);
     return 0;
 }
 
+template <class S, int NG, int MODE, int COLL>
+static void sweep2_launch1(int ntiles, hipStream_t st, const Geom& G, const Coeffs* C, const S* s, S* d, int tiles_x,
+                           unsigned bytes, int order) {
+    hipLaunchKernelGGL((k_sweep2<S, NG, MODE, COLL>), dim3(ntiles), dim3(Fuse2<S, NG>::NT), 0, st, G, C, s, d, tiles_x,
+                       bytes, order);
+}
+
 template <class S, int NG, int MODE>
-static void sweep2_launch(int coll, dim3 grid, hipStream_t st, const Geom& G, const Coeffs* C, const S* s, S* d,
+static void sweep2_launch(int coll, int ntiles, hipStream_t st, const Geom& G, const Coeffs* C, const S* s, S* d,
                           int tiles_x, unsigned bytes, int order) {
-    const dim3 block(Fuse2<S, NG>::NT);
-    if (coll == kCollBGK)
-        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollBGK>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, order);
-    else if (coll == kCollOrtho)
-        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollOrtho>), grid, block, 0, st, G, C, s, d, tiles_x, bytes,
-                           order);
-    else
-        hipLaunchKernelGGL((k_sweep2<S, NG, MODE, kCollMRT>), grid, block, 0, st, G, C, s, d, tiles_x, bytes, order);
+    if (coll == kCollBGK) sweep2_launch1<S, NG, MODE, kCollBGK>(ntiles, st, G, C, s, d, tiles_x, bytes, order);
+    else if (coll == kCollOrtho) sweep2_launch1<S, NG, MODE, kCollOrtho>(ntiles, st, G, C, s, d, tiles_x, bytes, order);
+    else sweep2_launch1<S, NG, MODE, kCollMRT>(ntiles, st, G, C, s, d, tiles_x, bytes, order);
 }
 
 template <class S, int NG>
@@ -970,11 +1043,12 @@ static hipError_t sweep2_t(const Launch& L, const Geom& G, const Coeffs& Ch, con
     const int order = (L.order == kXcdStrips && tiles_x % 8 != 0) ? kXcdBands : L.order;
     const S* s = static_cast<const S*>(src);
     S* d = static_cast<S*>(dst);
-    const dim3 grid(tiles_x * tiles_y);
-    if (L.keep) sweep2_launch<S, NG, kBufferKeep>(coll, grid, st, G, C, s, d, tiles_x, (unsigned)bytes, order);
-    else sweep2_launch<S, NG, kBufferNT>(coll, grid, st, G, C, s, d, tiles_x, (unsigned)bytes, order);
+    const int ntiles = tiles_x * tiles_y;
+    if (L.keep) sweep2_launch<S, NG, kBufferKeep>(coll, ntiles, st, G, C, s, d, tiles_x, (unsigned)bytes, order);
+    else sweep2_launch<S, NG, kBufferNT>(coll, ntiles, st, G, C, s, d, tiles_x, (unsigned)bytes, order);
     return hipGetLastError();
 }
+
 
 hipError_t launch_sweep2(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st) {
