@@ -61,10 +61,15 @@ enum lbm_status {
 
 /* Population storage in device memory.  LBM_F64 stores the populations
  * themselves and collides in FP64.  LBM_F32 and LBM_F16 store deviations
- * from the rest equilibrium (fbar_i - w_i rho0 and g_i - g_i^eq(T0, 0), the
- * latter scaled by a power of two for FP16) rounded to nearest even, and
- * collide in FP32; the conserved sums (rho, rho0 u, T) are accumulated in
- * FP64 in every mode. */
+ * from a rest equilibrium, rounded to nearest even, and collide in FP32;
+ * the conserved sums (rho, rho0 u, T) are accumulated in FP64 in every
+ * mode.  LBM_F32: fbar_i - w_i rho0 and g_i - g_i^eq(T0, 0).  LBM_F16
+ * (scaled by powers of two): g_i - g_i^eq(T_ref, 0), T_ref the linear
+ * conduction profile between the two link-wise Dirichlet walls of one
+ * axis when the other axis has none (else T0), and, on an x-periodic
+ * lattice with T_ref along y, fbar_i - w_i rho_ref(y) with rho_ref the
+ * hydrostatic density of T_ref (Eq. 4 at rest; else rho0); each value is
+ * stored relative to the reference of the node that pulls it. */
 enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
 
 enum lbm_side { LBM_LEFT = 0, LBM_RIGHT = 1, LBM_BOTTOM = 2, LBM_TOP = 3 };

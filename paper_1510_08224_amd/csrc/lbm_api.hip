@@ -509,16 +509,73 @@ static int derive(lbm_solver* h, const lbm_params* p) {
     C.ay = p->ay;
     C.tshift = dev ? 0.0 : -T0;
     C.toff = dev ? T0 : 0.0;
+    // FP16 reference temperature: the linear conduction profile between the
+    // two link-wise Dirichlet walls of one axis (walls half a spacing
+    // outside the first and last nodes), when the other axis has no
+    // Dirichlet wall and no wall is NEE; tau(p) = T_w0 - T0 + tg (p + 1/2)
+    // along that axis, tg = (T_w1 - T_w0) / n.
+    C.tb = C.tgx = C.tgy = 0.0;
+    for (int i = 0; i < 9; ++i) C.gdc[i] = 0.0f;
+    if (h->storage == LBM_F16 && !iso && !nee) {
+        const bool dx = p->bc_temp[LBM_LEFT] == LBM_T_DIRICHLET && p->bc_temp[LBM_RIGHT] == LBM_T_DIRICHLET;
+        const bool dy = p->bc_temp[LBM_BOTTOM] == LBM_T_DIRICHLET && p->bc_temp[LBM_TOP] == LBM_T_DIRICHLET;
+        const bool ax = p->bc_temp[LBM_LEFT] == LBM_T_DIRICHLET || p->bc_temp[LBM_RIGHT] == LBM_T_DIRICHLET;
+        const bool ay = p->bc_temp[LBM_BOTTOM] == LBM_T_DIRICHLET || p->bc_temp[LBM_TOP] == LBM_T_DIRICHLET;
+        if (dx && !ay) {
+            C.tgx = (p->wall_T[LBM_RIGHT] - p->wall_T[LBM_LEFT]) / (double)h->nx;
+            C.tb = p->wall_T[LBM_LEFT] - T0 + 0.5 * C.tgx;
+        } else if (dy && !ax) {
+            C.tgy = (p->wall_T[LBM_TOP] - p->wall_T[LBM_BOTTOM]) / (double)h->ny;
+            C.tb = p->wall_T[LBM_BOTTOM] - T0 + 0.5 * C.tgy;
+        }
+        for (int i = 0; i < 9; ++i) {
+            const double ci = q9 ? kW9[i] : (i == 0 ? 1.0 - p->varpi : 0.25 * p->varpi);
+            C.gdc[i] = (float)(ci * (C.tgx * ex(i) + C.tgy * ey(i)));
+        }
+    }
+    // FP16, x-periodic, temperature reference along y: the flow populations
+    // are kept relative to the hydrostatic density of that reference,
+    // rho_ref(y) = r0 + rA y + rB y^2 with 1/3 d rho_ref / dy = a_y + g beta
+    // tau(y) (Eq. 4 at rest), r0 making its mean over the rows zero.
+    C.r0 = C.rA = C.rB = 0.0;
+    C.frA = C.frB = 0.0f;
+    if (h->storage == LBM_F16 && C.tgy != 0.0 && p->bc_flow[LBM_LEFT] == LBM_BC_PERIODIC) {
+        C.rA = 3.0 * (p->ay + gbeta * C.tb);
+        C.rB = 1.5 * gbeta * C.tgy;
+        double m1 = 0.0, m2 = 0.0;
+        for (int y = 0; y < h->ny; ++y) {
+            m1 += (double)y;
+            m2 += (double)y * (double)y;
+        }
+        C.r0 = -(C.rA * m1 + C.rB * m2) / (double)h->ny;
+        C.frA = (float)C.rA;
+        C.frB = (float)C.rB;
+    }
     for (int s = 0; s < 4; ++s) {
         for (int i = 0; i < 9; ++i) {
             const double eu = ex(i) * p->wall_u[s][0] + ey(i) * p->wall_u[s][1];
             C.bbf[s][i] = p->bc_flow[s] == LBM_BC_WALL ? 6.0 * kW9[i] * eu : 0.0;
+            // a density reference: the stored opposite population is
+            // relative to the reference one row beyond the wall
+            if (p->bc_flow[s] == LBM_BC_WALL && s == LBM_BOTTOM && ey(i) == 1)
+                C.bbf[s][i] += kW9[i] * (-C.rA + C.rB);
+            if (p->bc_flow[s] == LBM_BC_WALL && s == LBM_TOP && ey(i) == -1)
+                C.bbf[s][i] += kW9[i] * (C.rA + C.rB * (2.0 * h->ny - 1.0));
         }
         // anti-bounce-back: twice the even part of g^eq at the wall (Eq. 30:
         // varpi T_w / 4 per link; Eq. 31: w_i T_w [1 + theta (4.5 (e.u_w)^2 - 1.5 u_w^2)]),
         // minus twice the stored rest part for deviation storage
         const bool dir = p->bc_temp[s] == LBM_T_DIRICHLET;
         C.gsign[s] = dir ? -1.0 : 1.0;
+        // With an FP16 reference temperature the stored opposite population
+        // is relative to the reference of the ghost node one spacing beyond
+        // the wall (the node's own, tau_w, less tgx e_x + tgy e_y for the
+        // pulled direction), and the rule's result must be relative to the
+        // node's own reference (tau_w is the same all along a wall of the
+        // reference axis): a Dirichlet wall's constant loses 2 c_i tau_w
+        // and gains gdc_i, an adiabatic wall's constant is -gdc_i.
+        const int n_side = (s == LBM_LEFT || s == LBM_RIGHT) ? h->nx : h->ny;
+        const double tau_w = (s == LBM_LEFT || s == LBM_BOTTOM) ? C.tb : C.tb + (C.tgx + C.tgy) * (n_side - 1);
         for (int i = 0; i < 9; ++i) {
             double c = 0.0;
             if (dir && i > 0) {
@@ -530,6 +587,10 @@ static int derive(lbm_solver* h, const lbm_params* p) {
                 } else if (i <= 4) {
                     c = dev ? 0.5 * p->varpi * (Tw - T0) : 0.5 * p->varpi * Tw;
                 }
+            }
+            if (C.tgx != 0.0 || C.tgy != 0.0) {
+                if (dir) c += -2.0 * (q9 ? kW9[i] : (i == 0 ? 1.0 - p->varpi : 0.25 * p->varpi)) * tau_w + C.gdc[i];
+                else c -= C.gdc[i];
             }
             C.gconst[s][i] = c;
         }

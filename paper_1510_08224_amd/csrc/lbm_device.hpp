@@ -106,6 +106,25 @@ struct Coeffs {
     double uw[4][2], wT[4];
     // Deviation storage scales (FP16): stored = value * scale.
     float fscale, finv, gscale, ginv;
+    // FP16 storage keeps temperature populations as deviations from the rest
+    // state at a reference temperature T0 + tau(x, y), linear in the node
+    // position: tau = tb + tgx x + tgy y (the conduction profile between the
+    // two Dirichlet walls of one axis; zero otherwise and for other
+    // storage).  A population is stored relative to the reference of the
+    // node that will pull it, so every pull yields deviations relative to
+    // the puller's own rest state: a node subtracts gdc[i] = c_i (tgx e_x +
+    // tgy e_y) from its post-collision g_i before storing it (c_i: the rest
+    // weights of g^eq, Eq. 30 or 31).
+    double tb, tgx, tgy;
+    float gdc[9];
+    // FP16 storage of a lattice periodic in x with its temperature reference
+    // along y also keeps the flow populations as deviations from the
+    // hydrostatic density of that reference, rho0 + r0 + rA y + rB y^2
+    // (1/3 d rho / dy = a_y + g beta tau(y), Eq. 4): w_i (rho(y + e_y) -
+    // rho(y)) comes off f_i before it is stored, (frA, frB: rA, rB in FP32).
+    // Zero otherwise.
+    double r0, rA, rB;
+    float frA, frB;
     int collision;      // 0 the paper's MRT, 1 BGK, 2 orthogonal MRT (Sec. 3.2)
     // The rates above in each collision arithmetic: FP64 storage collides
     // in double, FP32 and FP16 storage in float.
@@ -162,6 +181,47 @@ template <> struct Codec<__half> {
                                     reinterpret_cast<unsigned short*>(p));
     }
 };
+
+// Storage whose temperature deviations are taken from a position-dependent
+// reference (Coeffs::tb, tgx, tgy, gdc): FP16.
+template <class S>
+constexpr bool kRefT = std::is_same<S, __half>::value;
+
+// Reference temperature of node (x, y) above T0 (0 for other storage).
+template <class S>
+__device__ __forceinline__ double tref_at(const Coeffs& C, int x, int y) {
+    if constexpr (kRefT<S>) return C.tb + C.tgx * (double)x + C.tgy * (double)y;
+    else return 0.0;
+}
+
+// Reference density of node row y above rho0 (0 for other storage).
+template <class S>
+__device__ __forceinline__ double rref_at(const Coeffs& C, int y) {
+    if constexpr (kRefT<S>) return C.r0 + C.rA * (double)y + C.rB * (double)y * (double)y;
+    else return 0.0;
+}
+
+// Post-collision populations of a node in row y, in place, into the form
+// they are stored in: relative to the reference of the node that pulls
+// each of them (FP16: temperature by gdc; flow by the change of the
+// hydrostatic reference density over the link, w_i (rho_ref(y + e_y) -
+// rho_ref(y)) = w_i (rA + rB (2y + 1)) up, -w_i (rA + rB (2y - 1)) down).
+template <class S, int NG, class R>
+__device__ __forceinline__ void to_stored(R f[9], R g[NG > 0 ? NG : 1], const Coeffs& C, int y) {
+    if constexpr (kRefT<S>) {
+        const float up = C.frA + C.frB * (float)(2 * y + 1);
+        const float dn = -(C.frA + C.frB * (float)(2 * y - 1));
+        const float a9 = (float)(1.0 / 9.0), a36 = (float)(1.0 / 36.0);
+        f[2] -= a9 * up;
+        f[5] -= a36 * up;
+        f[6] -= a36 * up;
+        f[4] -= a9 * dn;
+        f[7] -= a36 * dn;
+        f[8] -= a36 * dn;
+#pragma unroll
+        for (int i = 1; i < NG; ++i) g[i] -= C.gdc[i];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Pull of one population with link-wise walls (Eqs. 9 and 25).
@@ -376,8 +436,10 @@ struct Macro {
     double Fx, Fy; // force per unit mass
 };
 
-template <class R, int NG>
-__device__ __forceinline__ Macro macro(const R f[9], const R g[NG > 0 ? NG : 1], const Coeffs& C) {
+// REF: the storage takes a reference temperature (kRefT); tau is then the
+// node's reference temperature above T0 (tref_at), ignored otherwise.
+template <class R, int NG, bool REF = false>
+__device__ __forceinline__ Macro macro(const R f[9], const R g[NG > 0 ? NG : 1], const Coeffs& C, double tau = 0.0) {
     Macro m;
     if constexpr (NG == 0) {
         m.Tsum = 0.0;
@@ -392,8 +454,13 @@ __device__ __forceinline__ Macro macro(const R f[9], const R g[NG > 0 ? NG : 1],
             t += (double)g[8];
         }
         m.Tsum = t;
-        m.T = t + C.toff;
-        m.Fy = C.ay + C.gbeta * (t + C.tshift);
+        if constexpr (REF) {
+            m.T = t + C.toff + tau;
+            m.Fy = C.ay + C.gbeta * (t + C.tshift + tau);
+        } else {
+            m.T = t + C.toff;
+            m.Fy = C.ay + C.gbeta * (t + C.tshift);
+        }
     }
     m.Fx = C.ax;
     const double f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4];
@@ -405,6 +472,13 @@ __device__ __forceinline__ Macro macro(const R f[9], const R g[NG > 0 ? NG : 1],
     m.ux = jx + 0.5 * m.Fx;
     m.uy = jy + 0.5 * m.Fy;
     return m;
+}
+
+// macro() at node (x, y) of a lattice stored as S.
+template <class S, class R, int NG>
+__device__ __forceinline__ Macro macro_at(const R f[9], const R g[NG > 0 ? NG : 1], const Coeffs& C, int x, int y) {
+    if constexpr (kRefT<S>) return macro<R, NG, true>(f, g, C, tref_at<S>(C, x, y));
+    else return macro<R, NG>(f, g, C);
 }
 
 // Rows 3..8 of the raw-moment transform M of Eq. 13 (rows 0..2 are the

@@ -134,8 +134,9 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
         }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-            const Macro m = macro<R, NG>(f[r], g[r], C);
+            const Macro m = macro_at<S, R, NG>(f[r], g[r], C, x, y0 + r);
             collide<R, NG, COLL>(f[r], g[r], m, C);
+            to_stored<S, NG>(f[r], g[r], C, y0 + r);
             if (MODE == kBufferNT)
                 store_node_buf<S, NG, kCachePolicyNT>(make_rsrc(dst, buf_bytes), G, C, boff[r], f[r], g[r]);
             else if (MODE == kBufferKeep)
@@ -153,8 +154,9 @@ __device__ __forceinline__ void sweep_nodes(const Geom& G, const Coeffs& C, cons
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         if (y0 + r < G.ny) {
-            const Macro m = macro<R, NG>(f[r], g[r], C);
+            const Macro m = macro_at<S, R, NG>(f[r], g[r], C, x, y0 + r);
             collide<R, NG, COLL>(f[r], g[r], m, C);
+            to_stored<S, NG>(f[r], g[r], C, y0 + r);
             store_node<S, NG>(dst + (long long)(y0 + r) * G.pitch, G, C, (unsigned)x * (unsigned)sizeof(S), f[r],
                               g[r]);
         }
@@ -422,12 +424,14 @@ __device__ __forceinline__ void fuse2_walls(typename Codec<S>::R* lds, const Geo
 // Collide the pulled populations of slot (sl, sm), round them as a store
 // to S would, and keep what the second step pulls (no wall rule).
 template <class S, int NG, int COLL>
-__device__ __forceinline__ void fuse2_keep_open(typename Codec<S>::R* lds, const Coeffs& C, int sl, int sm,
-                                                typename Codec<S>::R f[9], typename Codec<S>::R g[gdim(NG)]) {
+__device__ __forceinline__ void fuse2_keep_open(typename Codec<S>::R* lds, const Coeffs& C, int x0, int y0, int sl,
+                                                int sm, typename Codec<S>::R f[9],
+                                                typename Codec<S>::R g[gdim(NG)]) {
     using F = Fuse2<S, NG>;
     using R = typename Codec<S>::R;
-    const Macro m = macro<R, NG>(f, g, C);
+    const Macro m = macro_at<S, R, NG>(f, g, C, x0 + sl - 1, y0 + sm - 1);
     collide<R, NG, COLL>(f, g, m, C);
+    to_stored<S, NG>(f, g, C, y0 + sm - 1);
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = as_stored<S>(f[i], C.fscale, C.finv);
 #pragma unroll
@@ -451,7 +455,7 @@ __device__ __forceinline__ void fuse2_keep(typename Codec<S>::R* lds, const Geom
                                            int sl, int sm, typename Codec<S>::R f[9],
                                            typename Codec<S>::R g[gdim(NG)]) {
     using F = Fuse2<S, NG>;
-    fuse2_keep_open<S, NG, COLL>(lds, C, sl, sm, f, g);
+    fuse2_keep_open<S, NG, COLL>(lds, C, x0, y0, sl, sm, f, g);
     const int sx = sl - 1, sy = sm - 1;
     const int x = x0 + sx, y = y0 + sy;
     const bool in_tile = sx >= 0 && sx < F::TX && sy >= 0 && sy < F::TY;
@@ -492,7 +496,7 @@ __device__ __forceinline__ void open_phase1(__amdgpu_buffer_rsrc_t rs, const Geo
         R f[9], g[gdim(NG)];
         open_slot_load<S, NG>(rs, G, C, x0, y0, w, f, g);
         const int m = w / F::EW;
-        fuse2_keep_open<S, NG, COLL>(lds, C, w - m * F::EW, m, f, g);
+        fuse2_keep_open<S, NG, COLL>(lds, C, x0, y0, w - m * F::EW, m, f, g);
     }
 }
 
@@ -547,8 +551,9 @@ __device__ __forceinline__ void fused_phase2(__amdgpu_buffer_rsrc_t rd, const Ge
 #pragma unroll
             for (int i = 0; i < NG; ++i) g[i] = lds[pulled_at<F>(9 + i, i, ix, iy)];
         }
-        const Macro m = macro<R, NG>(f, g, C);
+        const Macro m = macro_at<S, R, NG>(f, g, C, x, y);
         collide<R, NG, COLL>(f, g, m, C);
+        to_stored<S, NG>(f, g, C, y);
         const unsigned boff = (unsigned)(y * G.pitch + x) * (unsigned)sizeof(S);
         if (MODE == kBufferKeep) store_node_buf<S, NG, kCachePolicyDefault>(rd, G, C, boff, f, g);
         else store_node_buf<S, NG, kCachePolicyNT>(rd, G, C, boff, f, g);
@@ -637,8 +642,8 @@ __global__ __launch_bounds__(256) void k_moments(Geom G, Coeffs C, const S* __re
     const int x = (int)(k % G.nx), y = (int)(k / G.nx);
     R f[9], g[gdim(NG)];
     load_node<S, NG>(src, G, C, x, y, f, g);
-    const Macro m = macro<R, NG>(f, g, C);
-    if (rho) rho[k] = Codec<S>::kDev ? 1.0 + m.rho : m.rho;
+    const Macro m = macro_at<S, R, NG>(f, g, C, x, y);
+    if (rho) rho[k] = Codec<S>::kDev ? 1.0 + rref_at<S>(C, y) + m.rho : m.rho;
     if (ux) ux[k] = m.ux;
     if (uy) uy[k] = m.uy;
     if (T) T[k] = m.T;
@@ -665,10 +670,11 @@ __global__ __launch_bounds__(256) void k_gather(Geom G, Coeffs C, const S* __res
     load_node<S, NG>(src, G, C, x, y, f, g);
     constexpr bool dev = Codec<S>::kDev;
     if (pf)
-        for (int i = 0; i < 9; ++i) pf[i * n + k] = dev ? rest_f(i) + (double)f[i] : (double)f[i];
+        for (int i = 0; i < 9; ++i)
+            pf[i * n + k] = dev ? rest_f(i) * (1.0 + rref_at<S>(C, y)) + (double)f[i] : (double)f[i];
     if (pg)
         for (int i = 0; i < NG; ++i)
-            pg[i * n + k] = dev ? rest_g<NG>(i, T0, C.varpi) + (double)g[i] : (double)g[i];
+            pg[i * n + k] = dev ? rest_g<NG>(i, T0 + tref_at<S>(C, x, y), C.varpi) + (double)g[i] : (double)g[i];
 }
 
 // Destination of the stored entry (i, x, y) under the pull: the node
@@ -694,19 +700,32 @@ __device__ __forceinline__ int target(const Geom& G, int x, int y, int& tx, int&
 // representation (full for FP64, deviation otherwise).
 // MODE 0: from FP64 arrays pf/pg ([i][node]); MODE 1: rest equilibrium
 // with the temperature field Tf (or T0 if Tf is null), Eqs. 22, 30, 31.
+// Deviations are relative to the node's reference state: temperature
+// T0 + tau, density rho0 + rho_ref (both zero but for FP16; tb, tgx, tgy,
+// r0, rA, rB of Coeffs, nx the lattice width).
 template <bool DEV, int NG, int MODE>
 struct PreValue {
     const double *pf, *pg, *Tf;
     long long n;
     double T0, varpi;
+    double tb, tgx, tgy;
+    double r0, rA, rB;
+    int nx;
+    __device__ double tau(long long k) const {
+        return tb + tgx * (double)(k % nx) + tgy * (double)(k / nx);
+    }
+    __device__ double rho_ref(long long k) const {
+        const double y = (double)(k / nx);
+        return r0 + rA * y + rB * y * y;
+    }
     __device__ double f(int i, long long k) const {
-        if (MODE == 0) return DEV ? pf[i * n + k] - rest_f(i) : pf[i * n + k];
-        return DEV ? 0.0 : rest_f(i);
+        if (MODE == 0) return DEV ? pf[i * n + k] - rest_f(i) * (1.0 + rho_ref(k)) : pf[i * n + k];
+        return DEV ? 0.0 - rest_f(i) * rho_ref(k) : rest_f(i);
     }
     __device__ double g(int i, long long k) const {
-        if (MODE == 0) return DEV ? pg[i * n + k] - rest_g<NG>(i, T0, varpi) : pg[i * n + k];
+        if (MODE == 0) return DEV ? pg[i * n + k] - rest_g<NG>(i, T0 + tau(k), varpi) : pg[i * n + k];
         const double T = Tf ? Tf[k] : T0;
-        return rest_g<NG>(i, DEV ? T - T0 : T, varpi);
+        return rest_g<NG>(i, DEV ? T - T0 - tau(k) : T, varpi);
     }
 };
 
@@ -742,7 +761,7 @@ __global__ __launch_bounds__(256) void k_unstream(Geom G, Coeffs C, S* __restric
     if (k >= n) return;
     const int x = (int)(k % G.nx), y = (int)(k / G.nx);
     const long long o = (long long)y * G.pitch + x;
-    const PreValue<Codec<S>::kDev, NG, MODE> pv{pf, pg, Tf, n, T0, C.varpi};
+    const PreValue<Codec<S>::kDev, NG, MODE> pv{pf, pg, Tf, n, T0, C.varpi, C.tb, C.tgx, C.tgy, C.r0, C.rA, C.rB, G.nx};
     Codec<S>::store(dst + o, (R)pv.f(0, k), C.fscale);
     unstream_f<S, NG, MODE, 1>(dst, G, C, pv, x, y, k, o);
     unstream_f<S, NG, MODE, 2>(dst, G, C, pv, x, y, k, o);
@@ -773,7 +792,7 @@ __device__ __forceinline__ double node_T(const S* __restrict__ src, const Geom& 
     using R = typename Codec<S>::R;
     R f[9], g[gdim(NG)];
     load_node<S, NG>(src, G, C, x, y, f, g);
-    return macro<R, NG>(f, g, C).T;
+    return macro_at<S, R, NG>(f, g, C, x, y).T;
 }
 
 // Fixed-order block reductions (wave64 shuffles, then LDS in wave order).
@@ -849,7 +868,7 @@ __device__ __forceinline__ void residual_node(const S* __restrict__ src, const G
     const long long n = (long long)G.nx * G.ny, k = (long long)y * G.nx + x;
     R f[9], g[gdim(NG)];
     load_node<S, NG>(src, G, C, x, y, f, g);
-    const Macro m = macro<R, NG>(f, g, C);
+    const Macro m = macro_at<S, R, NG>(f, g, C, x, y);
     const bool fin = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.T);
     bad = fin ? 0ull : 1ull;
     d = 0.0;

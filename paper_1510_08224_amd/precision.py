@@ -86,8 +86,12 @@ def main():
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--steps", type=int, default=50000)
     ap.add_argument("--ra", type=float, default=1e5)
+    ap.add_argument("--steps-list", default="",
+                    help="comma-separated step counts: one report (JSON line) per count, each from the start")
     args = ap.parse_args()
-    print(json.dumps(report(args.nx, args.ny, args.steps, args.ra)), flush=True)
+    counts = [int(v) for v in args.steps_list.split(",") if v] or [args.steps]
+    for n in counts:
+        print(json.dumps(report(args.nx, args.ny, n, args.ra)), flush=True)
 
 
 if __name__ == "__main__":

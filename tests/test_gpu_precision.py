@@ -44,7 +44,10 @@ def test_deviation_storage_error_bounds(storage, steps):
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-7), ("f16", 2e-3)])
 def test_deviation_storage_roundtrip(storage, tol):
     # populations near rest: the stored deviation keeps about 24 (FP32) or
-    # 11 (FP16) significant bits of the deviation, not of the population
+    # 11 (FP16) significant bits of the deviation, not of the population.
+    # FP32 deviations are from the rest state at T0; FP16 ones from the rest
+    # state at the conduction profile between the Dirichlet walls (here
+    # left T = 1, right T = 0: T_ref = 1 - (x + 1/2) / nx).
     pb = W.cavity(20, 1e4, ny=12)
     S = lbm.Solver(20, 12, storage)
     S.set_params(pb)
@@ -54,7 +57,8 @@ def test_deviation_storage_roundtrip(storage, tol):
     S.set_populations(f, g)
     fb, gb = S.get_populations()
     w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
-    grest = np.array([0.25] + [0.0625] * 4)[:, None, None]
+    tref = 0.5 if storage == "f32" else (1.0 - (np.arange(20) + 0.5) / 20)[None, None, :]
+    grest = np.array([0.5] + [0.125] * 4)[:, None, None] * tref
     assert np.max(np.abs(fb - f) / np.maximum(np.abs(f - w), 1e-6)) < tol * 4
     assert np.max(np.abs(gb - g) / np.maximum(np.abs(g - grest), 1e-6)) < tol * 4
     S.close()
