@@ -402,6 +402,24 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
  * other value. */
 int lbm_batch_set_policy(lbm_batch* b, int32_t policy);
 
+/* Launch tuning of the batch (the autotuner's knobs; results are bitwise
+ * the same with any setting):
+ *   xcd_order      order in which the tiles of the batch's tile tables go
+ *                  to the 8 XCDs: 1 contiguous bands (each XCD a range of
+ *                  the table), 0 round robin, -1 the default (bands);
+ *   keep_stores    1 stores keep their lines in the last-level cache, 0
+ *                  non-temporal stores, -1 the default (kept when all
+ *                  members' buffers fit the 256 MB last-level cache);
+ *   largest_first  1 the tile tables list the members largest lattice
+ *                  first, 0 in the order they were added (the default).
+ * Takes effect at the next lbm_batch_step.  LBM_ERR_ARG for other values. */
+int lbm_batch_set_tuning(lbm_batch* b, int32_t xcd_order, int32_t keep_stores, int32_t largest_first);
+
+/* The tuning in effect with the current members (defaults resolved):
+ * xcd_order 0 or 1, keep_stores 0 or 1, largest_first 0 or 1.  Rebuilds
+ * the tile tables if members changed. */
+int lbm_batch_get_tuning(lbm_batch* b, int32_t* xcd_order, int32_t* keep_stores, int32_t* largest_first);
+
 /* Time steps one batched launch advances with the current members and
  * policy (1 or 2); rebuilds the tile table if members changed. */
 int lbm_batch_steps_per_launch(lbm_batch* b, int32_t* steps);

@@ -11,11 +11,16 @@ for all members per time step, or per pair of steps with fused pairs,
 replayed from captured graphs) against one launch per instance per step
 on the same GPU.
 
-Autotuner: for each size class (lattice shape) the tile width block_x in
-{64, 128, 256} (never wider than the lattice) is chosen by coordinate
-descent on the measured time of the whole batched step, other classes held
-fixed.  Results are cached in a JSON file keyed by GPU architecture,
-storage and size class; a cached class is not re-measured.
+Autotuner, on the measured time of the whole batched step: for each size
+class (lattice shape) the tile width block_x in {64, 128, 256} of the
+one-step kernel (never wider than the lattice), by coordinate descent with
+the other classes held fixed; then the launch the batched step runs with:
+fused pairs or one step per launch, the XCD order of the tile tables, kept
+or non-temporal stores, and the members' order in the tables (as added, or
+largest first).  Choices are cached in a JSON file keyed by GPU
+architecture, storage and size class (tile widths) or mix of size classes
+(launch); cached choices are applied, not re-measured.  The report gives
+the library's untuned default beside the tuned step.
 """
 from __future__ import annotations
 
@@ -146,17 +151,70 @@ def autotune(B: lbm.Batch, solvers, candidates=(64, 128, 256), steps: int = 60, 
     return {"choice": choice, "trials": trials, "cache_key": key}
 
 
+def mix_key(solvers) -> str:
+    """The batch's size classes and their member counts, as a cache key."""
+    return ",".join(f"{c}:{len(v)}" for c, v in sorted(size_classes(solvers).items()))
+
+
+def autotune_launch(B: lbm.Batch, solvers, steps: int = 100, cache_path: str | None = None) -> dict:
+    """Choose the launch the batched step runs with: fused pairs or one step
+    per launch, the XCD order of the tile tables, kept or non-temporal
+    stores, and the members' order in the tables (as added, or largest
+    lattice first), by the measured time of the whole batched step (best of
+    two runs per setting).  The one-step kernel's tile widths per size class
+    come from `autotune` first.  Choices are cached per GPU architecture,
+    storage and mix of size classes; a cached mix is applied, not
+    re-measured.  Returns the choice and the trials."""
+    cache_path = cache_path or DEFAULT_CACHE
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    key = f"{_arch()}/{B.storage_name}/launch/{mix_key(solvers)}"
+    known = cache.get(key)
+    trials = []
+    if known is None:
+        best, best_t = None, None
+        for policy in (lbm.LBM_POLICY_FUSE2, 0):
+            for order in (1, 0):
+                for keep in (0, 1):
+                    for largest in (0, 1):
+                        B.set_policy(policy)
+                        B.set_tuning(order, keep, largest)
+                        t = min(time_batch(B, steps), time_batch(B, steps))
+                        c = {"policy": policy, "xcd_order": order, "keep_stores": keep, "largest_first": largest}
+                        trials.append(dict(c, us_per_step=round(t * 1e6, 2)))
+                        if best_t is None or t < best_t:
+                            best, best_t = c, t
+        known = best
+        if cache_path:
+            cache[key] = known
+            os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
+            with open(cache_path, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+    B.set_policy(known["policy"])
+    B.set_tuning(known["xcd_order"], known["keep_stores"], known["largest_first"])
+    return {"choice": known, "trials": trials, "cache_key": key}
+
+
 def report(count: int = 256, seed: int = 3, steps: int = 2000, base_steps: int = 200,
            storage: str = "f32", tune: bool = True, cache_path: str | None = None) -> dict:
     problems = W.batch_mix(count, seed)
     nodes = sum(p.nx * p.ny for p in problems)
     B, solvers = build(problems, storage)
-    # the tile widths matter to the one-step kernel only: tune and time it
-    # first, then the library's default (fused pairs where they apply)
+    # the library's default launch, untuned
+    B.set_policy(lbm.LBM_POLICY_DEFAULT)
+    default_tuning = B.get_tuning()
+    spl_default = B.steps_per_launch
+    t_default = time_batch(B, steps)
+    # tile widths of the one-step kernel per size class, timed alone
     B.set_policy(0)
     tuned = autotune(B, solvers, cache_path=cache_path) if tune else {"choice": {}, "trials": []}
     t_single = time_batch(B, steps)
-    B.set_policy(lbm.LBM_POLICY_DEFAULT)
+    # the launch the batched step runs with
+    launch = autotune_launch(B, solvers, cache_path=cache_path) if tune else None
+    if not tune:
+        B.set_policy(lbm.LBM_POLICY_DEFAULT)
     spl = B.steps_per_launch
     t_batch = time_batch(B, steps)
     t_inst = time_per_instance(solvers, base_steps)
@@ -168,7 +226,12 @@ def report(count: int = 256, seed: int = 3, steps: int = 2000, base_steps: int =
         "nodes": nodes,
         "size_classes": {c: len(v) for c, v in size_classes(solvers).items()},
         "batched": {"us_per_step": round(t_batch * 1e6, 2), "mlups": round(nodes / t_batch / 1e6, 1),
-                    "steps": steps, "graph_steps": 50, "steps_per_launch": spl},
+                    "steps": steps, "graph_steps": 50, "steps_per_launch": spl,
+                    "launch": None if launch is None else launch["choice"]},
+        "batched_untuned_default": {"us_per_step": round(t_default * 1e6, 2),
+                                    "mlups": round(nodes / t_default / 1e6, 1),
+                                    "steps_per_launch": spl_default, "tuning": default_tuning},
+        "tuned_over_default": round(t_default / t_batch, 3),
         "batched_one_step_per_launch": {"us_per_step": round(t_single * 1e6, 2),
                                         "mlups": round(nodes / t_single / 1e6, 1)},
         "one_launch_per_instance": {"us_per_step": round(t_inst * 1e6, 2), "mlups": round(nodes / t_inst / 1e6, 1),
@@ -180,6 +243,7 @@ def report(count: int = 256, seed: int = 3, steps: int = 2000, base_steps: int =
         "effective_GBs_batched": round(28 * {"f64": 8, "f32": 4, "f16": 2}[storage] * nodes / t_batch / 1e9, 1),
         "nonfinite_members": int((bad > 0).sum()),
         "autotune": tuned,
+        "autotune_launch": launch,
     }
     B.close()
     for S in solvers:

@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
@@ -80,6 +81,12 @@ struct lbm_batch {
     // buffers within the 256 MB last-level cache), and the 64 x 8 tile table.
     int policy = LBM_POLICY_DEFAULT;
     bool fuse = false, keep = false;
+    // Tuning of the launches (lbm_batch_set_tuning): XCD order of the tile
+    // tables (-1: bands; 0 round robin, 1 bands), stores (-1: the footprint
+    // rule; 0 non-temporal, 1 kept), tile-table order of the members (0 as
+    // added, 1 largest first); `order` is the order in effect.
+    int tune_order = -1, tune_keep = -1, tune_sort = 0;
+    int order = 1;
     BatchTile* d_ftiles = nullptr;
     size_t cap_ftiles = 0;
     int nftiles = 0;
@@ -1279,9 +1286,17 @@ static int batch_build(lbm_batch* b) {
     const int fty = fuse2_rows(b->storage, b->ng < 0 ? 5 : b->ng);
     bool can_fuse = fty > 0;
     double ws = 0.0;
-    for (size_t k = 0; k < b->slots.size(); ++k) {
+    // members in table order: as added, or the largest lattices first (their
+    // tiles then start the launch and the small ones fill its tail)
+    std::vector<size_t> order;
+    for (size_t k = 0; k < b->slots.size(); ++k)
+        if (b->slots[k]) order.push_back(k);
+    if (b->tune_sort == 1)
+        std::stable_sort(order.begin(), order.end(), [b](size_t a, size_t c) {
+            return (long long)b->slots[a]->nx * b->slots[a]->ny > (long long)b->slots[c]->nx * b->slots[c]->ny;
+        });
+    for (size_t k : order) {
         lbm_solver* h = b->slots[k];
-        if (!h) continue;
         BatchMember M{};
         M.G = h->G;
         M.C = h->C;
@@ -1315,7 +1330,8 @@ static int batch_build(lbm_batch* b) {
                           ? (b->storage == LBM_F64 || b->storage == LBM_F32)
                           : (b->policy & LBM_POLICY_FUSE2) != 0;
     b->fuse = want && can_fuse && b->buffer && !mem.empty();
-    b->keep = ws <= 256.0 * mib;
+    b->keep = b->tune_keep < 0 ? ws <= 256.0 * mib : b->tune_keep == 1;
+    b->order = b->tune_order < 0 ? 1 : b->tune_order;
     if (batch_table(&b->d_members, &b->cap_members, mem.size()) != hipSuccess)
         return bfail(b, LBM_ERR_NOMEM, "batch member table allocation");
     if (batch_table(&b->d_tiles, &b->cap_tiles, tiles.size()) != hipSuccess)
@@ -1347,11 +1363,12 @@ static hipError_t batch_launch_steps(lbm_batch* b, int parity, int64_t steps, in
     while (steps > 0) {
         hipError_t e;
         if (b->fuse && steps >= 2) {
-            e = launch_sweep2_batch(b->storage, b->ng, b->keep, b->d_members, b->d_ftiles, b->nftiles, parity, b->stream);
+            e = launch_sweep2_batch(b->storage, b->ng, b->keep, b->d_members, b->d_ftiles, b->nftiles, parity, b->order,
+                                    b->stream);
             steps -= 2;
         } else {
             e = launch_sweep_batch(b->storage, b->ng, b->buffer, b->keep, b->d_members, b->d_tiles, b->ntiles, parity,
-                                   b->stream);
+                                   b->order, b->stream);
             steps -= 1;
         }
         if (e != hipSuccess) return e;
@@ -1423,6 +1440,31 @@ int lbm_batch_set_policy(lbm_batch* b, int32_t policy) {
         return bfail(b, LBM_ERR_ARG, "lbm_batch_set_policy: LBM_POLICY_DEFAULT, 0 or LBM_POLICY_FUSE2");
     b->policy = policy;
     batch_invalidate(b);
+    return LBM_OK;
+}
+
+int lbm_batch_set_tuning(lbm_batch* b, int32_t xcd_order, int32_t keep_stores, int32_t largest_first) {
+    if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_set_tuning: NULL batch");
+    if (xcd_order < -1 || xcd_order > 1 || keep_stores < -1 || keep_stores > 1 || largest_first < 0 ||
+        largest_first > 1)
+        return bfail(b, LBM_ERR_ARG, "lbm_batch_set_tuning: xcd_order and keep_stores in -1..1, largest_first 0 or 1");
+    b->tune_order = xcd_order;
+    b->tune_keep = keep_stores;
+    b->tune_sort = largest_first;
+    batch_invalidate(b);
+    return LBM_OK;
+}
+
+int lbm_batch_get_tuning(lbm_batch* b, int32_t* xcd_order, int32_t* keep_stores, int32_t* largest_first) {
+    if (!b || !xcd_order || !keep_stores || !largest_first)
+        return bfail(b, LBM_ERR_ARG, "lbm_batch_get_tuning: NULL argument");
+    if (b->dirty) {
+        int rc = batch_build(b);
+        if (rc != LBM_OK) return rc;
+    }
+    *xcd_order = b->order;
+    *keep_stores = b->keep ? 1 : 0;
+    *largest_first = b->tune_sort;
     return LBM_OK;
 }
 

@@ -42,15 +42,16 @@ hipError_t launch_sweep2(int storage, int ng, const Launch& L, const Geom& G, co
                          const void* src, void* dst, hipStream_t st);
 int fuse2_rows(int storage, int ng);
 // Fused pairs of steps for a batch (buffer addressing; keep: default-policy stores).
+// order: XCD order of the tile table (0 round robin, 1 bands).
 hipError_t launch_sweep2_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
-                               int ntiles, int parity, hipStream_t st);
+                               int ntiles, int parity, int order, hipStream_t st);
 // C: the host copy (launch decisions); dC: the same constants in device
 // memory (read by the kernels).
 hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                         const void* src, void* dst, hipStream_t st);
 // keep: default-policy stores (the batch's state fits the last-level cache).
 hipError_t launch_sweep_batch(int storage, int ng, bool buffer, bool keep, const BatchMember* members,
-                              const BatchTile* tiles, int ntiles, int parity, hipStream_t st);
+                              const BatchTile* tiles, int ntiles, int parity, int order, hipStream_t st);
 hipError_t launch_residual_batch(int storage, int ng, const BatchMember* members, int nmembers, const BatchTile* tiles,
                                  int ntiles, int parity, double* tile_max, unsigned long long* tile_bad,
                                  double* out2, hipStream_t st);

@@ -605,10 +605,10 @@ __global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per
 template <class S, int NG, int MODE>
 __global__ __launch_bounds__((Fuse2<S, NG>::NT)) __attribute__((amdgpu_waves_per_eu(fuse2_waves<S>(NG), 8)))
 void k_sweep2_batch(
-    const BatchMember* __restrict__ members, const BatchTile* __restrict__ tiles, int parity) {
+    const BatchMember* __restrict__ members, const BatchTile* __restrict__ tiles, int parity, int order) {
     using F = Fuse2<S, NG>;
     __shared__ typename Codec<S>::R lds[F::NP * F::PLANE];
-    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, kXcdBands, 0)];
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, order, 0)];
     const BatchMember& M = members[t.member];
     const int sel = (M.cur0 + parity) & 1;
     fused_tile<S, NG, MODE, kCollMRT>(M.G, M.C, static_cast<const S*>(M.buf[sel]), static_cast<S*>(M.buf[sel ^ 1]),
@@ -621,8 +621,8 @@ void k_sweep2_batch(
 // (cur0 + parity) & 1 and writes the other one.
 template <class S, int NG, int MODE>
 __global__ __launch_bounds__(256) void k_sweep_batch(const BatchMember* __restrict__ members,
-                                                     const BatchTile* __restrict__ tiles, int parity) {
-    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, kXcdBands, 0)];
+                                                     const BatchTile* __restrict__ tiles, int parity, int order) {
+    const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, order, 0)];
     const BatchMember& M = members[t.member];
     const int sel = (M.cur0 + parity) & 1;
     const S* src = static_cast<const S*>(M.buf[sel]);
@@ -1082,29 +1082,32 @@ hipError_t launch_sweep(int storage, int ng, const Launch& L, const Geom& G, con
 }
 
 hipError_t launch_sweep_batch(int storage, int ng, bool buffer, bool keep, const BatchMember* members,
-                              const BatchTile* tiles, int ntiles, int parity, hipStream_t st) {
+                              const BatchTile* tiles, int ntiles, int parity, int order, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     LBM_DISPATCH(storage, ng, {
         if (buffer && keep)
-            hipLaunchKernelGGL((k_sweep_batch<S, NG, kBufferKeep>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            hipLaunchKernelGGL((k_sweep_batch<S, NG, kBufferKeep>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity,
+                               order);
         else if (buffer)
-            hipLaunchKernelGGL((k_sweep_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            hipLaunchKernelGGL((k_sweep_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity,
+                               order);
         else
-            hipLaunchKernelGGL((k_sweep_batch<S, NG, kGlobal>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity);
+            hipLaunchKernelGGL((k_sweep_batch<S, NG, kGlobal>), dim3(ntiles), dim3(256), 0, st, members, tiles, parity,
+                               order);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_sweep2_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
-                               int ntiles, int parity, hipStream_t st) {
+                               int ntiles, int parity, int order, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     LBM_DISPATCH(storage, ng, {
         if (keep)
             hipLaunchKernelGGL((k_sweep2_batch<S, NG, kBufferKeep>), dim3(ntiles), dim3(Fuse2<S, NG>::NT), 0, st,
-                               members, tiles, parity);
+                               members, tiles, parity, order);
         else
             hipLaunchKernelGGL((k_sweep2_batch<S, NG, kBufferNT>), dim3(ntiles), dim3(Fuse2<S, NG>::NT), 0, st,
-                               members, tiles, parity);
+                               members, tiles, parity, order);
     });
     return hipGetLastError();
 }

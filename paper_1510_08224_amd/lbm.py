@@ -108,6 +108,9 @@ _SIGS = {
     "lbm_batch_step": (ctypes.c_int, [_P, ctypes.c_int64]),
     "lbm_batch_set_graph_steps": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lbm_batch_set_policy": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbm_batch_set_tuning": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_batch_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_steps_per_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_synchronize": (ctypes.c_int, [_P]),
     "lbm_batch_residual": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
@@ -430,6 +433,14 @@ class Batch:
 
     def step(self, n: int = 1):
         _bcheck(lib().lbm_batch_step(self.h, int(n)), self.h)
+
+    def set_tuning(self, xcd_order: int = -1, keep_stores: int = -1, largest_first: int = 0):
+        _bcheck(lib().lbm_batch_set_tuning(self.h, int(xcd_order), int(keep_stores), int(largest_first)), self.h)
+
+    def get_tuning(self) -> dict:
+        o, k, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _bcheck(lib().lbm_batch_get_tuning(self.h, ctypes.byref(o), ctypes.byref(k), ctypes.byref(l)), self.h)
+        return {"xcd_order": o.value, "keep_stores": k.value, "largest_first": l.value}
 
     def set_graph_steps(self, steps: int):
         _bcheck(lib().lbm_batch_set_graph_steps(self.h, int(steps)), self.h)

@@ -266,3 +266,37 @@ def test_fused_batch_policy_rules():
         B.set_policy(0)
         assert B.steps_per_launch == 1
         B.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_batch_tuning_knobs_leave_results_unchanged(storage):
+    """The autotuner's knobs (XCD order of the tile tables, kept or
+    non-temporal stores, largest member first) change only where and how
+    tiles run: every member equals its solve alone under each setting, for
+    fused pairs and one step per launch, with graph replay."""
+    mix = _mix()
+    ref = [_alone(pb, mkT() if mkT else None, storage, 41) for pb, mkT in mix]
+    for policy in (lbm.LBM_POLICY_FUSE2, 0):
+        for order, keep, largest in ((0, 0, 1), (1, 1, 1), (0, 1, 0)):
+            B, sols = _batch(storage, mix, graph=8)
+            B.set_policy(policy)
+            B.set_tuning(order, keep, largest)
+            assert B.get_tuning() == {"xcd_order": order, "keep_stores": keep, "largest_first": largest}
+            B.step(41)
+            for (fa, ga), S in zip(ref, sols):
+                fb, gb = S.get_populations()
+                assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (policy, order, keep, largest)
+            B.close()
+
+
+def test_batch_tuning_defaults_and_arguments():
+    B, sols = _batch("f32", _mix()[:2])
+    # defaults: bands, kept stores for a footprint within the last-level cache, order as added
+    assert B.get_tuning() == {"xcd_order": 1, "keep_stores": 1, "largest_first": 0}
+    for bad in ((2, 0, 0), (0, -2, 0), (0, 0, 2), (-3, 1, 1)):
+        with pytest.raises(lbm.LbmError) as e:
+            B.set_tuning(*bad)
+        assert e.value.code == lbm.LBM_ERR_ARG
+    B.set_tuning(-1, 0, 0)
+    assert B.get_tuning()["keep_stores"] == 0
+    B.close()
