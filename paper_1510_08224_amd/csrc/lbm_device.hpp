@@ -481,6 +481,22 @@ __device__ __forceinline__ Macro macro_at(const R f[9], const R g[NG > 0 ? NG : 
     else return macro<R, NG>(f, g, C);
 }
 
+// a * b + c rounded once (a fused multiply-add).  The library is built
+// without contraction, so every kernel that inlines an expression rounds it
+// alike; the collisions name their multiply-adds explicitly.
+template <class R>
+__device__ __forceinline__ R fmaR(R a, R b, R c) {
+    if constexpr (std::is_same<R, float>::value) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
+// Relaxation of one moment toward its equilibrium with its source term
+// (Eq. 8): m - s (m - m_eq) + h S.
+template <class R>
+__device__ __forceinline__ R relax(R m, R s, R meq, R h, R S) {
+    return fmaR(h, S, fmaR(-s, m - meq, m));
+}
+
 // Rows 3..8 of the raw-moment transform M of Eq. 13 (rows 0..2 are the
 // conserved sums), and its inverse (Eq. A1) from the moments k0..k8.
 template <class R>
@@ -503,7 +519,7 @@ struct Moments9 {
 
 template <class R>
 __device__ __forceinline__ void inverse9(R v[9], R k0, R k1, R k2, R k3, R k4, R k5, R k6, R k7, R k8) {
-    const R q = (R)0.25 * k3 - (R)0.5 * k8;
+    const R q = fmaR((R)0.25, k3, (R)(-0.5) * k8);
     const R h4 = (R)0.25 * k4;
     const R bx = (R)0.5 * (k1 - k7);
     const R by = (R)0.5 * (k2 - k6);
@@ -535,32 +551,33 @@ __device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const 
     const R rho = (R)mc.rho;
     const R ux = (R)mc.ux, uy = (R)mc.uy;
     const R Fx = (R)mc.Fx, Fy = (R)mc.Fy;
-    const R usq = ux * ux + uy * uy;
-    const R uF = ux * Fx + uy * Fy;
+    const R uyy = uy * uy, uyFy = uy * Fy;
+    const R usq = fmaR(ux, ux, uyy);
+    const R uF = fmaR(ux, Fx, uyFy);
     const R third = (R)(1.0 / 3.0);
     if constexpr (FLOW_MRT) {
         const Moments9<R> m(f);
         // Relaxation toward m^eq (Eq. 16) with the source of Eq. 17.
         const Rates<R>& K = rates_of<R>(C);
         const R s3 = K.s3, s4 = K.s4, s6 = K.s6, s8 = K.s8;
-        const R e3 = (R)(2.0 / 3.0) * rho + usq;
-        const R e4 = ux * ux - uy * uy;
+        const R e3 = fmaR((R)(2.0 / 3.0), rho, usq);
+        const R e4 = fmaR(ux, ux, -uyy);
         const R e5 = ux * uy;
         const R e6 = third * uy;
         const R e7 = third * ux;
-        const R e8 = (R)(1.0 / 9.0) * rho + third * usq;
+        const R e8 = fmaR(third, usq, (R)(1.0 / 9.0) * rho);
         const R S3 = (R)2 * uF;
-        const R S4 = (R)2 * (ux * Fx - uy * Fy);
-        const R S5 = ux * Fy + uy * Fx;
+        const R S4 = (R)2 * fmaR(ux, Fx, -uyFy);
+        const R S5 = fmaR(ux, Fy, uy * Fx);
         const R S6 = third * Fy;
         const R S7 = third * Fx;
         const R S8 = (R)(2.0 / 3.0) * uF;
-        const R n3 = m.m3 - s3 * (m.m3 - e3) + K.h3 * S3;
-        const R n4 = m.m4 - s4 * (m.m4 - e4) + K.h4 * S4;
-        const R n5 = m.m5 - s4 * (m.m5 - e5) + K.h4 * S5;
-        const R n6 = m.m6 - s6 * (m.m6 - e6) + K.h6 * S6;
-        const R n7 = m.m7 - s6 * (m.m7 - e7) + K.h6 * S7;
-        const R n8 = m.m8 - s8 * (m.m8 - e8) + K.h8 * S8;
+        const R n3 = relax(m.m3, s3, e3, K.h3, S3);
+        const R n4 = relax(m.m4, s4, e4, K.h4, S4);
+        const R n5 = relax(m.m5, s4, e5, K.h4, S5);
+        const R n6 = relax(m.m6, s6, e6, K.h6, S6);
+        const R n7 = relax(m.m7, s6, e7, K.h6, S7);
+        const R n8 = relax(m.m8, s8, e8, K.h8, S8);
         // Conserved moments after collision: m0* = rho, m1* = jx + Fx,
         // m2* = jy + Fy (rates 1 in Eq. 20; Eq. 15 puts -F/2 in m_bar).
         const R n1 = (R)(mc.ux + 0.5 * mc.Fx);
@@ -577,16 +594,17 @@ __device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const 
         const R t4 = (g[1] + g[3]) - (g[2] + g[4]);
         const Rates<R>& K = rates_of<R>(C);
         const R z1 = K.z1, z3 = K.z3, z4 = K.z4;
-        const R k1 = t1 - z1 * (t1 - ux * T);
-        const R k2 = t2 - z1 * (t2 - uy * T);
-        const R k3 = t3 - z3 * (t3 - K.varpi * t0);
-        const R k4 = t4 - z4 * t4;
+        const R k1 = fmaR(-z1, fmaR(-ux, T, t1), t1);
+        const R k2 = fmaR(-z1, fmaR(-uy, T, t2), t2);
+        const R k3 = fmaR(-z3, fmaR(-K.varpi, t0, t3), t3);
+        const R k4 = fmaR(-z4, t4, t4);
         const R w3 = (R)0.25 * k3, w4 = (R)0.25 * k4;
+        const R wp = w3 + w4, wm = w3 - w4;
         g[0] = t0 - k3;
-        g[1] = (R)0.5 * k1 + (w3 + w4);
-        g[3] = (R)(-0.5) * k1 + (w3 + w4);
-        g[2] = (R)0.5 * k2 + (w3 - w4);
-        g[4] = (R)(-0.5) * k2 + (w3 - w4);
+        g[1] = fmaR((R)0.5, k1, wp);
+        g[3] = fmaR((R)(-0.5), k1, wp);
+        g[2] = fmaR((R)0.5, k2, wm);
+        g[4] = fmaR((R)(-0.5), k2, wm);
     }
     if constexpr (NG == 9) {
         // n = M g (Eq. 13), n^eq = M g^eq with g^eq of Eq. 31:
@@ -601,14 +619,15 @@ __device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const 
         const R n1 = m.d13 + m.m7;
         const R n2 = m.d24 + m.m6;
         const R z1 = K.z1, z3 = K.z3, z4 = K.z4, z6 = K.z6, z8 = K.z8;
-        const R k1 = n1 - z1 * (n1 - ux * T);
-        const R k2 = n2 - z1 * (n2 - uy * T);
-        const R k3 = m.m3 - z3 * (m.m3 - ((R)(2.0 / 3.0) * t0 + th * usq * T));
-        const R k4 = m.m4 - z4 * (m.m4 - th * (ux * ux - uy * uy) * T);
-        const R k5 = m.m5 - z4 * (m.m5 - th * ux * uy * T);
-        const R k6 = m.m6 - z6 * (m.m6 - third * uy * T);
-        const R k7 = m.m7 - z6 * (m.m7 - third * ux * T);
-        const R k8 = m.m8 - z8 * (m.m8 - ((R)(1.0 / 9.0) * t0 + third * th * usq * T));
+        const R thT = th * T;
+        const R k1 = fmaR(-z1, fmaR(-ux, T, n1), n1);
+        const R k2 = fmaR(-z1, fmaR(-uy, T, n2), n2);
+        const R k3 = fmaR(-z3, m.m3 - fmaR((R)(2.0 / 3.0), t0, thT * usq), m.m3);
+        const R k4 = fmaR(-z4, fmaR(-thT, fmaR(ux, ux, -uyy), m.m4), m.m4);
+        const R k5 = fmaR(-z4, fmaR(-thT, ux * uy, m.m5), m.m5);
+        const R k6 = fmaR(-z6, fmaR(-third * uy, T, m.m6), m.m6);
+        const R k7 = fmaR(-z6, fmaR(-third * ux, T, m.m7), m.m7);
+        const R k8 = fmaR(-z8, m.m8 - fmaR((R)(1.0 / 9.0), t0, third * thT * usq), m.m8);
         inverse9<R>(g, t0, k1, k2, k3, k4, k5, k6, k7, k8);
     }
 }
@@ -644,9 +663,9 @@ __device__ __forceinline__ void collide_flow_bgk(R f[9], const Macro& mc, const 
         const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
         const R eF = (R)ex(i) * Fx + (R)ey(i) * Fy;
         const R wi = (R)w9(i);
-        const R feq = wi * (rho + ((R)3 * eu + (R)4.5 * eu * eu - usq15));
-        const R S = wi * (((R)3 * eF - uF3) + (R)9 * eu * eF);
-        f[i] = f[i] - w * (f[i] - feq) + a * S;
+        const R feq = wi * (rho + (fmaR((R)4.5 * eu, eu, (R)3 * eu) - usq15));
+        const R S = wi * fmaR((R)9 * eu, eF, fmaR((R)3, eF, -uF3));
+        f[i] = relax(f[i], w, feq, a, S);
     }
 }
 
@@ -667,12 +686,12 @@ __device__ __forceinline__ void collide_flow_ortho(R f[9], const Macro& mc, cons
     const R m_xy = (f[5] - f[6]) + (f[7] - f[8]);
     const Rates<R>& K = rates_of<R>(C);
     const R s_e = K.s3, s_eps = K.s8, s_q = K.s6, s_nu = K.s4;
-    const R k_e = m_e - s_e * (m_e - ((R)-2 * rho + (R)3 * usq)) + K.h3 * ((R)6 * uF);
-    const R k_eps = m_eps - s_eps * (m_eps - (rho - (R)3 * usq)) + K.h8 * ((R)-6 * uF);
-    const R k_qx = m_qx - s_q * (m_qx + ux) - K.h6 * Fx;
-    const R k_qy = m_qy - s_q * (m_qy + uy) - K.h6 * Fy;
-    const R k_xx = m_xx - s_nu * (m_xx - (ux * ux - uy * uy)) + K.h4 * ((R)2 * (ux * Fx - uy * Fy));
-    const R k_xy = m_xy - s_nu * (m_xy - ux * uy) + K.h4 * (ux * Fy + uy * Fx);
+    const R k_e = relax(m_e, s_e, fmaR((R)-2, rho, (R)3 * usq), K.h3, (R)6 * uF);
+    const R k_eps = relax(m_eps, s_eps, fmaR((R)-3, usq, rho), K.h8, (R)-6 * uF);
+    const R k_qx = relax(m_qx, s_q, -ux, K.h6, -Fx);
+    const R k_qy = relax(m_qy, s_q, -uy, K.h6, -Fy);
+    const R k_xx = relax(m_xx, s_nu, fmaR(ux, ux, -uy * uy), K.h4, (R)2 * fmaR(ux, Fx, -uy * Fy));
+    const R k_xy = relax(m_xy, s_nu, ux * uy, K.h4, fmaR(ux, Fy, uy * Fx));
     // conserved moments after collision: rho, j + F (Eq. 15 puts -F/2 in j)
     const R jx = (R)(mc.ux + 0.5 * mc.Fx), jy = (R)(mc.uy + 0.5 * mc.Fy);
     // f = M_o^T D^-1 m*
