@@ -139,7 +139,7 @@ def _poiseuille(Ny, s_nu, re=49.4146):
     return e35, el2
 
 
-def test_nee_body_force_channel_and_table2():
+def test_nee_body_force_channel_second_order():
     table2 = {float(r[0]): [float(v) for v in r[1:]] for r in paper_tables()["table2"]}
     e30, l30 = _poiseuille(30, 1.6)
     e60, l60 = _poiseuille(60, 1.6)
