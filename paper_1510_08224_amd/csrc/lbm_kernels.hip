@@ -12,7 +12,9 @@
 //   k_gather         pre-collision populations at time t, FP64
 //   k_unstream       write a buffer whose pull yields given pre-collision
 //                    populations (state restore and initial equilibrium)
-//   k_nusselt        wall Nusselt number (Eq. 39), one block, fixed-order FP64
+//   k_nusselt_local  local wall Nusselt numbers (Eq. 39 and the local
+//                    definition before it), one thread per wall node
+//   k_nusselt_reduce their mean and maximum, one block, fixed-order FP64
 //   k_residual(_batch) steady-state residual and non-finite count, FP64,
 //                    reduced in a fixed order by k_reduce_final / k_reduce_members
 //
@@ -814,28 +816,39 @@ __device__ __forceinline__ void wave_maxloc(double& v, int& i) {
 // Link-wise walls: wall half a spacing outside node 1, dT/dn from
 // (9 T1 - T2 - 8 Tw) / 3, midpoint mean.  NEE walls (nee = 1): wall through
 // node 0, dT/dn from (-3 T0 + 4 T1 - T2) / 2, trapezoidal mean.
+// Local Nusselt numbers, one thread per wall node (the wall nodes' depth
+// profiles are independent).
 template <class S, int NG>
-__global__ __launch_bounds__(256) void k_nusselt(Geom G, Coeffs C, const S* __restrict__ src, int side, double tw,
-                                                 double length, double dT, int nee, double* local, double* out) {
+__global__ __launch_bounds__(256) void k_nusselt_local(Geom G, Coeffs C, const S* __restrict__ src, int side,
+                                                       double tw, double length, double dT, int nee, double* local) {
+    const int count = (side == kLeft || side == kRight) ? G.ny : G.nx;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const double sign = (side == kLeft || side == kBottom) ? 1.0 : -1.0;
+    double t[3];
+    for (int d = 0; d < 2 + nee; ++d) {
+        int x, y;
+        if (side == kLeft) { x = d; y = k; }
+        else if (side == kRight) { x = G.nx - 1 - d; y = k; }
+        else if (side == kBottom) { x = k; y = d; }
+        else { x = k; y = G.ny - 1 - d; }
+        t[d] = node_T<S, NG>(src, G, C, x, y);
+    }
+    const double dtdn = nee ? (-3.0 * t[0] + 4.0 * t[1] - t[2]) / 2.0 : (9.0 * t[0] - t[1] - 8.0 * tw) / 3.0;
+    local[k] = -length * (sign * dtdn) / dT;
+}
+
+// Mean (midpoint rule, or the trapezoidal rule for walls through the nodes)
+// and maximum with its index, one block in a fixed order: thread j sums
+// local[j], local[j + 256], ..., then waves, then the block.
+__global__ __launch_bounds__(256) void k_nusselt_reduce(const double* __restrict__ local, int count, int nee,
+                                                        double* out) {
     __shared__ double s_sum[4], s_max[4];
     __shared__ int s_idx[4];
-    const int count = (side == kLeft || side == kRight) ? G.ny : G.nx;
-    const double sign = (side == kLeft || side == kBottom) ? 1.0 : -1.0;
     double sum = 0.0, best = -DBL_MAX;
     int ibest = 0x7fffffff;
     for (int k = threadIdx.x; k < count; k += blockDim.x) {
-        double t[3];
-        for (int d = 0; d < 2 + nee; ++d) {
-            int x, y;
-            if (side == kLeft) { x = d; y = k; }
-            else if (side == kRight) { x = G.nx - 1 - d; y = k; }
-            else if (side == kBottom) { x = k; y = d; }
-            else { x = k; y = G.ny - 1 - d; }
-            t[d] = node_T<S, NG>(src, G, C, x, y);
-        }
-        const double dtdn = nee ? (-3.0 * t[0] + 4.0 * t[1] - t[2]) / 2.0 : (9.0 * t[0] - t[1] - 8.0 * tw) / 3.0;
-        const double nu = -length * (sign * dtdn) / dT;
-        if (local) local[k] = nu;
+        const double nu = local[k];
         sum += (nee && (k == 0 || k == count - 1)) ? 0.5 * nu : nu;
         if (nu > best) { best = nu; ibest = k; }
     }
@@ -1155,8 +1168,13 @@ hipError_t launch_unstream(int storage, int ng, const Geom& G, const Coeffs& C, 
 
 hipError_t launch_nusselt(int storage, int ng, const Geom& G, const Coeffs& C, const void* src, int side, double tw,
                           double length, double dT, int nee, double* local, double* out3, hipStream_t st) {
-    LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_nusselt<S, NG>), dim3(1), dim3(256), 0, st, G, C,
-                                                 static_cast<const S*>(src), side, tw, length, dT, nee, local, out3));
+    const int count = (side == kLeft || side == kRight) ? G.ny : G.nx;
+    LBM_DISPATCH(storage, ng, hipLaunchKernelGGL((k_nusselt_local<S, NG>), dim3(blocks_for(count, 256)), dim3(256), 0,
+                                                 st, G, C, static_cast<const S*>(src), side, tw, length, dT, nee,
+                                                 local));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_nusselt_reduce, dim3(1), dim3(256), 0, st, local, count, nee, out3);
     return hipGetLastError();
 }
 
