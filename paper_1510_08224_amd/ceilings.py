@@ -4,9 +4,11 @@
     python -m paper_1510_08224_amd.ceilings [--gib 2]
 
 Streams of 2 GiB buffers (far beyond the 256 MB Infinity Cache): copy
-(read + write), read-only, write-only, each over several grid sizes; and
-the step's 14-plane pull pattern without arithmetic on a 2048 x 2048 and a
-4096 x 4096 lattice.  Times come from HIP events; one JSON object."""
+(read + write), read-only, write-only, each over several grid sizes, and a
+copy of one 16-byte element per thread; and the step's 14-plane pull
+pattern without arithmetic on a 2048 x 2048 and a 4096 x 4096 lattice, in
+separate planes and in the step kernel's row-interleaved layout.  Times
+come from HIP events; one JSON object."""
 from __future__ import annotations
 
 import argparse
@@ -28,6 +30,8 @@ def _lib():
     L.bw_read.argtypes = [vp, ll, ctypes.c_int, vp, vp]
     L.bw_write.argtypes = [vp, ll, ctypes.c_int, vp]
     L.bw_pull14.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ll, vp]
+    L.bw_copy1.argtypes = [vp, vp, ll, vp]
+    L.bw_pull14_rows.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     return L
 
 
@@ -60,7 +64,8 @@ def measure(gib: float = 2.0) -> dict:
         res[f"copy_blocks{blocks}_GBs"] = round(2 * nb / _time(lambda: L.bw_copy(pa, pb, nb, blocks, st)) / 1e9, 1)
         res[f"read_blocks{blocks}_GBs"] = round(nb / _time(lambda: L.bw_read(pa, nb, blocks, po, st)) / 1e9, 1)
         res[f"write_blocks{blocks}_GBs"] = round(nb / _time(lambda: L.bw_write(pb, nb, blocks, st)) / 1e9, 1)
-    res["copy_best_GBs"] = max(v for k, v in res.items() if k.startswith("copy_blocks"))
+    res["copy_1x16B_GBs"] = round(2 * nb / _time(lambda: L.bw_copy1(pa, pb, nb, st)) / 1e9, 1)
+    res["copy_best_GBs"] = max(v for k, v in res.items() if k.startswith("copy_"))
     del a, b
     for n in (2048, 4096):
         for eb in (8, 4, 2):
@@ -70,6 +75,8 @@ def measure(gib: float = 2.0) -> dict:
             pA, pB = ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr())
             t = _time(lambda: L.bw_pull14(eb, pA, pB, n, n, n, plane, st))
             res[f"pull14_n{n}_b{eb}_GBs"] = round(28 * eb * n * n / t / 1e9, 1)
+            t = _time(lambda: L.bw_pull14_rows(eb, pA, pB, n, n, n, st))
+            res[f"pull14_rows_n{n}_b{eb}_GBs"] = round(28 * eb * n * n / t / 1e9, 1)
             del A, B
     return res
 

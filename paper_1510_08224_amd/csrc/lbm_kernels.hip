@@ -585,7 +585,8 @@ __device__ __forceinline__ void fused_tile(const Geom& G, const Coeffs& C, const
 // Waves per SIMD the fused kernels ask the compiler for: what their LDS
 // allows per CU (FP64 D2Q5 is bound by its LDS at four and asks nothing).
 // FP64: 6 without temperature, 4 for D2Q9 thermal (a 28-byte spill);
-// FP32/FP16: 8, 6 and 4.
+// FP32/FP16: 8, 6 and 4.  FP32/FP16 D2Q5 stops at 6 below the 8 its LDS
+// would allow: at 8 it spills 35 VGPRs for a 1% faster step on MI355X.
 template <class S>
 constexpr int fuse2_waves(int NG) {
     return std::is_same<S, double>::value ? (NG == 0 ? 6 : (NG == 9 ? 4 : 1)) : (NG == 0 ? 8 : (NG == 5 ? 6 : 4));
@@ -892,10 +893,11 @@ __device__ __forceinline__ void residual_node(const S* __restrict__ src, const G
     snap[2 * n + k] = m.T;
 }
 
-// Block max / sum of (d, bad) in a fixed order; lane 0 of wave 0 returns it.
+// Block max / sum of (d, bad) in a fixed order (blocks of up to 1024
+// threads); lane 0 of wave 0 returns it.
 __device__ __forceinline__ void block_maxsum(double& d, unsigned long long& bad) {
-    __shared__ double s_max[4];
-    __shared__ unsigned long long s_bad[4];
+    __shared__ double s_max[16];
+    __shared__ unsigned long long s_bad[16];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         d = fmax(d, __shfl_down(d, o, 64));
@@ -929,11 +931,30 @@ __global__ __launch_bounds__(256) void k_residual(Geom G, Coeffs C, const S* __r
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_final(const double* pmax, const unsigned long long* pbad, int nparts,
-                                                      double* out) {
+// One block of 1024 threads, each with eight partials in flight at a time
+// (a 256-thread loop of dependent loads took 22 us for the 16384 partials
+// of a 2048^2 lattice).  Maximum and integer sum are exact in any order.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* pmax, const unsigned long long* pbad,
+                                                                 int nparts, double* out) {
+    constexpr int U = 8;
     double d = 0.0;
     unsigned long long b = 0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) { d = fmax(d, pmax[i]); b += pbad[i]; }
+    for (int i0 = threadIdx.x; i0 < nparts; i0 += U * kReduceThreads) {
+        double v[U];
+        unsigned long long c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kReduceThreads;
+            v[u] = i < nparts ? pmax[i] : 0.0;
+            c[u] = i < nparts ? pbad[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            d = fmax(d, v[u]);
+            b += c[u];
+        }
+    }
     block_maxsum(d, b);
     if (threadIdx.x == 0) {
         out[0] = d;
@@ -1187,7 +1208,7 @@ hipError_t launch_residual(int storage, int ng, const Geom& G, const Coeffs& C, 
                                                  static_cast<const S*>(src), snap, update_only ? 1 : 0, pmax, pbad));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, pmax, pbad, nb, out2);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, st, pmax, pbad, nb, out2);
     return hipGetLastError();
 }
 
