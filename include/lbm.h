@@ -318,9 +318,11 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           per two steps.  Bitwise the same results.  Used
  *                           with every collision operator on buffers below
  *                           4 GiB and, with NEE walls, when no edge tile is
- *                           one node wide or high (tiles are 64 x 8 nodes:
- *                           nx % 64 == 1 or ny % 8 == 1); otherwise steps
- *                           run singly (lbm_steps_per_launch tells which).
+ *                           one node wide or high (tiles are 64 x 12 nodes
+ *                           for FP32/FP16 storage with the D2Q5 model, 64 x 8
+ *                           otherwise: nx % 64 == 1 or ny % 12 (8) == 1);
+ *                           otherwise steps run singly
+ *                           (lbm_steps_per_launch tells which).
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; fused pairs for FP64 and FP32
  * storage, and for FP16 storage with a temperature field unless
@@ -392,11 +394,11 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
 
 /* Fused pairs of time steps for the whole batch (the two-step kernel of
  * lbm_set_launch's LBM_POLICY_FUSE2, one launch per pair for all members,
- * 64 x 8 tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
+ * the same tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
  * or LBM_POLICY_FUSE2.  The default fuses pairs for FP64 and FP32
  * storage and steps FP16 once per launch.  Fused pairs apply only
  * when every member qualifies (buffers below 4 GiB; with walls by
- * non-equilibrium extrapolation, nx % 64 != 1 and ny % 8 != 1); else the
+ * non-equilibrium extrapolation, no one-node edge tile); else the
  * batch steps one launch per step.  Results are bitwise the same either
  * way.  Takes effect at the next lbm_batch_step.  LBM_ERR_ARG for any
  * other value. */

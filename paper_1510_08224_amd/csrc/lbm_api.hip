@@ -78,7 +78,7 @@ struct lbm_batch {
     // Fused pairs of steps: the policy asked for (LBM_POLICY_DEFAULT, 0 or
     // LBM_POLICY_FUSE2), whether the current members use them, whether the
     // stores of either kernel keep the default cache policy (all members'
-    // buffers within the 256 MB last-level cache), and the 64 x 8 tile table.
+    // buffers within the 256 MB last-level cache), and the fused tile table.
     int policy = LBM_POLICY_DEFAULT;
     bool fuse = false, keep = false;
     // Tuning of the launches (lbm_batch_set_tuning): XCD order of the tile
@@ -231,8 +231,9 @@ static void default_policy(lbm_solver* h) {
         // every plane) fits there; past that, strips of 8 tiles per XCD do.
         // FP64 lattices 48 or more tiles wide take strips at any row size
         // (3072^2 and 4096^2, every model: +2.3 to +5.4%; at 2048^2 bands
-        // win by up to 7%); FP32 keeps bands below 3 MiB per row (the one
-        // exception measured: D2Q5 at 4096^2, where strips are 4-5% faster).
+        // win by up to 7%); FP32 keeps bands below 3 MiB per row (D2Q5 at
+        // 4096^2, 3.3 MiB per row of its 12-row tiles, takes strips: 343.8
+        // against 357.7 us per launch with bands).
         const int ty = fuse2_rows(h->storage, h->ng);
         const int tiles_x = (h->nx + 63) / 64;
         const double row = (double)tiles_x * 66.0 * (ty + 2) * (9 + h->ng) * storage_bytes(h->storage);

@@ -216,11 +216,15 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const Coeffs* __restrict_
 // registers (a loop over rows made it hold them in vector registers, at
 // the cost of occupancy).  The kernel is bound by latency more than by
 // arithmetic or bandwidth; TY trades halo work against workgroups per CU.
-// Every fused kernel takes TY = 8 (measured on MI355X: FP64 D2Q5 2048^2
+// The fused kernels take TY = 8 (measured on MI355X: FP64 D2Q5 2048^2
 // 9.8 TB/s against 9.6 at TY = 4, 4096^2 10.4 against 9.8; with one slot
 // per thread, FP32 D2Q5 and both D2Q9 thermal kernels 2-13% faster than
 // at TY = 4, which they had taken while two slots per thread limited their
-// occupancy).
+// occupancy), except FP32/FP16 D2Q5, which takes TY = 12: 768-thread
+// workgroups, two per CU, 1.20 first-step slots per tile node against
+// 1.29, and 1.7% (2048^2), 2.3% (4096^2, strips) and 1.4% (a batch of 256
+// cavities) faster; TY = 10 and 16 were 10-18% slower, and TY = 12 cost the
+// FP32 flow alone 8% (it keeps 8).
 // Each thread steps one first-step slot at a time; the kernels ask the
 // compiler for as many waves per SIMD as their LDS allows (fuse2_waves).
 // Two slots per thread in flight together held twice the populations in
@@ -243,7 +247,7 @@ struct Fuse2 {
 #ifdef LBM_FUSE2_ROWS
     static constexpr int TY = LBM_FUSE2_ROWS;   // build-time override of the tile height
 #else
-    static constexpr int TY = 8;
+    static constexpr int TY = (!std::is_same<S, double>::value && NG == 5) ? 12 : 8;
 #endif
     static constexpr int NT = TX * TY;      // threads: one per tile node
     static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
