@@ -87,7 +87,7 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
     if launch:
         S.set_launch(*launch)
     if single_steps:
-        S.set_launch(policy=S.get_launch()[3] & ~lbm.LBM_POLICY_FUSE2)
+        S.set_launch(policy=S.get_launch()[3] & ~(lbm.LBM_POLICY_FUSE2 | lbm.LBM_POLICY_FUSE3))
     shape = S.get_launch()
     spl = S.steps_per_launch
     thermal = NG[model] > 0
@@ -102,12 +102,16 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
     done = 0
     while done < steps:
         k = min(REDUCE_EVERY, steps - done)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        # whole launches of spl steps between e0 and e1 (the roofline's launch
+        # time), the steps left over (shorter launches) between e1 and e2
+        kk = k - k % spl
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record(st)
-        S.step(k)
+        S.step(kk)
         e1.record(st)
-        segs.append((e0, e1, k))
+        S.step(k - kk)
+        e2.record(st)
+        segs.append((e0, e1, e2, kk))
         done += k
         if done % REDUCE_EVERY == 0 or done == steps:
             if thermal:
@@ -117,11 +121,13 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
     S.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in segs)
+    sweep_ms = sum(a.elapsed_time(c) for a, _, c, _ in segs)
+    whole_ms = sum(a.elapsed_time(b) for a, b, _, kk in segs if kk)
+    launches = sum(kk for *_, kk in segs) // spl
     nu = S.nusselt(1)[0] if thermal else None
     S.close()
     avg_step_s = sweep_ms / 1e3 / steps
-    avg_launch_s = spl * avg_step_s
+    avg_launch_s = whole_ms / 1e3 / launches if launches else spl * avg_step_s
     traffic = measured_traffic(storage if model == "d2q5" else f"{model}_{storage}", nodes, spl)
     return {
         "storage": storage,
@@ -142,7 +148,7 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
 
 def roofline(storage: str, model: str, nodes: int, spl: int, launch_s: float, traffic) -> dict:
     """Roofline of one launch of the step kernel.  A launch advances `spl`
-    steps (2 with fused pairs) and must read and write the whole state once:
+    steps (3 or 2 when fused) and must read and write the whole state once:
     its algorithmic HBM bytes are 2 (9 + NG) values per node whatever `spl`
     is, and `achieved` is those bytes over the launch time.  The
     single-step equivalent (spl times that: the bytes one-step launches
@@ -253,9 +259,9 @@ def main():
                 models[m]["workload"] = mpb.name
     colls, colls1 = {}, {}
     if args.collisions != "none":
-        # every operator in the default launch (fused pairs: the step is bound
-        # by latency and arithmetic, so operator costs can show) and one step
-        # per launch (bound by bandwidth)
+        # every operator in the default launch (fused steps: bound by latency
+        # and arithmetic, so operator costs can show) and one step per launch
+        # (bound by bandwidth)
         colls["mrt"] = main_res
         colls1["mrt"] = time_storage(args.storage, pb, args.steps, args.warmup, launch, single_steps=True)
         codes = {"bgk": W.COLL_BGK, "ortho_mrt": W.COLL_ORTHO}

@@ -322,21 +322,37 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           for FP32/FP16 storage with the D2Q5 model, 64 x 8
  *                           otherwise: nx % 64 == 1 or ny % 12 (8) == 1);
  *                           otherwise steps run singly
- *                           (lbm_steps_per_launch tells which).
+ *                           (lbm_steps_per_launch tells which);
+ *   LBM_POLICY_FUSE3        lbm_step runs three time steps in one launch
+ *                           where a kernel exists (FP64 and FP32 storage,
+ *                           the D2Q5 model or no temperature field, every
+ *                           collision operator): a workgroup steps its
+ *                           64 x 8 tile grown by two nodes from HBM into
+ *                           LDS, the tile grown by one node from LDS, and
+ *                           the tile into HBM, so the state crosses HBM
+ *                           once per three steps.  Bitwise the same
+ *                           results.  Same conditions as LBM_POLICY_FUSE2
+ *                           (8-row tiles: nx % 64 == 1 or ny % 8 == 1 with
+ *                           NEE walls falls back); steps left over run as
+ *                           a pair (with LBM_POLICY_FUSE2) or singly, and
+ *                           so does every step where no kernel exists.
  * The default follows the storage and the footprint F of both population
- * buffers: kept stores while F <= 256 MiB; fused pairs for FP64 and FP32
- * storage, and for FP16 storage with a temperature field unless
- * 128 MiB < F <= 256 MiB, with bands, or strips (with a multiple of 8
- * tiles per row) once one row of fused tiles (tiles and halos, every
+ * buffers: kept stores while F <= 256 MiB; three steps per launch with
+ * bands where that kernel exists and F > 256 MiB; otherwise fused pairs
+ * for FP64 and FP32 storage, and for FP16 storage with a temperature field
+ * unless 128 MiB < F <= 256 MiB, with bands, or strips (with a multiple of
+ * 8 tiles per row) once one row of fused tiles (tiles and halos, every
  * plane) exceeds 3 MiB or an FP64 lattice is 48 or more tiles wide;
- * otherwise (FP16) single steps with bands while F <= 500 MiB. */
+ * otherwise (FP16) single steps with bands while F <= 500 MiB.  Fused pairs
+ * stay allowed beside three-step launches. */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
     LBM_POLICY_XCD_BANDS = 1,
     LBM_POLICY_KEEP_STORES = 2,
     LBM_POLICY_XCD_STRIPS = 4,
-    LBM_POLICY_FUSE2 = 8
+    LBM_POLICY_FUSE2 = 8,
+    LBM_POLICY_FUSE3 = 16
 };
 
 /* Launch shape of the step kernel: block_x threads along x (64, 128 or
@@ -348,7 +364,8 @@ enum {
 int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread, int32_t policy);
 
 /* Time steps one step-kernel launch advances with the current parameters
- * and launch settings: 2 when fused pairs are in use, else 1. */
+ * and launch settings: 3 when three-step launches are in use, 2 when fused
+ * pairs are, else 1 (remainders of a step count run shorter launches). */
 int lbm_steps_per_launch(const lbm_solver* h, int32_t* steps);
 int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread,
                    int32_t* policy);

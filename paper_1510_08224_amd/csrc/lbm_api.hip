@@ -218,14 +218,23 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // states of 128-256 MiB, which stay in the last-level cache under kept
 // single stores (2048^2 D2Q5, 235 MB: 16% faster than fused pairs); without
 // temperature FP16 keeps single steps, which win from 1024^2 up.  Fused
-// pairs run best with XCD bands.
+// pairs run best with XCD bands.  Three steps per launch (FP64 and FP32
+// storage, D2Q5 or no temperature field) win once the state outgrows the
+// last-level cache: 2048^2 to 4096^2, FP64 D2Q5 22-25% and the flow alone
+// 21-22% less time per step than fused pairs, FP32 D2Q5 8-12% and the flow
+// alone 13%; at 1024^2 (a state within the cache) fused pairs stay 7%
+// (FP64) and 27% (FP32) faster.  Three-step launches need XCD bands: with
+// strips or round robin they took 13-55% longer (2048^2 to 4096^2).
 static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
     h->L.order = (ws <= 500.0 * mib || (h->storage == LBM_F64 && ws <= 1024.0 * mib)) ? 1 : 0;
     h->L.fuse2 = h->storage == LBM_F64 || h->storage == LBM_F32 ||
                  (h->storage == LBM_F16 && h->ng > 0 && !(ws > 128.0 * mib && ws <= 256.0 * mib));
-    if (h->L.fuse2) {
+    h->L.fuse3 = fuse3_rows(h->storage, h->ng) > 0 && ws > 256.0 * mib;
+    if (h->L.fuse3) {
+        h->L.order = 1;
+    } else if (h->L.fuse2) {
         // Bands keep the halo rows a fused tile shares with the tile row
         // below in the XCD's 4 MB L2 while one row of tiles (tile and halo,
         // every plane) fits there; past that, strips of 8 tiles per XCD do.
@@ -727,14 +736,30 @@ static bool fuse2_active(const lbm_solver* h) {
     return true;
 }
 
+// Whether lbm_step may run three time steps per launch: asked for by the
+// policy, a kernel built for the storage and model, buffers below 4 GiB,
+// and, with NEE walls, no last tile one node wide or high.
+static bool fuse3_active(const lbm_solver* h) {
+    if (!h->L.fuse3 || !h->L.buffer) return false;
+    if (h->buf_bytes >= (1ull << 32)) return false;
+    const int ty = fuse3_rows(h->storage, h->ng);
+    if (ty <= 0) return false;
+    if (h->C.any_nee && (h->nx % 64 == 1 || h->ny % ty == 1)) return false;
+    return true;
+}
+
 // Sweeps of `steps` time steps from buffer `cur`; returns the number of
 // launches (each swaps the buffers once) or a negative HIP error.
 static hipError_t launch_steps(lbm_solver* h, int cur, int64_t steps, int64_t* launches) {
-    const bool fuse = fuse2_active(h);
+    const bool fuse = fuse2_active(h), fuse3 = fuse3_active(h);
     int64_t n = 0;
     while (steps > 0) {
         hipError_t e;
-        if (fuse && steps >= 2) {
+        if (fuse3 && steps >= 3) {
+            e = launch_sweep3(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
+                              h->stream);
+            steps -= 3;
+        } else if (fuse && steps >= 2) {
             e = launch_sweep2(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
                               h->stream);
             steps -= 2;
@@ -1116,7 +1141,8 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
         !(L.rows == 1 || L.rows == 2))
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2}");
     if (policy < LBM_POLICY_DEFAULT ||
-        policy > (LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES | LBM_POLICY_XCD_STRIPS | LBM_POLICY_FUSE2) ||
+        policy > (LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES | LBM_POLICY_XCD_STRIPS | LBM_POLICY_FUSE2 |
+                  LBM_POLICY_FUSE3) ||
         (policy >= 0 && (policy & LBM_POLICY_XCD_BANDS) && (policy & LBM_POLICY_XCD_STRIPS)))
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: unknown policy (bands and strips exclude each other)");
     h->L = L;
@@ -1126,6 +1152,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
         h->L.order = (policy & LBM_POLICY_XCD_BANDS) ? 1 : ((policy & LBM_POLICY_XCD_STRIPS) ? 2 : 0);
         h->L.keep = (policy & LBM_POLICY_KEEP_STORES) != 0;
         h->L.fuse2 = (policy & LBM_POLICY_FUSE2) != 0;
+        h->L.fuse3 = (policy & LBM_POLICY_FUSE3) != 0;
     }
     drop_graphs(h);
     if (h->batch) batch_invalidate(h->batch);
@@ -1134,7 +1161,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
 
 int lbm_steps_per_launch(const lbm_solver* h, int32_t* steps) {
     if (!h || !steps) return fail(nullptr, LBM_ERR_ARG, "lbm_steps_per_launch: NULL argument");
-    *steps = fuse2_active(h) ? 2 : 1;
+    *steps = fuse3_active(h) ? 3 : (fuse2_active(h) ? 2 : 1);
     return LBM_OK;
 }
 
@@ -1146,7 +1173,8 @@ int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int3
     if (rows_per_thread) *rows_per_thread = h->L.rows;
     if (policy)
         *policy = (h->L.order == 1 ? LBM_POLICY_XCD_BANDS : 0) | (h->L.order == 2 ? LBM_POLICY_XCD_STRIPS : 0) |
-                  (h->L.keep ? LBM_POLICY_KEEP_STORES : 0) | (h->L.fuse2 ? LBM_POLICY_FUSE2 : 0);
+                  (h->L.keep ? LBM_POLICY_KEEP_STORES : 0) | (h->L.fuse2 ? LBM_POLICY_FUSE2 : 0) |
+                  (h->L.fuse3 ? LBM_POLICY_FUSE3 : 0);
     return LBM_OK;
 }
 

@@ -291,21 +291,22 @@ struct SlotOrder {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// w / d for 0 <= w < 2^12 and 1 <= d <= 68, with inv = 1 / d: the margin
-// of (w + 1/2) / d from an integer (at least 1 / 136) dwarfs the rounding
-// of the product.
+// w / d for 0 <= w < 2^12 and 1 <= d < 2^12, with inv = 1 / d: the margin
+// of (w + 1/2) / d from an integer (at least 1 / (2d)) dwarfs the rounding
+// of the product (below 2^12 / d * 2^-23).
 __device__ __forceinline__ int small_div(int w, float inv) { return (int)(((float)w + 0.5f) * inv); }
 
-template <class F>
-__device__ __forceinline__ SlotOrder slot_order(const Geom& G, int x0, int y0) {
+// The slot grid is EW x EH, the tile grown by MG nodes on every side.
+template <int EW, int EH, int MG>
+__device__ __forceinline__ SlotOrder slot_order_m(const Geom& G, int x0, int y0) {
     SlotOrder o;
-    // slot column l holds x = x0 - 1 + l; rows likewise
-    const int cv0 = G.px ? 0 : clampi(1 - x0, 0, F::EW), cv1 = G.px ? F::EW : clampi(G.nx - x0 + 1, cv0, F::EW);
-    const int rv0 = G.py ? 0 : clampi(1 - y0, 0, F::EH), rv1 = G.py ? F::EH : clampi(G.ny - y0 + 1, rv0, F::EH);
-    o.ci0 = clampi(2 - x0, cv0, cv1);
-    o.ci1 = clampi(G.nx - x0, o.ci0, cv1);
-    o.ri0 = clampi(2 - y0, rv0, rv1);
-    o.ri1 = clampi(G.ny - y0, o.ri0, rv1);
+    // slot column l holds x = x0 - MG + l; rows likewise
+    const int cv0 = G.px ? 0 : clampi(MG - x0, 0, EW), cv1 = G.px ? EW : clampi(G.nx - x0 + MG, cv0, EW);
+    const int rv0 = G.py ? 0 : clampi(MG - y0, 0, EH), rv1 = G.py ? EH : clampi(G.ny - y0 + MG, rv0, EH);
+    o.ci0 = clampi(MG + 1 - x0, cv0, cv1);
+    o.ci1 = clampi(G.nx - 1 - x0 + MG, o.ci0, cv1);
+    o.ri0 = clampi(MG + 1 - y0, rv0, rv1);
+    o.ri1 = clampi(G.ny - 1 - y0 + MG, o.ri0, rv1);
     o.cv0 = cv0;
     o.rv0 = rv0;
     o.wv = cv1 - cv0;
@@ -323,6 +324,11 @@ __device__ __forceinline__ SlotOrder slot_order(const Geom& G, int x0, int y0) {
     o.inv_wl = 1.0f / (float)(o.wl > 0 ? o.wl : 1);
     o.inv_wr = 1.0f / (float)(o.wr > 0 ? o.wr : 1);
     return o;
+}
+
+template <class F>
+__device__ __forceinline__ SlotOrder slot_order(const Geom& G, int x0, int y0) {
+    return slot_order_m<F::EW, F::EH, 1>(G, x0, y0);
 }
 
 // Slot coordinates (column l, row m of the slot grid) of work item w < count.
@@ -620,6 +626,346 @@ void k_sweep2_batch(
     const int sel = (M.cur0 + parity) & 1;
     fused_tile<S, NG, MODE, kCollMRT>(M.G, M.C, static_cast<const S*>(M.buf[sel]), static_cast<S*>(M.buf[sel ^ 1]),
                                       M.buf_bytes, t.x0, t.y0, lds);
+}
+
+// ---------------------------------------------------------------------------
+// K >= 3 time steps per launch.  A workgroup owns a 64 x TY tile.  Step 1
+// runs on the tile grown by K - 1 nodes on every side, reading the state
+// from HBM as the single-step kernel does; step s runs on the tile grown by
+// K - s nodes, pulling the post-collision populations of step s - 1 from
+// LDS; step K runs on the tile and stores to HBM.  The state crosses HBM
+// once per K steps; the margins cost sum_s (64 + 2(K - s))(TY + 2(K - s)) /
+// (64 TY K) - 1 extra collisions per node and step.  The result is bitwise
+// the result of K single steps.
+//
+// LDS holds one plane per population over the region of step 2 (the tile
+// grown by K - 2 nodes), indexed by the pulling node: a node of step s >= 2
+// reads every population at its own index; a node of step s - 1 writes
+// population i at the index of the node that pulls it, its own position +
+// e_i, when that node takes part in step s.  Steps 2 .. K - 1 update the
+// planes in place: every node reads and collides, a barrier, then every
+// node writes (each index has one writer and one reader per step).  Where
+// the link into a node of step s crosses a non-periodic side, no node
+// exists at its source; the node itself writes the wall rule of the pull at
+// its own index in that plane in step s - 1, the one index of the plane no
+// other node writes.  Wall nodes rebuilt by extrapolation read their fluid
+// neighbour's pulls, which lie in the same step's region (the launch rules
+// out one-node edge tiles on such sides).  FP64 and FP32 storage.
+// ---------------------------------------------------------------------------
+// Two LDS buffers (the middle steps read one and write the other, no
+// results held across a barrier) where both fit in half a CU's LDS: FP32.
+template <class S>
+constexpr bool fusek_double_buffer() {
+#ifdef LBM_FUSE3_DB
+    return LBM_FUSE3_DB && !std::is_same<S, double>::value;   // build-time override
+#else
+    return !std::is_same<S, double>::value;
+#endif
+}
+
+template <class S, int NG, int K, int TY_>
+struct FuseK {
+    using R = typename Codec<S>::R;
+    static constexpr bool DB = fusek_double_buffer<S>();
+    static_assert(K >= 3, "two steps per launch are the fused pair");
+    static_assert(!kRefT<S>, "FP16 storage references its deviations to the node position");
+    static constexpr int NP = 9 + NG;
+    static constexpr int TX = 64;
+    static constexpr int TY = TY_;
+    static constexpr int NT = TX * TY;          // threads: one per tile node
+    static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
+    static constexpr int WM = K - 2;            // margin of the LDS window (step 2's region)
+    static constexpr int WX = TX + 2 * WM, WY = TY + 2 * WM;
+    static constexpr int PLANE = WX * WY;
+    static constexpr int M1 = K - 1;            // margin of the first step
+    static constexpr int E1X = TX + 2 * M1, E1Y = TY + 2 * M1;
+    static constexpr int SLOTS1 = E1X * E1Y;
+    static constexpr int LDS_VALUES = (DB ? 2 : 1) * NP * PLANE;
+    static_assert(LDS_VALUES * (int)sizeof(R) <= 81920, "fused tile needs more than half the LDS of a CU");
+    // LDS index of plane p at the node (sx, sy) relative to the tile origin
+    static __device__ __forceinline__ int at(int p, int sx, int sy) { return p * PLANE + (sy + WM) * WX + (sx + WM); }
+};
+
+// Whether tile-relative (sx, sy) lies in the tile grown by MG nodes.
+template <class F, int MG>
+__device__ __forceinline__ bool in_region(int sx, int sy) {
+    return sx >= -MG && sx < F::TX + MG && sy >= -MG && sy < F::TY + MG;
+}
+
+// Population I of the node at (sx, sy) to the node (sx, sy) + e_I that
+// pulls it, if that node takes part in the next step (region of margin MN).
+template <class F, int MN, int P0, int I>
+__device__ __forceinline__ void fk_put(typename F::R* lds, int sx, int sy, typename F::R v) {
+    const int tx = sx + ex(I), ty = sy + ey(I);
+    if (in_region<F, MN>(tx, ty)) lds[F::at(P0 + I, tx, ty)] = v;
+}
+
+template <class F, int MN, int P0, int... I>
+__device__ __forceinline__ void fk_put_set(typename F::R* lds, int sx, int sy, const typename F::R* v,
+                                           std::integer_sequence<int, I...>) {
+    (fk_put<F, MN, P0, I>(lds, sx, sy, v[I]), ...);
+}
+
+// The wall rule of link I into lattice node (x, y), at tile-relative
+// (sx, sy), if the link crosses a non-periodic side (the arithmetic of the
+// pull); it goes to the node's own index in plane I.
+template <class F, int NG, int I>
+__device__ __forceinline__ void fk_wall(typename F::R* lds, const Geom& G, const Coeffs& C, int x, int y, int sx,
+                                        int sy, const typename F::R f[9], const typename F::R g[gdim(NG)]) {
+    using R = typename F::R;
+    constexpr int dx = ex(I), dy = ey(I);
+    const int px = x - dx, py = y - dy;
+    int side = -1;
+    if (dy != 0 && (py < 0 || py >= G.ny) && !G.py) side = py < 0 ? kBottom : kTop;
+    if (dx != 0 && (px < 0 || px >= G.nx) && !G.px && side < 0) side = px < 0 ? kLeft : kRight;
+    if (side < 0) return;
+    lds[F::at(I, sx, sy)] = f[opp(I)] + (R)C.bbf[side][I];
+    if constexpr (I < NG) lds[F::at(9 + I, sx, sy)] = (R)C.gsign[side] * g[opp(I)] + (R)C.gconst[side][I];
+}
+
+template <class F, int NG, int... I>
+__device__ __forceinline__ void fk_walls(typename F::R* lds, const Geom& G, const Coeffs& C, int x, int y, int sx,
+                                         int sy, const typename F::R f[9], const typename F::R g[gdim(NG)],
+                                         std::integer_sequence<int, I...>) {
+    (fk_wall<F, NG, I + 1>(lds, G, C, x, y, sx, sy, f, g), ...);
+}
+
+// The post-collision populations of lattice node (x, y) at tile-relative
+// (sx, sy) into LDS for the next step, whose region has margin MN: each to
+// the node that pulls it and, with WALLS, the wall rules of the node's own
+// links if it takes part in the next step.
+template <class F, int NG, int MN, bool WALLS>
+__device__ __forceinline__ void fk_keep(typename F::R* lds, const Geom& G, const Coeffs& C, int x, int y, int sx,
+                                        int sy, const typename F::R f[9], const typename F::R g[gdim(NG)]) {
+    fk_put_set<F, MN, 0>(lds, sx, sy, f, std::make_integer_sequence<int, 9>{});
+    if constexpr (NG > 0) fk_put_set<F, MN, 9>(lds, sx, sy, g, std::make_integer_sequence<int, NG>{});
+    if constexpr (WALLS) {
+        const bool wall = (!G.px && (x == 0 || x == G.nx - 1)) || (!G.py && (y == 0 || y == G.ny - 1));
+        if (wall && in_region<F, MN>(sx, sy))
+            fk_walls<F, NG>(lds, G, C, x, y, sx, sy, f, g, std::make_integer_sequence<int, 8>{});
+    }
+}
+
+// Pre-collision populations of a node of step s >= 2 at tile-relative
+// (sx, sy), lattice (x, y), from LDS: its own index, or, for a wall node
+// rebuilt by extrapolation (NEE), its fluid neighbour's.
+template <class F, int NG, bool NEE>
+__device__ __forceinline__ void fk_read(const typename F::R* lds, const Geom& G, const Coeffs& C, int x, int y, int sx,
+                                        int sy, typename F::R f[9], typename F::R g[gdim(NG)]) {
+    using R = typename F::R;
+    if (NEE && nee_node_at(G, C, x, y)) {
+        const NeeWall w = nee_wall(G, C, x, y);
+        const int fx = sx + (w.fx - x), fy = sy + (w.fy - y);
+        R ff[9], gf[gdim(NG)];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ff[i] = lds[F::at(i, fx, fy)];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) gf[i] = lds[F::at(9 + i, fx, fy)];
+        nee_rebuild<R, NG>(w, C, ff, gf, f, g);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = lds[F::at(i, sx, sy)];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) g[i] = lds[F::at(9 + i, sx, sy)];
+    }
+}
+
+// Lattice coordinate of tile-relative position v along an axis of n nodes
+// starting at v0; false outside a non-periodic axis.
+__device__ __forceinline__ bool fk_axis(int v0, int v, int n, int periodic, int& out) {
+    int a = v0 + v;
+    if (a < 0 || a >= n) {
+        if (!periodic) return false;
+        a = ((a % n) + n) % n;
+    }
+    out = a;
+    return true;
+}
+
+// Step 1 of a general tile (walls, wraps, lattice edges) from HBM into LDS,
+// slots in interior-first order.
+template <class S, int NG, class F, int COLL>
+__device__ __forceinline__ void fk_first_general(__amdgpu_buffer_rsrc_t rs, const S* __restrict__ src, const Geom& G,
+                                                 const Coeffs& C, int x0, int y0, typename F::R* lds) {
+    using R = typename F::R;
+    const SlotOrder o = slot_order_m<F::E1X, F::E1Y, F::M1>(G, x0, y0);
+#pragma unroll
+    for (int w = threadIdx.x; w < F::SLOTS1; w += F::NT) {
+        if (w >= o.count) break;
+        int l, m;
+        slot_of(o, w, l, m);
+        const int sx = l - F::M1, sy = m - F::M1;
+        int x, y;
+        if (!fk_axis(x0, sx, G.nx, G.px, x) || !fk_axis(y0, sy, G.ny, G.py, y)) continue;
+        R f[9], g[gdim(NG)];
+        if (x >= 1 && x <= G.nx - 2 && y >= 1 && y <= G.ny - 2)
+            pull_interior_buf<S, NG>(rs, G, C, (unsigned)(y * G.pitch + x) * (unsigned)sizeof(S), f, g);
+        else
+            load_node<S, NG>(src, G, C, x, y, f, g);
+        const Macro mc = macro_at<S, R, NG>(f, g, C, x, y);
+        collide<R, NG, COLL>(f, g, mc, C);
+        fk_keep<F, NG, F::WM, true>(lds, G, C, x, y, sx, sy, f, g);
+    }
+}
+
+// Step 1 of an open tile (every slot pulls with the fast path; no wall node,
+// no wrap) from HBM into LDS.
+template <class S, int NG, class F, int COLL>
+__device__ __forceinline__ void fk_first_open(__amdgpu_buffer_rsrc_t rs, const Geom& G, const Coeffs& C, int x0,
+                                              int y0, typename F::R* lds) {
+    using R = typename F::R;
+#pragma unroll
+    for (int w = threadIdx.x; w < F::SLOTS1; w += F::NT) {
+        const int m = w / F::E1X, l = w - m * F::E1X;
+        const int sx = l - F::M1, sy = m - F::M1;
+        const int x = x0 + sx, y = y0 + sy;
+        R f[9], g[gdim(NG)];
+        pull_interior_buf<S, NG>(rs, G, C, (unsigned)(y * G.pitch + x) * (unsigned)sizeof(S), f, g);
+        const Macro mc = macro_at<S, R, NG>(f, g, C, x, y);
+        collide<R, NG, COLL>(f, g, mc, C);
+        fk_keep<F, NG, F::WM, false>(lds, G, C, x, y, sx, sy, f, g);
+    }
+}
+
+// A middle step (2 .. K - 1) on the tile grown by MG nodes.  With one LDS
+// buffer (in == out) it runs in place: every node reads and collides, then
+// (after a barrier) writes for the step on the tile grown by MG - 1, each
+// thread holding the results of its nodes across the barrier.  With two,
+// each node reads `in` and writes `out` at once.  Ends with a barrier.
+template <class S, int NG, class F, int COLL, int MG, bool OPEN>
+__device__ __forceinline__ void fk_middle(const Geom& G, const Coeffs& C, int x0, int y0,
+                                          const typename F::R* in, typename F::R* out) {
+    using R = typename F::R;
+    constexpr int RX = F::TX + 2 * MG, RY = F::TY + 2 * MG, N = RX * RY;
+    const bool nee = !OPEN && C.any_nee;
+    if constexpr (F::DB) {
+#pragma unroll
+        for (int w = threadIdx.x; w < N; w += F::NT) {
+            const int sy = w / RX - MG, sx = w - (sy + MG) * RX - MG;
+            int x = x0 + sx, y = y0 + sy;
+            if (!OPEN && !(fk_axis(x0, sx, G.nx, G.px, x) && fk_axis(y0, sy, G.ny, G.py, y))) continue;
+            R f[9], g[gdim(NG)];
+            if (nee) fk_read<F, NG, true>(in, G, C, x, y, sx, sy, f, g);
+            else fk_read<F, NG, false>(in, G, C, x, y, sx, sy, f, g);
+            const Macro mc = macro_at<S, R, NG>(f, g, C, x, y);
+            collide<R, NG, COLL>(f, g, mc, C);
+            fk_keep<F, NG, MG - 1, !OPEN>(out, G, C, x, y, sx, sy, f, g);
+        }
+        __syncthreads();
+        return;
+    }
+    typename F::R* lds = out;
+    constexpr int P = (N + F::NT - 1) / F::NT;
+    R f[P][9], g[P][gdim(NG)];
+    int xs[P], ys[P];
+    bool ok[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int w = (int)threadIdx.x + k * F::NT;
+        const int sy = w / RX - MG, sx = w - (sy + MG) * RX - MG;
+        int x = x0 + sx, y = y0 + sy;
+        ok[k] = w < N;
+        if (!OPEN && ok[k]) ok[k] = fk_axis(x0, sx, G.nx, G.px, x) && fk_axis(y0, sy, G.ny, G.py, y);
+        xs[k] = x;
+        ys[k] = y;
+        if (ok[k]) {
+            if (nee) fk_read<F, NG, true>(lds, G, C, x, y, sx, sy, f[k], g[k]);
+            else fk_read<F, NG, false>(lds, G, C, x, y, sx, sy, f[k], g[k]);
+            const Macro mc = macro_at<S, R, NG>(f[k], g[k], C, x, y);
+            collide<R, NG, COLL>(f[k], g[k], mc, C);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int w = (int)threadIdx.x + k * F::NT;
+        const int sy = w / RX - MG, sx = w - (sy + MG) * RX - MG;
+        if (ok[k]) fk_keep<F, NG, MG - 1, !OPEN>(lds, G, C, xs[k], ys[k], sx, sy, f[k], g[k]);
+    }
+    __syncthreads();
+}
+
+// The middle steps, margins K - 2 down to 1 (J = 0 .. K - 3); with two
+// buffers step J reads buffer J % 2 and writes the other.
+template <class S, int NG, class F, int COLL, bool OPEN, int... J>
+__device__ __forceinline__ void fk_middles(const Geom& G, const Coeffs& C, int x0, int y0, typename F::R* lds,
+                                           std::integer_sequence<int, J...>) {
+    constexpr int B = F::NP * F::PLANE;
+    (fk_middle<S, NG, F, COLL, F::WM - J, OPEN>(G, C, x0, y0, lds + (F::DB ? (J % 2) * B : 0),
+                                                 lds + (F::DB ? ((J + 1) % 2) * B : 0)),
+     ...);
+}
+
+// The buffer the last step reads.
+template <class F>
+__device__ __forceinline__ const typename F::R* fk_last_buffer(const typename F::R* lds) {
+    constexpr int K = F::M1 + 1;
+    return lds + (F::DB ? ((K - 2) % 2) * F::NP * F::PLANE : 0);
+}
+
+// The last step on the tile, pulling from LDS, and the store.
+template <class S, int NG, class F, int MODE, int COLL, bool OPEN>
+__device__ __forceinline__ void fk_last(__amdgpu_buffer_rsrc_t rd, const Geom& G, const Coeffs& C, int x0, int y0,
+                                        const typename F::R* lds) {
+    using R = typename F::R;
+    const int ix = (int)threadIdx.x % F::TX, iy = (int)threadIdx.x / F::TX;
+    const int x = x0 + ix, y = y0 + iy;
+    if (!OPEN && (x >= G.nx || y >= G.ny)) return;
+    R f[9], g[gdim(NG)];
+    if (!OPEN && C.any_nee) fk_read<F, NG, true>(lds, G, C, x, y, ix, iy, f, g);
+    else fk_read<F, NG, false>(lds, G, C, x, y, ix, iy, f, g);
+    const Macro m = macro_at<S, R, NG>(f, g, C, x, y);
+    collide<R, NG, COLL>(f, g, m, C);
+    const unsigned boff = (unsigned)(y * G.pitch + x) * (unsigned)sizeof(S);
+    if (MODE == kBufferKeep) store_node_buf<S, NG, kCachePolicyDefault>(rd, G, C, boff, f, g);
+    else store_node_buf<S, NG, kCachePolicyNT>(rd, G, C, boff, f, g);
+}
+
+template <class F>
+__device__ __forceinline__ bool fk_open_tile(const Geom& G, int x0, int y0) {
+    constexpr int K = F::M1 + 1;
+    return x0 >= K && x0 + F::TX <= G.nx - K && y0 >= K && y0 + F::TY <= G.ny - K;
+}
+
+template <class S, int NG, int K>
+constexpr int fusek_rows() {
+#ifdef LBM_FUSE3_ROWS
+    return LBM_FUSE3_ROWS;   // build-time override of the tile height
+#else
+    return 8;
+#endif
+}
+
+// Waves per SIMD for two workgroups per CU (what the LDS of every variant
+// allows), asked of the compiler so that its register budget lets them in.
+template <class S, int NG, int K>
+constexpr int fusek_waves() {
+    return (2 * FuseK<S, NG, K, fusek_rows<S, NG, K>()>::NT / 64 + 3) / 4;
+}
+
+template <class S, int NG, int K, int MODE, int COLL>
+__global__ __launch_bounds__((FuseK<S, NG, K, fusek_rows<S, NG, K>()>::NT))
+__attribute__((amdgpu_waves_per_eu(fusek_waves<S, NG, K>(), 8))) void k_sweepk(
+    Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src, S* __restrict__ dst, int tiles_x,
+    unsigned buf_bytes, int order) {
+    using F = FuseK<S, NG, K, fusek_rows<S, NG, K>()>;
+    __shared__ typename F::R lds[F::LDS_VALUES];
+    const Coeffs& C = *Cp;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x, order, tiles_x);
+    const int x0 = (tile % tiles_x) * F::TX, y0 = (tile / tiles_x) * F::TY;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, buf_bytes);
+    if (fk_open_tile<F>(G, x0, y0)) {
+        fk_first_open<S, NG, F, COLL>(rs, G, C, x0, y0, lds);
+        __syncthreads();
+        fk_middles<S, NG, F, COLL, true>(G, C, x0, y0, lds, std::make_integer_sequence<int, K - 2>{});
+        fk_last<S, NG, F, MODE, COLL, true>(rd, G, C, x0, y0, fk_last_buffer<F>(lds));
+    } else {
+        fk_first_general<S, NG, F, COLL>(rs, src, G, C, x0, y0, lds);
+        __syncthreads();
+        fk_middles<S, NG, F, COLL, false>(G, C, x0, y0, lds, std::make_integer_sequence<int, K - 2>{});
+        fk_last<S, NG, F, MODE, COLL, false>(rd, G, C, x0, y0, fk_last_buffer<F>(lds));
+    }
 }
 
 // One time step of every lattice of a batch.  Each workgroup of 256
@@ -1106,6 +1452,59 @@ static hipError_t sweep2_t(const Launch& L, const Geom& G, const Coeffs& Ch, con
     return hipGetLastError();
 }
 
+
+// Three steps per launch: FP64 and FP32 storage with the D2Q5 model or no
+// temperature field, every collision operator.
+static constexpr bool fuse3_built(int storage, int ng) {
+    return (storage == kF64 || storage == kF32) && (ng == 5 || ng == 0);
+}
+
+int fuse3_rows(int storage, int ng) {
+    if (!fuse3_built(storage, ng)) return 0;
+    if (storage == kF64) return ng == 5 ? fusek_rows<double, 5, 3>() : fusek_rows<double, 0, 3>();
+    return ng == 5 ? fusek_rows<float, 5, 3>() : fusek_rows<float, 0, 3>();
+}
+
+template <class S, int NG, int MODE, int COLL>
+static void sweep3_launch1(int ntiles, hipStream_t st, const Geom& G, const Coeffs* C, const S* s, S* d, int tiles_x,
+                           unsigned bytes, int order) {
+    hipLaunchKernelGGL((k_sweepk<S, NG, 3, MODE, COLL>), dim3(ntiles), dim3(FuseK<S, NG, 3, fusek_rows<S, NG, 3>()>::NT),
+                       0, st, G, C, s, d, tiles_x, bytes, order);
+}
+
+template <class S, int NG>
+static hipError_t sweep3_t(const Launch& L, const Geom& G, const Coeffs& Ch, const Coeffs* C, const void* src,
+                           void* dst, hipStream_t st) {
+    using F = FuseK<S, NG, 3, fusek_rows<S, NG, 3>()>;
+    const unsigned long long bytes = buffer_bytes<S>(G);
+    const int coll = Ch.collision;
+    if (!L.buffer || bytes >= (1ull << 32) || coll < kCollMRT || coll > kCollOrtho) return hipErrorInvalidValue;
+    const int tiles_x = (G.nx + F::TX - 1) / F::TX;
+    const int tiles_y = (G.ny + F::TY - 1) / F::TY;
+    const int order = (L.order == kXcdStrips && tiles_x % 8 != 0) ? kXcdBands : L.order;
+    const S* s = static_cast<const S*>(src);
+    S* d = static_cast<S*>(dst);
+    const int ntiles = tiles_x * tiles_y;
+    const unsigned b = (unsigned)bytes;
+    if (L.keep) {
+        if (coll == kCollBGK) sweep3_launch1<S, NG, kBufferKeep, kCollBGK>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        else if (coll == kCollOrtho) sweep3_launch1<S, NG, kBufferKeep, kCollOrtho>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        else sweep3_launch1<S, NG, kBufferKeep, kCollMRT>(ntiles, st, G, C, s, d, tiles_x, b, order);
+    } else {
+        if (coll == kCollBGK) sweep3_launch1<S, NG, kBufferNT, kCollBGK>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        else if (coll == kCollOrtho) sweep3_launch1<S, NG, kBufferNT, kCollOrtho>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        else sweep3_launch1<S, NG, kBufferNT, kCollMRT>(ntiles, st, G, C, s, d, tiles_x, b, order);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep3(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
+                         const void* src, void* dst, hipStream_t st) {
+    if (!fuse3_built(storage, ng)) return hipErrorInvalidValue;
+    if (storage == kF64) return ng == 5 ? sweep3_t<double, 5>(L, G, C, dC, src, dst, st)
+                                        : sweep3_t<double, 0>(L, G, C, dC, src, dst, st);
+    return ng == 5 ? sweep3_t<float, 5>(L, G, C, dC, src, dst, st) : sweep3_t<float, 0>(L, G, C, dC, src, dst, st);
+}
 
 hipError_t launch_sweep2(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st) {

@@ -5,8 +5,8 @@
 
 Step kernels are keyed by storage ("f64") for the D2Q5 model and by
 model and storage ("d2q9t_f64", "isothermal_f64") for the others, with
-the time steps per launch appended ("f64/2": fused pairs, "f64/1": single
-steps).
+the time steps per launch appended ("f64/3": three steps per launch,
+"f64/2": fused pairs, "f64/1": single steps).
 
 ``stats`` turns the kernel statistics of a ``rocprofv3 --kernel-trace
 --stats -f csv`` run into a short Markdown table.  ``traffic`` reads two
@@ -28,9 +28,19 @@ import re
 import sys
 
 COPY_BYTES = 1 << 30
-# k_sweep<storage type, NG, ROWS, MODE, COLL> (one step per launch) and
-# k_sweep2<storage type, NG, MODE, COLL> (two): the MRT step of each model
-SWEEP = re.compile(r"k_sweep(2?)<(double|float|__half), (\d), (?:1, )?\d, 0>")
+# k_sweep<storage type, NG, ROWS, MODE, COLL> (one step per launch),
+# k_sweep2<storage type, NG, MODE, COLL> (two) and k_sweepk<storage type,
+# NG, K, MODE, COLL> (K): the MRT step of each model
+SWEEP = re.compile(r"k_sweep(2|k)?<(double|float|__half), (\d), (?:(\d), )?\d, 0>")
+
+
+def _steps(m) -> int:
+    """Time steps per launch of a SWEEP match."""
+    if m.group(1) == "2":
+        return 2
+    if m.group(1) == "k":
+        return int(m.group(4))
+    return 1
 STORAGE = {"double": "f64", "float": "f32", "__half": "f16"}
 MODEL = {"5": "d2q5", "9": "d2q9t", "0": "isothermal"}
 
@@ -122,7 +132,7 @@ def write_traffic(fetch_dir: str, write_dir: str, out_json: str, commands: str, 
         m = SWEEP.search(name)
         if not m:
             continue
-        steps = 2 if m.group(1) else 1
+        steps = _steps(m)
         st, model = STORAGE[m.group(2)], MODEL[m.group(3)]
         key = (st if model == "d2q5" else f"{model}_{st}") + f"/{steps}"
         wv = write.get(name, (float("nan"), 0))[0]

@@ -8,8 +8,9 @@ For every lattice size, temperature model and storage, times the step
 kernel (HIP events on the solver's stream) for each block width
 (64 x 4, 128 x 2, 256 x 1) and each memory policy of single steps (XCD
 order round robin, bands or strips; kept or non-temporal stores), and for
-fused pairs of steps (LBM_POLICY_FUSE2, whose 64 x TY tiles do not use the
-block width) in each XCD order and store policy, and prints one JSON line
+fused pairs of steps (LBM_POLICY_FUSE2) and three steps per launch
+(LBM_POLICY_FUSE3, where that kernel exists; their 64 x TY tiles do not use
+the block width) in each XCD order and store policy, and prints one JSON line
 with the library's default choice, the best choice and every figure
 (algorithmic GB/s: 2 (9 + NG) stored values per node and step).  Results
 do not depend on the shape or the policy; only the time does.
@@ -31,6 +32,8 @@ SHAPES = (64, 128, 256)
 POLICIES = tuple(order | keep for order in (0, lbm.LBM_POLICY_XCD_BANDS, lbm.LBM_POLICY_XCD_STRIPS)
                  for keep in (0, lbm.LBM_POLICY_KEEP_STORES))
 FUSED = tuple(lbm.LBM_POLICY_FUSE2 | p for p in POLICIES)
+FUSED3 = tuple(lbm.LBM_POLICY_FUSE3 | lbm.LBM_POLICY_FUSE2 | p for p in POLICIES)
+FUSE_ANY = lbm.LBM_POLICY_FUSE2 | lbm.LBM_POLICY_FUSE3
 
 
 def _time_steps(S, steps: int) -> float:
@@ -47,9 +50,10 @@ def _time_steps(S, steps: int) -> float:
 
 
 def _steps_for(S) -> int:
-    # about 2 GB of algorithmic traffic per setting, at least 40 steps, even
+    # about 2 GB of algorithmic traffic per setting, at least 42 steps, a
+    # multiple of 6 (whole pairs and whole triples)
     per_step = 2 * (9 + S.ng) * BYTES[{0: "f64", 1: "f32", 2: "f16"}[S.storage]] * S.nx * S.ny
-    return max(40, int(2e9 / per_step)) // 2 * 2
+    return max(42, int(2e9 / per_step)) // 6 * 6
 
 
 def measure(S, steps: int | None = None) -> dict:
@@ -61,9 +65,12 @@ def measure(S, steps: int | None = None) -> dict:
     per_step = 2 * (9 + S.ng) * BYTES[{0: "f64", 1: "f32", 2: "f16"}[S.storage]] * S.nx * S.ny
     out = {}
     trials = [(bx, pol) for bx in SHAPES for pol in POLICIES] + [(64, pol) for pol in FUSED]
+    S.set_launch(64, 4, 1, lbm.LBM_POLICY_FUSE3)
+    if S.steps_per_launch == 3:
+        trials += [(64, pol) for pol in FUSED3]
     for bx, pol in trials:
         S.set_launch(bx, 256 // bx, 1, pol)
-        S.step(10)
+        S.step(12)
         out[(bx, pol)] = per_step / _time_steps(S, steps) / 1e9
     S.set_launch(*keep)
     return out
@@ -82,7 +89,7 @@ def autotune(S, steps: int | None = None) -> tuple:
 
 def _key(bx: int, pol: int) -> tuple:
     # fused policies are measured under block width 64 (their tiles do not use it)
-    return (64, pol) if pol & lbm.LBM_POLICY_FUSE2 else (bx, pol)
+    return (64, pol) if pol & FUSE_ANY else (bx, pol)
 
 
 def sweep(sizes, models, storages, md: str | None = None):
@@ -99,7 +106,7 @@ def sweep(sizes, models, storages, md: str | None = None):
                 d = S.get_launch()
                 res = measure(S)
                 best = max(res, key=res.get)
-                single = max((k for k in res if not k[1] & lbm.LBM_POLICY_FUSE2), key=res.get)
+                single = max((k for k in res if not k[1] & FUSE_ANY), key=res.get)
                 dk = _key(d[0], d[3])
                 rec = {"n": n, "model": model, "storage": st,
                        "footprint_MB": round(lbm.lbm_required_bytes(n, n, S.storage, S.model) / 1e6, 1),
@@ -122,8 +129,9 @@ def markdown(rows, sizes, models, storages) -> str:
            "",
            "Algorithmic GB/s (2 (9 + NG) stored values per node and step) for block width bx (64 x 4, 128 x 2, "
            "256 x 1 threads) and policy mask p (1 XCD bands, 2 kept stores, 4 XCD strips, 8 fused pairs of "
-           "steps, 0 round-robin XCD order with non-temporal stores, one step per launch).  Fused policies "
-           "are listed under bx 64: their 64 x TY tiles do not use the block width.", "",
+           "steps, 16 three steps per launch (with 8: remainders as pairs), 0 round-robin XCD order with "
+           "non-temporal stores, one step per launch).  Fused policies are listed under bx 64: their 64 x TY "
+           "tiles do not use the block width.", "",
            "| n | model | storage | footprint MB | default bx/p | GB/s | best bx/p | GB/s | best single step bx/p | GB/s |",
            "|---:|---|---|---:|---|---:|---|---:|---|---:|"]
     for r in rows:

@@ -159,10 +159,15 @@ def test_xcd_strips_order_does_not_change_results(launch):
 
 
 @pytest.mark.parametrize("n,storage,model,policy", [
-    (64, "f64", "d2q5", 11), (2048, "f64", "d2q5", 9), (2048, "f32", "d2q5", 9), (1024, "f32", "d2q5", 11),
-    (4096, "f64", "d2q5", 12),
-    # FP64 48 or more tiles wide: XCD strips at any tile-row size (isothermal 3072^2: 2.2 MB per row)
-    (3072, "f64", "isothermal", 12), (2048, "f64", "isothermal", 9), (3072, "f32", "d2q5", 9),
+    # states within the last-level cache: kept stores, bands, fused pairs
+    (64, "f64", "d2q5", 11), (1024, "f32", "d2q5", 11), (1024, "f64", "d2q5", 11),
+    # beyond it, FP64 / FP32 with D2Q5 or no temperature: three steps per
+    # launch with bands (pairs allowed for remainders)
+    (2048, "f64", "d2q5", 25), (2048, "f32", "d2q5", 25), (4096, "f64", "d2q5", 25),
+    (3072, "f64", "isothermal", 25), (2048, "f64", "isothermal", 25), (3072, "f32", "d2q5", 25),
+    (2048, "f32", "isothermal", 25),
+    # no three-step kernel (D2Q9 thermal): FP64 48 or more tiles wide takes XCD strips
+    (3072, "f64", "d2q9t", 12), (2048, "f64", "d2q9t", 9),
     # FP16: fused pairs with a temperature field unless the state is 128-256 MiB (2048^2 D2Q5: 235 MB)
     (1024, "f16", "d2q5", 11), (2048, "f16", "d2q5", 3), (2048, "f16", "d2q9t", 9), (3072, "f16", "d2q5", 9),
     (4096, "f16", "d2q5", 9),
@@ -178,7 +183,7 @@ def test_default_policy_follows_footprint(n, storage, model, policy):
     with pytest.raises(lbm.LbmError):
         S.set_launch(policy=lbm.LBM_POLICY_XCD_BANDS | lbm.LBM_POLICY_XCD_STRIPS)
     with pytest.raises(lbm.LbmError):
-        S.set_launch(policy=16)
+        S.set_launch(policy=32)
     S.set_launch(policy=lbm.LBM_POLICY_XCD_STRIPS | lbm.LBM_POLICY_KEEP_STORES)
     assert S.get_launch()[3] == lbm.LBM_POLICY_XCD_STRIPS | lbm.LBM_POLICY_KEEP_STORES
     with pytest.raises(lbm.LbmError):
