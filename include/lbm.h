@@ -409,14 +409,17 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps);
  * 0 = launches issued one by one, the default). */
 int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
 
-/* Fused pairs of time steps for the whole batch (the two-step kernel of
- * lbm_set_launch's LBM_POLICY_FUSE2, one launch per pair for all members,
- * the same tiles).  policy: LBM_POLICY_DEFAULT, 0 (one launch per step)
- * or LBM_POLICY_FUSE2.  The default fuses pairs for FP64 and FP32
- * storage and steps FP16 once per launch.  Fused pairs apply only
- * when every member qualifies (buffers below 4 GiB; with walls by
- * non-equilibrium extrapolation, no one-node edge tile); else the
- * batch steps one launch per step.  Results are bitwise the same either
+/* Fused time steps for the whole batch (the kernels of lbm_set_launch's
+ * LBM_POLICY_FUSE2 and LBM_POLICY_FUSE3, one launch per pair or triple of
+ * steps for all members, the same tiles).  policy: LBM_POLICY_DEFAULT, or
+ * a mask of LBM_POLICY_FUSE2 and LBM_POLICY_FUSE3 (0: one launch per
+ * step).  The default fuses pairs for FP64 and FP32 storage and steps FP16
+ * once per launch, and takes three steps per launch for FP64 storage (the
+ * D2Q5 model or no temperature field) once the members' buffers together
+ * exceed 256 MiB.  A kind of fused launch
+ * applies only when every member qualifies (buffers below 4 GiB; with
+ * walls by non-equilibrium extrapolation, no one-node edge tile); steps
+ * left over run as a pair or singly.  Results are bitwise the same either
  * way.  Takes effect at the next lbm_batch_step.  LBM_ERR_ARG for any
  * other value. */
 int lbm_batch_set_policy(lbm_batch* b, int32_t policy);
@@ -458,7 +461,9 @@ void* lbm_batch_stream(const lbm_batch* b);
  * create when b is NULL). */
 const char* lbm_batch_last_error(const lbm_batch* b);
 
-/* Free the batch (members are released, not destroyed).  NULL-safe. */
+/* Free the batch (members are released, not destroyed).  A batch created
+ * with its own stream destroys that stream: solvers created on it must be
+ * destroyed first.  NULL-safe. */
 void lbm_batch_destroy(lbm_batch* b);
 
 /* Message for the last failure on this handle (or of the last failed

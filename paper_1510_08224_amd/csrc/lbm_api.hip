@@ -90,6 +90,12 @@ struct lbm_batch {
     BatchTile* d_ftiles = nullptr;
     size_t cap_ftiles = 0;
     int nftiles = 0;
+    // Three steps per launch (LBM_POLICY_FUSE3): whether the current members
+    // use them, and their tile table (64 x 8 tiles).
+    bool fuse3 = false;
+    BatchTile* d_f3tiles = nullptr;
+    size_t cap_f3tiles = 0;
+    int nf3tiles = 0;
     std::vector<int> member_slot;     // tile-table member index -> slot
     double* d_tile_max = nullptr;     // batched residual scratch
     unsigned long long* d_tile_bad = nullptr;
@@ -752,13 +758,14 @@ static bool fuse3_active(const lbm_solver* h) {
 // launches (each swaps the buffers once) or a negative HIP error.
 static hipError_t launch_steps(lbm_solver* h, int cur, int64_t steps, int64_t* launches) {
     const bool fuse = fuse2_active(h), fuse3 = fuse3_active(h);
+    const int64_t k3 = fuse3_steps(h->storage, h->ng);
     int64_t n = 0;
     while (steps > 0) {
         hipError_t e;
-        if (fuse3 && steps >= 3) {
+        if (fuse3 && steps >= k3) {
             e = launch_sweep3(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
                               h->stream);
-            steps -= 3;
+            steps -= k3;
         } else if (fuse && steps >= 2) {
             e = launch_sweep2(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
                               h->stream);
@@ -1161,7 +1168,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
 
 int lbm_steps_per_launch(const lbm_solver* h, int32_t* steps) {
     if (!h || !steps) return fail(nullptr, LBM_ERR_ARG, "lbm_steps_per_launch: NULL argument");
-    *steps = fuse3_active(h) ? 3 : (fuse2_active(h) ? 2 : 1);
+    *steps = fuse3_active(h) ? fuse3_steps(h->storage, h->ng) : (fuse2_active(h) ? 2 : 1);
     return LBM_OK;
 }
 
@@ -1230,6 +1237,7 @@ void lbm_batch_destroy(lbm_batch* b) {
     if (b->d_members) (void)hipFree(b->d_members);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_ftiles) (void)hipFree(b->d_ftiles);
+    if (b->d_f3tiles) (void)hipFree(b->d_f3tiles);
     if (b->d_tile_max) (void)hipFree(b->d_tile_max);
     if (b->d_tile_bad) (void)hipFree(b->d_tile_bad);
     if (b->d_rout) (void)hipFree(b->d_rout);
@@ -1309,11 +1317,12 @@ static hipError_t batch_table(T** d, size_t* cap, size_t n) {
 
 static int batch_build(lbm_batch* b) {
     std::vector<BatchMember> mem;
-    std::vector<BatchTile> tiles, ftiles;
+    std::vector<BatchTile> tiles, ftiles, f3tiles;
     b->member_slot.clear();
     b->buffer = true;
     const int fty = fuse2_rows(b->storage, b->ng < 0 ? 5 : b->ng);
-    bool can_fuse = fty > 0;
+    const int f3ty = fuse3_rows(b->storage, b->ng < 0 ? 5 : b->ng);
+    bool can_fuse = fty > 0, can_fuse3 = f3ty > 0;
     double ws = 0.0;
     // members in table order: as added, or the largest lattices first (their
     // tiles then start the launch and the small ones fill its tail)
@@ -1343,9 +1352,13 @@ static int batch_build(lbm_batch* b) {
         M.ntiles = (int)tiles.size() - M.tile0;
         for (int y0 = 0; y0 < h->ny; y0 += fty)
             for (int x0 = 0; x0 < h->nx; x0 += 64) ftiles.push_back(BatchTile{id, x0, y0, 64});
+        if (can_fuse3)
+            for (int y0 = 0; y0 < h->ny; y0 += f3ty)
+                for (int x0 = 0; x0 < h->nx; x0 += 64) f3tiles.push_back(BatchTile{id, x0, y0, 64});
         // a wall node rebuilt by extrapolation must find its fluid
         // neighbour inside the same fused tile
         if (h->C.any_nee && (h->nx % 64 == 1 || h->ny % fty == 1)) can_fuse = false;
+        if (h->C.any_nee && f3ty > 0 && (h->nx % 64 == 1 || h->ny % f3ty == 1)) can_fuse3 = false;
         ws += 2.0 * (double)h->buf_bytes;
         mem.push_back(M);
         b->member_slot.push_back((int)k);
@@ -1355,10 +1368,18 @@ static int batch_build(lbm_batch* b) {
     // all, sides 64 to 1024: FP32 1.1x to 1.6x, FP64 1.3x to 1.9x over one
     // step per launch); FP16 batches keep single steps, like FP16 lattices.
     const double mib = 1024.0 * 1024.0;
+    // Three steps per launch for FP64 batches whose states together
+    // outgrow the last-level cache (batches of equal cavities, 6.7e6 nodes
+    // in all: 3-20% less time per step than fused pairs, sides 64 to 1024);
+    // FP32 batches keep fused pairs, which were 4-27% faster at every side
+    // (the two-node margins of small members take the general path).
     const bool want = b->policy == LBM_POLICY_DEFAULT
                           ? (b->storage == LBM_F64 || b->storage == LBM_F32)
                           : (b->policy & LBM_POLICY_FUSE2) != 0;
+    const bool want3 = b->policy == LBM_POLICY_DEFAULT ? (b->storage == LBM_F64 && ws > 256.0 * mib)
+                                                       : (b->policy & LBM_POLICY_FUSE3) != 0;
     b->fuse = want && can_fuse && b->buffer && !mem.empty();
+    b->fuse3 = want3 && can_fuse3 && b->buffer && !mem.empty();
     b->keep = b->tune_keep < 0 ? ws <= 256.0 * mib : b->tune_keep == 1;
     b->order = b->tune_order < 0 ? 1 : b->tune_order;
     if (batch_table(&b->d_members, &b->cap_members, mem.size()) != hipSuccess)
@@ -1367,6 +1388,8 @@ static int batch_build(lbm_batch* b) {
         return bfail(b, LBM_ERR_NOMEM, "batch tile table allocation");
     if (b->fuse && batch_table(&b->d_ftiles, &b->cap_ftiles, ftiles.size()) != hipSuccess)
         return bfail(b, LBM_ERR_NOMEM, "batch fused tile table allocation");
+    if (b->fuse3 && batch_table(&b->d_f3tiles, &b->cap_f3tiles, f3tiles.size()) != hipSuccess)
+        return bfail(b, LBM_ERR_NOMEM, "batch three-step tile table allocation");
     if (!mem.empty()) {
         hipError_t e = hipMemcpyAsync(b->d_members, mem.data(), mem.size() * sizeof(BatchMember), hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess)
@@ -1374,11 +1397,15 @@ static int batch_build(lbm_batch* b) {
         if (e == hipSuccess && b->fuse)
             e = hipMemcpyAsync(b->d_ftiles, ftiles.data(), ftiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
                                b->stream);
+        if (e == hipSuccess && b->fuse3)
+            e = hipMemcpyAsync(b->d_f3tiles, f3tiles.data(), f3tiles.size() * sizeof(BatchTile),
+                               hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // host vectors die on return
         if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("batch table upload: ") + hipGetErrorString(e));
     }
     b->ntiles = (int)tiles.size();
     b->nftiles = b->fuse ? (int)ftiles.size() : 0;
+    b->nf3tiles = b->fuse3 ? (int)f3tiles.size() : 0;
     b->parity = 0;
     b->dirty = false;
     return LBM_OK;
@@ -1389,9 +1416,14 @@ static int batch_build(lbm_batch* b) {
 // member's buffers once.  Returns the number of launches in *launches.
 static hipError_t batch_launch_steps(lbm_batch* b, int parity, int64_t steps, int64_t* launches) {
     int64_t n = 0;
+    const int64_t k3 = fuse3_steps(b->storage, b->ng < 0 ? 5 : b->ng);
     while (steps > 0) {
         hipError_t e;
-        if (b->fuse && steps >= 2) {
+        if (b->fuse3 && steps >= k3) {
+            e = launch_sweep3_batch(b->storage, b->ng, b->keep, b->d_members, b->d_f3tiles, b->nf3tiles, parity,
+                                    b->order, b->stream);
+            steps -= k3;
+        } else if (b->fuse && steps >= 2) {
             e = launch_sweep2_batch(b->storage, b->ng, b->keep, b->d_members, b->d_ftiles, b->nftiles, parity, b->order,
                                     b->stream);
             steps -= 2;
@@ -1465,8 +1497,9 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps) {
 
 int lbm_batch_set_policy(lbm_batch* b, int32_t policy) {
     if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_set_policy: NULL batch");
-    if (policy != LBM_POLICY_DEFAULT && policy != 0 && policy != LBM_POLICY_FUSE2)
-        return bfail(b, LBM_ERR_ARG, "lbm_batch_set_policy: LBM_POLICY_DEFAULT, 0 or LBM_POLICY_FUSE2");
+    if (policy != LBM_POLICY_DEFAULT && (policy < 0 || (policy & ~(LBM_POLICY_FUSE2 | LBM_POLICY_FUSE3)) != 0))
+        return bfail(b, LBM_ERR_ARG,
+                     "lbm_batch_set_policy: LBM_POLICY_DEFAULT or a mask of LBM_POLICY_FUSE2 and LBM_POLICY_FUSE3");
     b->policy = policy;
     batch_invalidate(b);
     return LBM_OK;
@@ -1503,7 +1536,7 @@ int lbm_batch_steps_per_launch(lbm_batch* b, int32_t* steps) {
         int rc = batch_build(b);
         if (rc != LBM_OK) return rc;
     }
-    *steps = b->fuse ? 2 : 1;
+    *steps = b->fuse3 ? fuse3_steps(b->storage, b->ng < 0 ? 5 : b->ng) : (b->fuse ? 2 : 1);
     return LBM_OK;
 }
 

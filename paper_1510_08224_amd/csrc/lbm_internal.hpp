@@ -42,10 +42,14 @@ inline int storage_bytes(int storage) { return storage == kF64 ? 8 : (storage ==
 hipError_t launch_sweep2(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st);
 int fuse2_rows(int storage, int ng);
-// Tile rows of the three-step kernel, or 0 where none is built.
+// Tile rows and time steps per launch of the multi-step kernel, or 0 where
+// none is built.
 int fuse3_rows(int storage, int ng);
+int fuse3_steps(int storage, int ng);
 hipError_t launch_sweep3(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st);
+hipError_t launch_sweep3_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
+                               int ntiles, int parity, int order, hipStream_t st);
 // Fused pairs of steps for a batch (buffer addressing; keep: default-policy stores).
 // order: XCD order of the tile table (0 round robin, 1 bands).
 hipError_t launch_sweep2_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,

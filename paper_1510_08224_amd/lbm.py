@@ -231,6 +231,7 @@ class Solver:
         self.ng = MODEL_NG[self.model]
         self._mem = None
         self.h = None
+        self._owner = None     # the Batch whose stream this solver launches on
         if torch_memory:
             import torch
             nbytes = lbm_required_bytes(self.nx, self.ny, self.storage, self.model)
@@ -252,6 +253,9 @@ class Solver:
             lbm_destroy(self.h)
             self.h = None
         self._mem = None
+        if self._owner is not None:
+            owner, self._owner = self._owner, None
+            owner._solver_closed(self)
 
     def __del__(self):
         try:
@@ -399,7 +403,9 @@ def _bcheck(rc: int, b=None):
 class Batch:
     """A set of solvers advanced together (one launch per step for all).
     Solvers for a batch are created with :meth:`new_solver` so that they
-    share its storage and stream."""
+    share its storage and stream.  The batch's stream must outlive them:
+    :meth:`close` releases the batch at once when they are all closed, and
+    otherwise when the last of them closes."""
 
     def __init__(self, storage: str = "f32", stream=None):
         self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
@@ -408,13 +414,25 @@ class Batch:
         _bcheck(lib().lbm_batch_create(ctypes.byref(h), self.storage, stream))
         self.h = h
         self.members: dict[int, Solver] = {}
+        self._spawned: set[int] = set()   # ids of open solvers on this batch's stream
+        self._closing = False
 
     @property
     def stream(self):
         return lib().lbm_batch_stream(self.h)
 
     def new_solver(self, nx: int, ny: int, torch_memory: bool = False, model="d2q5") -> Solver:
-        return Solver(nx, ny, self.storage, torch_memory=torch_memory, stream=self.stream, model=model)
+        if self._closing:
+            raise RuntimeError("the batch is closed")
+        S = Solver(nx, ny, self.storage, torch_memory=torch_memory, stream=self.stream, model=model)
+        S._owner = self
+        self._spawned.add(id(S))
+        return S
+
+    def _solver_closed(self, S: Solver):
+        self._spawned.discard(id(S))
+        if self._closing and not self._spawned:
+            self._destroy()
 
     def add(self, solver: Solver) -> int:
         slot = ctypes.c_int32()
@@ -446,7 +464,8 @@ class Batch:
         _bcheck(lib().lbm_batch_set_graph_steps(self.h, int(steps)), self.h)
 
     def set_policy(self, policy: int):
-        """LBM_POLICY_DEFAULT, 0 (one launch per step) or LBM_POLICY_FUSE2."""
+        """LBM_POLICY_DEFAULT, or a mask of LBM_POLICY_FUSE2 and
+        LBM_POLICY_FUSE3 (0: one launch per step)."""
         _bcheck(lib().lbm_batch_set_policy(self.h, int(policy)), self.h)
 
     @property
@@ -468,9 +487,17 @@ class Batch:
         return r[:slots], bad[:slots]
 
     def close(self):
+        """Release the batch; its stream stays until every solver made by
+        :meth:`new_solver` is closed."""
+        self._closing = True
+        if not self._spawned:
+            self._destroy()
+
+    def _destroy(self):
         if self.h:
             lib().lbm_batch_destroy(self.h)
             self.h = None
+        self.members = {}
 
     def __del__(self):
         try:

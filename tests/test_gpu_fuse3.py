@@ -112,3 +112,92 @@ def test_three_steps_degenerate_sizes(storage, nx, ny):
             (fa, ga), _ = _run("d2q5", pb, storage, [1, 3, 2, 6], 0, 0, T, spl=1)
             (fb, gb), _ = _run("d2q5", pb, storage, [1, 3, 2, 6], F3, 0, T, spl=3)
             assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (px, py)
+
+
+# ---------------------------------------------------------------------------
+# Three steps per launch for a whole batch (lbm_batch_set_policy).
+# ---------------------------------------------------------------------------
+from test_gpu_batch import _alone, _batch  # noqa: E402
+from test_gpu_batch import _fused_mix  # noqa: E402
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_three_step_batch_matches_alone_bitwise(storage):
+    mix = _fused_mix()
+    B, sols = _batch(storage, mix)
+    B.set_policy(F3 | F2)
+    assert B.steps_per_launch == (3 if storage != "f16" else 2)
+    B.step(37)            # 12 three-step launches and one single step
+    B.step(26)            # 8 three-step launches and a pair
+    B.residual()          # first call: snapshot only
+    B.step(1)
+    r, bad = B.residual()
+    for k, ((pb, mkT), S) in enumerate(zip(mix, sols)):
+        A = lbm.Solver(pb.nx, pb.ny, storage)
+        A.set_params(pb)
+        A.set_launch(policy=0)
+        if mkT:
+            A.init_temperature(mkT())
+        A.step(63)
+        A.residual()
+        A.step(1)
+        ra, _ = A.residual()
+        fa, ga = A.get_populations()
+        A.close()
+        fb, gb = S.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), pb.name
+        assert S.time == 64 and bad[k] == 0
+        assert r[k] == ra, pb.name
+    B.close()
+
+
+def test_three_step_batch_graphs_and_membership():
+    # graphs of 6 steps hold 2 three-step launches (an even count); of 8,
+    # two three-step launches and a pair (an odd count swaps the buffers)
+    for graph in (6, 8):
+        mix = _fused_mix()
+        B, sols = _batch("f32", mix, graph=graph)
+        B.set_policy(F3 | F2)
+        B.step(13)
+        B.remove(3)
+        B.step(12)
+        sols[0].step(1)       # a member stepped on its own
+        B.step(7)
+        expect = {0: 33, 3: 13}
+        for k, S in enumerate(sols):
+            pb, mkT = mix[k]
+            fa, ga = _alone(pb, mkT() if mkT else None, "f32", expect.get(k, 32), launch=(64, 4, 1, 0))
+            fb, gb = S.get_populations()
+            assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (graph, k)
+            assert S.time == expect.get(k, 32)
+        B.close()
+
+
+def test_three_step_batch_policy_rules():
+    B = lbm.Batch("f32")
+    S = B.new_solver(64, 64)
+    S.set_params(W.cavity(64, 1e4))
+    B.add(S)
+    assert B.steps_per_launch == 2            # a small batch within the last-level cache: pairs
+    B.set_policy(F3)
+    assert B.steps_per_launch == 3
+    B.set_policy(F3 | F2)
+    assert B.steps_per_launch == 3
+    # a wall rebuilt by extrapolation on a one-row edge tile of the 8-row
+    # three-step tiles (41 rows; the FP32 pair's 12-row tiles leave 5): pairs
+    S2 = B.new_solver(100, 41)
+    pb2 = W.with_nee_walls(W.cavity(100, 1e4, ny=41))
+    S2.set_params(pb2)
+    slot2 = B.add(S2)
+    assert B.steps_per_launch == 2
+    B.set_policy(F3)
+    assert B.steps_per_launch == 1
+    B.step(9)
+    fa, ga = _alone(pb2, None, "f32", 9)
+    assert np.array_equal(fa, S2.get_populations()[0])
+    B.remove(slot2)
+    assert B.steps_per_launch == 3
+    for bad in (1, 4, 32, F3 | 1, -3):
+        with pytest.raises(lbm.LbmError):
+            B.set_policy(bad)
+    B.close()
