@@ -338,13 +338,11 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           so does every step where no kernel exists.
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; three steps per launch with
- * bands where that kernel exists and F > 256 MiB; otherwise fused pairs
- * for FP64 and FP32 storage, and for FP16 storage with a temperature field
- * unless 128 MiB < F <= 256 MiB, with bands, or strips (with a multiple of
- * 8 tiles per row) once one row of fused tiles (tiles and halos, every
- * plane) exceeds 3 MiB or an FP64 lattice is 48 or more tiles wide;
- * otherwise (FP16) single steps with bands while F <= 500 MiB.  Fused pairs
- * stay allowed beside three-step launches. */
+ * bands where that kernel exists, for FP64 at any F and for FP32 once
+ * F > 256 MiB; otherwise fused pairs, with bands, or strips (with a
+ * multiple of 8 tiles per row) once one row of fused tiles (tiles and
+ * halos, every plane) exceeds 3 MiB or an FP64 lattice is 48 or more tiles
+ * wide.  Fused pairs stay allowed beside three-step launches. */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
@@ -415,8 +413,7 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
  * a mask of LBM_POLICY_FUSE2 and LBM_POLICY_FUSE3 (0: one launch per
  * step).  The default fuses pairs for FP64 and FP32 storage and steps FP16
  * once per launch, and takes three steps per launch for FP64 storage (the
- * D2Q5 model or no temperature field) once the members' buffers together
- * exceed 256 MiB.  A kind of fused launch
+ * D2Q5 model or no temperature field).  A kind of fused launch
  * applies only when every member qualifies (buffers below 4 GiB; with
  * walls by non-equilibrium extrapolation, no one-node edge tile); steps
  * left over run as a pair or singly.  Results are bitwise the same either

@@ -208,47 +208,36 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 }
 
 // Memory policy from the footprint of both population buffers, measured on
-// MI355X (1024^2 to 4096^2 lattices, every model and storage): when both
-// fit the 256 MB last-level cache, stores keep their lines there (FP16
-// 2048^2: +34%); above it non-temporal stores win.  XCD row bands win up
-// to about half a gigabyte (FP32 2048^2, 470 MB: +16%) and tie with the
-// round-robin order for FP64 states up to a gigabyte, where they fetch each
-// line once (round robin fetches 7% more: the x-shifted pulls of
-// neighbouring 64-wide tiles on different XCDs); the round-robin order wins
-// above (FP16 3072^2, 528 MB: +11%; FP64 4096^2: +2%).  Contiguous strips
-// per XCD (LBM_POLICY_XCD_STRIPS) are within a few percent either way and
-// left to the autotuner.  Fused pairs of steps (LBM_POLICY_FUSE2) win for
-// FP64 and FP32 at every size measured (1024^2 to 4096^2: FP64 1.6x to
-// 1.9x, FP32 1.4x to 1.7x over the best single step).  FP16 fuses with a
-// temperature field (512^2 to 4096^2: 8-49% over single steps) except for
-// states of 128-256 MiB, which stay in the last-level cache under kept
-// single stores (2048^2 D2Q5, 235 MB: 16% faster than fused pairs); without
-// temperature FP16 keeps single steps, which win from 1024^2 up.  Fused
-// pairs run best with XCD bands.  Three steps per launch (FP64 and FP32
-// storage, D2Q5 or no temperature field) win once the state outgrows the
-// last-level cache: 2048^2 to 4096^2, FP64 D2Q5 22-25% and the flow alone
-// 21-22% less time per step than fused pairs, FP32 D2Q5 8-12% and the flow
-// alone 13%; at 1024^2 (a state within the cache) fused pairs stay 7%
-// (FP64) and 27% (FP32) faster.  Three-step launches need XCD bands: with
-// strips or round robin they took 13-55% longer (2048^2 to 4096^2).
+// MI355X (512^2 to 4096^2 lattices, every model and storage,
+// `tuning.py`): when both fit the 256 MB last-level cache, stores keep their
+// lines there; above it non-temporal stores win.  Three steps per launch
+// (LBM_POLICY_FUSE3; FP64 and FP32 storage, the D2Q5 model or no
+// temperature field) win for FP64 at every size (D2Q5 over the best fused
+// pair: 512^2 +10%, 1024^2 +12% with kept stores, 2048^2 +30%, 4096^2 +32%;
+// the flow alone +2% to +26%) and for FP32 beyond the last-level cache
+// (2048^2 and 4096^2: D2Q5 +6% and +12%, the flow alone +14% and +20%; at
+// 1024^2 the pair is 11% faster); they need XCD bands (strips or round
+// robin took 14-55% longer).  Fused pairs (LBM_POLICY_FUSE2) win over
+// single steps for every storage and model at every size (FP16 included:
+// 2048^2 D2Q5, a 235 MB state, +13% over kept single stores; the flow
+// alone +9% to +22%), with bands, or strips (with a multiple of 8 tiles
+// per row) once one row of fused tiles exceeds 3 MiB or an FP64 lattice is
+// 48 or more tiles wide; pairs stay on for remainders and wherever three
+// steps do not apply.
 static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
-    h->L.order = (ws <= 500.0 * mib || (h->storage == LBM_F64 && ws <= 1024.0 * mib)) ? 1 : 0;
-    h->L.fuse2 = h->storage == LBM_F64 || h->storage == LBM_F32 ||
-                 (h->storage == LBM_F16 && h->ng > 0 && !(ws > 128.0 * mib && ws <= 256.0 * mib));
-    h->L.fuse3 = fuse3_rows(h->storage, h->ng) > 0 && ws > 256.0 * mib;
+    h->L.fuse2 = true;
+    h->L.fuse3 = fuse3_rows(h->storage, h->ng) > 0 && (h->storage == LBM_F64 || ws > 256.0 * mib);
     if (h->L.fuse3) {
         h->L.order = 1;
-    } else if (h->L.fuse2) {
+    } else {
         // Bands keep the halo rows a fused tile shares with the tile row
         // below in the XCD's 4 MB L2 while one row of tiles (tile and halo,
         // every plane) fits there; past that, strips of 8 tiles per XCD do.
         // FP64 lattices 48 or more tiles wide take strips at any row size
         // (3072^2 and 4096^2, every model: +2.3 to +5.4%; at 2048^2 bands
-        // win by up to 7%); FP32 keeps bands below 3 MiB per row (D2Q5 at
-        // 4096^2, 3.3 MiB per row of its 12-row tiles, takes strips: 343.8
-        // against 357.7 us per launch with bands).
+        // win by up to 7%); FP32 keeps bands below 3 MiB per row.
         const int ty = fuse2_rows(h->storage, h->ng);
         const int tiles_x = (h->nx + 63) / 64;
         const double row = (double)tiles_x * 66.0 * (ty + 2) * (9 + h->ng) * storage_bytes(h->storage);
@@ -1368,16 +1357,15 @@ static int batch_build(lbm_batch* b) {
     // all, sides 64 to 1024: FP32 1.1x to 1.6x, FP64 1.3x to 1.9x over one
     // step per launch); FP16 batches keep single steps, like FP16 lattices.
     const double mib = 1024.0 * 1024.0;
-    // Three steps per launch for FP64 batches whose states together
-    // outgrow the last-level cache (batches of equal cavities, 6.7e6 nodes
-    // in all: 3-20% less time per step than fused pairs, sides 64 to 1024);
+    // Three steps per launch for FP64 batches (batches of equal cavities,
+    // 6.7e6 nodes in all: 3-20% less time per step than fused pairs, sides
+    // 64 to 1024; single FP64 lattices gain at every size);
     // FP32 batches keep fused pairs, which were 4-27% faster at every side
     // (the two-node margins of small members take the general path).
     const bool want = b->policy == LBM_POLICY_DEFAULT
                           ? (b->storage == LBM_F64 || b->storage == LBM_F32)
                           : (b->policy & LBM_POLICY_FUSE2) != 0;
-    const bool want3 = b->policy == LBM_POLICY_DEFAULT ? (b->storage == LBM_F64 && ws > 256.0 * mib)
-                                                       : (b->policy & LBM_POLICY_FUSE3) != 0;
+    const bool want3 = b->policy == LBM_POLICY_DEFAULT ? b->storage == LBM_F64 : (b->policy & LBM_POLICY_FUSE3) != 0;
     b->fuse = want && can_fuse && b->buffer && !mem.empty();
     b->fuse3 = want3 && can_fuse3 && b->buffer && !mem.empty();
     b->keep = b->tune_keep < 0 ? ws <= 256.0 * mib : b->tune_keep == 1;
