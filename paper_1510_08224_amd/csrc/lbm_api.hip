@@ -228,7 +228,9 @@ static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
     h->L.fuse2 = true;
-    h->L.fuse3 = fuse3_rows(h->storage, h->ng) > 0 && (h->storage == LBM_F64 || ws > 256.0 * mib);
+    const bool d2q5_or_flow = h->ng == 5 || h->ng == 0;
+    h->L.fuse3 = fuse3_rows(h->storage, h->ng) > 0 && d2q5_or_flow &&
+                 (h->storage == LBM_F64 || (h->storage == LBM_F32 && ws > 256.0 * mib));
     if (h->L.fuse3) {
         h->L.order = 1;
     } else {

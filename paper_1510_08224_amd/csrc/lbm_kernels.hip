@@ -655,8 +655,8 @@ void k_sweep2_batch(
 template <class S, int NG, int K, int TY_>
 struct FuseK {
     using R = typename Codec<S>::R;
+    using Store = S;
     static_assert(K >= 3, "two steps per launch are the fused pair");
-    static_assert(!kRefT<S>, "FP16 storage references its deviations to the node position");
     static constexpr int NP = 9 + NG;
     static constexpr int TX = 64;
     static constexpr int TY = TY_;
@@ -727,12 +727,20 @@ __device__ __forceinline__ void fk_walls(typename F::R* lds, const Geom& G, cons
 }
 
 // The post-collision populations of lattice node (x, y) at tile-relative
-// (sx, sy) into LDS for the next step, whose region has margin MN: each to
-// the node that pulls it and, with WALLS, the wall rules of the node's own
+// (sx, sy) into LDS for the next step, whose region has margin MN: in the
+// form and rounding a store and a load of the storage type would give
+// them (FP16: relative to the reference of the pulling node), each to the
+// node that pulls it and, with WALLS, the wall rules of the node's own
 // links if it takes part in the next step.
 template <class F, int NG, int MN, bool WALLS>
 __device__ __forceinline__ void fk_keep(typename F::R* lds, const Geom& G, const Coeffs& C, int x, int y, int sx,
-                                        int sy, const typename F::R f[9], const typename F::R g[gdim(NG)]) {
+                                        int sy, typename F::R f[9], typename F::R g[gdim(NG)]) {
+    using S = typename F::Store;
+    to_stored<S, NG>(f, g, C, y);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = as_stored<S>(f[i], C.fscale, C.finv);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) g[i] = as_stored<S>(g[i], C.gscale, C.ginv);
     fk_put_set<F, MN, 0>(lds, sx, sy, f, std::make_integer_sequence<int, 9>{});
     if constexpr (NG > 0) fk_put_set<F, MN, 9>(lds, sx, sy, g, std::make_integer_sequence<int, NG>{});
     if constexpr (WALLS) {
@@ -966,6 +974,7 @@ __device__ __forceinline__ void fk_last(__amdgpu_buffer_rsrc_t rd, const Geom& G
     else fk_read<F, NG, false>(lds, G, C, x, y, ix, iy, f, g);
     const Macro m = macro_at<S, R, NG>(f, g, C, x, y);
     collide<R, NG, COLL>(f, g, m, C);
+    to_stored<S, NG>(f, g, C, y);
     const unsigned boff = (unsigned)(y * G.pitch + x) * (unsigned)sizeof(S);
     if (MODE == kBufferKeep) store_node_buf<S, NG, kCachePolicyDefault>(rd, G, C, boff, f, g);
     else store_node_buf<S, NG, kCachePolicyNT>(rd, G, C, boff, f, g);
@@ -1536,25 +1545,41 @@ static hipError_t sweep2_t(const Launch& L, const Geom& G, const Coeffs& Ch, con
 }
 
 
-// Three steps per launch: FP64 and FP32 storage with the D2Q5 model or no
-// temperature field, every collision operator.
+// Three steps per launch, every collision operator: FP64 and FP32 storage
+// with the D2Q5 model or no temperature field.  Not for the D2Q9 thermal
+// model: its FP64 window (18 planes of 66 x 10 doubles) would take more
+// than half a CU's LDS, and in FP32 / FP16 the in-place middle step spills
+// about 1 KB per lane at the four waves per SIMD two workgroups per CU
+// need.  Not for FP16 storage: the kernel is generic over the storage
+// (bitwise equal to single steps, tested), but on MI355X it lost to FP16
+// fused pairs at every size (2048^2 D2Q5 45.7 against 33.6 us per step,
+// 4096^2 172 against 140), the conversions of every value to and from FP16
+// making the longer launch issue-bound.
 static constexpr bool fuse3_built(int storage, int ng) {
     return (storage == kF64 || storage == kF32) && (ng == 5 || ng == 0);
 }
+
+// Runs the statement with S and NG bound for every built three-step kernel.
+#define LBM_DISPATCH3(storage, ng, ...)                                                   \
+    switch ((storage) * 16 + (ng)) {                                                      \
+        case kF64 * 16 + 0: { using S = double; constexpr int NG = 0; __VA_ARGS__; } break; \
+        case kF64 * 16 + 5: { using S = double; constexpr int NG = 5; __VA_ARGS__; } break; \
+        case kF32 * 16 + 0: { using S = float; constexpr int NG = 0; __VA_ARGS__; } break;  \
+        case kF32 * 16 + 5: { using S = float; constexpr int NG = 5; __VA_ARGS__; } break;  \
+        default: break;                                                                   \
+    }
 
 template <class S, int NG>
 using FuseKOf = FuseK<S, NG, fusek_steps<S, NG>(), fusek_rows<S, NG, fusek_steps<S, NG>()>()>;
 
 int fuse3_rows(int storage, int ng) {
-    if (!fuse3_built(storage, ng)) return 0;
-    if (storage == kF64) return ng == 5 ? FuseKOf<double, 5>::TY : FuseKOf<double, 0>::TY;
-    return ng == 5 ? FuseKOf<float, 5>::TY : FuseKOf<float, 0>::TY;
+    LBM_DISPATCH3(storage, ng, return FuseKOf<S, NG>::TY);
+    return 0;
 }
 
 int fuse3_steps(int storage, int ng) {
-    if (!fuse3_built(storage, ng)) return 0;
-    if (storage == kF64) return ng == 5 ? fusek_steps<double, 5>() : fusek_steps<double, 0>();
-    return ng == 5 ? fusek_steps<float, 5>() : fusek_steps<float, 0>();
+    LBM_DISPATCH3(storage, ng, return fusek_steps<S, NG>());
+    return 0;
 }
 
 template <class S, int NG, int MODE, int COLL>
@@ -1593,9 +1618,8 @@ static hipError_t sweep3_t(const Launch& L, const Geom& G, const Coeffs& Ch, con
 hipError_t launch_sweep3(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st) {
     if (!fuse3_built(storage, ng)) return hipErrorInvalidValue;
-    if (storage == kF64) return ng == 5 ? sweep3_t<double, 5>(L, G, C, dC, src, dst, st)
-                                        : sweep3_t<double, 0>(L, G, C, dC, src, dst, st);
-    return ng == 5 ? sweep3_t<float, 5>(L, G, C, dC, src, dst, st) : sweep3_t<float, 0>(L, G, C, dC, src, dst, st);
+    LBM_DISPATCH3(storage, ng, return sweep3_t<S, NG>(L, G, C, dC, src, dst, st));
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep3_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
@@ -1613,13 +1637,7 @@ hipError_t launch_sweep3_batch(int storage, int ng, bool keep, const BatchMember
             hipLaunchKernelGGL((k_sweepk_batch<S, NG, K, kBufferNT>), dim3(ntiles), dim3(FuseKOf<S, NG>::NT), 0, st,
                                members, tiles, parity, order);
     };
-    if (storage == kF64) {
-        if (ng == 5) go(double{}, std::integral_constant<int, 5>{});
-        else go(double{}, std::integral_constant<int, 0>{});
-    } else {
-        if (ng == 5) go(float{}, std::integral_constant<int, 5>{});
-        else go(float{}, std::integral_constant<int, 0>{});
-    }
+    LBM_DISPATCH3(storage, ng, go(S{}, std::integral_constant<int, NG>{}));
     return hipGetLastError();
 }
 

@@ -4,9 +4,9 @@ LDS, and the tile again into HBM.  It must give bitwise the populations of
 three single steps for FP64 and FP32 storage, the D2Q5 model and the flow
 alone, every collision operator and wall family, ragged, periodic and open
 tiles, graph replay, and remainders run as pairs or single steps.  Where no
-three-step kernel exists (FP16, D2Q9 thermal) or NEE walls leave a one-node
-edge tile, lbm_step falls back to the pair (or single steps) and says so
-through lbm_steps_per_launch."""
+three-step kernel exists (FP16 storage, the D2Q9 thermal model) or NEE
+walls leave a one-node edge tile, lbm_step falls back to the pair (or
+single steps) and says so through lbm_steps_per_launch."""
 import numpy as np
 import pytest
 
@@ -19,16 +19,18 @@ pytestmark = pytest.mark.gpu
 F2, F3 = lbm.LBM_POLICY_FUSE2, lbm.LBM_POLICY_FUSE3
 BANDS, STRIPS, KEEP = lbm.LBM_POLICY_XCD_BANDS, lbm.LBM_POLICY_XCD_STRIPS, lbm.LBM_POLICY_KEEP_STORES
 
-# built for FP64 / FP32 storage, D2Q5 or no temperature field; 64 x 8
+# built for FP64 and FP32 storage with D2Q5 or no temperature field; 64 x 8
 # tiles (NEE with nx % 64 == 1 or ny % 8 == 1 falls back)
-BUILT_MODELS = {"d2q5", "isothermal"}
 FALLBACK3 = {"nee_last_column_one_wide", "nee_top_row_one_high"}
+
+
+def _built(model, storage):
+    return model in ("d2q5", "isothermal") and storage in ("f64", "f32")
 
 
 def _triple(case, storage):
     model, mk, _ = CASES[case]
-    pb = mk()
-    return storage in ("f64", "f32") and model in BUILT_MODELS and case not in FALLBACK3
+    return _built(model, storage) and case not in FALLBACK3
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
