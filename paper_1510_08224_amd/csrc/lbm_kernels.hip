@@ -8,6 +8,9 @@
 //   k_sweep_batch    the same step for every lattice of a batch
 //   k_sweep2(_batch) two time steps per launch: the first on a tile and its
 //                    halo into LDS, the second from LDS to memory
+//   k_sweepk(_batch) three time steps per launch (FP64 / FP32, D2Q5 or no
+//                    temperature): the tile grown by two nodes from memory
+//                    into LDS, grown by one node within LDS, the tile to memory
 //   k_moments        rho, u, T at time t (Eqs. 18, 19, 27)
 //   k_gather         pre-collision populations at time t, FP64
 //   k_unstream       write a buffer whose pull yields given pre-collision
@@ -670,12 +673,9 @@ struct FuseK {
     static constexpr int SLOTS1 = E1X * E1Y;
     // Two LDS buffers (the middle steps read one and write the other, no
     // results held across a barrier) where both fit in half a CU's LDS
-    // (FP32); otherwise one, updated in place (FP64).
-#ifdef LBM_FUSE3_DB
-    static constexpr bool DB = LBM_FUSE3_DB && 2 * NP * PLANE * (int)sizeof(R) <= 81920;   // build-time override
-#else
+    // (FP32: 2048^2 step 43.0 against 44.2 us with one buffer in place);
+    // otherwise one, updated in place (FP64).
     static constexpr bool DB = 2 * NP * PLANE * (int)sizeof(R) <= 81920;
-#endif
     static constexpr int LDS_VALUES = (DB ? 2 : 1) * NP * PLANE;
     static_assert(LDS_VALUES * (int)sizeof(R) <= 81920, "fused tile needs more than half the LDS of a CU");
     // LDS index of plane p at the node (sx, sy) relative to the tile origin
@@ -986,12 +986,11 @@ __device__ __forceinline__ bool fk_open_tile(const Geom& G, int x0, int y0) {
     return x0 >= K && x0 + F::TX <= G.nx - K && y0 >= K && y0 + F::TY <= G.ny - K;
 }
 
-// Time steps per launch of the multi-step kernel.
+// Time steps per launch of the multi-step kernel (the kernel takes any
+// K >= 3; four steps for FP32, its window over the 68 x 12 region updated
+// in place, took 45.0 against 42.4 us per 2048^2 step on MI355X).
 template <class S, int NG>
 constexpr int fusek_steps() {
-#ifdef LBM_FUSEK_F32_STEPS
-    if (!std::is_same<S, double>::value) return LBM_FUSEK_F32_STEPS;   // build-time override
-#endif
     return 3;
 }
 
