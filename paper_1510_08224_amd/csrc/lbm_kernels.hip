@@ -645,15 +645,17 @@ void k_sweep2_batch(
 // grown by K - 2 nodes), indexed by the pulling node: a node of step s >= 2
 // reads every population at its own index; a node of step s - 1 writes
 // population i at the index of the node that pulls it, its own position +
-// e_i, when that node takes part in step s.  Steps 2 .. K - 1 update the
-// planes in place: every node reads and collides, a barrier, then every
-// node writes (each index has one writer and one reader per step).  Where
+// e_i, when that node takes part in step s.  With one buffer (FP64) steps
+// 2 .. K - 1 update the planes in place: every node reads and collides, a
+// barrier, then every node writes (each index has one writer and one reader
+// per step); with two (FP32) they read one buffer and write the other.  Where
 // the link into a node of step s crosses a non-periodic side, no node
 // exists at its source; the node itself writes the wall rule of the pull at
 // its own index in that plane in step s - 1, the one index of the plane no
 // other node writes.  Wall nodes rebuilt by extrapolation read their fluid
 // neighbour's pulls, which lie in the same step's region (the launch rules
-// out one-node edge tiles on such sides).  FP64 and FP32 storage.
+// out one-node edge tiles on such sides).  Generic over the storage; built
+// for FP64 and FP32 (fuse3_built).
 // ---------------------------------------------------------------------------
 template <class S, int NG, int K, int TY_>
 struct FuseK {
