@@ -87,7 +87,7 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
     if launch:
         S.set_launch(*launch)
     if single_steps:
-        S.set_launch(policy=S.get_launch()[3] & ~(lbm.LBM_POLICY_FUSE2 | lbm.LBM_POLICY_FUSE3))
+        S.set_launch(policy=S.get_launch()[3] & ~(lbm.LBM_POLICY_FUSE2 | lbm.LBM_POLICY_FUSEK))
     shape = S.get_launch()
     spl = S.steps_per_launch
     thermal = NG[model] > 0
@@ -148,7 +148,7 @@ def time_storage(storage: str, pb, steps: int, warmup: int, launch=None, model: 
 
 def roofline(storage: str, model: str, nodes: int, spl: int, launch_s: float, traffic) -> dict:
     """Roofline of one launch of the step kernel.  A launch advances `spl`
-    steps (3 or 2 when fused) and must read and write the whole state once:
+    steps (4 or 2 when fused) and must read and write the whole state once:
     its algorithmic HBM bytes are 2 (9 + NG) values per node whatever `spl`
     is, and `achieved` is those bytes over the launch time.  The
     single-step equivalent (spl times that: the bytes one-step launches

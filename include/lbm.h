@@ -323,26 +323,27 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           otherwise: nx % 64 == 1 or ny % 12 (8) == 1);
  *                           otherwise steps run singly
  *                           (lbm_steps_per_launch tells which);
- *   LBM_POLICY_FUSE3        lbm_step runs three time steps in one launch
+ *   LBM_POLICY_FUSEK        lbm_step runs K = 4 time steps in one launch
  *                           where a kernel exists (FP64 and FP32 storage,
  *                           the D2Q5 model or no temperature field, every
  *                           collision operator): a workgroup steps its
- *                           64 x 8 tile grown by two nodes from HBM into
- *                           LDS, the tile grown by one node from LDS, and
- *                           the tile into HBM, so the state crosses HBM
- *                           once per three steps.  Bitwise the same
- *                           results.  Same conditions as LBM_POLICY_FUSE2
- *                           (8-row tiles: nx % 64 == 1 or ny % 8 == 1 with
- *                           NEE walls falls back); steps left over run as
- *                           a pair (with LBM_POLICY_FUSE2) or singly, and
- *                           so does every step where no kernel exists.
+ *                           32 x 16 tile grown by three nodes from HBM into
+ *                           LDS, the tile grown by two and by one node from
+ *                           LDS, and the tile into HBM, so the state crosses
+ *                           HBM once per four steps (lbm_steps_per_launch
+ *                           gives K).  Bitwise the same results.  Same
+ *                           conditions as LBM_POLICY_FUSE2 (32 x 16 tiles:
+ *                           nx % 32 == 1 or ny % 16 == 1 with NEE walls
+ *                           falls back); steps left over run as a pair
+ *                           (with LBM_POLICY_FUSE2) or singly, and so does
+ *                           every step where no kernel exists.
  * The default follows the storage and the footprint F of both population
- * buffers: kept stores while F <= 256 MiB; three steps per launch with
- * bands where that kernel exists, for FP64 at any F and for FP32 once
+ * buffers: kept stores while F <= 256 MiB; K steps per launch with bands
+ * where that kernel exists, for FP64 at any F and for FP32 once
  * F > 256 MiB; otherwise fused pairs, with bands, or strips (with a
  * multiple of 8 tiles per row) once one row of fused tiles (tiles and
  * halos, every plane) exceeds 3 MiB or an FP64 lattice is 48 or more tiles
- * wide.  Fused pairs stay allowed beside three-step launches. */
+ * wide.  Fused pairs stay allowed beside K-step launches. */
 enum {
     LBM_POLICY_DEFAULT = -2,     /* back to the footprint rule */
     LBM_POLICY_KEEP = -1,        /* leave the policy as it is */
@@ -350,7 +351,7 @@ enum {
     LBM_POLICY_KEEP_STORES = 2,
     LBM_POLICY_XCD_STRIPS = 4,
     LBM_POLICY_FUSE2 = 8,
-    LBM_POLICY_FUSE3 = 16
+    LBM_POLICY_FUSEK = 16
 };
 
 /* Launch shape of the step kernel: block_x threads along x (64, 128 or
@@ -362,7 +363,7 @@ enum {
 int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread, int32_t policy);
 
 /* Time steps one step-kernel launch advances with the current parameters
- * and launch settings: 3 when three-step launches are in use, 2 when fused
+ * and launch settings: K (4) when K-step launches are in use, 2 when fused
  * pairs are, else 1 (remainders of a step count run shorter launches). */
 int lbm_steps_per_launch(const lbm_solver* h, int32_t* steps);
 int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread,
@@ -408,11 +409,11 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps);
 int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
 
 /* Fused time steps for the whole batch (the kernels of lbm_set_launch's
- * LBM_POLICY_FUSE2 and LBM_POLICY_FUSE3, one launch per pair or triple of
+ * LBM_POLICY_FUSE2 and LBM_POLICY_FUSEK, one launch per pair or per K
  * steps for all members, the same tiles).  policy: LBM_POLICY_DEFAULT, or
- * a mask of LBM_POLICY_FUSE2 and LBM_POLICY_FUSE3 (0: one launch per
+ * a mask of LBM_POLICY_FUSE2 and LBM_POLICY_FUSEK (0: one launch per
  * step).  The default fuses pairs for FP64 and FP32 storage and steps FP16
- * once per launch, and takes three steps per launch for FP64 storage (the
+ * once per launch, and takes K steps per launch for FP64 storage (the
  * D2Q5 model or no temperature field).  A kind of fused launch
  * applies only when every member qualifies (buffers below 4 GiB; with
  * walls by non-equilibrium extrapolation, no one-node edge tile); steps

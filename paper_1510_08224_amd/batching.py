@@ -157,7 +157,7 @@ def mix_key(solvers) -> str:
 
 
 def autotune_launch(B: lbm.Batch, solvers, steps: int = 100, cache_path: str | None = None) -> dict:
-    """Choose the launch the batched step runs with: three steps per launch,
+    """Choose the launch the batched step runs with: K steps per launch,
     fused pairs or one step per launch, the XCD order of the tile tables, kept or non-temporal
     stores, and the members' order in the tables (as added, or largest
     lattice first), by the measured time of the whole batched step (best of
@@ -175,10 +175,10 @@ def autotune_launch(B: lbm.Batch, solvers, steps: int = 100, cache_path: str | N
     trials = []
     if known is None:
         best, best_t = None, None
-        for policy in (lbm.LBM_POLICY_FUSE3 | lbm.LBM_POLICY_FUSE2, lbm.LBM_POLICY_FUSE2, 0):
+        for policy in (lbm.LBM_POLICY_FUSEK | lbm.LBM_POLICY_FUSE2, lbm.LBM_POLICY_FUSE2, 0):
             B.set_policy(policy)
-            if policy & lbm.LBM_POLICY_FUSE3 and B.steps_per_launch != 3:
-                continue   # no three-step kernel for this storage
+            if policy & lbm.LBM_POLICY_FUSEK and B.steps_per_launch <= 2:
+                continue   # no multi-step kernel for this storage
             for order in (1, 0):
                 for keep in (0, 1):
                     for largest in (0, 1):
@@ -266,7 +266,8 @@ def size_sweep(storages=("f32", "f64"), sides=(64, 96, 128, 192, 256, 384, 512, 
             count = max(1, int(round(total / side ** 2)))
             B, sols = build([W.cavity(side, 1e5)] * count, storage)
             t = {}
-            for pol in (0, lbm.LBM_POLICY_FUSE2, lbm.LBM_POLICY_FUSE3 | lbm.LBM_POLICY_FUSE2):
+            multi = lbm.LBM_POLICY_FUSEK | lbm.LBM_POLICY_FUSE2
+            for pol in (0, lbm.LBM_POLICY_FUSE2, multi):
                 B.set_policy(pol)
                 t[pol] = time_batch(B, steps)
             B.set_policy(lbm.LBM_POLICY_DEFAULT)
@@ -274,10 +275,9 @@ def size_sweep(storages=("f32", "f64"), sides=(64, 96, 128, 192, 256, 384, 512, 
             print(json.dumps({"storage": storage, "side": side, "members": count,
                               "single_us": round(t[0] * 1e6, 2),
                               "fused_us": round(t[lbm.LBM_POLICY_FUSE2] * 1e6, 2),
-                              "three_us": round(t[lbm.LBM_POLICY_FUSE3 | lbm.LBM_POLICY_FUSE2] * 1e6, 2),
+                              "multi_us": round(t[multi] * 1e6, 2),
                               "single_over_fused": round(t[0] / t[lbm.LBM_POLICY_FUSE2], 3),
-                              "fused_over_three": round(t[lbm.LBM_POLICY_FUSE2] /
-                                                        t[lbm.LBM_POLICY_FUSE3 | lbm.LBM_POLICY_FUSE2], 3),
+                              "fused_over_multi": round(t[lbm.LBM_POLICY_FUSE2] / t[multi], 3),
                               "single_mlups": round(nodes / t[0] / 1e6),
                               "fused_mlups": round(nodes / t[lbm.LBM_POLICY_FUSE2] / 1e6),
                               "default_steps_per_launch": B.steps_per_launch}), flush=True)

@@ -98,10 +98,10 @@ static void one_solver(int nx, int ny, int storage, int model, int coll, bool ne
     EXPECT(lbm_save_state(h, blob.data(), sb) == LBM_OK);
     EXPECT(lbm_save_state(h, blob.data(), sb - 1) != LBM_OK);
     for (int pol : {0, (int)(LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES), (int)LBM_POLICY_FUSE2,
-                    (int)(LBM_POLICY_FUSE3 | LBM_POLICY_FUSE2 | LBM_POLICY_XCD_BANDS), (int)LBM_POLICY_DEFAULT}) {
+                    (int)(LBM_POLICY_FUSEK | LBM_POLICY_FUSE2 | LBM_POLICY_XCD_BANDS), (int)LBM_POLICY_DEFAULT}) {
         EXPECT(lbm_set_launch(h, 0, 0, 0, pol) == LBM_OK);
         int32_t spl = 0;
-        EXPECT(lbm_steps_per_launch(h, &spl) == LBM_OK && spl >= 1 && spl <= 3);
+        EXPECT(lbm_steps_per_launch(h, &spl) == LBM_OK && spl >= 1 && (spl == 4 || spl <= 2));
         EXPECT(lbm_step(h, 3) == LBM_OK);
         EXPECT(lbm_step(h, 5) == LBM_OK);
     }
@@ -129,8 +129,8 @@ static void batches(int storage) {
         EXPECT(lbm_batch_add(b, h, &slot) == LBM_OK && slot >= 0);
         members.push_back(h);
     }
-    for (int pol : {(int)LBM_POLICY_DEFAULT, 0, (int)LBM_POLICY_FUSE2, (int)(LBM_POLICY_FUSE3 | LBM_POLICY_FUSE2),
-                    (int)LBM_POLICY_FUSE3}) {
+    for (int pol : {(int)LBM_POLICY_DEFAULT, 0, (int)LBM_POLICY_FUSE2, (int)(LBM_POLICY_FUSEK | LBM_POLICY_FUSE2),
+                    (int)LBM_POLICY_FUSEK}) {
         EXPECT(lbm_batch_set_policy(b, pol) == LBM_OK);
         EXPECT(lbm_batch_step(b, 7) == LBM_OK);
     }

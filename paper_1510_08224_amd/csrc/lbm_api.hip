@@ -90,12 +90,12 @@ struct lbm_batch {
     BatchTile* d_ftiles = nullptr;
     size_t cap_ftiles = 0;
     int nftiles = 0;
-    // Three steps per launch (LBM_POLICY_FUSE3): whether the current members
-    // use them, and their tile table (64 x 8 tiles).
-    bool fuse3 = false;
-    BatchTile* d_f3tiles = nullptr;
-    size_t cap_f3tiles = 0;
-    int nf3tiles = 0;
+    // K steps per launch (LBM_POLICY_FUSEK): whether the current members
+    // use them, and their tile table (tiles of the multi-step kernel).
+    bool fusek = false;
+    BatchTile* d_fktiles = nullptr;
+    size_t cap_fktiles = 0;
+    int nfktiles = 0;
     std::vector<int> member_slot;     // tile-table member index -> slot
     double* d_tile_max = nullptr;     // batched residual scratch
     unsigned long long* d_tile_bad = nullptr;
@@ -210,28 +210,27 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // Memory policy from the footprint of both population buffers, measured on
 // MI355X (512^2 to 4096^2 lattices, every model and storage,
 // `tuning.py`): when both fit the 256 MB last-level cache, stores keep their
-// lines there; above it non-temporal stores win.  Three steps per launch
-// (LBM_POLICY_FUSE3; FP64 and FP32 storage, the D2Q5 model or no
+// lines there; above it non-temporal stores win.  K = 4 steps per launch
+// (LBM_POLICY_FUSEK; FP64 and FP32 storage, the D2Q5 model or no
 // temperature field) win for FP64 at every size (D2Q5 over the best fused
-// pair: 512^2 +10%, 1024^2 +12% with kept stores, 2048^2 +30%, 4096^2 +32%;
-// the flow alone +2% to +26%) and for FP32 beyond the last-level cache
-// (2048^2 and 4096^2: D2Q5 +6% and +12%, the flow alone +14% and +20%; at
-// 1024^2 the pair is 11% faster); they need XCD bands (strips or round
-// robin took 14-55% longer).  Fused pairs (LBM_POLICY_FUSE2) win over
-// single steps for every storage and model at every size (FP16 included:
-// 2048^2 D2Q5, a 235 MB state, +13% over kept single stores; the flow
-// alone +9% to +22%), with bands, or strips (with a multiple of 8 tiles
-// per row) once one row of fused tiles exceeds 3 MiB or an FP64 lattice is
-// 48 or more tiles wide; pairs stay on for remainders and wherever three
-// steps do not apply.
+// pair: 512^2 +17%, 1024^2 +14% with kept stores, 2048^2 and 4096^2 +52%;
+// the flow alone +9% to +56%, within 5% of the pair at 512^2) and for FP32
+// beyond the last-level cache (2048^2 and 4096^2: D2Q5 +9% and +14%, the
+// flow alone +22% and +29%; at 1024^2 the D2Q5 pair is 11% faster); they
+// need XCD bands (strips or round robin took 8-59% longer).  Fused pairs
+// (LBM_POLICY_FUSE2) win over single steps for every storage and model at
+// every size (FP16 included: 2048^2 D2Q5, a 235 MB state, +13% over kept
+// single stores; the flow alone +9% to +22%), with bands, or strips (with
+// a multiple of 8 tiles per row) once one row of fused tiles exceeds 3 MiB
+// or an FP64 lattice is 48 or more tiles wide; pairs stay on for
+// remainders and wherever K-step launches do not apply.
 static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
     h->L.fuse2 = true;
-    const bool d2q5_or_flow = h->ng == 5 || h->ng == 0;
-    h->L.fuse3 = fuse3_rows(h->storage, h->ng) > 0 && d2q5_or_flow &&
+    h->L.fusek = fusek_launch_steps(h->storage, h->ng) > 0 &&
                  (h->storage == LBM_F64 || (h->storage == LBM_F32 && ws > 256.0 * mib));
-    if (h->L.fuse3) {
+    if (h->L.fusek) {
         h->L.order = 1;
     } else {
         // Bands keep the halo rows a fused tile shares with the tile row
@@ -733,30 +732,30 @@ static bool fuse2_active(const lbm_solver* h) {
     return true;
 }
 
-// Whether lbm_step may run three time steps per launch: asked for by the
+// Whether lbm_step may run K time steps per launch: asked for by the
 // policy, a kernel built for the storage and model, buffers below 4 GiB,
 // and, with NEE walls, no last tile one node wide or high.
-static bool fuse3_active(const lbm_solver* h) {
-    if (!h->L.fuse3 || !h->L.buffer) return false;
+static bool fusek_active(const lbm_solver* h) {
+    if (!h->L.fusek || !h->L.buffer) return false;
     if (h->buf_bytes >= (1ull << 32)) return false;
-    const int ty = fuse3_rows(h->storage, h->ng);
-    if (ty <= 0) return false;
-    if (h->C.any_nee && (h->nx % 64 == 1 || h->ny % ty == 1)) return false;
+    const int tx = fusek_tile_cols(h->storage, h->ng), ty = fusek_tile_rows(h->storage, h->ng);
+    if (tx <= 0 || ty <= 0) return false;
+    if (h->C.any_nee && (h->nx % tx == 1 || h->ny % ty == 1)) return false;
     return true;
 }
 
 // Sweeps of `steps` time steps from buffer `cur`; returns the number of
 // launches (each swaps the buffers once) or a negative HIP error.
 static hipError_t launch_steps(lbm_solver* h, int cur, int64_t steps, int64_t* launches) {
-    const bool fuse = fuse2_active(h), fuse3 = fuse3_active(h);
-    const int64_t k3 = fuse3_steps(h->storage, h->ng);
+    const bool fuse = fuse2_active(h), fusek = fusek_active(h);
+    const int64_t k = fusek_launch_steps(h->storage, h->ng);
     int64_t n = 0;
     while (steps > 0) {
         hipError_t e;
-        if (fuse3 && steps >= k3) {
-            e = launch_sweep3(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
+        if (fusek && steps >= k) {
+            e = launch_sweepk(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
                               h->stream);
-            steps -= k3;
+            steps -= k;
         } else if (fuse && steps >= 2) {
             e = launch_sweep2(h->storage, h->ng, h->L, h->G, h->C, h->d_coeffs, h->buf[cur], h->buf[cur ^ 1],
                               h->stream);
@@ -1140,7 +1139,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: block_x in {64,128,256}, block_x*block_y <= 256, rows in {1,2}");
     if (policy < LBM_POLICY_DEFAULT ||
         policy > (LBM_POLICY_XCD_BANDS | LBM_POLICY_KEEP_STORES | LBM_POLICY_XCD_STRIPS | LBM_POLICY_FUSE2 |
-                  LBM_POLICY_FUSE3) ||
+                  LBM_POLICY_FUSEK) ||
         (policy >= 0 && (policy & LBM_POLICY_XCD_BANDS) && (policy & LBM_POLICY_XCD_STRIPS)))
         return fail(h, LBM_ERR_ARG, "lbm_set_launch: unknown policy (bands and strips exclude each other)");
     h->L = L;
@@ -1150,7 +1149,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
         h->L.order = (policy & LBM_POLICY_XCD_BANDS) ? 1 : ((policy & LBM_POLICY_XCD_STRIPS) ? 2 : 0);
         h->L.keep = (policy & LBM_POLICY_KEEP_STORES) != 0;
         h->L.fuse2 = (policy & LBM_POLICY_FUSE2) != 0;
-        h->L.fuse3 = (policy & LBM_POLICY_FUSE3) != 0;
+        h->L.fusek = (policy & LBM_POLICY_FUSEK) != 0;
     }
     drop_graphs(h);
     if (h->batch) batch_invalidate(h->batch);
@@ -1159,7 +1158,7 @@ int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows
 
 int lbm_steps_per_launch(const lbm_solver* h, int32_t* steps) {
     if (!h || !steps) return fail(nullptr, LBM_ERR_ARG, "lbm_steps_per_launch: NULL argument");
-    *steps = fuse3_active(h) ? fuse3_steps(h->storage, h->ng) : (fuse2_active(h) ? 2 : 1);
+    *steps = fusek_active(h) ? fusek_launch_steps(h->storage, h->ng) : (fuse2_active(h) ? 2 : 1);
     return LBM_OK;
 }
 
@@ -1172,7 +1171,7 @@ int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int3
     if (policy)
         *policy = (h->L.order == 1 ? LBM_POLICY_XCD_BANDS : 0) | (h->L.order == 2 ? LBM_POLICY_XCD_STRIPS : 0) |
                   (h->L.keep ? LBM_POLICY_KEEP_STORES : 0) | (h->L.fuse2 ? LBM_POLICY_FUSE2 : 0) |
-                  (h->L.fuse3 ? LBM_POLICY_FUSE3 : 0);
+                  (h->L.fusek ? LBM_POLICY_FUSEK : 0);
     return LBM_OK;
 }
 
@@ -1228,7 +1227,7 @@ void lbm_batch_destroy(lbm_batch* b) {
     if (b->d_members) (void)hipFree(b->d_members);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_ftiles) (void)hipFree(b->d_ftiles);
-    if (b->d_f3tiles) (void)hipFree(b->d_f3tiles);
+    if (b->d_fktiles) (void)hipFree(b->d_fktiles);
     if (b->d_tile_max) (void)hipFree(b->d_tile_max);
     if (b->d_tile_bad) (void)hipFree(b->d_tile_bad);
     if (b->d_rout) (void)hipFree(b->d_rout);
@@ -1308,12 +1307,13 @@ static hipError_t batch_table(T** d, size_t* cap, size_t n) {
 
 static int batch_build(lbm_batch* b) {
     std::vector<BatchMember> mem;
-    std::vector<BatchTile> tiles, ftiles, f3tiles;
+    std::vector<BatchTile> tiles, ftiles, fktiles;
     b->member_slot.clear();
     b->buffer = true;
     const int fty = fuse2_rows(b->storage, b->ng < 0 ? 5 : b->ng);
-    const int f3ty = fuse3_rows(b->storage, b->ng < 0 ? 5 : b->ng);
-    bool can_fuse = fty > 0, can_fuse3 = f3ty > 0;
+    const int ng = b->ng < 0 ? 5 : b->ng;
+    const int ktx = fusek_tile_cols(b->storage, ng), kty = fusek_tile_rows(b->storage, ng);
+    bool can_fuse = fty > 0, can_fusek = ktx > 0 && kty > 0;
     double ws = 0.0;
     // members in table order: as added, or the largest lattices first (their
     // tiles then start the launch and the small ones fill its tail)
@@ -1343,13 +1343,13 @@ static int batch_build(lbm_batch* b) {
         M.ntiles = (int)tiles.size() - M.tile0;
         for (int y0 = 0; y0 < h->ny; y0 += fty)
             for (int x0 = 0; x0 < h->nx; x0 += 64) ftiles.push_back(BatchTile{id, x0, y0, 64});
-        if (can_fuse3)
-            for (int y0 = 0; y0 < h->ny; y0 += f3ty)
-                for (int x0 = 0; x0 < h->nx; x0 += 64) f3tiles.push_back(BatchTile{id, x0, y0, 64});
+        if (can_fusek)
+            for (int y0 = 0; y0 < h->ny; y0 += kty)
+                for (int x0 = 0; x0 < h->nx; x0 += ktx) fktiles.push_back(BatchTile{id, x0, y0, ktx});
         // a wall node rebuilt by extrapolation must find its fluid
         // neighbour inside the same fused tile
         if (h->C.any_nee && (h->nx % 64 == 1 || h->ny % fty == 1)) can_fuse = false;
-        if (h->C.any_nee && f3ty > 0 && (h->nx % 64 == 1 || h->ny % f3ty == 1)) can_fuse3 = false;
+        if (h->C.any_nee && can_fusek && (h->nx % ktx == 1 || h->ny % kty == 1)) can_fusek = false;
         ws += 2.0 * (double)h->buf_bytes;
         mem.push_back(M);
         b->member_slot.push_back((int)k);
@@ -1359,17 +1359,18 @@ static int batch_build(lbm_batch* b) {
     // all, sides 64 to 1024: FP32 1.1x to 1.6x, FP64 1.3x to 1.9x over one
     // step per launch); FP16 batches keep single steps, like FP16 lattices.
     const double mib = 1024.0 * 1024.0;
-    // Three steps per launch for FP64 batches (batches of equal cavities,
-    // 6.7e6 nodes in all: 3-20% less time per step than fused pairs, sides
-    // 64 to 1024; single FP64 lattices gain at every size);
-    // FP32 batches keep fused pairs, which were 4-27% faster at every side
-    // (the two-node margins of small members take the general path).
+    // K steps per launch for FP64 batches (batches of equal cavities,
+    // 6.7e6 nodes in all: 9-31% less time per step than fused pairs, sides
+    // 64 to 1024; single FP64 lattices gain at every size); FP32 batches
+    // keep fused pairs, which were up to 16% faster at sides 128 to 512 (the
+    // margins of small members take the general path; K steps won by 3-14%
+    // at sides 64, 96 and 1024).
     const bool want = b->policy == LBM_POLICY_DEFAULT
                           ? (b->storage == LBM_F64 || b->storage == LBM_F32)
                           : (b->policy & LBM_POLICY_FUSE2) != 0;
-    const bool want3 = b->policy == LBM_POLICY_DEFAULT ? b->storage == LBM_F64 : (b->policy & LBM_POLICY_FUSE3) != 0;
+    const bool wantk = b->policy == LBM_POLICY_DEFAULT ? b->storage == LBM_F64 : (b->policy & LBM_POLICY_FUSEK) != 0;
     b->fuse = want && can_fuse && b->buffer && !mem.empty();
-    b->fuse3 = want3 && can_fuse3 && b->buffer && !mem.empty();
+    b->fusek = wantk && can_fusek && b->buffer && !mem.empty();
     b->keep = b->tune_keep < 0 ? ws <= 256.0 * mib : b->tune_keep == 1;
     b->order = b->tune_order < 0 ? 1 : b->tune_order;
     if (batch_table(&b->d_members, &b->cap_members, mem.size()) != hipSuccess)
@@ -1378,8 +1379,8 @@ static int batch_build(lbm_batch* b) {
         return bfail(b, LBM_ERR_NOMEM, "batch tile table allocation");
     if (b->fuse && batch_table(&b->d_ftiles, &b->cap_ftiles, ftiles.size()) != hipSuccess)
         return bfail(b, LBM_ERR_NOMEM, "batch fused tile table allocation");
-    if (b->fuse3 && batch_table(&b->d_f3tiles, &b->cap_f3tiles, f3tiles.size()) != hipSuccess)
-        return bfail(b, LBM_ERR_NOMEM, "batch three-step tile table allocation");
+    if (b->fusek && batch_table(&b->d_fktiles, &b->cap_fktiles, fktiles.size()) != hipSuccess)
+        return bfail(b, LBM_ERR_NOMEM, "batch multi-step tile table allocation");
     if (!mem.empty()) {
         hipError_t e = hipMemcpyAsync(b->d_members, mem.data(), mem.size() * sizeof(BatchMember), hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess)
@@ -1387,15 +1388,15 @@ static int batch_build(lbm_batch* b) {
         if (e == hipSuccess && b->fuse)
             e = hipMemcpyAsync(b->d_ftiles, ftiles.data(), ftiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
                                b->stream);
-        if (e == hipSuccess && b->fuse3)
-            e = hipMemcpyAsync(b->d_f3tiles, f3tiles.data(), f3tiles.size() * sizeof(BatchTile),
+        if (e == hipSuccess && b->fusek)
+            e = hipMemcpyAsync(b->d_fktiles, fktiles.data(), fktiles.size() * sizeof(BatchTile),
                                hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // host vectors die on return
         if (e != hipSuccess) return bfail(b, LBM_ERR_DEVICE, std::string("batch table upload: ") + hipGetErrorString(e));
     }
     b->ntiles = (int)tiles.size();
     b->nftiles = b->fuse ? (int)ftiles.size() : 0;
-    b->nf3tiles = b->fuse3 ? (int)f3tiles.size() : 0;
+    b->nfktiles = b->fusek ? (int)fktiles.size() : 0;
     b->parity = 0;
     b->dirty = false;
     return LBM_OK;
@@ -1406,13 +1407,13 @@ static int batch_build(lbm_batch* b) {
 // member's buffers once.  Returns the number of launches in *launches.
 static hipError_t batch_launch_steps(lbm_batch* b, int parity, int64_t steps, int64_t* launches) {
     int64_t n = 0;
-    const int64_t k3 = fuse3_steps(b->storage, b->ng < 0 ? 5 : b->ng);
+    const int64_t k = fusek_launch_steps(b->storage, b->ng < 0 ? 5 : b->ng);
     while (steps > 0) {
         hipError_t e;
-        if (b->fuse3 && steps >= k3) {
-            e = launch_sweep3_batch(b->storage, b->ng, b->keep, b->d_members, b->d_f3tiles, b->nf3tiles, parity,
+        if (b->fusek && steps >= k) {
+            e = launch_sweepk_batch(b->storage, b->ng, b->keep, b->d_members, b->d_fktiles, b->nfktiles, parity,
                                     b->order, b->stream);
-            steps -= k3;
+            steps -= k;
         } else if (b->fuse && steps >= 2) {
             e = launch_sweep2_batch(b->storage, b->ng, b->keep, b->d_members, b->d_ftiles, b->nftiles, parity, b->order,
                                     b->stream);
@@ -1487,9 +1488,9 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps) {
 
 int lbm_batch_set_policy(lbm_batch* b, int32_t policy) {
     if (!b) return bfail(nullptr, LBM_ERR_ARG, "lbm_batch_set_policy: NULL batch");
-    if (policy != LBM_POLICY_DEFAULT && (policy < 0 || (policy & ~(LBM_POLICY_FUSE2 | LBM_POLICY_FUSE3)) != 0))
+    if (policy != LBM_POLICY_DEFAULT && (policy < 0 || (policy & ~(LBM_POLICY_FUSE2 | LBM_POLICY_FUSEK)) != 0))
         return bfail(b, LBM_ERR_ARG,
-                     "lbm_batch_set_policy: LBM_POLICY_DEFAULT or a mask of LBM_POLICY_FUSE2 and LBM_POLICY_FUSE3");
+                     "lbm_batch_set_policy: LBM_POLICY_DEFAULT or a mask of LBM_POLICY_FUSE2 and LBM_POLICY_FUSEK");
     b->policy = policy;
     batch_invalidate(b);
     return LBM_OK;
@@ -1526,7 +1527,7 @@ int lbm_batch_steps_per_launch(lbm_batch* b, int32_t* steps) {
         int rc = batch_build(b);
         if (rc != LBM_OK) return rc;
     }
-    *steps = b->fuse3 ? fuse3_steps(b->storage, b->ng < 0 ? 5 : b->ng) : (b->fuse ? 2 : 1);
+    *steps = b->fusek ? fusek_launch_steps(b->storage, b->ng < 0 ? 5 : b->ng) : (b->fuse ? 2 : 1);
     return LBM_OK;
 }
 

@@ -15,7 +15,7 @@ struct Launch {
     int order = 1;       // XCD tile order: 0 round robin, 1 bands, 2 strips (lbm_kernels.hip)
     bool keep = false;   // default-policy stores (true) or non-temporal stores (false)
     bool fuse2 = false;  // two time steps per launch where the lattice allows it
-    bool fuse3 = false;  // three time steps per launch where the kernel exists and the lattice allows it
+    bool fusek = false;  // K time steps per launch where the kernel exists and the lattice allows it
 };
 
 // A lattice of a batch as the batched step kernel sees it.
@@ -42,13 +42,14 @@ inline int storage_bytes(int storage) { return storage == kF64 ? 8 : (storage ==
 hipError_t launch_sweep2(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st);
 int fuse2_rows(int storage, int ng);
-// Tile rows and time steps per launch of the multi-step kernel, or 0 where
-// none is built.
-int fuse3_rows(int storage, int ng);
-int fuse3_steps(int storage, int ng);
-hipError_t launch_sweep3(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
+// Tile rows, tile columns and time steps per launch of the multi-step
+// kernel, or 0 where none is built.
+int fusek_tile_rows(int storage, int ng);
+int fusek_tile_cols(int storage, int ng);
+int fusek_launch_steps(int storage, int ng);
+hipError_t launch_sweepk(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st);
-hipError_t launch_sweep3_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
+hipError_t launch_sweepk_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
                                int ntiles, int parity, int order, hipStream_t st);
 // Fused pairs of steps for a batch (buffer addressing; keep: default-policy stores).
 // order: XCD order of the tile table (0 round robin, 1 bands).

@@ -8,9 +8,10 @@
 //   k_sweep_batch    the same step for every lattice of a batch
 //   k_sweep2(_batch) two time steps per launch: the first on a tile and its
 //                    halo into LDS, the second from LDS to memory
-//   k_sweepk(_batch) three time steps per launch (FP64 / FP32, D2Q5 or no
-//                    temperature): the tile grown by two nodes from memory
-//                    into LDS, grown by one node within LDS, the tile to memory
+//   k_sweepk(_batch) four time steps per launch (FP64 / FP32, D2Q5 or no
+//                    temperature): the tile grown by three nodes from memory
+//                    into LDS, grown by two and one within LDS, the tile to
+//                    memory
 //   k_moments        rho, u, T at time t (Eqs. 18, 19, 27)
 //   k_gather         pre-collision populations at time t, FP64
 //   k_unstream       write a buffer whose pull yields given pre-collision
@@ -632,13 +633,13 @@ void k_sweep2_batch(
 }
 
 // ---------------------------------------------------------------------------
-// K >= 3 time steps per launch.  A workgroup owns a 64 x TY tile.  Step 1
+// K >= 3 time steps per launch.  A workgroup owns a TX x TY tile.  Step 1
 // runs on the tile grown by K - 1 nodes on every side, reading the state
 // from HBM as the single-step kernel does; step s runs on the tile grown by
 // K - s nodes, pulling the post-collision populations of step s - 1 from
 // LDS; step K runs on the tile and stores to HBM.  The state crosses HBM
-// once per K steps; the margins cost sum_s (64 + 2(K - s))(TY + 2(K - s)) /
-// (64 TY K) - 1 extra collisions per node and step.  The result is bitwise
+// once per K steps; the margins cost sum_s (TX + 2(K - s))(TY + 2(K - s)) /
+// (TX TY K) - 1 extra collisions per node and step.  The result is bitwise
 // the result of K single steps.
 //
 // LDS holds one plane per population over the region of step 2 (the tile
@@ -655,15 +656,15 @@ void k_sweep2_batch(
 // other node writes.  Wall nodes rebuilt by extrapolation read their fluid
 // neighbour's pulls, which lie in the same step's region (the launch rules
 // out one-node edge tiles on such sides).  Generic over the storage; built
-// for FP64 and FP32 (fuse3_built).
+// for FP64 and FP32 (fusek_built).
 // ---------------------------------------------------------------------------
-template <class S, int NG, int K, int TY_>
+template <class S, int NG, int K, int TY_, int TX_>
 struct FuseK {
     using R = typename Codec<S>::R;
     using Store = S;
     static_assert(K >= 3, "two steps per launch are the fused pair");
     static constexpr int NP = 9 + NG;
-    static constexpr int TX = 64;
+    static constexpr int TX = TX_;
     static constexpr int TY = TY_;
     static constexpr int NT = TX * TY;          // threads: one per tile node
     static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
@@ -680,6 +681,9 @@ struct FuseK {
     static constexpr bool DB = 2 * NP * PLANE * (int)sizeof(R) <= 81920;
     static constexpr int LDS_VALUES = (DB ? 2 : 1) * NP * PLANE;
     static_assert(LDS_VALUES * (int)sizeof(R) <= 81920, "fused tile needs more than half the LDS of a CU");
+    // workgroups per CU the LDS (160 KiB) and the CU's 32 wave slots allow
+    static constexpr int WG_PER_CU = (163840 / (LDS_VALUES * (int)sizeof(R)) < 2048 / NT)
+                                         ? 163840 / (LDS_VALUES * (int)sizeof(R)) : 2048 / NT;
     // LDS index of plane p at the node (sx, sy) relative to the tile origin
     static __device__ __forceinline__ int at(int p, int sx, int sy) { return p * PLANE + (sy + WM) * WX + (sx + WM); }
 };
@@ -988,28 +992,42 @@ __device__ __forceinline__ bool fk_open_tile(const Geom& G, int x0, int y0) {
     return x0 >= K && x0 + F::TX <= G.nx - K && y0 >= K && y0 + F::TY <= G.ny - K;
 }
 
-// Time steps per launch of the multi-step kernel (the kernel takes any
-// K >= 3; four steps for FP32, its window over the 68 x 12 region updated
-// in place, took 45.0 against 42.4 us per 2048^2 step on MI355X).
+// Time steps per launch of the multi-step kernel and its tile.  Four steps
+// on 32 x 16 tiles: the FP64 D2Q5 window (14 planes of 36 x 20) takes
+// 80.6 KB, so two workgroups share a CU, and a launch collides 5.23 times
+// per tile node (1.31 per step).  Measured on MI355X (2048^2 heated cavity,
+// FP64, per step): 55.7 us against 63.8 for three steps on 64 x 8 tiles
+// (4096^2 200.8 against 238.6; the flow alone 38.0 against 44.4; FP32 42.0
+// against 43.6).  The tile shape alone gains nothing: three steps on
+// 32 x 16 or 32 x 8 tiles (four workgroups per CU) took 64.8 us each,
+// on 32 x 12 (three per CU, spilling) 82.5; four steps on 64 x 8 tiles
+// would need 91 KB for FP64, one workgroup per CU, and took 45.0 against
+// 42.4 us per FP32 step, its window updated in place.  The kernel takes any
+// K >= 3 and any tile whose window fits half the LDS.
 template <class S, int NG>
 constexpr int fusek_steps() {
-    return 3;
+    return 4;
 }
 
 template <class S, int NG, int K>
 constexpr int fusek_rows() {
-#ifdef LBM_FUSE3_ROWS
-    return LBM_FUSE3_ROWS;   // build-time override of the tile height
-#else
-    return 8;
-#endif
+    return 16;
 }
 
-// Waves per SIMD for two workgroups per CU (what the LDS of every variant
-// allows), asked of the compiler so that its register budget lets them in.
+template <class S, int NG, int K>
+constexpr int fusek_cols() {
+    return 32;
+}
+
+template <class S, int NG, int K>
+using FuseKT = FuseK<S, NG, K, fusek_rows<S, NG, K>(), fusek_cols<S, NG, K>()>;
+
+// Waves per SIMD for as many workgroups per CU as the LDS allows, asked of
+// the compiler so that its register budget lets them in.
 template <class S, int NG, int K>
 constexpr int fusek_waves() {
-    return (2 * FuseK<S, NG, K, fusek_rows<S, NG, K>()>::NT / 64 + 3) / 4;
+    constexpr int w = (FuseKT<S, NG, K>::WG_PER_CU * FuseKT<S, NG, K>::NT / 64 + 3) / 4;
+    return w < 8 ? w : 8;
 }
 
 // K fused steps on the tile at (x0, y0) of one lattice (the body of the
@@ -1018,7 +1036,7 @@ template <class S, int NG, int K, int MODE, int COLL>
 __device__ __forceinline__ void fusek_tile(const Geom& G, const Coeffs& C, const S* __restrict__ src,
                                            S* __restrict__ dst, unsigned buf_bytes, int x0, int y0,
                                            typename Codec<S>::R* lds) {
-    using F = FuseK<S, NG, K, fusek_rows<S, NG, K>()>;
+    using F = FuseKT<S, NG, K>;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, buf_bytes);
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, buf_bytes);
     if (fk_open_tile<F>(G, x0, y0)) {
@@ -1035,11 +1053,11 @@ __device__ __forceinline__ void fusek_tile(const Geom& G, const Coeffs& C, const
 }
 
 template <class S, int NG, int K, int MODE, int COLL>
-__global__ __launch_bounds__((FuseK<S, NG, K, fusek_rows<S, NG, K>()>::NT))
+__global__ __launch_bounds__((FuseKT<S, NG, K>::NT))
 __attribute__((amdgpu_waves_per_eu(fusek_waves<S, NG, K>(), 8))) void k_sweepk(
     Geom G, const Coeffs* __restrict__ Cp, const S* __restrict__ src, S* __restrict__ dst, int tiles_x,
     unsigned buf_bytes, int order) {
-    using F = FuseK<S, NG, K, fusek_rows<S, NG, K>()>;
+    using F = FuseKT<S, NG, K>;
     __shared__ typename F::R lds[F::LDS_VALUES];
     const int tile = xcd_remap(blockIdx.x, gridDim.x, order, tiles_x);
     fusek_tile<S, NG, K, MODE, COLL>(G, *Cp, src, dst, buf_bytes, (tile % tiles_x) * F::TX, (tile / tiles_x) * F::TY,
@@ -1047,12 +1065,12 @@ __attribute__((amdgpu_waves_per_eu(fusek_waves<S, NG, K>(), 8))) void k_sweepk(
 }
 
 // K fused steps for every lattice of a batch: each workgroup takes one
-// entry of the K-step tile table (a member and its 64 x TY tile).
+// entry of the K-step tile table (a member and its TX x TY tile).
 template <class S, int NG, int K, int MODE>
-__global__ __launch_bounds__((FuseK<S, NG, K, fusek_rows<S, NG, K>()>::NT))
+__global__ __launch_bounds__((FuseKT<S, NG, K>::NT))
 __attribute__((amdgpu_waves_per_eu(fusek_waves<S, NG, K>(), 8))) void k_sweepk_batch(
     const BatchMember* __restrict__ members, const BatchTile* __restrict__ tiles, int parity, int order) {
-    using F = FuseK<S, NG, K, fusek_rows<S, NG, K>()>;
+    using F = FuseKT<S, NG, K>;
     __shared__ typename F::R lds[F::LDS_VALUES];
     const BatchTile t = tiles[xcd_remap(blockIdx.x, gridDim.x, order, 0)];
     const BatchMember& M = members[t.member];
@@ -1546,22 +1564,23 @@ static hipError_t sweep2_t(const Launch& L, const Geom& G, const Coeffs& Ch, con
 }
 
 
-// Three steps per launch, every collision operator: FP64 and FP32 storage
-// with the D2Q5 model or no temperature field.  Not for the D2Q9 thermal
-// model: its FP64 window (18 planes of 66 x 10 doubles) would take more
-// than half a CU's LDS, and in FP32 / FP16 the in-place middle step spills
-// about 1 KB per lane at the four waves per SIMD two workgroups per CU
-// need.  Not for FP16 storage: the kernel is generic over the storage
-// (bitwise equal to single steps, tested), but on MI355X it lost to FP16
-// fused pairs at every size (2048^2 D2Q5 45.7 against 33.6 us per step,
-// 4096^2 172 against 140), the conversions of every value to and from FP16
-// making the longer launch issue-bound.
-static constexpr bool fuse3_built(int storage, int ng) {
+// K steps per launch, every collision operator: FP64 and FP32 storage with
+// the D2Q5 model or no temperature field.  Not for the D2Q9 thermal model:
+// its FP64 window (18 planes of 36 x 20 doubles) would take more than half
+// a CU's LDS, and in FP32 the in-place middle step spilled about 1 KB per
+// lane (three steps on 64 x 8 tiles) at the four waves per SIMD two
+// workgroups per CU need.  Not for FP16 storage: the kernel is generic over
+// the storage (bitwise equal to single steps, tested), but on MI355X three
+// steps per launch on 64 x 8 tiles lost to FP16 fused pairs at every size
+// (2048^2 D2Q5 45.7 against 33.6 us per step, 4096^2 172 against 140), the
+// conversions of every value to and from FP16 making the longer launch
+// issue-bound.
+static constexpr bool fusek_built(int storage, int ng) {
     return (storage == kF64 || storage == kF32) && (ng == 5 || ng == 0);
 }
 
-// Runs the statement with S and NG bound for every built three-step kernel.
-#define LBM_DISPATCH3(storage, ng, ...)                                                   \
+// Runs the statement with S and NG bound for every built multi-step kernel.
+#define LBM_DISPATCHK(storage, ng, ...)                                                   \
     switch ((storage) * 16 + (ng)) {                                                      \
         case kF64 * 16 + 0: { using S = double; constexpr int NG = 0; __VA_ARGS__; } break; \
         case kF64 * 16 + 5: { using S = double; constexpr int NG = 5; __VA_ARGS__; } break; \
@@ -1571,27 +1590,32 @@ static constexpr bool fuse3_built(int storage, int ng) {
     }
 
 template <class S, int NG>
-using FuseKOf = FuseK<S, NG, fusek_steps<S, NG>(), fusek_rows<S, NG, fusek_steps<S, NG>()>()>;
+using FuseKOf = FuseKT<S, NG, fusek_steps<S, NG>()>;
 
-int fuse3_rows(int storage, int ng) {
-    LBM_DISPATCH3(storage, ng, return FuseKOf<S, NG>::TY);
+int fusek_tile_rows(int storage, int ng) {
+    LBM_DISPATCHK(storage, ng, return FuseKOf<S, NG>::TY);
     return 0;
 }
 
-int fuse3_steps(int storage, int ng) {
-    LBM_DISPATCH3(storage, ng, return fusek_steps<S, NG>());
+int fusek_tile_cols(int storage, int ng) {
+    LBM_DISPATCHK(storage, ng, return FuseKOf<S, NG>::TX);
+    return 0;
+}
+
+int fusek_launch_steps(int storage, int ng) {
+    LBM_DISPATCHK(storage, ng, return fusek_steps<S, NG>());
     return 0;
 }
 
 template <class S, int NG, int MODE, int COLL>
-static void sweep3_launch1(int ntiles, hipStream_t st, const Geom& G, const Coeffs* C, const S* s, S* d, int tiles_x,
+static void sweepk_launch1(int ntiles, hipStream_t st, const Geom& G, const Coeffs* C, const S* s, S* d, int tiles_x,
                            unsigned bytes, int order) {
     hipLaunchKernelGGL((k_sweepk<S, NG, fusek_steps<S, NG>(), MODE, COLL>), dim3(ntiles), dim3(FuseKOf<S, NG>::NT),
                        0, st, G, C, s, d, tiles_x, bytes, order);
 }
 
 template <class S, int NG>
-static hipError_t sweep3_t(const Launch& L, const Geom& G, const Coeffs& Ch, const Coeffs* C, const void* src,
+static hipError_t sweepk_t(const Launch& L, const Geom& G, const Coeffs& Ch, const Coeffs* C, const void* src,
                            void* dst, hipStream_t st) {
     using F = FuseKOf<S, NG>;
     const unsigned long long bytes = buffer_bytes<S>(G);
@@ -1605,28 +1629,28 @@ static hipError_t sweep3_t(const Launch& L, const Geom& G, const Coeffs& Ch, con
     const int ntiles = tiles_x * tiles_y;
     const unsigned b = (unsigned)bytes;
     if (L.keep) {
-        if (coll == kCollBGK) sweep3_launch1<S, NG, kBufferKeep, kCollBGK>(ntiles, st, G, C, s, d, tiles_x, b, order);
-        else if (coll == kCollOrtho) sweep3_launch1<S, NG, kBufferKeep, kCollOrtho>(ntiles, st, G, C, s, d, tiles_x, b, order);
-        else sweep3_launch1<S, NG, kBufferKeep, kCollMRT>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        if (coll == kCollBGK) sweepk_launch1<S, NG, kBufferKeep, kCollBGK>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        else if (coll == kCollOrtho) sweepk_launch1<S, NG, kBufferKeep, kCollOrtho>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        else sweepk_launch1<S, NG, kBufferKeep, kCollMRT>(ntiles, st, G, C, s, d, tiles_x, b, order);
     } else {
-        if (coll == kCollBGK) sweep3_launch1<S, NG, kBufferNT, kCollBGK>(ntiles, st, G, C, s, d, tiles_x, b, order);
-        else if (coll == kCollOrtho) sweep3_launch1<S, NG, kBufferNT, kCollOrtho>(ntiles, st, G, C, s, d, tiles_x, b, order);
-        else sweep3_launch1<S, NG, kBufferNT, kCollMRT>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        if (coll == kCollBGK) sweepk_launch1<S, NG, kBufferNT, kCollBGK>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        else if (coll == kCollOrtho) sweepk_launch1<S, NG, kBufferNT, kCollOrtho>(ntiles, st, G, C, s, d, tiles_x, b, order);
+        else sweepk_launch1<S, NG, kBufferNT, kCollMRT>(ntiles, st, G, C, s, d, tiles_x, b, order);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep3(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
+hipError_t launch_sweepk(int storage, int ng, const Launch& L, const Geom& G, const Coeffs& C, const Coeffs* dC,
                          const void* src, void* dst, hipStream_t st) {
-    if (!fuse3_built(storage, ng)) return hipErrorInvalidValue;
-    LBM_DISPATCH3(storage, ng, return sweep3_t<S, NG>(L, G, C, dC, src, dst, st));
+    if (!fusek_built(storage, ng)) return hipErrorInvalidValue;
+    LBM_DISPATCHK(storage, ng, return sweepk_t<S, NG>(L, G, C, dC, src, dst, st));
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep3_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
+hipError_t launch_sweepk_batch(int storage, int ng, bool keep, const BatchMember* members, const BatchTile* tiles,
                                int ntiles, int parity, int order, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (!fuse3_built(storage, ng)) return hipErrorInvalidValue;
+    if (!fusek_built(storage, ng)) return hipErrorInvalidValue;
     auto go = [&](auto s, auto n) {
         using S = decltype(s);
         constexpr int NG = decltype(n)::value;
@@ -1638,7 +1662,7 @@ hipError_t launch_sweep3_batch(int storage, int ng, bool keep, const BatchMember
             hipLaunchKernelGGL((k_sweepk_batch<S, NG, K, kBufferNT>), dim3(ntiles), dim3(FuseKOf<S, NG>::NT), 0, st,
                                members, tiles, parity, order);
     };
-    LBM_DISPATCH3(storage, ng, go(S{}, std::integral_constant<int, NG>{}));
+    LBM_DISPATCHK(storage, ng, go(S{}, std::integral_constant<int, NG>{}));
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ LBM_T_PERIODIC, LBM_T_DIRICHLET, LBM_T_ADIABATIC, LBM_T_NEE_DIRICHLET, LBM_T_NEE
 
 LBM_MODEL_D2Q5, LBM_MODEL_D2Q9T, LBM_MODEL_ISOTHERMAL = 0, 1, 2
 LBM_POLICY_DEFAULT, LBM_POLICY_KEEP, LBM_POLICY_XCD_BANDS, LBM_POLICY_KEEP_STORES = -2, -1, 1, 2
-LBM_POLICY_XCD_STRIPS, LBM_POLICY_FUSE2, LBM_POLICY_FUSE3 = 4, 8, 16
+LBM_POLICY_XCD_STRIPS, LBM_POLICY_FUSE2, LBM_POLICY_FUSEK = 4, 8, 16
 LBM_COLLISION_MRT, LBM_COLLISION_BGK, LBM_COLLISION_ORTHO_MRT = 0, 1, 2
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16}
 MODEL = {"d2q5": LBM_MODEL_D2Q5, "d2q9t": LBM_MODEL_D2Q9T, "isothermal": LBM_MODEL_ISOTHERMAL}
@@ -465,7 +465,7 @@ class Batch:
 
     def set_policy(self, policy: int):
         """LBM_POLICY_DEFAULT, or a mask of LBM_POLICY_FUSE2 and
-        LBM_POLICY_FUSE3 (0: one launch per step)."""
+        LBM_POLICY_FUSEK (0: one launch per step)."""
         _bcheck(lib().lbm_batch_set_policy(self.h, int(policy)), self.h)
 
     @property

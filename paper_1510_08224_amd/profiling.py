@@ -5,7 +5,7 @@
 
 Step kernels are keyed by storage ("f64") for the D2Q5 model and by
 model and storage ("d2q9t_f64", "isothermal_f64") for the others, with
-the time steps per launch appended ("f64/3": three steps per launch,
+the time steps per launch appended ("f64/4": four steps per launch,
 "f64/2": fused pairs, "f64/1": single steps).
 
 ``stats`` turns the kernel statistics of a ``rocprofv3 --kernel-trace

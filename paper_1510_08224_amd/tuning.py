@@ -8,9 +8,9 @@ For every lattice size, temperature model and storage, times the step
 kernel (HIP events on the solver's stream) for each block width
 (64 x 4, 128 x 2, 256 x 1) and each memory policy of single steps (XCD
 order round robin, bands or strips; kept or non-temporal stores), and for
-fused pairs of steps (LBM_POLICY_FUSE2) and three steps per launch
-(LBM_POLICY_FUSE3, where that kernel exists; their 64 x TY tiles do not use
-the block width) in each XCD order and store policy, and prints one JSON line
+fused pairs of steps (LBM_POLICY_FUSE2) and K steps per launch
+(LBM_POLICY_FUSEK, where that kernel exists; fused tiles do not use the
+block width) in each XCD order and store policy, and prints one JSON line
 with the library's default choice, the best choice and every figure
 (algorithmic GB/s: 2 (9 + NG) stored values per node and step).  Results
 do not depend on the shape or the policy; only the time does.
@@ -32,8 +32,8 @@ SHAPES = (64, 128, 256)
 POLICIES = tuple(order | keep for order in (0, lbm.LBM_POLICY_XCD_BANDS, lbm.LBM_POLICY_XCD_STRIPS)
                  for keep in (0, lbm.LBM_POLICY_KEEP_STORES))
 FUSED = tuple(lbm.LBM_POLICY_FUSE2 | p for p in POLICIES)
-FUSED3 = tuple(lbm.LBM_POLICY_FUSE3 | lbm.LBM_POLICY_FUSE2 | p for p in POLICIES)
-FUSE_ANY = lbm.LBM_POLICY_FUSE2 | lbm.LBM_POLICY_FUSE3
+FUSEDK = tuple(lbm.LBM_POLICY_FUSEK | lbm.LBM_POLICY_FUSE2 | p for p in POLICIES)
+FUSE_ANY = lbm.LBM_POLICY_FUSE2 | lbm.LBM_POLICY_FUSEK
 
 
 def _time_steps(S, steps: int) -> float:
@@ -50,10 +50,10 @@ def _time_steps(S, steps: int) -> float:
 
 
 def _steps_for(S) -> int:
-    # about 2 GB of algorithmic traffic per setting, at least 42 steps, a
-    # multiple of 6 (whole pairs and whole triples)
+    # about 2 GB of algorithmic traffic per setting, at least 48 steps, a
+    # multiple of 12 (whole pairs and whole launches of four)
     per_step = 2 * (9 + S.ng) * BYTES[{0: "f64", 1: "f32", 2: "f16"}[S.storage]] * S.nx * S.ny
-    return max(42, int(2e9 / per_step)) // 6 * 6
+    return max(48, int(2e9 / per_step)) // 12 * 12
 
 
 def measure(S, steps: int | None = None) -> dict:
@@ -65,9 +65,9 @@ def measure(S, steps: int | None = None) -> dict:
     per_step = 2 * (9 + S.ng) * BYTES[{0: "f64", 1: "f32", 2: "f16"}[S.storage]] * S.nx * S.ny
     out = {}
     trials = [(bx, pol) for bx in SHAPES for pol in POLICIES] + [(64, pol) for pol in FUSED]
-    S.set_launch(64, 4, 1, lbm.LBM_POLICY_FUSE3)
-    if S.steps_per_launch == 3:
-        trials += [(64, pol) for pol in FUSED3]
+    S.set_launch(64, 4, 1, lbm.LBM_POLICY_FUSEK)
+    if S.steps_per_launch > 2:
+        trials += [(64, pol) for pol in FUSEDK]
     for bx, pol in trials:
         S.set_launch(bx, 256 // bx, 1, pol)
         S.step(12)
@@ -129,9 +129,9 @@ def markdown(rows, sizes, models, storages) -> str:
            "",
            "Algorithmic GB/s (2 (9 + NG) stored values per node and step) for block width bx (64 x 4, 128 x 2, "
            "256 x 1 threads) and policy mask p (1 XCD bands, 2 kept stores, 4 XCD strips, 8 fused pairs of "
-           "steps, 16 three steps per launch (with 8: remainders as pairs), 0 round-robin XCD order with "
-           "non-temporal stores, one step per launch).  Fused policies are listed under bx 64: their 64 x TY "
-           "tiles do not use the block width.", "",
+           "steps, 16 K = 4 steps per launch (with 8: remainders as pairs), 0 round-robin XCD order with "
+           "non-temporal stores, one step per launch).  Fused policies are listed under bx 64: their tiles "
+           "do not use the block width.", "",
            "| n | model | storage | footprint MB | default bx/p | GB/s | best bx/p | GB/s | best single step bx/p | GB/s |",
            "|---:|---|---|---:|---|---:|---|---:|---|---:|"]
     for r in rows:

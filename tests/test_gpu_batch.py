@@ -235,11 +235,11 @@ def test_fused_batch_policy_rules():
     S = B.new_solver(64, 64)
     S.set_params(W.cavity(64, 1e4))
     B.add(S)
-    assert B.steps_per_launch == 3            # FP64: three steps per launch by default
+    assert B.steps_per_launch == 4            # FP64: four steps per launch by default
     B.set_policy(0)
     assert B.steps_per_launch == 1
     B.set_policy(lbm.LBM_POLICY_DEFAULT)
-    assert B.steps_per_launch == 3
+    assert B.steps_per_launch == 4
     # a wall rebuilt by extrapolation on a one-column edge tile: single steps
     S2 = B.new_solver(129, 40)
     pb2 = W.with_nee_walls(W.cavity(129, 1e4, ny=40))
@@ -250,7 +250,7 @@ def test_fused_batch_policy_rules():
     fa, ga = _alone(pb2, None, "f64", 9)
     assert np.array_equal(fa, S2.get_populations()[0])
     B.remove(slot2)
-    assert B.steps_per_launch == 3
+    assert B.steps_per_launch == 4
     for bad in (1, 4, 8 | 1, -3):
         with pytest.raises(lbm.LbmError):
             B.set_policy(bad)

@@ -159,15 +159,15 @@ def test_xcd_strips_order_does_not_change_results(launch):
 
 
 @pytest.mark.parametrize("n,storage,model,policy", [
-    # FP64 with D2Q5 or no temperature: three steps per launch with bands at
+    # FP64 with D2Q5 or no temperature: K steps per launch with bands at
     # every size (pairs allowed for remainders), kept stores within the
     # last-level cache
     (64, "f64", "d2q5", 27), (1024, "f64", "d2q5", 27), (2048, "f64", "d2q5", 25), (4096, "f64", "d2q5", 25),
     (3072, "f64", "isothermal", 25), (2048, "f64", "isothermal", 25), (512, "f64", "isothermal", 27),
-    # FP32: fused pairs within the last-level cache, three steps beyond it
+    # FP32: fused pairs within the last-level cache, K steps beyond it
     (1024, "f32", "d2q5", 11), (2048, "f32", "d2q5", 25), (3072, "f32", "d2q5", 25), (2048, "f32", "isothermal", 25),
     (1024, "f32", "isothermal", 11),
-    # no three-step kernel (D2Q9 thermal): FP64 48 or more tiles wide takes XCD strips
+    # no multi-step kernel (D2Q9 thermal): FP64 48 or more tiles wide takes XCD strips
     (3072, "f64", "d2q9t", 12), (2048, "f64", "d2q9t", 9),
     # FP16: fused pairs with bands for every model and size
     (1024, "f16", "d2q5", 11), (2048, "f16", "d2q5", 11), (2048, "f16", "d2q9t", 9), (3072, "f16", "d2q5", 9),
@@ -357,7 +357,7 @@ def test_graph_replays_match_eager_launches():
 def test_buffers_above_4gib_match_the_buffer_path():
     """A population buffer of 4 GiB or more is addressed with 64-bit
     pointers and steps singly; a buffer below 4 GiB uses buffer descriptors
-    and, for FP64, three steps per launch.  An x-periodic Rayleigh-Benard cell 6208
+    and, for FP64, four steps per launch.  An x-periodic Rayleigh-Benard cell 6208
     wide (4.3 GB per buffer) whose initial temperature repeats every 64
     columns must equal, column for column and bitwise, the 64-wide cell."""
     ny, nx_big, reps = 6208, 6208, 97
@@ -370,7 +370,7 @@ def test_buffers_above_4gib_match_the_buffer_path():
         S = lbm.Solver(nx, ny, "f64")
         S.set_params(pb)
         S.init_temperature(np.tile(T, (1, nx // 64)))
-        assert S.steps_per_launch == (3 if nx == 64 else 1)
+        assert S.steps_per_launch == (4 if nx == 64 else 1)
         S.step(5)
         out.append(S.get_populations())
         S.close()
@@ -390,8 +390,8 @@ def test_profile_trace(capfd, monkeypatch):
     S.set_params(pb)
     S.step(100)          # a captured graph of 64 steps and a tail of 36
     S.step(7)
-    # three steps per launch (FP64): the graph holds 21 and a single step,
-    # the tail 12, the call of 7 two and a single step
+    # four steps per launch (FP64): the graph holds 16, the tail 9, the
+    # call of 7 one, a pair and a single step
     S.step(0)
     S.close()
     lines = [l for l in capfd.readouterr().err.splitlines() if l.startswith('{"lbm_profile"')]
@@ -399,7 +399,7 @@ def test_profile_trace(capfd, monkeypatch):
     rec = json.loads(lines[0])["lbm_profile"]
     assert rec["nx"] == 64 and rec["ny"] == 64 and rec["storage"] == "f64"
     assert rec["calls"] == 2 and rec["steps"] == 107
-    assert rec["launches"] == 22 + 12 + 3 and rec["gpu_ms"] > 0 and rec["mlups"] > 0
+    assert rec["launches"] == 16 + 9 + 3 and rec["gpu_ms"] > 0 and rec["mlups"] > 0
     S2 = lbm.Solver(64, 64, "f64")     # not traced
     S2.set_params(pb)
     S2.step(10)
