@@ -339,8 +339,8 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           every step where no kernel exists.
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; K steps per launch with bands
- * where that kernel exists, for FP64 at any F and for FP32 once
- * F > 256 MiB; otherwise fused pairs, with bands, or strips (with a
+ * where that kernel exists, for FP64 at any F and for FP32 with
+ * F > 256 MiB or F <= 96 MiB; otherwise fused pairs, with bands, or strips (with a
  * multiple of 8 tiles per row) once one row of fused tiles (tiles and
  * halos, every plane) exceeds 3 MiB or an FP64 lattice is 48 or more tiles
  * wide.  Fused pairs stay allowed beside K-step launches. */

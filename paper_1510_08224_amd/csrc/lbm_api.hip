@@ -213,10 +213,12 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // lines there; above it non-temporal stores win.  K = 4 steps per launch
 // (LBM_POLICY_FUSEK; FP64 and FP32 storage, the D2Q5 model or no
 // temperature field) win for FP64 at every size (D2Q5 over the best fused
-// pair: 512^2 +17%, 1024^2 +14% with kept stores, 2048^2 and 4096^2 +52%;
-// the flow alone +9% to +56%, within 5% of the pair at 512^2) and for FP32
-// beyond the last-level cache (2048^2 and 4096^2: D2Q5 +9% and +14%, the
-// flow alone +22% and +29%; at 1024^2 the D2Q5 pair is 11% faster); they
+// pair: 512^2 +16%, 1024^2 +15% with kept stores, 2048^2 +52%, 4096^2
+// +55%; the flow alone +9% to +55%, within 4% of the pair at 512^2) and for
+// FP32 beyond the last-level cache (2048^2 and 4096^2: D2Q5 +10% and +15%, the
+// flow alone +23% and +29%) and up to 96 MiB (512^2: D2Q5 +11%, the flow
+// alone +15%; 1024^2 flow alone, 75 MB, +5%), but not for the 117 MB FP32
+// D2Q5 state of 1024^2 (the pair with kept stores 10% faster); they
 // need XCD bands (strips or round robin took 8-59% longer).  Fused pairs
 // (LBM_POLICY_FUSE2) win over single steps for every storage and model at
 // every size (FP16 included: 2048^2 D2Q5, a 235 MB state, +13% over kept
@@ -228,8 +230,9 @@ static void default_policy(lbm_solver* h) {
     const double ws = 2.0 * (double)h->buf_bytes, mib = 1024.0 * 1024.0;
     h->L.keep = ws <= 256.0 * mib;
     h->L.fuse2 = true;
+    const bool f32k = ws > 256.0 * mib || ws <= 96.0 * mib;
     h->L.fusek = fusek_launch_steps(h->storage, h->ng) > 0 &&
-                 (h->storage == LBM_F64 || (h->storage == LBM_F32 && ws > 256.0 * mib));
+                 (h->storage == LBM_F64 || (h->storage == LBM_F32 && f32k));
     if (h->L.fusek) {
         h->L.order = 1;
     } else {

@@ -164,9 +164,10 @@ def test_xcd_strips_order_does_not_change_results(launch):
     # last-level cache
     (64, "f64", "d2q5", 27), (1024, "f64", "d2q5", 27), (2048, "f64", "d2q5", 25), (4096, "f64", "d2q5", 25),
     (3072, "f64", "isothermal", 25), (2048, "f64", "isothermal", 25), (512, "f64", "isothermal", 27),
-    # FP32: fused pairs within the last-level cache, K steps beyond it
+    # FP32: K steps beyond the last-level cache and up to 96 MiB (kept
+    # stores), fused pairs between
     (1024, "f32", "d2q5", 11), (2048, "f32", "d2q5", 25), (3072, "f32", "d2q5", 25), (2048, "f32", "isothermal", 25),
-    (1024, "f32", "isothermal", 11),
+    (1024, "f32", "isothermal", 27), (512, "f32", "d2q5", 27), (64, "f32", "d2q5", 27), (1200, "f32", "isothermal", 11),
     # no multi-step kernel (D2Q9 thermal): FP64 48 or more tiles wide takes XCD strips
     (3072, "f64", "d2q9t", 12), (2048, "f64", "d2q9t", 9),
     # FP16: fused pairs with bands for every model and size
