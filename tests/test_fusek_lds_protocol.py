@@ -120,6 +120,9 @@ def _cases(shape):
     TX, TY, _ = shape
     sizes = [(1, 1), (1, 6), (7, 1), (2, 2), (3, 7), (2, 11), (33, 3), (32, 16), (34, 17), (65, 3), (64, 8),
              (66, 9), (129, 17), (70, 45), (130, 70), (200, 33)]
+    if shape != BUILT:
+        # the generic form, not built: lattices up to a few tiles
+        sizes = [sz for sz in sizes if sz[0] * sz[1] <= 129 * 17]
     for nx, ny in sizes:
         for px in (False, True):
             for py in (False, True):
