@@ -323,20 +323,22 @@ int32_t lbm_model_of(const lbm_solver* h);
  *                           otherwise: nx % 64 == 1 or ny % 12 (8) == 1);
  *                           otherwise steps run singly
  *                           (lbm_steps_per_launch tells which);
- *   LBM_POLICY_FUSEK        lbm_step runs K = 4 time steps in one launch
- *                           where a kernel exists (FP64 and FP32 storage,
- *                           the D2Q5 model or no temperature field, every
- *                           collision operator): a workgroup steps its
- *                           32 x 16 tile grown by three nodes from HBM into
- *                           LDS, the tile grown by two and by one node from
- *                           LDS, and the tile into HBM, so the state crosses
- *                           HBM once per four steps (lbm_steps_per_launch
- *                           gives K).  Bitwise the same results.  Same
- *                           conditions as LBM_POLICY_FUSE2 (32 x 16 tiles:
- *                           nx % 32 == 1 or ny % 16 == 1 with NEE walls
- *                           falls back); steps left over run as a pair
- *                           (with LBM_POLICY_FUSE2) or singly, and so does
- *                           every step where no kernel exists.
+ *   LBM_POLICY_FUSEK        lbm_step runs K time steps in one launch where
+ *                           a kernel exists (every collision operator):
+ *                           K = 4 on 32 x 16 tiles for FP64 and FP32
+ *                           storage with the D2Q5 model or no temperature
+ *                           field, K = 3 on 32 x 8 tiles for FP64 storage
+ *                           with the D2Q9 thermal model.  A workgroup steps
+ *                           its tile grown by K - 1 nodes from HBM into LDS,
+ *                           the tile grown by K - 2 .. 1 nodes from LDS, and
+ *                           the tile into HBM, so the state crosses HBM once
+ *                           per K steps (lbm_steps_per_launch gives K).
+ *                           Bitwise the same results.  Same conditions as
+ *                           LBM_POLICY_FUSE2 (with NEE walls, a last tile
+ *                           one node wide or high, nx % 32 == 1 or
+ *                           ny % 16 (8) == 1, falls back); steps left over
+ *                           run as a pair (with LBM_POLICY_FUSE2) or singly,
+ *                           and so does every step where no kernel exists.
  * The default follows the storage and the footprint F of both population
  * buffers: kept stores while F <= 256 MiB; K steps per launch with bands
  * where that kernel exists, for FP64 at any F and for FP32 with
@@ -363,7 +365,8 @@ enum {
 int lbm_set_launch(lbm_solver* h, int32_t block_x, int32_t block_y, int32_t rows_per_thread, int32_t policy);
 
 /* Time steps one step-kernel launch advances with the current parameters
- * and launch settings: K (4) when K-step launches are in use, 2 when fused
+ * and launch settings: K (4, or 3 for the D2Q9 thermal model) when K-step
+ * launches are in use, 2 when fused
  * pairs are, else 1 (remainders of a step count run shorter launches). */
 int lbm_steps_per_launch(const lbm_solver* h, int32_t* steps);
 int lbm_get_launch(const lbm_solver* h, int32_t* block_x, int32_t* block_y, int32_t* rows_per_thread,
@@ -413,8 +416,7 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
  * steps for all members, the same tiles).  policy: LBM_POLICY_DEFAULT, or
  * a mask of LBM_POLICY_FUSE2 and LBM_POLICY_FUSEK (0: one launch per
  * step).  The default fuses pairs for FP64 and FP32 storage and steps FP16
- * once per launch, and takes K steps per launch for FP64 storage (the
- * D2Q5 model or no temperature field).  A kind of fused launch
+ * once per launch, and takes K steps per launch for FP64 storage.  A kind of fused launch
  * applies only when every member qualifies (buffers below 4 GiB; with
  * walls by non-equilibrium extrapolation, no one-node edge tile); steps
  * left over run as a pair or singly.  Results are bitwise the same either

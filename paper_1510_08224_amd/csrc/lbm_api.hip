@@ -219,7 +219,9 @@ int lbm_required_bytes(int32_t nx, int32_t ny, int32_t storage, int32_t model, u
 // flow alone +23% and +29%) and up to 96 MiB (512^2: D2Q5 +11%, the flow
 // alone +15%; 1024^2 flow alone, 75 MB, +5%), but not for the 117 MB FP32
 // D2Q5 state of 1024^2 (the pair with kept stores 10% faster); they
-// need XCD bands (strips or round robin took 8-59% longer).  Fused pairs
+// need XCD bands (strips or round robin took 8-59% longer).  The FP64 D2Q9
+// thermal model takes three steps per launch on 32 x 8 tiles (per step:
+// 512^2 -3%, 1024^2 -16%, 2048^2 and 4096^2 -21% against the best pair).  Fused pairs
 // (LBM_POLICY_FUSE2) win over single steps for every storage and model at
 // every size (FP16 included: 2048^2 D2Q5, a 235 MB state, +13% over kept
 // single stores; the flow alone +9% to +22%), with bands, or strips (with
@@ -1364,10 +1366,11 @@ static int batch_build(lbm_batch* b) {
     const double mib = 1024.0 * 1024.0;
     // K steps per launch for FP64 batches (batches of equal cavities,
     // 6.7e6 nodes in all: 9-31% less time per step than fused pairs, sides
-    // 64 to 1024; single FP64 lattices gain at every size); FP32 batches
-    // keep fused pairs, which were up to 16% faster at sides 128 to 512 (the
-    // margins of small members take the general path; K steps won by 3-14%
-    // at sides 64, 96 and 1024).
+    // 64 to 1024; the D2Q9 thermal model 7-19% less at sides 64, 256, 512
+    // and 1024, 5% more at 128; single FP64 lattices gain at every size);
+    // FP32 batches keep fused pairs, which were up to 16% faster at sides
+    // 128 to 512 (the margins of small members take the general path; K
+    // steps won by 3-14% at sides 64, 96 and 1024).
     const bool want = b->policy == LBM_POLICY_DEFAULT
                           ? (b->storage == LBM_F64 || b->storage == LBM_F32)
                           : (b->policy & LBM_POLICY_FUSE2) != 0;

@@ -8,10 +8,10 @@
 //   k_sweep_batch    the same step for every lattice of a batch
 //   k_sweep2(_batch) two time steps per launch: the first on a tile and its
 //                    halo into LDS, the second from LDS to memory
-//   k_sweepk(_batch) four time steps per launch (FP64 / FP32, D2Q5 or no
-//                    temperature): the tile grown by three nodes from memory
-//                    into LDS, grown by two and one within LDS, the tile to
-//                    memory
+//   k_sweepk(_batch) K time steps per launch (FP64 / FP32, D2Q5 or no
+//                    temperature: four; FP64 D2Q9 thermal: three): the tile
+//                    grown by K - 1 nodes from memory into LDS, grown by
+//                    K - 2 .. 1 within LDS, the tile to memory
 //   k_moments        rho, u, T at time t (Eqs. 18, 19, 27)
 //   k_gather         pre-collision populations at time t, FP64
 //   k_unstream       write a buffer whose pull yields given pre-collision
@@ -1002,16 +1002,19 @@ __device__ __forceinline__ bool fk_open_tile(const Geom& G, int x0, int y0) {
 // 32 x 16 or 32 x 8 tiles (four workgroups per CU) took 64.8 us each,
 // on 32 x 12 (three per CU, spilling) 82.5; four steps on 64 x 8 tiles
 // would need 91 KB for FP64, one workgroup per CU, and took 45.0 against
-// 42.4 us per FP32 step, its window updated in place.  The kernel takes any
-// K >= 3 and any tile whose window fits half the LDS.
+// 42.4 us per FP32 step, its window updated in place.  The D2Q9 thermal
+// model (18 planes) takes three steps on 32 x 8 tiles: a 49 KB FP64 window,
+// three workgroups per CU; 2048^2 FP64 85.7 against 108.8 us per step for
+// fused pairs (4096^2 323.0 against 409.9, 1024^2 26.2 against 31.3).  The
+// kernel takes any K >= 3 and any tile whose window fits half the LDS.
 template <class S, int NG>
 constexpr int fusek_steps() {
-    return 4;
+    return NG == 9 ? 3 : 4;
 }
 
 template <class S, int NG, int K>
 constexpr int fusek_rows() {
-    return 16;
+    return NG == 9 ? 8 : 16;
 }
 
 template <class S, int NG, int K>
@@ -1565,18 +1568,17 @@ static hipError_t sweep2_t(const Launch& L, const Geom& G, const Coeffs& Ch, con
 
 
 // K steps per launch, every collision operator: FP64 and FP32 storage with
-// the D2Q5 model or no temperature field.  Not for the D2Q9 thermal model:
-// its FP64 window (18 planes of 36 x 20 doubles) would take more than half
-// a CU's LDS, and in FP32 the in-place middle step spilled about 1 KB per
-// lane (three steps on 64 x 8 tiles) at the four waves per SIMD two
-// workgroups per CU need.  Not for FP16 storage: the kernel is generic over
-// the storage (bitwise equal to single steps, tested), but on MI355X three
-// steps per launch on 64 x 8 tiles lost to FP16 fused pairs at every size
-// (2048^2 D2Q5 45.7 against 33.6 us per step, 4096^2 172 against 140), the
-// conversions of every value to and from FP16 making the longer launch
-// issue-bound.
+// the D2Q5 model or no temperature field, and FP64 storage with the D2Q9
+// thermal model.  Not for FP32 D2Q9 thermal: three steps on 32 x 8 tiles
+// (two buffers, no spill) were only 1-3% faster than fused pairs at 2048^2
+// and 4096^2 and 22% slower at 512^2.  Not for FP16 storage: the kernel is
+// generic over the storage (bitwise equal to single steps, tested), but on
+// MI355X three steps per launch on 64 x 8 tiles lost to FP16 fused pairs at
+// every size (2048^2 D2Q5 45.7 against 33.6 us per step, 4096^2 172
+// against 140), the conversions of every value to and from FP16 making the
+// longer launch issue-bound.
 static constexpr bool fusek_built(int storage, int ng) {
-    return (storage == kF64 || storage == kF32) && (ng == 5 || ng == 0);
+    return ((storage == kF64 || storage == kF32) && (ng == 5 || ng == 0)) || (storage == kF64 && ng == 9);
 }
 
 // Runs the statement with S and NG bound for every built multi-step kernel.
@@ -1584,6 +1586,7 @@ static constexpr bool fusek_built(int storage, int ng) {
     switch ((storage) * 16 + (ng)) {                                                      \
         case kF64 * 16 + 0: { using S = double; constexpr int NG = 0; __VA_ARGS__; } break; \
         case kF64 * 16 + 5: { using S = double; constexpr int NG = 5; __VA_ARGS__; } break; \
+        case kF64 * 16 + 9: { using S = double; constexpr int NG = 9; __VA_ARGS__; } break; \
         case kF32 * 16 + 0: { using S = float; constexpr int NG = 0; __VA_ARGS__; } break;  \
         case kF32 * 16 + 5: { using S = float; constexpr int NG = 5; __VA_ARGS__; } break;  \
         default: break;                                                                   \

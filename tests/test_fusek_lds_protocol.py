@@ -12,13 +12,17 @@ For every tile of lattices from 1 x 1 up, with periodic, link-wise and
 extrapolation sides, it checks: every access lies in the window, no entry
 has two writers in a step, and every entry a step reads was written by the
 step before it (with one buffer updated in place, an entry left from an
-earlier step must not be read).  The built kernel (32 x 16 tiles, K = 4)
-and the generic form with 64 x 8 tiles and K = 3 are modelled.  No GPU is
+earlier step must not be read).  The built kernels (32 x 16 tiles with
+K = 4 for the D2Q5 model and the flow alone, 32 x 8 tiles with K = 3 for
+the D2Q9 thermal model) and the generic form with 64 x 8 tiles and K = 3 are
+modelled.  No GPU is
 used; the GPU tests check the values."""
 import pytest
 
-BUILT = (32, 16, 4)
-SHAPES = [BUILT, (64, 8, 3)]
+# (tile and K, temperature populations) of the built kernels, then the
+# generic form with 64 x 8 tiles and K = 3
+BUILT = [((32, 16, 4), 5), ((32, 16, 4), 0), ((32, 8, 3), 9)]
+FORMS = BUILT + [((64, 8, 3), 5)]
 EX = (0, 1, 0, -1, 0, 1, -1, -1, 1)
 EY = (0, 0, 1, 0, -1, 1, 1, -1, -1)
 LEFT, RIGHT, BOTTOM, TOP = 0, 1, 2, 3
@@ -116,28 +120,27 @@ def _tile_protocol(shape, nx, ny, px, py, nee, ng, x0, y0):
     return counts
 
 
-def _cases(shape):
+def _cases(shape, ng):
     TX, TY, _ = shape
     sizes = [(1, 1), (1, 6), (7, 1), (2, 2), (3, 7), (2, 11), (33, 3), (32, 16), (34, 17), (65, 3), (64, 8),
              (66, 9), (129, 17), (70, 45), (130, 70), (200, 33)]
-    if shape != BUILT:
+    if (shape, ng) not in BUILT:
         # the generic form, not built: lattices up to a few tiles
         sizes = [sz for sz in sizes if sz[0] * sz[1] <= 129 * 17]
     for nx, ny in sizes:
         for px in (False, True):
             for py in (False, True):
-                yield shape, nx, ny, px, py, (False,) * 4
+                yield shape, ng, nx, ny, px, py, (False,) * 4
                 # extrapolation walls on the non-periodic sides, where the
                 # launch allows them (no one-node last tile on such an axis)
                 nee = (not px and nx % TX != 1 and nx >= 3, not px and nx % TX != 1 and nx >= 3,
                        not py and ny % TY != 1 and ny >= 3, not py and ny % TY != 1 and ny >= 3)
                 if any(nee):
-                    yield shape, nx, ny, px, py, nee
+                    yield shape, ng, nx, ny, px, py, nee
 
 
-@pytest.mark.parametrize("ng", [5, 0])
-@pytest.mark.parametrize("shape,nx,ny,px,py,nee", [c for sh in SHAPES for c in _cases(sh)])
-def test_multi_step_lds_protocol(shape, nx, ny, px, py, nee, ng):
+@pytest.mark.parametrize("shape,ng,nx,ny,px,py,nee", [c for sh, ng in FORMS for c in _cases(sh, ng)])
+def test_multi_step_lds_protocol(shape, ng, nx, ny, px, py, nee):
     TX, TY, K = shape
     total = None
     for y0 in range(0, ny, TY):
@@ -154,7 +157,7 @@ def test_multi_step_lds_protocol(shape, nx, ny, px, py, nee, ng):
             assert sum(c) == sum((TX + 2 * m) * (TY + 2 * m) for m in range(K))
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", sorted({sh for sh, _ in FORMS}))
 def test_one_node_edge_tile_breaks_extrapolation(shape):
     """Why the launch falls back to single steps when a lattice with walls
     by extrapolation leaves a one-node last tile: the wall node's fluid

@@ -1,12 +1,14 @@
-"""K = 4 time steps per launch (LBM_POLICY_FUSEK): the kernel steps a 32 x 16
-tile grown by three nodes from HBM into LDS, the tile grown by two and by
-one node within LDS, and the tile again into HBM.  It must give bitwise the
-populations of four single steps for FP64 and FP32 storage, the D2Q5 model
-and the flow alone, every collision operator and wall family, ragged,
-periodic and open tiles, graph replay, and remainders run as pairs or
-single steps.  Where no multi-step kernel exists (FP16 storage, the D2Q9
-thermal model) or NEE walls leave a one-node edge tile, lbm_step falls back
-to the pair (or single steps) and says so through lbm_steps_per_launch."""
+"""K time steps per launch (LBM_POLICY_FUSEK): the kernel steps a tile grown
+by K - 1 nodes from HBM into LDS, the tile grown by K - 2 .. 1 nodes within
+LDS, and the tile again into HBM (K = 4 on 32 x 16 tiles for FP64 and FP32
+storage with the D2Q5 model or the flow alone; K = 3 on 32 x 8 tiles for
+FP64 storage with the D2Q9 thermal model).  It must give bitwise the
+populations of K single steps for every collision operator and wall family,
+ragged, periodic and open tiles, graph replay, and remainders run as pairs
+or single steps.  Where no multi-step kernel exists (FP16 storage, FP32 with
+the D2Q9 thermal model) or NEE walls leave a one-node edge tile, lbm_step
+falls back to the pair (or single steps) and says so through
+lbm_steps_per_launch."""
 import numpy as np
 import pytest
 
@@ -17,7 +19,8 @@ from test_gpu_fuse2 import CASES, _lid, _run, _sides
 
 pytestmark = pytest.mark.gpu
 F2, FK = lbm.LBM_POLICY_FUSE2, lbm.LBM_POLICY_FUSEK
-K = 4
+K = 4        # D2Q5 and the flow alone
+K9 = 3       # the D2Q9 thermal model (FP64)
 BANDS, STRIPS, KEEP = lbm.LBM_POLICY_XCD_BANDS, lbm.LBM_POLICY_XCD_STRIPS, lbm.LBM_POLICY_KEEP_STORES
 
 # built for FP64 and FP32 storage with D2Q5 or no temperature field; 32 x 16
@@ -27,7 +30,11 @@ FALLBACKK = {"nee_last_column_one_wide", "nee_top_row_one_high"}
 
 
 def _built(model, storage):
-    return model in ("d2q5", "isothermal") and storage in ("f64", "f32")
+    return (model in ("d2q5", "isothermal") and storage in ("f64", "f32")) or (model == "d2q9t" and storage == "f64")
+
+
+def _k(model):
+    return K9 if model == "d2q9t" else K
 
 
 def _multi(case, storage):
@@ -45,7 +52,7 @@ def test_k_steps_equal_single_steps(case, storage):
     # three steps over
     steps = [1, 4, 2, 8, 9, 10, 11]
     (fa, ga), ta = _run(model, pb, storage, steps, 0, 0, T, spl=1)
-    k = K if _multi(case, storage) else 1
+    k = _k(model) if _multi(case, storage) else 1
     for pol in (FK, FK | BANDS | KEEP, FK | STRIPS):
         (fb, gb), tb = _run(model, pb, storage, steps, pol, 0, T, spl=k)
         assert ta == tb == sum(steps)
@@ -53,7 +60,7 @@ def test_k_steps_equal_single_steps(case, storage):
     # with pairs allowed too: remainders of two run as a pair, and lattices
     # without a multi-step kernel take pairs
     pair = 1 if case in ("nee_last_column_one_wide", "nee_top_row_one_high") else 2
-    (fb, gb), tb = _run(model, pb, storage, steps, FK | F2 | BANDS, 0, T, spl=K if k == K else pair)
+    (fb, gb), tb = _run(model, pb, storage, steps, FK | F2 | BANDS, 0, T, spl=k if k > 1 else pair)
     assert ta == tb
     assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
 
@@ -72,11 +79,11 @@ def test_k_steps_graph_replay(storage):
         assert np.array_equal(got[0][0], ref[0][0]) and np.array_equal(got[0][1], ref[0][1]), graph
 
 
-@pytest.mark.parametrize("model", ["d2q5", "isothermal"])
+@pytest.mark.parametrize("model", ["d2q5", "isothermal", "d2q9t"])
 def test_k_steps_match_oracle(model):
     pb = W.with_nee_walls(W.cavity(100, 1e5, ny=44)) if model != "isothermal" else _lid(100).replace(ny=44)
     S, L = run_pair(pb, 42, launch=(0, 0, 0, FK | BANDS), model=model)
-    assert S.steps_per_launch == K
+    assert S.steps_per_launch == _k(model)
     fa, ga = S.get_populations()
     fo, go = L.get_state()
     ef, eg = max_rel_pop_error(pb, fa, ga, fo, go)
@@ -84,19 +91,19 @@ def test_k_steps_match_oracle(model):
     S.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_k_steps_full_size(storage):
+@pytest.mark.parametrize("storage,model", [("f64", "d2q5"), ("f32", "d2q5"), ("f64", "d2q9t")])
+def test_k_steps_full_size(storage, model):
     """The 2048^2 heated cavity of the benchmark, in the launch it times:
     K steps per launch equal K single steps bitwise."""
     pb = W.workload_cavity2048()
     runs = []
     for pol in (0, FK | BANDS):
-        S = lbm.Solver(2048, 2048, storage)
+        S = lbm.Solver(2048, 2048, storage, model=model)
         S.set_params(pb)
         S.set_launch(policy=pol)
         S.step(9)
         runs.append(S.get_populations())
-        assert S.steps_per_launch == (K if pol else 1)
+        assert S.steps_per_launch == (_k(model) if pol else 1)
         S.close()
     assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
 
@@ -104,18 +111,18 @@ def test_k_steps_full_size(storage):
 # lattices narrower or shorter than the tile and its three-node margin, one
 # node wide, and sizes one past a tile edge: every step's region must still
 # visit each node once (periodic axes wrap the margins several times)
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage,model", [("f64", "d2q5"), ("f32", "d2q5"), ("f64", "d2q9t")])
 @pytest.mark.parametrize("nx,ny", [(1, 1), (1, 6), (7, 1), (2, 2), (3, 7), (2, 11), (33, 3), (32, 16), (34, 17),
                                    (65, 3), (66, 9), (129, 17), (70, 5)])
-def test_k_steps_degenerate_sizes(storage, nx, ny):
+def test_k_steps_degenerate_sizes(storage, model, nx, ny):
     T = W.random_temperature(nx, ny, 0.0, 1.0, seed=nx * 100 + ny + 7)
     for px in (False, True):
         for py in (False, True):
             pb = _sides(W.cavity(max(nx, ny), 1e4).replace(nx=nx, ny=ny, wall_u=((0.0, 0.01), (0.0, -0.02),
                                                                                    (0.03, 0.0), (0.05, 0.0))),
                         px, py)
-            (fa, ga), _ = _run("d2q5", pb, storage, [1, 4, 3, 8], 0, 0, T, spl=1)
-            (fb, gb), _ = _run("d2q5", pb, storage, [1, 4, 3, 8], FK, 0, T, spl=K)
+            (fa, ga), _ = _run(model, pb, storage, [1, 4, 3, 8], 0, 0, T, spl=1)
+            (fb, gb), _ = _run(model, pb, storage, [1, 4, 3, 8], FK, 0, T, spl=_k(model))
             assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (px, py)
 
 
@@ -206,4 +213,32 @@ def test_k_step_batch_policy_rules():
     for bad in (1, 4, 32, FK | 1, -3):
         with pytest.raises(lbm.LbmError):
             B.set_policy(bad)
+    B.close()
+
+
+def test_d2q9t_k_step_batch_matches_alone_bitwise():
+    """FP64 batches of D2Q9 thermal members take three steps per launch by
+    default; every member equals its single steps alone."""
+    mix = [W.cavity(70, 1e5, ny=45), W.with_nee_walls(W.cavity(96, 2e5, ny=70)), W.rayleigh_benard(130, 37, 2e4),
+           W.cavity(33, 1e4, ny=17)]
+    B = lbm.Batch("f64")
+    sols = []
+    for pb in mix:
+        S = B.new_solver(pb.nx, pb.ny, model="d2q9t")
+        S.set_params(pb)
+        B.add(S)
+        sols.append(S)
+    assert B.steps_per_launch == K9
+    B.step(37)            # 12 three-step launches and one single step
+    B.step(26)            # 8 three-step launches and a pair
+    for pb, S in zip(mix, sols):
+        A = lbm.Solver(pb.nx, pb.ny, "f64", model="d2q9t")
+        A.set_params(pb)
+        A.set_launch(policy=0)
+        A.step(63)
+        fa, ga = A.get_populations()
+        A.close()
+        fb, gb = S.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), pb.name
+        assert S.time == 63
     B.close()

@@ -168,8 +168,8 @@ def test_xcd_strips_order_does_not_change_results(launch):
     # stores), fused pairs between
     (1024, "f32", "d2q5", 11), (2048, "f32", "d2q5", 25), (3072, "f32", "d2q5", 25), (2048, "f32", "isothermal", 25),
     (1024, "f32", "isothermal", 27), (512, "f32", "d2q5", 27), (64, "f32", "d2q5", 27), (1200, "f32", "isothermal", 11),
-    # no multi-step kernel (D2Q9 thermal): FP64 48 or more tiles wide takes XCD strips
-    (3072, "f64", "d2q9t", 12), (2048, "f64", "d2q9t", 9),
+    # D2Q9 thermal: K steps for FP64 too; FP32 (no multi-step kernel) fused pairs
+    (3072, "f64", "d2q9t", 25), (2048, "f64", "d2q9t", 25), (512, "f64", "d2q9t", 27), (2048, "f32", "d2q9t", 9),
     # FP16: fused pairs with bands for every model and size
     (1024, "f16", "d2q5", 11), (2048, "f16", "d2q5", 11), (2048, "f16", "d2q9t", 9), (3072, "f16", "d2q5", 9),
     (4096, "f16", "d2q5", 9), (1024, "f16", "isothermal", 11), (4096, "f16", "isothermal", 9)])
