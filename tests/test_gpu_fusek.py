@@ -242,3 +242,25 @@ def test_d2q9t_k_step_batch_matches_alone_bitwise():
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb), pb.name
         assert S.time == 63
     B.close()
+
+
+# walls rebuilt by extrapolation with a one-node last tile: K-step tiles are
+# 32 wide and 16 (D2Q5, no temperature) or 8 (D2Q9 thermal) high, pair tiles
+# 64 wide and 8 high (12 for FP32 D2Q5); each launch kind falls back on its
+# own, so a lattice may lose the K-step launch and keep the pair
+@pytest.mark.parametrize("model,storage,nx,ny,spl", [
+    ("d2q5", "f64", 97, 40, 2),      # 97 % 32 == 1: pairs
+    ("d2q5", "f64", 100, 49, 1),     # 49 % 16 == 1 and 49 % 8 == 1: single steps
+    ("d2q5", "f64", 100, 41, 4),     # 41 % 16 == 9: K steps
+    ("d2q5", "f32", 97, 40, 2),      # FP32 pair tiles are 12 high: 40 % 12 == 4
+    ("d2q9t", "f64", 100, 41, 1),    # 41 % 8 == 1 for both tiles
+    ("d2q9t", "f64", 97, 44, 2),     # 97 % 32 == 1, 97 % 64 == 33: pairs
+    ("d2q9t", "f64", 100, 44, 3),
+])
+def test_nee_one_node_edge_tiles_fall_back_per_launch_kind(model, storage, nx, ny, spl):
+    pb = W.with_nee_walls(W.cavity(nx, 1e5, ny=ny))
+    T = W.random_temperature(nx, ny, 0.0, 1.0, seed=nx + ny)
+    (fa, ga), ta = _run(model, pb, storage, [5, 6], 0, 0, T, spl=1)
+    (fb, gb), tb = _run(model, pb, storage, [5, 6], FK | F2 | BANDS, 0, T, spl=spl)
+    assert ta == tb == 11
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
