@@ -652,6 +652,17 @@ __device__ __forceinline__ void collide_mrt(R f[9], R g[NG > 0 ? NG : 1], const 
 // ---------------------------------------------------------------------------
 enum Collision { kCollMRT = 0, kCollBGK = 1, kCollOrtho = 2 };
 
+// e_i . (ax, ay) for the lattice vector e_i (components -1, 0 or 1): the
+// value of ex * ax + ey * ay without its products by 0 and 1, which the
+// compiler may not drop from IEEE arithmetic.
+template <class R>
+__device__ __forceinline__ R edot(int i, R ax, R ay) {
+    const int dx = ex(i), dy = ey(i);
+    if (dx == 0) return dy == 0 ? (R)0 : (dy > 0 ? ay : -ay);
+    const R px = dx > 0 ? ax : -ax;
+    return dy == 0 ? px : (dy > 0 ? px + ay : px - ay);
+}
+
 template <class R>
 __device__ __forceinline__ void collide_flow_bgk(R f[9], const Macro& mc, const Coeffs& C) {
     const R rho = (R)mc.rho, ux = (R)mc.ux, uy = (R)mc.uy, Fx = (R)mc.Fx, Fy = (R)mc.Fy;
@@ -660,8 +671,8 @@ __device__ __forceinline__ void collide_flow_bgk(R f[9], const Macro& mc, const 
     const R uF3 = (R)3 * (ux * Fx + uy * Fy);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
-        const R eF = (R)ex(i) * Fx + (R)ey(i) * Fy;
+        const R eu = edot<R>(i, ux, uy);
+        const R eF = edot<R>(i, Fx, Fy);
         const R wi = (R)w9(i);
         const R feq = wi * (rho + (fmaR((R)4.5 * eu, eu, (R)3 * eu) - usq15));
         const R S = wi * fmaR((R)9 * eu, eF, fmaR((R)3, eF, -uF3));
@@ -725,14 +736,14 @@ __device__ __forceinline__ void collide_thermal_bgk(R g[NG > 0 ? NG : 1], const 
             g[0] = g[0] - z * (g[0] - K.one_m_varpi * t0);
 #pragma unroll
             for (int i = 1; i < 5; ++i) {
-                const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
+                const R eu = edot<R>(i, ux, uy);
                 g[i] = g[i] - z * (g[i] - ((R)0.25 * vp * t0 + (R)0.5 * eu * T));
             }
         } else {
             const R th = K.theta, usq15 = (R)1.5 * (ux * ux + uy * uy);
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const R eu = (R)ex(i) * ux + (R)ey(i) * uy;
+                const R eu = edot<R>(i, ux, uy);
                 const R geq = (R)w9(i) * (t0 + T * ((R)3 * eu + th * ((R)4.5 * eu * eu - usq15)));
                 g[i] = g[i] - z * (g[i] - geq);
             }
